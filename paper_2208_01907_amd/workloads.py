@@ -1,0 +1,375 @@
+"""Seeded synthetic inputs shared by the GPU path, the oracle, the tests and the bench.
+
+This module builds problems only: sparse symmetric matrices in CSR form, a geometric
+nested-dissection ordering handed over as data, known kernel bases and right-hand
+sides. It contains none of the factorization method's arithmetic.
+
+Workloads (they stand in for the paper's matrices, which are not available: a
+singular pure-Neumann problem class, a floating-elastic-body class with a six
+dimensional rigid-mode kernel like the Stokes example of Sec. 4.2, and strong
+coefficient contrast like the semiconductor example of Sec. 4.3):
+
+* ``neumann2d``   -- 2D cell-centred 5-point finite-volume Laplacian, no boundary
+  terms (pure Neumann), per-cell coefficient log-uniform, harmonic-mean faces.
+* ``inclusions3d`` -- 3D 7-point version on an n^3 grid, coefficient 1 with
+  random spherical inclusions at a high value.
+* ``elasticity``  -- trilinear (Q1) hexahedral linear elasticity on a cube,
+  full 2x2x2 Gauss quadrature, no Dirichlet condition (floating body).
+
+Ordering: geometric nested dissection (the m-level bisection of Sec. 2.2,
+following George 1977): the box is split across its longest axis (ties x, y, z)
+at lo + ext//2 by a one-point-thick plane; recursion stops when a box holds at
+most ``leaf_max`` points or its longest extent is below 3.  Nodes are emitted in
+postorder (left subtree, right subtree, separator); within a node points are in
+lexicographic order (x fastest) and the dofs of a point stay together.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+
+# ----------------------------------------------------------------------------
+# nested-dissection ordering (data for both sides)
+# ----------------------------------------------------------------------------
+
+def grid_nested_dissection(shape, leaf_max, dofs_per_point=1):
+    """Geometric nested dissection of a box of points.
+
+    Returns ``(perm, node_ptr, parent)``: ``perm[k]`` is the original index of the
+    k-th unknown in elimination order; node ``j`` owns positions
+    ``node_ptr[j]:node_ptr[j+1]``; ``parent[root] == -1``; nodes are in postorder.
+    Points are indexed ``x + nx*(y + ny*z)`` and dof ``c`` of point ``p`` is
+    ``dofs_per_point*p + c``.
+    """
+    shape = tuple(int(s) for s in shape)
+    dim = len(shape)
+    strides = [1]
+    for s in shape[:-1]:
+        strides.append(strides[-1] * s)
+    strides = np.array(strides, dtype=np.int64)
+
+    nodes = []      # list of point-index arrays, postorder
+    parents = []    # parent node id, filled after creation
+
+    def box_points(lo, hi):
+        axes = [np.arange(lo[a], hi[a], dtype=np.int64) for a in range(dim)]
+        grids = np.meshgrid(*axes, indexing="ij")
+        idx = np.zeros(grids[0].shape, dtype=np.int64)
+        for a in range(dim):
+            idx = idx + grids[a] * strides[a]
+        return np.sort(idx.ravel())
+
+    def rec(lo, hi):
+        ext = [hi[a] - lo[a] for a in range(dim)]
+        if min(ext) <= 0:
+            return None
+        npts = int(np.prod(ext))
+        if npts <= leaf_max or max(ext) < 3:
+            nodes.append(box_points(lo, hi))
+            parents.append(-1)
+            return len(nodes) - 1
+        axis = int(np.argmax(ext))
+        mid = lo[axis] + ext[axis] // 2
+        lhi = list(hi); lhi[axis] = mid
+        rlo = list(lo); rlo[axis] = mid + 1
+        slo = list(lo); slo[axis] = mid
+        shi = list(hi); shi[axis] = mid + 1
+        c1 = rec(list(lo), lhi)
+        c2 = rec(rlo, list(hi))
+        nodes.append(box_points(slo, shi))
+        parents.append(-1)
+        me = len(nodes) - 1
+        for c in (c1, c2):
+            if c is not None:
+                parents[c] = me
+        return me
+
+    rec([0] * dim, list(shape))
+    d = int(dofs_per_point)
+    sizes = np.array([len(n) * d for n in nodes], dtype=np.int64)
+    node_ptr = np.zeros(len(nodes) + 1, dtype=np.int32)
+    node_ptr[1:] = np.cumsum(sizes)
+    pts = np.concatenate(nodes)
+    perm = (pts[:, None] * d + np.arange(d, dtype=np.int64)[None, :]).ravel().astype(np.int32)
+    return perm, node_ptr, np.array(parents, dtype=np.int32)
+
+
+# ----------------------------------------------------------------------------
+# matrices
+# ----------------------------------------------------------------------------
+
+def _to_csr(rows, cols, vals, n):
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return A
+
+
+def fv_laplacian(cell_coef):
+    """Pure-Neumann cell-centred FV Laplacian (5-point in 2D, 7-point in 3D).
+
+    Face coefficient = harmonic mean 2 c_i c_j / (c_i + c_j); off-diagonal
+    -face, diagonal = sum of faces; no boundary terms, so constants span the
+    kernel.  ``cell_coef`` is indexed [x, y(, z)] and flattened x fastest.
+    """
+    c = np.asarray(cell_coef, dtype=np.float64)
+    shape = c.shape
+    n = c.size
+    flat = c.reshape(-1, order="F")
+    idx = np.arange(n, dtype=np.int64).reshape(shape, order="F")
+    rows, cols, vals = [], [], []
+    diag = np.zeros(n)
+    for axis in range(c.ndim):
+        a = np.take(idx, np.arange(shape[axis] - 1), axis=axis).ravel()
+        b = np.take(idx, np.arange(1, shape[axis]), axis=axis).ravel()
+        ca, cb = flat[a], flat[b]
+        face = 2.0 * ca * cb / (ca + cb)
+        rows += [a, b]
+        cols += [b, a]
+        vals += [-face, -face]
+        np.add.at(diag, a, face)
+        np.add.at(diag, b, face)
+    rows.append(np.arange(n)); cols.append(np.arange(n)); vals.append(diag)
+    return _to_csr(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), n)
+
+
+def q1_element_stiffness(h, nu):
+    """24x24 stiffness of a cubic Q1 element of side h for unit Young's modulus.
+
+    Full 2x2x2 Gauss quadrature (reduced integration would add hourglass kernel
+    modes).  Local node a = (ax, ay, az) in {0,1}^3 with x fastest; dofs are
+    interleaved (ux, uy, uz) per node.
+    """
+    lam = nu / ((1 + nu) * (1 - 2 * nu))
+    mu = 1.0 / (2 * (1 + nu))
+    C = np.zeros((6, 6))
+    C[:3, :3] = lam
+    C[np.arange(3), np.arange(3)] += 2 * mu
+    C[3, 3] = C[4, 4] = C[5, 5] = mu
+    corners = np.array([[ax, ay, az] for az in (0, 1) for ay in (0, 1) for ax in (0, 1)], dtype=float)
+    sgn = 2 * corners - 1
+    g = 1.0 / math.sqrt(3.0)
+    Ke = np.zeros((24, 24))
+    detJ = (h / 2) ** 3
+    for gz in (-g, g):
+        for gy in (-g, g):
+            for gx in (-g, g):
+                xi = np.array([gx, gy, gz])
+                dN = np.zeros((8, 3))
+                for a in range(8):
+                    f = (1 + sgn[a] * xi) / 2
+                    dN[a, 0] = sgn[a, 0] / 2 * f[1] * f[2]
+                    dN[a, 1] = f[0] * sgn[a, 1] / 2 * f[2]
+                    dN[a, 2] = f[0] * f[1] * sgn[a, 2] / 2
+                dN *= 2.0 / h
+                B = np.zeros((6, 24))
+                for a in range(8):
+                    dx, dy, dz = dN[a]
+                    B[0, 3 * a] = dx
+                    B[1, 3 * a + 1] = dy
+                    B[2, 3 * a + 2] = dz
+                    B[3, 3 * a + 1] = dz; B[3, 3 * a + 2] = dy
+                    B[4, 3 * a] = dz;     B[4, 3 * a + 2] = dx
+                    B[5, 3 * a] = dy;     B[5, 3 * a + 1] = dx
+                Ke += B.T @ C @ B * detJ
+    return 0.5 * (Ke + Ke.T)
+
+
+def q1_elasticity(ne, young, nu=0.3):
+    """Floating-body Q1 elasticity on the unit cube with ne^3 elements.
+
+    ``young`` holds one Young's modulus per element (x fastest).  Node-major
+    interleaved dofs; no boundary condition, so the 6 rigid modes span the kernel.
+    """
+    nn = ne + 1
+    h = 1.0 / ne
+    Ke = q1_element_stiffness(h, nu)
+    ex, ey, ez = np.meshgrid(np.arange(ne), np.arange(ne), np.arange(ne), indexing="ij")
+    ex, ey, ez = ex.ravel(order="F"), ey.ravel(order="F"), ez.ravel(order="F")
+    local = [(ax, ay, az) for az in (0, 1) for ay in (0, 1) for ax in (0, 1)]
+    enodes = np.stack([(ex + ax) + nn * ((ey + ay) + nn * (ez + az)) for ax, ay, az in local], axis=1)
+    edofs = (3 * enodes[:, :, None] + np.arange(3)[None, None, :]).reshape(len(ex), 24)
+    E = np.asarray(young, dtype=np.float64).ravel(order="F")
+    rows = np.repeat(edofs, 24, axis=1).ravel()
+    cols = np.tile(edofs, (1, 24)).ravel()
+    vals = (E[:, None, None] * Ke[None, :, :]).ravel()
+    K = _to_csr(rows, cols, vals, 3 * nn ** 3)
+    # exact symmetry of the stored values (assembly sums in different orders)
+    K = ((K + K.T) * 0.5).tocsr()
+    K.sort_indices()
+    return K
+
+
+def rigid_modes(ne):
+    nn = ne + 1
+    h = 1.0 / ne
+    x, y, z = np.meshgrid(np.arange(nn) * h, np.arange(nn) * h, np.arange(nn) * h, indexing="ij")
+    x, y, z = x.ravel(order="F"), y.ravel(order="F"), z.ravel(order="F")
+    n = nn ** 3
+    Z = np.zeros((3 * n, 6))
+    for c in range(3):
+        Z[c::3, c] = 1.0
+    Z[1::3, 3] = -z; Z[2::3, 3] = y
+    Z[0::3, 4] = z;  Z[2::3, 4] = -x
+    Z[0::3, 5] = -y; Z[1::3, 5] = x
+    return Z
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    indptr: np.ndarray      # int64 [L+1]
+    indices: np.ndarray     # int32 [nnz]
+    values: np.ndarray      # float64 [nnz]
+    perm: np.ndarray        # int32 [L]
+    node_ptr: np.ndarray    # int32 [n_nodes+1]
+    parent: np.ndarray      # int32 [n_nodes]
+    kernel: np.ndarray      # float64 [L, k] closed-form kernel basis (orthonormal)
+    x_star: np.ndarray      # float64 [L, r] exact solution, orthogonal to the kernel
+    b: np.ndarray           # float64 [L, r] right-hand sides K x_star
+    tau: float
+    gcr_block: int
+    meta: dict
+
+    @property
+    def n(self):
+        return len(self.indptr) - 1
+
+    @property
+    def nnz(self):
+        return len(self.indices)
+
+    @property
+    def n_nodes(self):
+        return len(self.parent)
+
+    def csr(self):
+        return sp.csr_matrix((self.values, self.indices, self.indptr), shape=(self.n, self.n))
+
+
+def _orthonormal(Z):
+    if Z.shape[1] == 0:
+        return Z
+    q, _ = np.linalg.qr(Z)
+    return q
+
+
+def make_rhs(K, kernel, r, rng):
+    """x* ~ N(0,1) projected orthogonal to the kernel, b = K x*."""
+    n = K.shape[0]
+    x = rng.standard_normal((n, r))
+    if kernel.shape[1]:
+        x = x - kernel @ (kernel.T @ x)
+    return x, np.asarray(K @ x)
+
+
+def _finish(name, K, perm, node_ptr, parent, kernel, r, seed, tau, gcr_block, meta):
+    rng = np.random.default_rng(seed + 1000)
+    kernel = _orthonormal(kernel)
+    x_star, b = make_rhs(K, kernel, r, rng)
+    return Workload(name=name, indptr=K.indptr.astype(np.int64), indices=K.indices.astype(np.int32),
+                    values=K.data.astype(np.float64), perm=perm, node_ptr=node_ptr, parent=parent,
+                    kernel=kernel, x_star=x_star, b=b, tau=tau, gcr_block=gcr_block, meta=meta)
+
+
+def neumann2d(nx, ny, seed, lo=-3.0, hi=3.0, leaf_max=64, r=1, tau=1e-2, gcr_block=0):
+    """2D pure-Neumann FV Laplacian with per-cell coefficient 10^U(lo,hi)."""
+    rng = np.random.default_rng(seed)
+    coef = 10.0 ** rng.uniform(lo, hi, size=(nx, ny))
+    K = fv_laplacian(coef)
+    perm, node_ptr, parent = grid_nested_dissection((nx, ny), leaf_max)
+    kernel = np.ones((nx * ny, 1))
+    return _finish(f"neumann2d_{nx}x{ny}", K, perm, node_ptr, parent, kernel, r, seed, tau, gcr_block,
+                   {"grid": (nx, ny), "leaf_max": leaf_max, "seed": seed})
+
+
+def inclusions3d(n, n_incl, seed, radius=(2.0, 6.0), value=1e6, leaf_max=512, r=16, tau=1e-2,
+                 gcr_block=16):
+    """3D pure-Neumann 7-point FV Laplacian, coefficient 1 with spherical inclusions.
+
+    A cell is inside a sphere when its centre (i+1/2, j+1/2, k+1/2) lies within
+    distance r of the sphere centre; r ~ U[radius], centre ~ U[0,n)^3; overlaps allowed.
+    """
+    rng = np.random.default_rng(seed)
+    coef = np.ones((n, n, n))
+    c = np.arange(n) + 0.5
+    X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+    for _ in range(n_incl):
+        rad = rng.uniform(*radius)
+        cen = rng.uniform(0, n, size=3)
+        inside = (X - cen[0]) ** 2 + (Y - cen[1]) ** 2 + (Z - cen[2]) ** 2 <= rad * rad
+        coef[inside] = value
+    K = fv_laplacian(coef)
+    perm, node_ptr, parent = grid_nested_dissection((n, n, n), leaf_max)
+    kernel = np.ones((n ** 3, 1))
+    return _finish(f"inclusions3d_{n}", K, perm, node_ptr, parent, kernel, r, seed, tau, gcr_block,
+                   {"grid": (n, n, n), "n_incl": n_incl, "leaf_max": leaf_max, "seed": seed,
+                    "incl_frac": float((coef > 1).mean())})
+
+
+def elasticity(ne, seed, lo=0.0, hi=6.0, leaf_max=64, r=32, tau=1e-2, gcr_block=32):
+    """Floating Q1 elastic cube with per-element Young's modulus 10^U(lo,hi), nu=0.3."""
+    rng = np.random.default_rng(seed)
+    young = 10.0 ** rng.uniform(lo, hi, size=(ne, ne, ne))
+    K = q1_elasticity(ne, young)
+    perm, node_ptr, parent = grid_nested_dissection((ne + 1,) * 3, leaf_max, dofs_per_point=3)
+    kernel = rigid_modes(ne)
+    return _finish(f"elasticity_{ne}", K, perm, node_ptr, parent, kernel, r, seed, tau, gcr_block,
+                   {"elements": (ne, ne, ne), "leaf_max": leaf_max, "seed": seed})
+
+
+# The three single-GPU configurations of the benchmark, with the paper-derived
+# settings: tau = 1e-2, block width = RHS count.
+def config_c1():
+    """2D Neumann 32x32, coefficients 10^U(-3,3), tau 1e-2, 1 RHS, kernel 1."""
+    return neumann2d(32, 32, seed=1, leaf_max=64, r=1, tau=1e-2, gcr_block=0)
+
+
+def config_c2():
+    """3D Neumann 64^3 with 200 inclusions at 1e6, leaf 512, 16 RHS, kernel 1."""
+    return inclusions3d(64, 200, seed=2, leaf_max=512, r=16, tau=1e-2, gcr_block=16)
+
+
+def config_c3():
+    """Floating Q1 elastic cube, 24^3 elements, E = 10^U(0,6), 32 RHS, kernel 6."""
+    return elasticity(24, seed=3, leaf_max=64, r=32, tau=1e-2, gcr_block=32)
+
+
+CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3}
+
+
+def single_node_tree(n):
+    """Trivial ordering: identity permutation, one node holding everything."""
+    return (np.arange(n, dtype=np.int32), np.array([0, n], dtype=np.int32),
+            np.array([-1], dtype=np.int32))
+
+
+def random_dense_workload(n, seed, kernel_dim=0, indefinite=False, cond=1e3, r=2, tau=1e-2):
+    """Small dense symmetric matrix K = V diag(s) V^T with a planted kernel.
+
+    ``kernel_dim`` eigenvalues are exactly zero (the kernel basis is returned);
+    the others are log-spaced in [1/cond, 1] with random signs when ``indefinite``.
+    Single-node ordering.
+    """
+    rng = np.random.default_rng(seed)
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.logspace(0, -math.log10(cond), n - kernel_dim)
+    if indefinite:
+        s = s * rng.choice([-1.0, 1.0], size=s.shape)
+    s = np.concatenate([s, np.zeros(kernel_dim)])
+    A = (V * s) @ V.T
+    A = 0.5 * (A + A.T)
+    K = sp.csr_matrix(A)
+    K.sort_indices()
+    perm, node_ptr, parent = single_node_tree(n)
+    kernel = V[:, n - kernel_dim:]
+    return _finish(f"dense{n}_k{kernel_dim}{'_indef' if indefinite else ''}", K, perm, node_ptr, parent,
+                   kernel, r, seed, tau, 0, {"seed": seed})
