@@ -1,0 +1,236 @@
+/*
+ * hf.h -- C ABI of the hybrid mixed-precision sparse LDL^T factorization
+ * (Suzuki, "A Hybrid Factorization Algorithm for Sparse Matrix with Mixed
+ * Precision Arithmetic", arXiv 2208.01907) for AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Sec. 2): a sparse symmetric matrix Kbar of order L, given in CSR
+ * form with the full pattern (both triangles).  The library scales it to
+ * K = Q Kbar Q with unit / zero diagonal, splits the indices into a moderate part
+ * Lambda_1 and a hard part Lambda_2 by a low-precision LDL^T with symmetric
+ * pivoting and threshold postponing (Sec. 2.1-2.2, Algorithm 1 step 1), builds
+ * the Schur complement S22 = K22 - K21 K11^{-1} K12 with preconditioned block GCR
+ * (Algorithm 5, Algorithm 1 steps 3-4) and factorizes S22 in FP64 with a
+ * rank-revealing symmetric pivoting (Algorithm 1 step 5).  Solves follow
+ * Algorithm 2.
+ *
+ * Conventions
+ *   - Host pointers are marked _host, device pointers _dev.  Device buffers are
+ *     plain hipMalloc'ed memory; streams are hipStream_t passed as void*.
+ *     NULL stream means the default stream.
+ *   - Every call returns HF_OK (0) or a negative HF_ERR_* code.  On error the
+ *     outputs are left untouched and the context stays usable: a failed
+ *     hf_factorize leaves the context in the "analysed" state.
+ *   - A context is not thread-safe; different contexts may be used concurrently.
+ *   - The library copies what it needs from its inputs; it keeps no pointer to
+ *     caller memory after a call returns.
+ */
+#ifndef HF_H_
+#define HF_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+  HF_OK = 0,
+  HF_ERR_ARG = -1,             /* invalid argument (NULL, sizes, options) */
+  HF_ERR_PATTERN = -2,         /* CSR not square/sorted/symmetric, diagonal missing,
+                                  or the tree is not a valid nested dissection */
+  HF_ERR_VALUE = -3,           /* NaN or Inf among the values */
+  HF_ERR_STATE = -4,           /* call order violated (e.g. solve before factorize) */
+  HF_ERR_NO_CONVERGENCE = -5,  /* block GCR did not reach the tolerance */
+  HF_ERR_BREAKDOWN = -6,       /* block GCR Gram matrix lost all directions */
+  HF_ERR_OOM = -7,             /* device or host allocation failed */
+  HF_ERR_HIP = -8,             /* a HIP runtime call failed */
+  HF_ERR_NOT_IMPLEMENTED = -9
+};
+
+/* precision of the step-1 factorization (the preconditioner) */
+enum { HF_PREC_FP32 = 32, HF_PREC_FP64 = 64 };
+
+typedef struct hf_ctx hf_ctx;
+
+typedef struct hf_options {
+  double tau;               /* postponing threshold of Sec. 2.2 (default 1e-2) */
+  int32_t low_precision;    /* HF_PREC_FP32 (mixed, default) or HF_PREC_FP64 */
+  int32_t first_pivot_unit; /* 1 (default): the first pivot of a node is compared
+                               with 1, the unit diagonal of the scaled matrix;
+                               0: it is accepted whenever nonzero */
+  int32_t n_enlarge;        /* enlargement count n of Sec. 2.2 (default 4) */
+  int32_t gcr_block;        /* block width of the Schur-complement block GCR;
+                               0 (default) = all postponed columns in one block,
+                               as in Sec. 3.5 (blocks of at most 64) */
+  double gcr_tol;           /* per-column relative residual (default 1e-15) */
+  int32_t gcr_maxit;        /* iteration cap of block GCR (default 50) */
+  double ker_tol;           /* kernel pivots of S22: magnitude <= ker_tol in the
+                               units of the scaled matrix (default 1e-10) */
+  int32_t refine_steps;     /* hf_solve: residual-correction passes of
+                               Algorithm 2 after the first one, the residual
+                               taken in the caller's variables (default 1) */
+} hf_options;
+
+typedef struct hf_info_t {
+  int64_t n;                /* order L */
+  int64_t nnz;
+  int32_t n_nodes;          /* nested-dissection tree nodes */
+  int32_t n_levels;         /* levels of the factorization schedule */
+  int32_t max_front;        /* largest frontal matrix order */
+  int32_t max_pivots;       /* largest node */
+  int64_t factor_entries;   /* E: stored low-precision factor entries (symbolic) */
+  double factor_flops;      /* F: step-1 flops of the symbolic structure */
+  double factor_flops_done; /* step-1 flops actually performed (after postponing) */
+  int64_t front_bytes;      /* device arena of the frontal matrices */
+  int32_t M;                /* size of the hard part Lambda_2 */
+  int32_t kernel_dim;       /* k */
+  int32_t gcr_blocks;       /* Schur-complement block GCR runs */
+  int32_t gcr_iters_max;    /* largest iteration count of those runs */
+  int32_t gcr_iters_total;
+  int32_t solve_gcr_iters;  /* iterations of the last hf_solve */
+  double rank_gap;          /* smallest non-kernel / largest kernel candidate pivot */
+  int32_t rank_candidates;  /* postponed set of the second stage after enlargement */
+  int32_t state;            /* 0 empty, 1 analysed, 2 factorized */
+  double t_analyse_ms;
+  double t_step1_ms;        /* scale + low-precision factorization + split */
+  double t_gcr_ms;          /* block GCR for X12 */
+  double t_s22_ms;          /* S22, its LDL^T, kernel */
+  double t_solve_ms;        /* last hf_solve */
+} hf_info_t;
+
+/* Fill *opt with the defaults listed above.  Always succeeds for non-NULL opt. */
+void hf_default_options(hf_options* opt);
+
+/*
+ * Symbolic analysis (host only; Sec. 2.2 nested dissection).
+ *   n                 order L (>= 0)
+ *   indptr_host       int64 [n+1], CSR row pointers, indptr[0] = 0
+ *   indices_host      int32 [indptr[n]], column indices, sorted and unique in
+ *                     every row, full symmetric pattern, diagonal present
+ *   perm_host         int32 [n] or NULL: perm[k] = original index eliminated
+ *                     k-th (nested-dissection order); NULL = identity
+ *   n_nodes           number of tree nodes (>= 1 when n > 0)
+ *   node_ptr_host     int32 [n_nodes+1]: node j owns positions
+ *                     node_ptr[j] .. node_ptr[j+1]-1 of the permuted order
+ *   parent_host       int32 [n_nodes]: parent node, -1 for roots; nodes are in
+ *                     postorder (children before parents, subtrees contiguous)
+ *   opt               options or NULL for defaults
+ *   out               receives the new context
+ * With node_ptr_host == NULL and parent_host == NULL the whole matrix is one
+ * node (a dense front); usable only for small n.
+ * Errors: HF_ERR_ARG, HF_ERR_PATTERN (includes couplings between sibling
+ * subtrees), HF_ERR_OOM, HF_ERR_HIP.
+ */
+int hf_analyse(int64_t n, const int64_t* indptr_host, const int32_t* indices_host,
+               const int32_t* perm_host, int32_t n_nodes, const int32_t* node_ptr_host,
+               const int32_t* parent_host, const hf_options* opt, hf_ctx** out);
+
+/*
+ * Numerical factorization, Algorithm 1 (Sec. 3).
+ *   values_dev   float64 [nnz] on the device, the values of Kbar on the analysed
+ *                pattern (same order as indices_host)
+ *   stream       hipStream_t (void*); all work is ordered on it.  The call returns
+ *                after the small device-to-host reads it needs (the hard part,
+ *                convergence flags, the kernel dimension).
+ * May be called again with new values on the same pattern.
+ * Errors: HF_ERR_STATE (not analysed), HF_ERR_VALUE, HF_ERR_NO_CONVERGENCE,
+ * HF_ERR_BREAKDOWN, HF_ERR_OOM, HF_ERR_HIP.
+ */
+int hf_factorize(hf_ctx* ctx, const double* values_dev, void* stream);
+
+/*
+ * Solve Kbar X = B, Algorithm 2 (Sec. 3).
+ *   r         number of right-hand sides (>= 0)
+ *   B_dev     float64, column-major n x r, leading dimension ldb >= n
+ *   X_dev     float64, column-major n x r, leading dimension ldx >= n; must not
+ *             alias B_dev
+ * For singular Kbar the returned solution is orthogonal (Euclidean, original
+ * variables) to the detected kernel, i.e. the minimum-norm solution of a
+ * consistent system.
+ * Errors: HF_ERR_STATE (not factorized), HF_ERR_ARG, HF_ERR_NO_CONVERGENCE,
+ * HF_ERR_OOM, HF_ERR_HIP.
+ */
+int hf_solve(hf_ctx* ctx, int32_t r, const double* B_dev, int64_t ldb, double* X_dev, int64_t ldx,
+             void* stream);
+
+/* Kernel dimension k found by the rank-revealing LDL^T of S22 (Sec. 2.2, Algorithm 1 step 5).
+ * Errors: HF_ERR_ARG, HF_ERR_STATE. */
+int hf_kernel_dim(const hf_ctx* ctx, int32_t* k_host);
+
+/*
+ * Orthonormal kernel basis of Kbar in original variables, float64 column-major
+ * n x k (leading dimension ldn >= n), lifted from the null vectors of S22.
+ * Errors: HF_ERR_ARG, HF_ERR_STATE, HF_ERR_HIP.
+ */
+int hf_kernel_basis(const hf_ctx* ctx, double* N_dev, int64_t ldn, void* stream);
+
+/*
+ * Schur complement of the hard part, Algorithm 1 step 4.
+ *   m_host          receives M = #Lambda_2
+ *   lambda2_host    int32 [M] or NULL: the hard-part indices in original
+ *                   numbering, ascending
+ *   S22_dev         float64 [M x M] column-major (leading dimension lds >= M) or
+ *                   NULL: S22 of the scaled matrix K = Q Kbar Q, rows and
+ *                   columns in the order of lambda2_host
+ * Call with NULL buffers to query M.  Errors: HF_ERR_ARG, HF_ERR_STATE, HF_ERR_HIP.
+ */
+int hf_schur(const hf_ctx* ctx, int32_t* m_host, int32_t* lambda2_host, double* S22_dev, int64_t lds,
+             void* stream);
+
+/*
+ * Diagonal scaling Q (Sec. 2) as float64 [n] on the device: K = Q Kbar Q.
+ * Errors: HF_ERR_ARG, HF_ERR_STATE, HF_ERR_HIP.
+ */
+int hf_scaling(const hf_ctx* ctx, double* q_dev, void* stream);
+
+/* Diagnostics.  Errors: HF_ERR_ARG. */
+int hf_info(const hf_ctx* ctx, hf_info_t* info_host);
+
+/*
+ * Per-kernel-class timing (measurement support).  When enabled, every launch of
+ * an instrumented kernel is bracketed by HIP events on the caller's stream; the
+ * elapsed times are accumulated at the end of each hf_factorize / hf_solve,
+ * together with the algorithmic bytes and flops of each launch (computed on the
+ * host from the sizes of the fronts involved).  Enabling resets the counters.
+ */
+enum {
+  HF_K_PANEL = 0,        /* pivot search + panel of F11 (serial pivot chain) */
+  HF_K_F11_UPDATE = 1,   /* trailing update of F11 after each panel */
+  HF_K_TRSM = 2,         /* L21 = F21 L11^{-T} D^{-1} */
+  HF_K_SYRK = 3,         /* contribution block F22 -= L21 D L21^T */
+  HF_K_EXTEND_ADD = 4,   /* assembly of the children's contribution blocks */
+  HF_K_SOLVE_DIAG = 5,   /* diagonal-block steps of the triangular sweeps */
+  HF_K_SOLVE_UPDATE = 6, /* off-diagonal products of the triangular sweeps */
+  HF_K_SOLVE_GATHER = 7, /* gathers / extend-adds of the triangular sweeps */
+  HF_K_SPMM = 8,         /* FP64 CSR products with K */
+  HF_K_GRAM = 9,         /* FP64 Gram products of block GCR */
+  HF_K_OTHER = 10,       /* everything else */
+  HF_K_NCLASS = 11
+};
+
+typedef struct hf_kstat_t {
+  double ms;             /* summed event time */
+  int64_t launches;
+  double bytes;          /* summed algorithmic bytes */
+  double flops;          /* summed algorithmic flops */
+} hf_kstat_t;
+
+/* Enable (1) or disable (0) the timing; enabling clears the counters.
+ * Errors: HF_ERR_ARG. */
+int hf_timing_enable(hf_ctx* ctx, int32_t on);
+
+/* Counters of one class (0 <= cls < HF_K_NCLASS).  Errors: HF_ERR_ARG. */
+int hf_timing_get(const hf_ctx* ctx, int32_t cls, hf_kstat_t* out_host);
+
+/* Static message for a status code (never NULL). */
+const char* hf_strerror(int status);
+
+/* Release the context and all device memory it owns.  NULL is ignored. */
+void hf_destroy(hf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HF_H_ */

@@ -576,6 +576,7 @@ class HybridFactor:
     gcr_tol: float
     gcr_maxit: int
     gcr_iters: list
+    Kbar: sp.csr_matrix = None   # the caller's matrix (residual correction of the solve)
 
     @property
     def M(self):
@@ -653,22 +654,17 @@ def hybrid_factorize(Kbar, perm, node_ptr, parent, tau=1e-2, low=np.float32, gcr
         kern, _ = np.linalg.qr(nb)
     return HybridFactor(n=n, q=q, perm=np.asarray(perm), Kp=Kp, step1=f1, lambda1_mask=keep, X12=X12,
                         S22=S22, ldl=ld, rank=rk, kernel=kern, gcr_block=gcr_block, gcr_tol=gcr_tol,
-                        gcr_maxit=gcr_maxit, gcr_iters=iters)
+                        gcr_maxit=gcr_maxit, gcr_iters=iters, Kbar=sp.csr_matrix(Kbar))
 
 
-def hybrid_solve(hf: HybridFactor, Bbar):
-    """Algorithm 2 with the minimum-norm choice for singular K (reading).
+def _algorithm2(hf: HybridFactor, b):
+    """Algorithm 2 on scaled right-hand sides b in elimination order: returns x.
 
-    b = Pi Q bbar; y1 = Algorithm 5 on K11 y1 = b1; y2 = b2 - K21 y1;
-    x2 solves S22 x2 = y2 with 0 on the kernel pivots; x1 = y1 - X12 x2;
-    xbar = Q Pi^T x, projected orthogonally to the detected kernel.
+    y1 = Algorithm 5 on K11 y1 = b1; y2 = b2 - K21 y1; x2 solves S22 x2 = y2 with
+    0 on the kernel pivots; x1 = y1 - X12 x2.
     """
-    Bbar = np.asarray(Bbar, dtype=np.float64)
-    one = Bbar.ndim == 1
-    Bbar = Bbar.reshape(hf.n, -1)
     f1 = hf.step1
     l2 = f1.lambda2
-    b = (hf.q[:, None] * Bbar)[hf.perm]
     b1 = b.copy()
     b1[l2] = 0.0
     apply_A = _masked_ops(hf.Kp, f1.is_l2)
@@ -680,9 +676,37 @@ def hybrid_solve(hf: HybridFactor, Bbar):
         x2 = ldlt_solve_partial(hf.ldl, hf.k, y2)
         x = y1 - hf.X12 @ x2
         x[l2] = x2
-    xbar = np.zeros_like(x)
-    xbar[hf.perm] = x
-    xbar = hf.q[:, None] * xbar
+    return x
+
+
+def hybrid_solve(hf: HybridFactor, Bbar, refine_steps=1, Kbar=None):
+    """Algorithm 2, plus residual correction, with the minimum-norm choice for singular K.
+
+    b = Pi Q bbar; x = Algorithm2(b); then refine_steps times
+    x += Algorithm2(Pi Q (bbar - Kbar xbar)) with xbar = Q Pi^T x: the residual is
+    taken in the caller's variables (the scaled K has an exactly unit diagonal and
+    differs from Q Kbar Q by rounding, so its residual does not measure the
+    caller's).  The correction is not part of the paper's Algorithm 2; it is added
+    for the 1e-14 backward-error target.  Finally xbar is projected orthogonally to
+    the detected kernel (reading for singular K).  Kbar defaults to the matrix
+    given to hybrid_factorize.
+    """
+    Bbar = np.asarray(Bbar, dtype=np.float64)
+    one = Bbar.ndim == 1
+    Bbar = Bbar.reshape(hf.n, -1)
+    b = (hf.q[:, None] * Bbar)[hf.perm]
+    x = _algorithm2(hf, b)
+
+    def to_orig(xp):
+        out = np.zeros_like(xp)
+        out[hf.perm] = xp
+        return hf.q[:, None] * out
+
+    Kbar = hf.Kbar if Kbar is None else sp.csr_matrix(Kbar)
+    for _ in range(refine_steps):
+        rbar = Bbar - Kbar @ to_orig(x)
+        x = x + _algorithm2(hf, (hf.q[:, None] * rbar)[hf.perm])
+    xbar = to_orig(x)
     if hf.k:
         xbar = xbar - hf.kernel @ (hf.kernel.T @ xbar)
     return xbar[:, 0] if one else xbar

@@ -1,0 +1,130 @@
+// C entry points of include/hf.h.
+#include <new>
+
+#include "hf_internal.h"
+
+hf_ctx::~hf_ctx() { hf::free_work(this); }
+
+extern "C" {
+
+void hf_default_options(hf_options* opt) {
+  if (!opt) return;
+  opt->tau = 1e-2;
+  opt->low_precision = HF_PREC_FP32;
+  opt->first_pivot_unit = 1;
+  opt->n_enlarge = 4;
+  opt->gcr_block = 0;
+  opt->gcr_tol = 1e-15;
+  opt->gcr_maxit = 50;
+  opt->ker_tol = 1e-10;
+  opt->refine_steps = 1;
+}
+
+int hf_analyse(int64_t n, const int64_t* indptr_host, const int32_t* indices_host, const int32_t* perm_host,
+               int32_t n_nodes, const int32_t* node_ptr_host, const int32_t* parent_host,
+               const hf_options* opt, hf_ctx** out) {
+  return hf::analyse_impl(n, indptr_host, indices_host, perm_host, n_nodes, node_ptr_host, parent_host,
+                          opt, out);
+}
+
+int hf_factorize(hf_ctx* ctx, const double* values_dev, void* stream) {
+  if (!ctx) return HF_ERR_ARG;
+  return hf::factorize_impl(ctx, values_dev, static_cast<hipStream_t>(stream));
+}
+
+int hf_solve(hf_ctx* ctx, int32_t r, const double* B_dev, int64_t ldb, double* X_dev, int64_t ldx,
+             void* stream) {
+  if (!ctx) return HF_ERR_ARG;
+  if (B_dev && X_dev && B_dev == X_dev && r > 0) return HF_ERR_ARG;
+  return hf::solve_impl(ctx, r, B_dev, ldb, X_dev, ldx, static_cast<hipStream_t>(stream));
+}
+
+int hf_kernel_dim(const hf_ctx* ctx, int32_t* k_host) {
+  if (!ctx || !k_host) return HF_ERR_ARG;
+  if (ctx->state < 2) return HF_ERR_STATE;
+  *k_host = ctx->kdim;
+  return HF_OK;
+}
+
+int hf_kernel_basis(const hf_ctx* ctx, double* N_dev, int64_t ldn, void* stream) {
+  if (!ctx) return HF_ERR_ARG;
+  return hf::kernel_basis_impl(ctx, N_dev, ldn, static_cast<hipStream_t>(stream));
+}
+
+int hf_schur(const hf_ctx* ctx, int32_t* m_host, int32_t* lambda2_host, double* S22_dev, int64_t lds,
+             void* stream) {
+  if (!ctx || !m_host) return HF_ERR_ARG;
+  return hf::schur_impl(ctx, m_host, lambda2_host, S22_dev, lds, static_cast<hipStream_t>(stream));
+}
+
+int hf_scaling(const hf_ctx* ctx, double* q_dev, void* stream) {
+  if (!ctx) return HF_ERR_ARG;
+  return hf::scaling_impl(ctx, q_dev, static_cast<hipStream_t>(stream));
+}
+
+int hf_info(const hf_ctx* ctx, hf_info_t* info) {
+  if (!ctx || !info) return HF_ERR_ARG;
+  hf_info_t o{};
+  o.n = ctx->n;
+  o.nnz = ctx->nnz;
+  o.n_nodes = ctx->n_nodes;
+  o.n_levels = ctx->level_ptr.empty() ? 0 : (int32_t)ctx->level_ptr.size() - 1;
+  o.max_front = ctx->max_front;
+  o.max_pivots = ctx->max_p;
+  o.factor_entries = ctx->factor_entries;
+  o.factor_flops = ctx->flops_sym;
+  o.factor_flops_done = ctx->flops_done;
+  o.front_bytes = ctx->front_elems * (ctx->opt.low_precision == HF_PREC_FP32 ? 4 : 8);
+  o.M = ctx->M;
+  o.kernel_dim = ctx->kdim;
+  o.gcr_blocks = ctx->gcr_blocks;
+  o.gcr_iters_max = ctx->gcr_iters_max;
+  o.gcr_iters_total = ctx->gcr_iters_total;
+  o.solve_gcr_iters = ctx->solve_iters;
+  o.rank_gap = ctx->rank_gap;
+  o.rank_candidates = ctx->rank_candidates;
+  o.state = ctx->state;
+  o.t_analyse_ms = ctx->t_analyse;
+  o.t_step1_ms = ctx->t_step1;
+  o.t_gcr_ms = ctx->t_gcr;
+  o.t_s22_ms = ctx->t_s22;
+  o.t_solve_ms = ctx->t_solve;
+  *info = o;
+  return HF_OK;
+}
+
+const char* hf_strerror(int status) {
+  switch (status) {
+    case HF_OK: return "ok";
+    case HF_ERR_ARG: return "invalid argument";
+    case HF_ERR_PATTERN: return "invalid sparsity pattern or ordering tree";
+    case HF_ERR_VALUE: return "NaN or Inf among the matrix values";
+    case HF_ERR_STATE: return "call out of order (analyse / factorize first)";
+    case HF_ERR_NO_CONVERGENCE: return "block GCR did not converge";
+    case HF_ERR_BREAKDOWN: return "block GCR breakdown";
+    case HF_ERR_OOM: return "out of memory";
+    case HF_ERR_HIP: return "HIP runtime error";
+    case HF_ERR_NOT_IMPLEMENTED: return "not implemented for these sizes";
+    default: return "unknown status";
+  }
+}
+
+int hf_timing_enable(hf_ctx* ctx, int32_t on) {
+  if (!ctx) return HF_ERR_ARG;
+  ctx->timer.reset();
+  ctx->timer.on = on != 0;
+  return HF_OK;
+}
+
+int hf_timing_get(const hf_ctx* ctx, int32_t cls, hf_kstat_t* out) {
+  if (!ctx || !out || cls < 0 || cls >= HF_K_NCLASS) return HF_ERR_ARG;
+  out->ms = ctx->timer.ms[cls];
+  out->launches = ctx->timer.n[cls];
+  out->bytes = ctx->timer.bytes[cls];
+  out->flops = ctx->timer.flops[cls];
+  return HF_OK;
+}
+
+void hf_destroy(hf_ctx* ctx) { delete ctx; }
+
+}  // extern "C"

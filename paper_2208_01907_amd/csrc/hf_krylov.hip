@@ -1,0 +1,1065 @@
+// FP64 part of the hybrid factorization on the GPU.
+//
+//   - CSR SpMM with the moderate / hard masks (A = K11 of Algorithm 1 step 2)
+//   - tall-skinny Gram products with a fixed-order two-stage reduction
+//   - small dense kernels: pivoted Cholesky with deflation of the block-GCR
+//     Gram matrices, coefficient solves, block combinations
+//   - Algorithm 5 (preconditioned block GCR) driven from the host, one small
+//     device-to-host read of the residual norms per iteration
+//   - Algorithm 1 steps 2-5: K12 blocks, X12, S22 = K22 - K21 X12, the FP64
+//     rank-revealing LDL^T of S22 (1x1 / 2x2 symmetric pivoting), kernel lift
+//   - Algorithm 2 (solve)
+// All vectors are row-major n x m (m right-hand sides contiguous per row) in
+// elimination order unless stated otherwise.
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+
+#include "hf_internal.h"
+#include "hf_kernels.h"
+
+namespace hf {
+
+static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+constexpr int GRAM_WG = 256;   // partial sums of a Gram product (fixed: reduction order)
+constexpr int MAXM = 64;       // widest block handled by the small dense kernels
+
+// ---------------------------------------------------------------------------
+// SpMM and friends
+// ---------------------------------------------------------------------------
+
+// Y = K11 W (rows and columns of the hard part masked out)
+__global__ void k_spmm_k11(int64_t n, const int64_t* __restrict__ ip, const int32_t* __restrict__ ix,
+                           const double* __restrict__ kv, const uint8_t* __restrict__ isl2, int m,
+                           const double* __restrict__ W, double* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = e / m;
+  const int col = (int)(e - row * m);
+  if (row >= n) return;
+  double acc = 0.0;
+  if (!isl2[row]) {
+    for (int64_t q = ip[row]; q < ip[row + 1]; ++q) {
+      const int32_t c = ix[q];
+      if (!isl2[c]) acc += kv[q] * W[(int64_t)c * m + col];
+    }
+  }
+  Y[e] = acc;
+}
+
+// Residual of the caller's system, returned scaled: for row g (elimination
+// order) r_g = q_g (bbar_{perm g} - sum_e Kbar_e xbar_{perm c_e}) with
+// xbar = Q Pi^T x formed exactly as the solution handed back.  B is the caller's
+// column-major right-hand side block (columns c0.., leading dimension ldb).
+__global__ void k_residual_orig(int64_t n, const int64_t* __restrict__ ip, const int32_t* __restrict__ ix,
+                                const double* __restrict__ kbar, const double* __restrict__ qp,
+                                const int32_t* __restrict__ perm, int m, const double* __restrict__ B,
+                                int64_t ldb, int c0, const double* __restrict__ X, double* __restrict__ R) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = e / m;
+  const int col = (int)(e - row * m);
+  if (row >= n) return;
+  double acc = B[(int64_t)(c0 + col) * ldb + perm[row]];
+  for (int64_t q = ip[row]; q < ip[row + 1]; ++q) {
+    const int32_t c = ix[q];
+    acc -= kbar[q] * (qp[c] * X[(int64_t)c * m + col]);
+  }
+  R[e] = qp[row] * acc;
+}
+
+__global__ void k_add(int64_t nm, double* __restrict__ x, const double* __restrict__ d) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nm) x[e] += d[e];
+}
+
+// out = B - Y   (elementwise, n*m)
+__global__ void k_sub(int64_t nm, const double* __restrict__ B, const double* __restrict__ Y,
+                      double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nm) out[e] = B[e] - Y[e];
+}
+
+// K12 column block: B[g, c] = K[g, l2[c0+c]] for g in the moderate part, 0 else.
+__global__ void k_gather_k12(const int64_t* __restrict__ ip, const int32_t* __restrict__ ix,
+                             const double* __restrict__ kv, const uint8_t* __restrict__ isl2,
+                             const int32_t* __restrict__ l2, int c0, int nbc, int mb,
+                             double* __restrict__ B) {
+  const int c = blockIdx.x;
+  if (c >= nbc) return;
+  const int32_t x = l2[c0 + c];
+  for (int64_t q = ip[x] + threadIdx.x; q < ip[x + 1]; q += blockDim.x) {
+    const int32_t g = ix[q];
+    if (!isl2[g]) B[(int64_t)g * mb + c] = kv[q];  // K symmetric: K[g, x] = K[x, g]
+  }
+}
+
+// S22 column block: S[i, c0+c] = sum_q K[l2_i, x_q] W[x_q, c], W = [-X12; I].
+__global__ void k_s22_block(const int64_t* __restrict__ ip, const int32_t* __restrict__ ix,
+                            const double* __restrict__ kv, const uint8_t* __restrict__ isl2,
+                            const int32_t* __restrict__ l2, int M, int c0, int nbc, int mb,
+                            const double* __restrict__ Xb, double* __restrict__ S) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = e / nbc, c = e - (e / nbc) * nbc;
+  if (i >= M) return;
+  const int32_t g = l2[i];
+  const int32_t target = l2[c0 + c];
+  double acc = 0.0;
+  for (int64_t q = ip[g]; q < ip[g + 1]; ++q) {
+    const int32_t x = ix[q];
+    if (isl2[x]) {
+      if (x == target) acc += kv[q];
+    } else {
+      acc -= kv[q] * Xb[(int64_t)x * mb + c];
+    }
+  }
+  S[(int64_t)(c0 + c) * M + i] = acc;
+}
+
+__global__ void k_symmetrize(int M, double* __restrict__ S) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = e / M, j = e - (e / M) * M;
+  if (i >= M || j >= i) return;
+  const double a = 0.5 * (S[(int64_t)j * M + i] + S[(int64_t)i * M + j]);
+  S[(int64_t)j * M + i] = a;
+  S[(int64_t)i * M + j] = a;
+}
+
+// y2[i, c] = b[l2_i, c] - sum_{x moderate} K[l2_i, x] y1[x, c]
+__global__ void k_y2(const int64_t* __restrict__ ip, const int32_t* __restrict__ ix,
+                     const double* __restrict__ kv, const uint8_t* __restrict__ isl2,
+                     const int32_t* __restrict__ l2, int M, int m, const double* __restrict__ b,
+                     const double* __restrict__ y1, double* __restrict__ y2) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = e / m, c = e - (e / m) * m;
+  if (i >= M) return;
+  const int32_t g = l2[i];
+  double acc = b[(int64_t)g * m + c];
+  for (int64_t q = ip[g]; q < ip[g + 1]; ++q) {
+    const int32_t x = ix[q];
+    if (!isl2[x]) acc -= kv[q] * y1[(int64_t)x * m + c];
+  }
+  y2[(int64_t)i * m + c] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Gram products C = A^T B (A: n x a, B: n x b, row-major), fixed-order sums
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256)
+k_gram_partial(int64_t n, int a, const double* __restrict__ A, int64_t sA, int b,
+               const double* __restrict__ B, double* __restrict__ partial) {
+  const int blk = blockIdx.y;
+  const double* Ab = A + (int64_t)blk * sA;
+  const int64_t chunk = (n + GRAM_WG - 1) / GRAM_WG;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = min(n, r0 + chunk);
+  __shared__ double As[32 * MAXM];
+  __shared__ double Bs[32 * MAXM];
+  const int tid = threadIdx.x;
+  const int ab = a * b;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int64_t rr = r0; rr < r1; rr += 32) {
+    const int nr = (int)min((int64_t)32, r1 - rr);
+    for (int e = tid; e < nr * a; e += 256) As[e] = Ab[rr * a + e];
+    for (int e = tid; e < nr * b; e += 256) Bs[e] = B[rr * b + e];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int pidx = tid + q * 256;
+      if (pidx < ab) {
+        const int i = pidx / b, jj = pidx - (pidx / b) * b;
+        double s = acc[q];
+        for (int r = 0; r < nr; ++r) s += As[r * a + i] * Bs[r * b + jj];
+        acc[q] = s;
+      }
+    }
+    __syncthreads();
+  }
+  double* out = partial + ((int64_t)blk * GRAM_WG + blockIdx.x) * ab;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int pidx = tid + q * 256;
+    if (pidx < ab) out[pidx] = acc[q];
+  }
+}
+
+__global__ void k_gram_reduce(int nblk, int ab, const double* __restrict__ partial,
+                              double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nblk * ab) return;
+  const int blk = e / ab, pidx = e - (e / ab) * ab;
+  double s = 0.0;
+  const double* P = partial + (int64_t)blk * GRAM_WG * ab + pidx;
+  for (int w = 0; w < GRAM_WG; ++w) s += P[(int64_t)w * ab];
+  out[e] = s;
+}
+
+// ---------------------------------------------------------------------------
+// small dense FP64 kernels (one workgroup per matrix)
+// ---------------------------------------------------------------------------
+
+// Pivoted Cholesky of an SPSD m x m Gram matrix (row-major), deflating pivots
+// <= rel * max diag.  Output: Lc (m x m row-major, lower), piv[m], rank.
+__global__ void k_chol_piv(int m, const double* __restrict__ Mm, int64_t sM, double* __restrict__ Lc,
+                           int32_t* __restrict__ piv, int32_t* __restrict__ rank, double rel) {
+  const int blk = blockIdx.x;
+  const double* G = Mm + (int64_t)blk * sM;
+  double* L = Lc + (int64_t)blk * m * m;
+  int32_t* P = piv + (int64_t)blk * m;
+  __shared__ double A[MAXM * MAXM];
+  __shared__ int s_k, s_stop;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < m * m; e += blockDim.x) { A[e] = G[e]; L[e] = 0.0; }
+  for (int e = tid; e < m; e += blockDim.x) P[e] = e;
+  __syncthreads();
+  double dmax = 0.0;
+  for (int i = 0; i < m; ++i) dmax = fmax(dmax, A[i * m + i]);
+  int i;
+  for (i = 0; i < m; ++i) {
+    if (tid == 0) {
+      int k = i;
+      for (int t = i + 1; t < m; ++t)
+        if (A[t * m + t] > A[k * m + k]) k = t;
+      s_k = k;
+      s_stop = (A[k * m + k] <= rel * dmax || A[k * m + k] <= 0.0) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_stop) break;
+    const int k = s_k;
+    if (k != i) {
+      for (int t = tid; t < m; t += blockDim.x) {
+        const double x = A[i * m + t]; A[i * m + t] = A[k * m + t]; A[k * m + t] = x;
+      }
+      __syncthreads();
+      for (int t = tid; t < m; t += blockDim.x) {
+        const double x = A[t * m + i]; A[t * m + i] = A[t * m + k]; A[t * m + k] = x;
+      }
+      for (int t = tid; t < i; t += blockDim.x) {
+        const double x = L[i * m + t]; L[i * m + t] = L[k * m + t]; L[k * m + t] = x;
+      }
+      if (tid == 0) { const int32_t x = P[i]; P[i] = P[k]; P[k] = x; }
+      __syncthreads();
+    }
+    const double lii = sqrt(A[i * m + i]);
+    for (int r = i + tid; r < m; r += blockDim.x) L[r * m + i] = (r == i) ? lii : A[r * m + i] / lii;
+    __syncthreads();
+    for (int e = tid; e < (m - i - 1) * (m - i - 1); e += blockDim.x) {
+      const int r = i + 1 + e / (m - i - 1), c = i + 1 + e % (m - i - 1);
+      A[r * m + c] -= L[r * m + i] * L[c * m + i];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) rank[blk] = i;
+}
+
+// out = sign * M^{-1} R for every batch item (R: m x nc row-major), deflated
+// directions get 0.  One thread per right-hand-side column.
+__global__ void k_chol_solve(int m, int nc, const double* __restrict__ Lc, const int32_t* __restrict__ piv,
+                             const int32_t* __restrict__ rank, const double* __restrict__ R,
+                             int64_t sR, double* __restrict__ out, int64_t sO, double sign) {
+  const int blk = blockIdx.x;
+  const int c = threadIdx.x;
+  if (c >= nc) return;
+  const double* L = Lc + (int64_t)blk * m * m;
+  const int32_t* P = piv + (int64_t)blk * m;
+  const int rk = rank[blk];
+  const double* Rb = R + (int64_t)blk * sR;
+  double* O = out + (int64_t)blk * sO;
+  double z[MAXM];
+  for (int i = 0; i < rk; ++i) {
+    double v = Rb[(int64_t)P[i] * nc + c];
+    for (int t = 0; t < i; ++t) v -= L[i * m + t] * z[t];
+    z[i] = v / L[i * m + i];
+  }
+  for (int i = rk - 1; i >= 0; --i) {
+    double v = z[i];
+    for (int t = i + 1; t < rk; ++t) v -= L[t * m + i] * z[t];
+    z[i] = v / L[i * m + i];
+  }
+  for (int i = 0; i < m; ++i) O[(int64_t)P[i] * nc + c] = (i < rk) ? sign * z[i] : 0.0;
+}
+
+// out[row, col] = (base ? base[row, col] : 0) + sum_t sum_k V_t[row, k] coef_t[k, col]
+// V_t = V + t*sV (n x a, row-major), coef_t = coef + t*a*b (a x b), out n x b.
+__global__ void k_combine(int64_t n, int a, int b, double* out, const double* base, int nterms,
+                          const double* __restrict__ V, int64_t sV, const double* __restrict__ coef) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t row = e / b;
+  const int col = (int)(e - row * b);
+  if (row >= n) return;
+  double acc = base ? base[e] : 0.0;
+  for (int t = 0; t < nterms; ++t) {
+    const double* v = V + (int64_t)t * sV + row * a;
+    const double* cf = coef + (int64_t)t * a * b + col;
+    for (int k = 0; k < a; ++k) acc += v[k] * cf[(int64_t)k * b];
+  }
+  out[e] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 step 5: FP64 LDL^T of S22 with complete (Bunch-Parlett) pivoting,
+// second-stage postponing, enlargement and the kernel decision.  One workgroup.
+// A (M x M, col-major, destroyed), L (M x M col-major, unit lower), D (M x M),
+// perm[M], mags[M]; info: [0] k, [1] postponed, [2] candidates, [3] gap (double).
+// ---------------------------------------------------------------------------
+
+__device__ inline double& at(double* A, int M, int r, int c) { return A[(int64_t)c * M + r]; }
+
+__global__ void __launch_bounds__(256)
+k_s22_ldlt(int M, double* __restrict__ A, double* __restrict__ L, double* __restrict__ D,
+           int32_t* __restrict__ perm, double* __restrict__ mags, int32_t* __restrict__ bsize,
+           double tau, int n_enlarge, double ker_tol, double* __restrict__ info) {
+  const int tid = threadIdx.x;
+  const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+  __shared__ double rv[256];
+  __shared__ int rk[256];
+  __shared__ int s_kd, s_r, s_c, s_mode;
+  for (int64_t e = tid; e < (int64_t)M * M; e += 256) {
+    const int r = (int)(e % M), c = (int)(e / M);
+    L[e] = (r == c) ? 1.0 : 0.0;
+    D[e] = 0.0;
+  }
+  for (int e = tid; e < M; e += 256) { perm[e] = e; mags[e] = 0.0; bsize[e] = 1; }
+  __syncthreads();
+  auto swap = [&](int i, int k) {
+    if (i == k) return;
+    for (int t = tid; t < M; t += 256) { const double x = at(A, M, i, t); at(A, M, i, t) = at(A, M, k, t); at(A, M, k, t) = x; }
+    __syncthreads();
+    for (int t = tid; t < M; t += 256) { const double x = at(A, M, t, i); at(A, M, t, i) = at(A, M, t, k); at(A, M, t, k) = x; }
+    for (int t = tid; t < i; t += 256) { const double x = at(L, M, i, t); at(L, M, i, t) = at(L, M, k, t); at(L, M, k, t) = x; }
+    if (tid == 0) { const int32_t x = perm[i]; perm[i] = perm[k]; perm[k] = x; }
+    __syncthreads();
+  };
+  int i = 0;
+  while (i < M) {
+    const int w = M - i;
+    // largest |diagonal| (first occurrence)
+    double bv = -1.0;
+    int bk = INT_MAX;
+    for (int t = tid; t < w; t += 256) {
+      const double v = fabs(at(A, M, i + t, i + t));
+      if (v > bv) { bv = v; bk = t; }
+    }
+    rv[tid] = bv; rk[tid] = bk;
+    __syncthreads();
+    if (tid == 0) {
+      for (int t = 1; t < 256; ++t)
+        if (rv[t] > bv || (rv[t] == bv && rk[t] < bk)) { bv = rv[t]; bk = rk[t]; }
+      rv[0] = bv; s_kd = bk;
+    }
+    __syncthreads();
+    const double gd = rv[0];
+    const int kd = s_kd;
+    __syncthreads();
+    // largest |off-diagonal| (first in row-major order over the upper triangle)
+    double ov = -1.0;
+    int ok = INT_MAX;
+    for (int64_t e = tid; e < (int64_t)w * w; e += 256) {
+      const int r = (int)(e / w), c = (int)(e % w);
+      if (c <= r) continue;
+      const double v = fabs(at(A, M, i + r, i + c));
+      if (v > ov) { ov = v; ok = (int)e; }
+    }
+    rv[tid] = ov; rk[tid] = ok;
+    __syncthreads();
+    if (tid == 0) {
+      for (int t = 1; t < 256; ++t)
+        if (rv[t] > ov || (rv[t] == ov && rk[t] < ok)) { ov = rv[t]; ok = rk[t]; }
+      const double go = (w > 1) ? ov : 0.0;
+      int mode;
+      if (gd == 0.0 && go == 0.0) mode = 0;
+      else if (gd >= alpha * go) mode = 1;
+      else mode = 2;
+      s_mode = mode;
+      s_r = (w > 1) ? ok / w : 0;
+      s_c = (w > 1) ? ok % w : 0;
+    }
+    __syncthreads();
+    const int mode = s_mode;
+    if (mode == 0) break;  // exactly zero remainder: zero pivots
+    if (mode == 1) {
+      swap(i, i + kd);
+      const double d = at(A, M, i, i);
+      at(D, M, i, i) = d;
+      for (int r = i + 1 + tid; r < M; r += 256) at(L, M, r, i) = at(A, M, r, i) / d;
+      __syncthreads();
+      for (int64_t e = tid; e < (int64_t)(w - 1) * (w - 1); e += 256) {
+        const int r = i + 1 + (int)(e % (w - 1)), c = i + 1 + (int)(e / (w - 1));
+        at(A, M, r, c) -= at(L, M, r, i) * at(A, M, i, c);
+      }
+      __syncthreads();
+      for (int r = i + 1 + tid; r < M; r += 256) { at(A, M, r, i) = 0.0; at(A, M, i, r) = 0.0; }
+      if (tid == 0) mags[i] = fabs(d);
+      __syncthreads();
+      i += 1;
+    } else {
+      const int r = s_r, c = s_c;
+      swap(i, i + r);
+      swap(i + 1, i + c);
+      const double e11 = at(A, M, i, i), e12 = at(A, M, i + 1, i), e22 = at(A, M, i + 1, i + 1);
+      const double det = e11 * e22 - e12 * e12;
+      // Lc = C E^{-1}, C = A[i+2:, i:i+2]
+      for (int rr = i + 2 + tid; rr < M; rr += 256) {
+        const double c1 = at(A, M, rr, i), c2 = at(A, M, rr, i + 1);
+        at(L, M, rr, i) = (c1 * e22 - c2 * e12) / det;
+        at(L, M, rr, i + 1) = (c2 * e11 - c1 * e12) / det;
+      }
+      __syncthreads();
+      for (int64_t e = tid; e < (int64_t)(w - 2) * (w - 2); e += 256) {
+        const int rr = i + 2 + (int)(e % (w - 2)), cc = i + 2 + (int)(e / (w - 2));
+        at(A, M, rr, cc) -= at(L, M, rr, i) * at(A, M, cc, i) + at(L, M, rr, i + 1) * at(A, M, cc, i + 1);
+      }
+      __syncthreads();
+      for (int rr = i + 2 + tid; rr < M; rr += 256) {
+        at(A, M, rr, i) = 0.0; at(A, M, i, rr) = 0.0;
+        at(A, M, rr, i + 1) = 0.0; at(A, M, i + 1, rr) = 0.0;
+      }
+      if (tid == 0) {
+        at(D, M, i, i) = e11; at(D, M, i + 1, i) = e12; at(D, M, i, i + 1) = e12; at(D, M, i + 1, i + 1) = e22;
+        const double h = 0.5 * (e11 + e22), q = sqrt(0.25 * (e11 - e22) * (e11 - e22) + e12 * e12);
+        const double mg = fmin(fabs(h - q), fabs(h + q));
+        mags[i] = mg; mags[i + 1] = mg;
+        bsize[i] = 2; bsize[i + 1] = 0;
+      }
+      __syncthreads();
+      i += 2;
+    }
+  }
+  // rank decision (same rule as the oracle)
+  if (tid == 0) {
+    // second-stage postponing: the first pivot is compared with 1 (unit diagonal
+    // of the scaled matrix), later ones with their predecessor
+    int t = M;
+    double prev = 1.0;
+    for (int q = 0; q < M; ++q) {
+      if (mags[q] == 0.0 || mags[q] < tau * prev) { t = q; break; }
+      prev = mags[q];
+    }
+    const int postponed = M - t;
+    const int e = postponed > 0 ? min(n_enlarge, t) : 0;
+    const int start = t - e;
+    int k = 0;
+    for (int q = M - 1; q >= start; --q) {
+      if (mags[q] <= ker_tol) ++k;
+      else break;
+    }
+    double gap = INFINITY;
+    if (k > 0 && start < M - k) {
+      double mn = INFINITY, mx = 0.0;
+      for (int q = start; q < M - k; ++q) mn = fmin(mn, mags[q]);
+      for (int q = M - k; q < M; ++q) mx = fmax(mx, mags[q]);
+      gap = mn / fmax(mx, 1e-300);
+    }
+    info[0] = k;
+    info[1] = postponed;
+    info[2] = M - start;
+    info[3] = gap;
+  }
+}
+
+// Null vectors of S22: N2 = P^T [-L11^{-T} L21^T; I_k]  (row-major M x k)
+__global__ void k_s22_null(int M, int k, const double* __restrict__ L, const int32_t* __restrict__ perm,
+                           double* __restrict__ N2) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= k) return;
+  const int r = M - k;
+  // Y = L11^{-T} L21^T[:, q]; backward substitution, kept in N2 rows (scattered at the end)
+  // work in place in column q of a scratch: use N2 rows of perm order
+  for (int i = 0; i < M; ++i) N2[(int64_t)perm[i] * k + q] = 0.0;
+  for (int i = r - 1; i >= 0; --i) {
+    double v = at(const_cast<double*>(L), M, r + q, i);
+    for (int t = i + 1; t < r; ++t) v -= at(const_cast<double*>(L), M, t, i) * N2[(int64_t)perm[t] * k + q];
+    N2[(int64_t)perm[i] * k + q] = v;
+  }
+  for (int i = 0; i < r; ++i) N2[(int64_t)perm[i] * k + q] = -N2[(int64_t)perm[i] * k + q];
+  for (int t = 0; t < k; ++t) N2[(int64_t)perm[r + t] * k + q] = (t == q) ? 1.0 : 0.0;
+}
+
+// x = S22^+ y restricted to the nonsingular pivots (kernel pivots get 0).
+// Y, X: row-major M x nc.  One thread per column.
+__global__ void k_s22_solve(int M, int k, const double* __restrict__ L, const double* __restrict__ D,
+                            const int32_t* __restrict__ perm, const int32_t* __restrict__ bsize, int nc,
+                            const double* __restrict__ Y, double* __restrict__ X, double* __restrict__ work) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  double* z = work + (int64_t)c * M;
+  double* Lm = const_cast<double*>(L);
+  double* Dm = const_cast<double*>(D);
+  for (int i = 0; i < M; ++i) {
+    double v = Y[(int64_t)perm[i] * nc + c];
+    for (int t = 0; t < i; ++t) v -= at(Lm, M, i, t) * z[t];
+    z[i] = v;
+  }
+  const int r = M - k;
+  for (int i = 0; i < M;) {
+    if (i >= r) { z[i] = 0.0; ++i; continue; }
+    if (bsize[i] == 2 && i + 1 < r) {
+      const double e11 = at(Dm, M, i, i), e12 = at(Dm, M, i + 1, i), e22 = at(Dm, M, i + 1, i + 1);
+      const double det = e11 * e22 - e12 * e12;
+      const double a = z[i], b = z[i + 1];
+      z[i] = (a * e22 - b * e12) / det;
+      z[i + 1] = (b * e11 - a * e12) / det;
+      i += 2;
+    } else {
+      z[i] = z[i] / at(Dm, M, i, i);
+      ++i;
+    }
+  }
+  for (int i = M - 1; i >= 0; --i) {
+    double v = z[i];
+    for (int t = i + 1; t < M; ++t) v -= at(Lm, M, t, i) * z[t];
+    z[i] = v;
+  }
+  for (int i = 0; i < M; ++i) X[(int64_t)perm[i] * nc + c] = z[i];
+}
+
+// unpivoted Cholesky G = R^T R of a small SPD matrix (row-major k x k); coef = R^{-1}
+__global__ void k_chol_inv(int k, const double* __restrict__ G, double* __restrict__ Rinv) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double R[MAXM * MAXM];
+  for (int e = 0; e < k * k; ++e) R[e] = 0.0;
+  for (int j = 0; j < k; ++j) {
+    double s = G[j * k + j];
+    for (int t = 0; t < j; ++t) s -= R[t * k + j] * R[t * k + j];
+    s = sqrt(fmax(s, 0.0));
+    R[j * k + j] = s;
+    for (int c = j + 1; c < k; ++c) {
+      double v = G[j * k + c];
+      for (int t = 0; t < j; ++t) v -= R[t * k + j] * R[t * k + c];
+      R[j * k + c] = s > 0.0 ? v / s : 0.0;
+    }
+  }
+  // invert the upper-triangular R
+  for (int e = 0; e < k * k; ++e) Rinv[e] = 0.0;
+  for (int c = 0; c < k; ++c) {
+    for (int i = c; i >= 0; --i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int t = i + 1; t <= c; ++t) v -= R[i * k + t] * Rinv[t * k + c];
+      Rinv[i * k + c] = R[i * k + i] > 0.0 ? v / R[i * k + i] : 0.0;
+    }
+  }
+}
+
+// kernel lift in elimination order -> original order, scaled by Q:
+// Nout[perm[g], q] = qp[g] * Nin[g, q], with rows of the hard part set from N2.
+__global__ void k_kernel_finish(int64_t n, int k, const int32_t* __restrict__ perm,
+                                const double* __restrict__ qp, const double* __restrict__ Nin,
+                                double* __restrict__ Nout) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = e / k;
+  const int q = (int)(e - g * k);
+  if (g >= n) return;
+  Nout[(int64_t)perm[g] * k + q] = qp[g] * Nin[e];
+}
+
+__global__ void k_set_rows(int M, int k, const int32_t* __restrict__ l2, const double* __restrict__ N2,
+                           double* __restrict__ N) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * k) return;
+  const int i = e / k, q = e - (e / k) * k;
+  N[(int64_t)l2[i] * k + q] = N2[e];
+}
+
+// user B (col-major, original order) -> b (row-major, elimination order, scaled)
+__global__ void k_load_rhs(int64_t n, int m, const int32_t* __restrict__ perm, const double* __restrict__ qp,
+                           const double* __restrict__ B, int64_t ldb, int c0, double* __restrict__ b) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = e / m;
+  const int c = (int)(e - g * m);
+  if (g >= n) return;
+  b[e] = qp[g] * B[(int64_t)(c0 + c) * ldb + perm[g]];
+}
+
+__global__ void k_mask_rows(int64_t n, int m, const uint8_t* __restrict__ isl2, const double* __restrict__ in,
+                            double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = e / m;
+  if (g >= n) return;
+  out[e] = isl2[g] ? 0.0 : in[e];
+}
+
+// x (row-major elimination order) -> xo (row-major original order), scaled
+__global__ void k_unperm(int64_t n, int m, const int32_t* __restrict__ perm, const double* __restrict__ qp,
+                         const double* __restrict__ x, double* __restrict__ xo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = e / m;
+  const int c = (int)(e - g * m);
+  if (g >= n) return;
+  xo[(int64_t)perm[g] * m + c] = qp[g] * x[e];
+}
+
+__global__ void k_store_cols(int64_t n, int m, const double* __restrict__ xo, double* __restrict__ X,
+                             int64_t ldx, int c0) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = e / m;
+  const int c = (int)(e - o * m);
+  if (o >= n) return;
+  X[(int64_t)(c0 + c) * ldx + o] = xo[e];
+}
+
+__global__ void k_neg(int64_t nm, double* __restrict__ a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nm) a[e] = -a[e];
+}
+
+__global__ void k_reorder_s22(int M, const int32_t* __restrict__ order, const double* __restrict__ S,
+                              double* __restrict__ out, int64_t lds) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * M) return;
+  const int a = e % M, b = e / M;
+  out[(int64_t)b * lds + a] = S[(int64_t)order[b] * M + order[a]];
+}
+
+__global__ void k_scatter_q(int64_t n, const int32_t* __restrict__ perm, const double* __restrict__ qp,
+                            double* __restrict__ q) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) q[perm[g]] = qp[g];
+}
+
+__global__ void k_kernel_out(int64_t n, int k, const double* __restrict__ N, double* __restrict__ out,
+                             int64_t ldn) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = e / k;
+  const int q = (int)(e - o * k);
+  if (o >= n) return;
+  out[(int64_t)q * ldn + o] = N[e];
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+
+struct BgcrWork {
+  int64_t n = 0;
+  int m = 0, slots = 0;
+  DBuf P, Qv, R, Z, T1, partial, gram, Lc, piv, rank, coef, norms;
+};
+
+void free_work(hf_ctx* ctx) {
+  delete ctx->work;
+  ctx->work = nullptr;
+}
+
+static BgcrWork& get_work(hf_ctx* ctx, int m) {
+  if (!ctx->work) ctx->work = new BgcrWork();
+  BgcrWork& w = *ctx->work;
+  const int slots = ctx->opt.gcr_maxit + 1;
+  if (w.n != ctx->n || w.m < m || w.slots < slots) {
+    const int mm = std::max(m, w.m);
+    const size_t vec = (size_t)std::max<int64_t>(ctx->n, 1) * mm * sizeof(double);
+    w.P.alloc(vec * slots);
+    w.Qv.alloc(vec * slots);
+    w.R.alloc(vec);
+    w.Z.alloc(vec);
+    w.T1.alloc(vec);
+    w.partial.alloc((size_t)slots * GRAM_WG * mm * mm * sizeof(double));
+    w.gram.alloc((size_t)slots * MAXM * MAXM * sizeof(double));
+    w.Lc.alloc((size_t)slots * MAXM * MAXM * sizeof(double));
+    w.piv.alloc((size_t)slots * MAXM * sizeof(int32_t));
+    w.rank.alloc((size_t)slots * sizeof(int32_t));
+    w.coef.alloc((size_t)slots * MAXM * MAXM * sizeof(double));
+    w.norms.alloc((size_t)MAXM * sizeof(double));
+    w.n = ctx->n;
+    w.m = mm;
+    w.slots = slots;
+  }
+  return w;
+}
+
+// C (nA blocks of a x b) = [A_blk^T B]
+static void gram(hf_ctx* ctx, int64_t n, int a, const double* A, int64_t sA, int nA, int b,
+                 const double* B, double* C, hipStream_t s) {
+  BgcrWork& w = *ctx->work;
+  dim3 grid(GRAM_WG, nA);
+  const double by = (double)n * (a * (double)nA + b) * 8.0, fl = 2.0 * n * a * b * (double)nA;
+  timed(ctx->timer, HF_K_GRAM, by, fl, s, [&] {
+    k_gram_partial<<<grid, 256, 0, s>>>(n, a, A, sA, b, B, w.partial.as<double>());
+    k_gram_reduce<<<cdiv((int64_t)nA * a * b, 256), 256, 0, s>>>(nA, a * b, w.partial.as<double>(), C);
+  });
+}
+
+static void spmm_k11(hf_ctx* ctx, int m, const double* W, double* Y, hipStream_t s) {
+  const int64_t nm = ctx->n * m;
+  if (nm == 0) return;
+  const double by = ctx->nnz * 12.0 + ctx->n * 8.0 + 2.0 * nm * 8.0, fl = 2.0 * ctx->nnz * m;
+  timed(ctx->timer, HF_K_SPMM, by, fl, s, [&] {
+    k_spmm_k11<<<cdiv(nm, 256), 256, 0, s>>>(ctx->n, ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(),
+                                             ctx->d_kval.as<double>(), ctx->d_isl2.as<uint8_t>(), m, W, Y);
+  });
+}
+
+static void precond(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s) {
+  if (ctx->factor_prec == HF_PREC_FP32) precond_apply<float>(ctx, m, R, Y, s);
+  else precond_apply<double>(ctx, m, R, Y, s);
+}
+
+// Algorithm 5 on A = K11 for m right-hand sides B (row-major n x m, zero on the
+// hard part); X receives the solution.  Returns the iteration count.
+static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, hipStream_t s) {
+  const int64_t n = ctx->n;
+  const int64_t nm = n * m;
+  BgcrWork& w = get_work(ctx, m);
+  const int64_t sv = (int64_t)n * m;
+  double* P = w.P.as<double>();
+  double* Qv = w.Qv.as<double>();
+  double* R = w.R.as<double>();
+  double* Z = w.Z.as<double>();
+  double* G = w.gram.as<double>();
+  double* Lc = w.Lc.as<double>();
+  int32_t* piv = w.piv.as<int32_t>();
+  int32_t* rank = w.rank.as<int32_t>();
+  double* coef = w.coef.as<double>();
+  const double tol = ctx->opt.gcr_tol;
+  const double rel = 1e-14;
+  std::vector<double> hb(m * m), hr(m * m);
+  std::vector<double> bn2(m);
+  // ||b_k||^2
+  gram(ctx, n, m, B, 0, 1, m, B, G, s);
+  HF_HIP(hipMemcpyAsync(hb.data(), G, sizeof(double) * m * m, hipMemcpyDeviceToHost, s));
+  HF_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < m; ++k) bn2[k] = hb[k * m + k];
+  auto converged = [&](const double* Rd) {
+    gram(ctx, n, m, Rd, 0, 1, m, Rd, G, s);
+    HF_HIP(hipMemcpyAsync(hr.data(), G, sizeof(double) * m * m, hipMemcpyDeviceToHost, s));
+    HF_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < m; ++k) {
+      if (bn2[k] <= 0.0) continue;
+      const double rr = hr[k * m + k];
+      if (!(rr <= tol * tol * bn2[k])) return false;
+    }
+    return true;
+  };
+  // X0 = Q^{-1} B, R0 = B - A X0
+  precond(ctx, m, B, X, s);
+  spmm_k11(ctx, m, X, Z, s);
+  k_sub<<<cdiv(nm, 256), 256, 0, s>>>(nm, B, Z, R);
+  if (converged(R)) return 0;
+  // P0 = Q^{-1} R0, Qv0 = A P0, M0
+  precond(ctx, m, R, P, s);
+  spmm_k11(ctx, m, P, Qv, s);
+  gram(ctx, n, m, Qv, 0, 1, m, Qv, G, s);
+  k_chol_piv<<<1, 64, 0, s>>>(m, G, 0, Lc, piv, rank, rel);
+  const int maxit = ctx->opt.gcr_maxit;
+  for (int it = 0; it < maxit; ++it) {
+    double* Pn = P + it * sv;
+    double* Qn = Qv + it * sv;
+    // alpha = M_n^{-1} Qv_n^T R
+    gram(ctx, n, m, Qn, 0, 1, m, R, G, s);
+    k_chol_solve<<<1, 64, 0, s>>>(m, m, Lc + (int64_t)it * m * m, piv + (int64_t)it * m, rank + it, G, 0,
+                                  coef, 0, 1.0);
+    k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, m, m, X, X, 1, Pn, 0, coef);
+    k_neg<<<cdiv((int64_t)m * m, 256), 256, 0, s>>>((int64_t)m * m, coef);
+    k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, m, m, R, R, 1, Qn, 0, coef);
+    HF_HIP(hipGetLastError());
+    if (converged(R)) return it + 1;
+    if (it + 1 >= maxit) break;
+    // W = Q^{-1} R -> P_{n+1}; Z = A W -> Qv_{n+1}
+    double* Pn1 = P + (it + 1) * sv;
+    double* Qn1 = Qv + (it + 1) * sv;
+    precond(ctx, m, R, Pn1, s);
+    spmm_k11(ctx, m, Pn1, Qn1, s);
+    // beta_m = -M_m^{-1} Qv_m^T Z, for m = 0..n
+    const int nb = it + 1;
+    gram(ctx, n, m, Qv, sv, nb, m, Qn1, G, s);
+    for (int q = 0; q < nb; ++q)
+      k_chol_solve<<<1, 64, 0, s>>>(m, m, Lc + (int64_t)q * m * m, piv + (int64_t)q * m, rank + q,
+                                    G + (int64_t)q * m * m, 0, coef + (int64_t)q * m * m, 0, -1.0);
+    k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, m, m, Pn1, Pn1, nb, P, sv, coef);
+    k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, m, m, Qn1, Qn1, nb, Qv, sv, coef);
+    gram(ctx, n, m, Qn1, 0, 1, m, Qn1, G, s);
+    k_chol_piv<<<1, 64, 0, s>>>(m, G, 0, Lc + (int64_t)(it + 1) * m * m, piv + (int64_t)(it + 1) * m,
+                                rank + it + 1, rel);
+    HF_HIP(hipGetLastError());
+  }
+  throw Status{HF_ERR_NO_CONVERGENCE};
+}
+
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
+  if (ctx->state < 1) return HF_ERR_STATE;
+  if (ctx->nnz > 0 && !values) return HF_ERR_ARG;
+  const int64_t n = ctx->n;
+  try {
+    ctx->state = 1;
+    auto t0 = std::chrono::steady_clock::now();
+    ctx->factor_prec = ctx->opt.low_precision;
+    if (ctx->factor_prec == HF_PREC_FP32) step1<float>(ctx, values, s);
+    else step1<double>(ctx, values, s);
+    // step 2: the split
+    std::vector<uint8_t> isl2(n);
+    std::vector<NodeState> hst(ctx->n_nodes);
+    if (n) HF_HIP(hipMemcpyAsync(isl2.data(), ctx->d_isl2.ptr, n, hipMemcpyDeviceToHost, s));
+    if (ctx->n_nodes)
+      HF_HIP(hipMemcpyAsync(hst.data(), ctx->d_state.ptr, sizeof(NodeState) * ctx->n_nodes,
+                            hipMemcpyDeviceToHost, s));
+    HF_HIP(hipStreamSynchronize(s));
+    ctx->hstate = hst;
+    ctx->lambda2.clear();
+    for (int64_t g = 0; g < n; ++g)
+      if (isl2[g]) ctx->lambda2.push_back((int32_t)g);
+    const int M = (int)ctx->lambda2.size();
+    ctx->M = M;
+    ctx->flops_done = 0.0;
+    for (int32_t j = 0; j < ctx->n_nodes; ++j) {
+      const double pt = hst[j].npiv, f = ctx->nodes[j].f;
+      ctx->flops_done += pt * f * f - pt * pt * f + pt * pt * pt / 3.0;
+    }
+    upload(ctx->d_l2, ctx->lambda2, s);
+    ctx->t_step1 = ms_since(t0);
+    // step 3: K11 X12 = K12 by block GCR, column blocks of width mb
+    t0 = std::chrono::steady_clock::now();
+    const int mb = ctx->opt.gcr_block > 0 ? std::min(ctx->opt.gcr_block, std::max(M, 1))
+                                          : std::min(std::max(M, 1), MAXM);  // 0: all columns (<= 64)
+    ctx->mb = mb;
+    ctx->nblk = M > 0 ? (M + mb - 1) / mb : 0;
+    ctx->gcr_blocks = ctx->nblk;
+    ctx->gcr_iters_max = ctx->gcr_iters_total = 0;
+    ctx->d_X12.alloc((size_t)std::max(ctx->nblk, 1) * std::max<int64_t>(n, 1) * mb * sizeof(double));
+    double* X12 = ctx->d_X12.as<double>();
+    if (M > 0) {
+      BgcrWork& w = get_work(ctx, mb);
+      double* Bk = w.T1.as<double>();
+      for (int blk = 0; blk < ctx->nblk; ++blk) {
+        const int c0 = blk * mb, nbc = std::min(mb, M - c0);
+        HF_HIP(hipMemsetAsync(Bk, 0, (size_t)n * mb * sizeof(double), s));
+        k_gather_k12<<<nbc, 256, 0, s>>>(ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(),
+                                         ctx->d_kval.as<double>(), ctx->d_isl2.as<uint8_t>(),
+                                         ctx->d_l2.as<int32_t>(), c0, nbc, mb, Bk);
+        const int its = bgcr(ctx, mb, Bk, X12 + (int64_t)blk * n * mb, s);
+        ctx->gcr_iters_max = std::max(ctx->gcr_iters_max, its);
+        ctx->gcr_iters_total += its;
+      }
+    }
+    ctx->t_gcr = ms_since(t0);
+    // step 4: S22 = K22 - K21 X12 (symmetrized); step 5: its LDL^T and kernel
+    t0 = std::chrono::steady_clock::now();
+    ctx->d_S22.alloc((size_t)std::max(M, 1) * std::max(M, 1) * sizeof(double));
+    ctx->d_S22f.alloc((size_t)std::max(M, 1) * std::max(M, 1) * sizeof(double) * 3);
+    ctx->d_s22perm.alloc((size_t)std::max(M, 1) * sizeof(int32_t) * 2);
+    ctx->d_s22mag.alloc((size_t)std::max(M, 1) * sizeof(double));
+    ctx->d_s22info.alloc(8 * sizeof(double));
+    double* S = ctx->d_S22.as<double>();
+    double* Aw = ctx->d_S22f.as<double>();
+    double* Lw = Aw + (int64_t)std::max(M, 1) * std::max(M, 1);
+    double* Dw = Lw + (int64_t)std::max(M, 1) * std::max(M, 1);
+    int32_t* sperm = ctx->d_s22perm.as<int32_t>();
+    int32_t* sbs = sperm + std::max(M, 1);
+    ctx->kdim = 0;
+    ctx->rank_gap = INFINITY;
+    ctx->rank_candidates = 0;
+    if (M > 0) {
+      for (int blk = 0; blk < ctx->nblk; ++blk) {
+        const int c0 = blk * mb, nbc = std::min(mb, M - c0);
+        k_s22_block<<<cdiv((int64_t)M * nbc, 256), 256, 0, s>>>(
+            ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(), ctx->d_kval.as<double>(),
+            ctx->d_isl2.as<uint8_t>(), ctx->d_l2.as<int32_t>(), M, c0, nbc, mb, X12 + (int64_t)blk * n * mb, S);
+      }
+      k_symmetrize<<<cdiv((int64_t)M * M, 256), 256, 0, s>>>(M, S);
+      HF_HIP(hipMemcpyAsync(Aw, S, sizeof(double) * M * M, hipMemcpyDeviceToDevice, s));
+      k_s22_ldlt<<<1, 256, 0, s>>>(M, Aw, Lw, Dw, sperm, ctx->d_s22mag.as<double>(), sbs, ctx->opt.tau,
+                                   ctx->opt.n_enlarge, ctx->opt.ker_tol, ctx->d_s22info.as<double>());
+      double info[4];
+      HF_HIP(hipMemcpyAsync(info, ctx->d_s22info.ptr, sizeof(info), hipMemcpyDeviceToHost, s));
+      HF_HIP(hipStreamSynchronize(s));
+      ctx->kdim = (int)info[0];
+      ctx->rank_candidates = (int)info[2];
+      ctx->rank_gap = info[3];
+    }
+    const int k = ctx->kdim;
+    if (k > MAXM) throw Status{HF_ERR_NOT_IMPLEMENTED};
+    if (k > 0) {
+      // lift: N = [-X12 N2; N2], then Q Pi^T, then orthonormalize (CholeskyQR twice)
+      BgcrWork& w = get_work(ctx, std::max(mb, k));
+      const int rows = ctx->nblk * mb;
+      ctx->d_N2.alloc((size_t)rows * k * sizeof(double));
+      double* N2 = ctx->d_N2.as<double>();
+      HF_HIP(hipMemsetAsync(N2, 0, (size_t)rows * k * sizeof(double), s));
+      k_s22_null<<<1, 64, 0, s>>>(M, k, Lw, sperm, N2);
+      double* Nperm = w.T1.as<double>();
+      k_combine<<<cdiv(n * k, 256), 256, 0, s>>>(n, mb, k, Nperm, nullptr, ctx->nblk, X12, (int64_t)n * mb, N2);
+      k_neg<<<cdiv(n * k, 256), 256, 0, s>>>(n * k, Nperm);
+      k_set_rows<<<cdiv((int64_t)M * k, 256), 256, 0, s>>>(M, k, ctx->d_l2.as<int32_t>(), N2, Nperm);
+      ctx->d_kern.alloc((size_t)n * k * sizeof(double));
+      double* N = ctx->d_kern.as<double>();
+      double* tmp = w.Z.as<double>();
+      k_kernel_finish<<<cdiv(n * k, 256), 256, 0, s>>>(n, k, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(),
+                                                       Nperm, tmp);
+      double* G = w.gram.as<double>();
+      double* Ri = w.coef.as<double>();
+      for (int pass = 0; pass < 2; ++pass) {
+        double* src = pass == 0 ? tmp : N;
+        double* dst = pass == 0 ? N : tmp;
+        gram(ctx, n, k, src, 0, 1, k, src, G, s);
+        k_chol_inv<<<1, 1, 0, s>>>(k, G, Ri);
+        k_combine<<<cdiv(n * k, 256), 256, 0, s>>>(n, k, k, dst, nullptr, 1, src, 0, Ri);
+      }
+      HF_HIP(hipMemcpyAsync(N, tmp, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    HF_HIP(hipGetLastError());
+    HF_HIP(hipStreamSynchronize(s));
+    ctx->timer.flush();
+    ctx->t_s22 = ms_since(t0);
+    ctx->state = 2;
+  } catch (const HipError&) {
+    return HF_ERR_HIP;
+  } catch (const Status& st) {
+    return st.code;
+  } catch (const std::bad_alloc&) {
+    return HF_ERR_OOM;
+  }
+  return HF_OK;
+}
+
+// Algorithm 2 on scaled right-hand sides b (row-major n x m, elimination order):
+// x receives [x1; x2].  Scratch: b1 and the block-GCR work space.
+static int solve_core(hf_ctx* ctx, int m, const double* b, double* x, double* b1, hipStream_t s) {
+  const int64_t n = ctx->n;
+  const int64_t nm = n * m;
+  const int M = ctx->M, k = ctx->kdim;
+  k_mask_rows<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_isl2.as<uint8_t>(), b, b1);
+  const int its = bgcr(ctx, m, b1, x, s);  // y1
+  if (M > 0) {
+    ctx->d_y2.alloc((size_t)M * m * sizeof(double) * 3);
+    double* y2 = ctx->d_y2.as<double>();
+    double* x2 = y2 + (int64_t)M * m;
+    double* wk = x2 + (int64_t)M * m;
+    k_y2<<<cdiv((int64_t)M * m, 256), 256, 0, s>>>(ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(),
+                                                   ctx->d_kval.as<double>(), ctx->d_isl2.as<uint8_t>(),
+                                                   ctx->d_l2.as<int32_t>(), M, m, b, x, y2);
+    double* S = ctx->d_S22f.as<double>();
+    const int64_t MM = (int64_t)M * M;
+    int32_t* sperm = ctx->d_s22perm.as<int32_t>();
+    k_s22_solve<<<1, 64, 0, s>>>(M, k, S + MM, S + 2 * MM, sperm, sperm + M, m, y2, x2, wk);
+    // x1 = y1 - X12 x2 (x2 rows padded per block)
+    const int mb = ctx->mb;
+    ctx->d_x2pad.alloc((size_t)ctx->nblk * mb * m * sizeof(double));
+    double* x2p = ctx->d_x2pad.as<double>();
+    HF_HIP(hipMemsetAsync(x2p, 0, (size_t)ctx->nblk * mb * m * sizeof(double), s));
+    HF_HIP(hipMemcpyAsync(x2p, x2, (size_t)M * m * sizeof(double), hipMemcpyDeviceToDevice, s));
+    k_neg<<<cdiv((int64_t)ctx->nblk * mb * m, 256), 256, 0, s>>>((int64_t)ctx->nblk * mb * m, x2p);
+    k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, mb, m, x, x, ctx->nblk, ctx->d_X12.as<double>(), (int64_t)n * mb,
+                                            x2p);
+    k_set_rows<<<cdiv((int64_t)M * m, 256), 256, 0, s>>>(M, m, ctx->d_l2.as<int32_t>(), x2, x);
+  }
+  HF_HIP(hipGetLastError());
+  return its;
+}
+
+int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, int64_t ldx,
+               hipStream_t s) {
+  if (ctx->state < 2) return HF_ERR_STATE;
+  const int64_t n = ctx->n;
+  if (r < 0 || (r > 0 && n > 0 && (!B || !X || ldb < n || ldx < n))) return HF_ERR_ARG;
+  if (r == 0 || n == 0) return HF_OK;
+  try {
+    auto t0 = std::chrono::steady_clock::now();
+    const int k = ctx->kdim;
+    ctx->solve_iters = 0;
+    for (int c0 = 0; c0 < r; c0 += MAXM) {
+      const int m = std::min(MAXM, r - c0);
+      BgcrWork& w = get_work(ctx, std::max(m, std::max(ctx->mb, k)));
+      const int64_t nm = n * m;
+      ctx->d_rhs_b.alloc((size_t)nm * sizeof(double) * 5);
+      double* b = ctx->d_rhs_b.as<double>();
+      double* b1 = b + nm;
+      double* x = b1 + nm;
+      double* res = x + nm;
+      double* dx = res + nm;
+      k_load_rhs<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(), B, ldb,
+                                               c0, b);
+      ctx->solve_iters = std::max(ctx->solve_iters, solve_core(ctx, m, b, x, b1, s));
+      // residual correction: x += Algorithm2(Q Pi (bbar - Kbar xbar)), the residual
+      // taken in the caller's variables (the scaled matrix has an exactly unit
+      // diagonal and differs from Q Kbar Q by rounding)
+      for (int it = 0; it < ctx->opt.refine_steps; ++it) {
+        k_residual_orig<<<cdiv(nm, 256), 256, 0, s>>>(n, ctx->d_pindptr.as<int64_t>(),
+                                                      ctx->d_pindices.as<int32_t>(), ctx->d_kbar.as<double>(),
+                                                      ctx->d_q.as<double>(), ctx->d_perm.as<int32_t>(), m, B, ldb, c0,
+                                                      x, res);
+        ctx->solve_iters = std::max(ctx->solve_iters, solve_core(ctx, m, res, dx, b1, s));
+        k_add<<<cdiv(nm, 256), 256, 0, s>>>(nm, x, dx);
+      }
+      // back to original variables, projection orthogonal to the kernel
+      double* xo = b1;
+      k_unperm<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(), x, xo);
+      if (k > 0) {
+        double* G = w.gram.as<double>();
+        gram(ctx, n, k, ctx->d_kern.as<double>(), 0, 1, m, xo, G, s);
+        k_neg<<<cdiv((int64_t)k * m, 256), 256, 0, s>>>((int64_t)k * m, G);
+        k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, k, m, xo, xo, 1, ctx->d_kern.as<double>(), 0, G);
+      }
+      k_store_cols<<<cdiv(nm, 256), 256, 0, s>>>(n, m, xo, X, ldx, c0);
+      HF_HIP(hipGetLastError());
+    }
+    HF_HIP(hipStreamSynchronize(s));
+    ctx->timer.flush();
+    ctx->t_solve = ms_since(t0);
+  } catch (const HipError&) {
+    return HF_ERR_HIP;
+  } catch (const Status& st) {
+    return st.code;
+  } catch (const std::bad_alloc&) {
+    return HF_ERR_OOM;
+  }
+  return HF_OK;
+}
+
+// accessors used by the C entry points
+int schur_impl(const hf_ctx* ctx, int32_t* m, int32_t* lambda2, double* S, int64_t lds, hipStream_t s) {
+  if (ctx->state < 2) return HF_ERR_STATE;
+  const int M = ctx->M;
+  *m = M;
+  if (!lambda2 && !S) return HF_OK;
+  std::vector<std::pair<int32_t, int32_t>> ord(M);
+  for (int i = 0; i < M; ++i) ord[i] = {ctx->perm[ctx->lambda2[i]], i};
+  std::sort(ord.begin(), ord.end());
+  if (lambda2)
+    for (int i = 0; i < M; ++i) lambda2[i] = ord[i].first;
+  if (S && M > 0) {
+    if (lds < M) return HF_ERR_ARG;
+    try {
+      std::vector<int32_t> order(M);
+      for (int i = 0; i < M; ++i) order[i] = ord[i].second;
+      DBuf d_order;
+      upload(d_order, order, s);
+      k_reorder_s22<<<cdiv((int64_t)M * M, 256), 256, 0, s>>>(M, d_order.as<int32_t>(), ctx->d_S22.as<double>(), S,
+                                                             lds);
+      HF_HIP(hipGetLastError());
+      HF_HIP(hipStreamSynchronize(s));
+    } catch (const HipError&) {
+      return HF_ERR_HIP;
+    } catch (const Status& st) {
+      return st.code;
+    }
+  }
+  return HF_OK;
+}
+
+int kernel_basis_impl(const hf_ctx* ctx, double* N, int64_t ldn, hipStream_t s) {
+  if (ctx->state < 2) return HF_ERR_STATE;
+  const int k = ctx->kdim;
+  if (k == 0) return HF_OK;
+  if (!N || ldn < ctx->n) return HF_ERR_ARG;
+  k_kernel_out<<<cdiv(ctx->n * k, 256), 256, 0, s>>>(ctx->n, k, ctx->d_kern.as<double>(), N, ldn);
+  if (hipGetLastError() != hipSuccess) return HF_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return HF_ERR_HIP;
+  return HF_OK;
+}
+
+int scaling_impl(const hf_ctx* ctx, double* q, hipStream_t s) {
+  if (ctx->state < 2) return HF_ERR_STATE;
+  if (!q) return HF_ERR_ARG;
+  if (ctx->n == 0) return HF_OK;
+  k_scatter_q<<<cdiv(ctx->n, 256), 256, 0, s>>>(ctx->n, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(), q);
+  if (hipGetLastError() != hipSuccess) return HF_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return HF_ERR_HIP;
+  return HF_OK;
+}
+
+}  // namespace hf

@@ -1,0 +1,517 @@
+// The preconditioner Q^{-1} of Sec. 3.2 on the GPU: forward and backward
+// substitution with the low-precision factor of K11, multifrontal.
+//
+// Every tree node j owns an f_j x m block of a solve arena (T, row-major, m
+// right-hand sides per row); its first rows are in pivot order.  Forward sweep,
+// leaves first, per level:
+//   gather   : own accepted rows from the FP64 input (cast to T), children's
+//              border blocks added (extend-add, pivot-order aware);
+//   steps of TB = 256 columns of L11:
+//     diag   : z_J = L_JJ^{-1} w_J with four 64x64 sub-blocks whose inverses
+//              were formed once after the factorization (k_inv_diag);
+//     update : w_rows -= L[rows, J] z_J for every row below the step (the rest
+//              of L11 and the border L21), 64-row strips, many workgroups.
+// Backward sweep, root first, per level:
+//   border   : t = D^{-1} z - L21^T x_border (column strips, x_border read from
+//              the FP64 result of the ancestors);
+//   steps from the last one: diag (L_JJ^{-T} with the same inverses, result
+//              scattered to FP64) and update of the columns left of the step.
+// Rows of the hard part are never written, so they stay zero in the result.
+#include <algorithm>
+
+#include "hf_internal.h"
+#include "hf_kernels.h"
+
+namespace hf {
+
+constexpr int TB = 256;  // columns of L11 per sweep step
+constexpr int SB = 64;   // sub-block with an explicit inverse
+constexpr int KC = 32;   // k-chunk of the update products staged in LDS
+
+static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// inverses of the 64x64 unit-lower diagonal blocks of every L11
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ void __launch_bounds__(256)
+k_inv_diag(const int32_t* __restrict__ blk_node, const int32_t* __restrict__ blk_first,
+           const NodeInfo* __restrict__ nodes, const NodeState* __restrict__ st,
+           const T* __restrict__ front, const int64_t* __restrict__ linv_off, T* __restrict__ linv) {
+  const int bi = blockIdx.x;
+  const int j = blk_node[bi];
+  const int B = bi - blk_first[j];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int J0 = B * SB;
+  if (J0 >= npiv) return;
+  const int nc = min(SB, npiv - J0);
+  const int64_t f = ni.f;
+  const T* F = front + ni.front_off;
+  __shared__ T Ls[SB][SB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < SB * SB; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    T v = (r == c) ? (T)1 : (T)0;
+    if (r > c && r < nc) v = F[(int64_t)(J0 + c) * f + J0 + r];
+    Ls[r][c] = v;
+  }
+  __syncthreads();
+  T* out = linv + linv_off[j] + (int64_t)B * SB * SB;  // column-major 64x64
+  if (tid < SB) {
+    const int c = tid;
+    T x[SB];
+#pragma unroll
+    for (int r = 0; r < SB; ++r) x[r] = (T)0;
+    x[c] = (T)1;
+    for (int r = c + 1; r < SB; ++r) {
+      T v = (T)0;
+      for (int t = c; t < r; ++t) v -= Ls[r][t] * x[t];
+      x[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < SB; ++r) out[(int64_t)c * SB + r] = x[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward sweep
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ void __launch_bounds__(256)
+k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+             const NodeState* __restrict__ st, const int32_t* __restrict__ piv,
+             const int32_t* __restrict__ relmap, const int32_t* __restrict__ child_list,
+             const int32_t* __restrict__ ipos, int m, const double* __restrict__ R, T* __restrict__ rb) {
+  const int j = lnodes[blockIdx.x];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int p = ni.p, f = ni.f;
+  T* W = rb + ni.rhs_off * m;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < f * m; e += 256) {
+    const int r = e / m, col = e - r * m;
+    W[e] = (r < npiv) ? (T)R[(int64_t)piv[ni.start + r] * m + col] : (T)0;
+  }
+  __syncthreads();
+  for (int ci = ni.child_begin; ci < ni.child_end; ++ci) {
+    const NodeInfo cn = nodes[child_list[ci]];
+    const T* Wc = rb + (cn.rhs_off + cn.p) * m;
+    const int32_t* rel = relmap + cn.border_off;
+    for (int e = tid; e < cn.b * m; e += 256) {
+      const int r = e / m, col = e - r * m;
+      int pr = rel[r];
+      if (pr < p) pr = ipos[ni.start + pr];  // own rows are stored in pivot order
+      W[(int64_t)pr * m + col] += Wc[e];
+    }
+    __syncthreads();
+  }
+}
+
+// z_J = L_JJ^{-1} w_J for the step at J0 (one workgroup per front)
+template <class T>
+__global__ void __launch_bounds__(256)
+k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+           const NodeState* __restrict__ st, const T* __restrict__ front,
+           const int64_t* __restrict__ linv_off, const T* __restrict__ linv, int J0, int m,
+           T* __restrict__ rb) {
+  const int j = lnodes[blockIdx.x];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  if (J0 >= npiv) return;
+  const int nc = min(TB, npiv - J0);
+  const int64_t f = ni.f;
+  const T* F = front + ni.front_off;
+  T* W = rb + ni.rhs_off * m;
+  __shared__ T Lt[SB][SB + 1];
+  __shared__ T acc[SB * 64];
+  const int tid = threadIdx.x;
+  for (int s0 = J0; s0 < J0 + nc; s0 += SB) {
+    const int ns = min(SB, J0 + nc - s0);
+    for (int e = tid; e < SB * m; e += 256) acc[e] = (e / m < ns) ? W[(int64_t)s0 * m + e] : (T)0;
+    __syncthreads();
+    for (int t0 = J0; t0 < s0; t0 += SB) {
+      for (int e = tid; e < SB * SB; e += 256) {
+        const int r = e & 63, c = e >> 6;
+        Lt[r][c] = (r < ns) ? F[(int64_t)(t0 + c) * f + s0 + r] : (T)0;
+      }
+      __syncthreads();
+      for (int e = tid; e < ns * m; e += 256) {
+        const int r = e / m, col = e - r * m;
+        T v = (T)0;
+        for (int k = 0; k < SB; ++k) v += Lt[r][k] * W[(int64_t)(t0 + k) * m + col];
+        acc[e] -= v;
+      }
+      __syncthreads();
+    }
+    const T* Li = linv + linv_off[j] + (int64_t)((s0) / SB) * SB * SB;
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int r = e & 63, c = e >> 6;
+      Lt[r][c] = Li[(int64_t)c * SB + r];
+    }
+    __syncthreads();
+    for (int e = tid; e < ns * m; e += 256) {
+      const int r = e / m, col = e - r * m;
+      T v = (T)0;
+      for (int k = 0; k <= r; ++k) v += Lt[r][k] * acc[k * m + col];
+      W[(int64_t)(s0 + r) * m + col] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// w_rows -= L[rows, J0:J0+nc] z_J for the rows below the step, 64-row strips
+template <class T>
+__global__ void __launch_bounds__(256)
+k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+          const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int m,
+          T* __restrict__ rb) {
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  if (J0 >= npiv) return;
+  const int nc = min(TB, npiv - J0);
+  const int f = ni.f, p = ni.p;
+  const int rs = J0 + nc + blockIdx.x * 64;
+  if (rs >= f) return;
+  const int64_t lf = f;
+  const T* F = front + ni.front_off;
+  T* W = rb + ni.rhs_off * m;
+  __shared__ T Lt[KC][64 + 1];
+  __shared__ T zs[KC * 64];
+  const int tid = threadIdx.x;
+  const int row = tid & 63, cg = tid >> 6;
+  const int r = rs + row;
+  T a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) a[q] = (T)0;
+  for (int k0 = 0; k0 < nc; k0 += KC) {
+    const int kc = min(KC, nc - k0);
+    for (int e = tid; e < KC * 64; e += 256) {
+      const int rr = e & 63, kk = e >> 6;
+      Lt[kk][rr] = (kk < kc && rs + rr < f) ? F[(int64_t)(J0 + k0 + kk) * lf + rs + rr] : (T)0;
+    }
+    for (int e = tid; e < kc * m; e += 256) zs[e] = W[(int64_t)(J0 + k0) * m + e];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = cg + 4 * q;
+      if (col < m) {
+        T v = a[q];
+        for (int kk = 0; kk < kc; ++kk) v += Lt[kk][row] * zs[kk * m + col];
+        a[q] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if (r < f && !(r >= npiv && r < p)) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = cg + 4 * q;
+      if (col < m) W[(int64_t)r * m + col] -= a[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward sweep
+// ---------------------------------------------------------------------------
+
+// t_k = z_k / d_k - sum_r L21[r, k] x_border[r]   (64-column strips)
+template <class T>
+__global__ void __launch_bounds__(256)
+k_bwd_border(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+             const NodeState* __restrict__ st, const T* __restrict__ front, const T* __restrict__ dval,
+             const int32_t* __restrict__ border, int m, const double* __restrict__ Y,
+             T* __restrict__ rb) {
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int cs = blockIdx.x * 64;
+  if (cs >= npiv) return;
+  const int p = ni.p, b = ni.b;
+  const int64_t lf = ni.f;
+  const T* F = front + ni.front_off;
+  T* W = rb + ni.rhs_off * m;
+  __shared__ T Lt[KC][64 + 1];
+  __shared__ T xs[KC * 64];
+  const int tid = threadIdx.x;
+  const int kl = tid & 63, cg = tid >> 6;
+  const int k = cs + kl;
+  T a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) a[q] = (T)0;
+  for (int r0 = 0; r0 < b; r0 += KC) {
+    const int rc = min(KC, b - r0);
+    for (int e = tid; e < KC * 64; e += 256) {
+      const int rr = e & (KC - 1), kk = e / KC;
+      Lt[rr][kk] = (rr < rc && cs + kk < npiv) ? F[(int64_t)(cs + kk) * lf + p + r0 + rr] : (T)0;
+    }
+    for (int e = tid; e < rc * m; e += 256) {
+      const int rr = e / m, col = e - rr * m;
+      xs[e] = (T)Y[(int64_t)border[ni.border_off + r0 + rr] * m + col];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = cg + 4 * q;
+      if (col < m) {
+        T v = a[q];
+        for (int rr = 0; rr < rc; ++rr) v += Lt[rr][kl] * xs[rr * m + col];
+        a[q] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if (k < npiv) {
+    const T dinv = (T)1 / dval[ni.start + k];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = cg + 4 * q;
+      if (col < m) W[(int64_t)k * m + col] = W[(int64_t)k * m + col] * dinv - a[q];
+    }
+  }
+}
+
+// x_J = L_JJ^{-T} t_J for the step at J0, scattered to the FP64 result
+template <class T>
+__global__ void __launch_bounds__(256)
+k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+           const NodeState* __restrict__ st, const T* __restrict__ front,
+           const int64_t* __restrict__ linv_off, const T* __restrict__ linv,
+           const int32_t* __restrict__ piv, int J0, int m, double* __restrict__ Y, T* __restrict__ rb) {
+  const int j = lnodes[blockIdx.x];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  if (J0 >= npiv) return;
+  const int nc = min(TB, npiv - J0);
+  const int64_t f = ni.f;
+  const T* F = front + ni.front_off;
+  T* W = rb + ni.rhs_off * m;
+  __shared__ T Lt[SB][SB + 1];
+  __shared__ T acc[SB * 64];
+  const int tid = threadIdx.x;
+  const int nsub = (nc + SB - 1) / SB;
+  for (int si = nsub - 1; si >= 0; --si) {
+    const int s0 = J0 + si * SB;
+    const int ns = min(SB, J0 + nc - s0);
+    for (int e = tid; e < SB * m; e += 256) acc[e] = (e / m < ns) ? W[(int64_t)s0 * m + e] : (T)0;
+    __syncthreads();
+    for (int t0 = s0 + SB; t0 < J0 + nc; t0 += SB) {
+      const int nt = min(SB, J0 + nc - t0);
+      // Lt[c][k] = L[t0 + k, s0 + c]
+      for (int e = tid; e < SB * SB; e += 256) {
+        const int kk = e & 63, c = e >> 6;
+        Lt[c][kk] = (kk < nt && c < ns) ? F[(int64_t)(s0 + c) * f + t0 + kk] : (T)0;
+      }
+      __syncthreads();
+      for (int e = tid; e < ns * m; e += 256) {
+        const int c = e / m, col = e - c * m;
+        T v = (T)0;
+        for (int kk = 0; kk < nt; ++kk) v += Lt[c][kk] * W[(int64_t)(t0 + kk) * m + col];
+        acc[e] -= v;
+      }
+      __syncthreads();
+    }
+    const T* Li = linv + linv_off[j] + (int64_t)(s0 / SB) * SB * SB;
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int r = e & 63, c = e >> 6;
+      Lt[r][c] = Li[(int64_t)c * SB + r];  // Lt[r][c] = Linv(r, c)
+    }
+    __syncthreads();
+    // x = Linv^T acc: x_c = sum_{r >= c} Linv(r, c) acc_r
+    for (int e = tid; e < ns * m; e += 256) {
+      const int c = e / m, col = e - c * m;
+      T v = (T)0;
+      for (int r = c; r < ns; ++r) v += Lt[r][c] * acc[r * m + col];
+      W[(int64_t)(s0 + c) * m + col] = v;
+      Y[(int64_t)piv[ni.start + s0 + c] * m + col] = (double)v;
+    }
+    __syncthreads();
+  }
+}
+
+// t_k -= sum_{r in step} L[r, k] x_r for the columns k < J0 (64-column strips)
+template <class T>
+__global__ void __launch_bounds__(256)
+k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+          const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int m,
+          T* __restrict__ rb) {
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  if (J0 >= npiv) return;
+  const int cs = blockIdx.x * 64;
+  if (cs >= J0) return;
+  const int nc = min(TB, npiv - J0);
+  const int64_t lf = ni.f;
+  const T* F = front + ni.front_off;
+  T* W = rb + ni.rhs_off * m;
+  __shared__ T Lt[KC][64 + 1];
+  __shared__ T xs[KC * 64];
+  const int tid = threadIdx.x;
+  const int kl = tid & 63, cg = tid >> 6;
+  T a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) a[q] = (T)0;
+  for (int r0 = 0; r0 < nc; r0 += KC) {
+    const int rc = min(KC, nc - r0);
+    for (int e = tid; e < KC * 64; e += 256) {
+      const int rr = e & (KC - 1), kk = e / KC;
+      Lt[rr][kk] = (rr < rc && cs + kk < J0) ? F[(int64_t)(cs + kk) * lf + J0 + r0 + rr] : (T)0;
+    }
+    for (int e = tid; e < rc * m; e += 256) xs[e] = W[(int64_t)(J0 + r0) * m + e];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = cg + 4 * q;
+      if (col < m) {
+        T v = a[q];
+        for (int rr = 0; rr < rc; ++rr) v += Lt[rr][kl] * xs[rr * m + col];
+        a[q] = v;
+      }
+    }
+    __syncthreads();
+  }
+  const int k = cs + kl;
+  if (k < J0) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = cg + 4 * q;
+      if (col < m) W[(int64_t)k * m + col] -= a[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// drivers
+// ---------------------------------------------------------------------------
+
+template <class T>
+void prepare_solve(hf_ctx* ctx, hipStream_t s) {
+  const int64_t nb = ctx->blk_first.empty() ? 0 : (int64_t)ctx->blk_node.size();
+  ctx->d_linv.alloc((size_t)std::max<int64_t>(ctx->linv_elems, 1) * sizeof(T));
+  if (nb > 0)
+    k_inv_diag<T><<<(unsigned)nb, 256, 0, s>>>(ctx->d_blk_node.as<int32_t>(), ctx->d_blk_first.as<int32_t>(),
+                                               ctx->d_nodes.as<NodeInfo>(), ctx->d_state.as<NodeState>(),
+                                               ctx->d_front.as<T>(), ctx->d_linv_off.as<int64_t>(),
+                                               ctx->d_linv.as<T>());
+  HF_HIP(hipGetLastError());
+}
+
+template <class T>
+void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s) {
+  const int nlev = (int)ctx->level_ptr.size() - 1;
+  ctx->d_rhs_arena.alloc((size_t)std::max<int64_t>(ctx->rhs_rows, 1) * m * sizeof(T));
+  T* rb = ctx->d_rhs_arena.as<T>();
+  const T* front = ctx->d_front.as<T>();
+  const T* linv = ctx->d_linv.as<T>();
+  const int64_t* loff = ctx->d_linv_off.as<int64_t>();
+  const NodeInfo* nodes = ctx->d_nodes.as<NodeInfo>();
+  const NodeState* st = ctx->d_state.as<NodeState>();
+  const int32_t* lall = ctx->d_level_nodes.as<int32_t>();
+  KTimer& tm = ctx->timer;
+  const double sz = sizeof(T), dm = m;
+  // algorithmic work of one launch over a level, with the actual pivot counts
+  auto level_sum = [&](int l, auto&& fn) {
+    double by = 0.0, fl = 0.0;
+    if (!tm.on) return std::make_pair(by, fl);
+    for (int32_t q = ctx->level_ptr[l]; q < ctx->level_ptr[l + 1]; ++q) {
+      const int32_t j = ctx->level_nodes[q];
+      fn(ctx->nodes[j], (double)ctx->hstate[j].npiv, by, fl);
+    }
+    return std::make_pair(by, fl);
+  };
+  HF_HIP(hipMemsetAsync(Y, 0, (size_t)ctx->n * m * sizeof(double), s));
+  for (int l = 0; l < nlev; ++l) {
+    const int nl = ctx->level_ptr[l + 1] - ctx->level_ptr[l];
+    const int32_t* ln = lall + ctx->level_ptr[l];
+    auto wg = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
+      by += ni.f * dm * sz + np * dm * 8.0;
+      for (int32_t c = ni.child_begin; c < ni.child_end; ++c) {
+        const double bc = ctx->nodes[ctx->child_list[c]].b;
+        by += 2.0 * bc * dm * sz;
+        fl += bc * dm;
+      }
+    });
+    timed(tm, HF_K_SOLVE_GATHER, wg.first, wg.second, s, [&] {
+      k_fwd_gather<T><<<nl, 256, 0, s>>>(ln, nodes, st, ctx->d_piv.as<int32_t>(), ctx->d_relmap.as<int32_t>(),
+                                         ctx->d_child_list.as<int32_t>(), ctx->d_ipos.as<int32_t>(), m, R, rb);
+    });
+    const int maxp = ctx->level_maxp[l], maxf = ctx->level_maxf[l];
+    for (int J0 = 0; J0 < maxp; J0 += TB) {
+      auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
+        if (np <= J0) return;
+        const double nc = std::min<double>(TB, np - J0);
+        by += (nc * SB + 0.5 * nc * nc) * sz + 2.0 * nc * dm * sz;
+        fl += 2.0 * dm * (nc * SB * 0.5 + 0.5 * nc * nc);
+      });
+      timed(tm, HF_K_SOLVE_DIAG, wd.first, wd.second, s, [&] {
+        k_fwd_diag<T><<<nl, 256, 0, s>>>(ln, nodes, st, front, loff, linv, J0, m, rb);
+      });
+      const int rows = maxf - J0 - 1;
+      if (rows > 0) {
+        dim3 g(cdiv(rows, 64), nl);
+        auto wu = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
+          if (np <= J0) return;
+          const double nc = std::min<double>(TB, np - J0);
+          const double below = ni.f - J0 - nc - (ni.p - np);
+          if (below <= 0) return;
+          by += below * nc * sz + 2.0 * below * dm * sz + nc * dm * sz;
+          fl += 2.0 * dm * below * nc;
+        });
+        timed(tm, HF_K_SOLVE_UPDATE, wu.first, wu.second, s, [&] {
+          k_fwd_upd<T><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, rb);
+        });
+      }
+    }
+  }
+  for (int l = nlev - 1; l >= 0; --l) {
+    const int nl = ctx->level_ptr[l + 1] - ctx->level_ptr[l];
+    const int32_t* ln = lall + ctx->level_ptr[l];
+    const int maxp = ctx->level_maxp[l];
+    if (maxp == 0) continue;
+    dim3 gb(cdiv(maxp, 64), nl);
+    auto wb = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
+      by += ni.b * np * sz + 2.0 * np * dm * sz + ni.b * dm * 8.0;
+      fl += 2.0 * dm * ni.b * np;
+    });
+    timed(tm, HF_K_SOLVE_UPDATE, wb.first, wb.second, s, [&] {
+      k_bwd_border<T><<<gb, 256, 0, s>>>(ln, nodes, st, front, ctx->d_dval.as<T>(), ctx->d_border.as<int32_t>(), m,
+                                         Y, rb);
+    });
+    for (int J0 = ((maxp - 1) / TB) * TB; J0 >= 0; J0 -= TB) {
+      auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
+        if (np <= J0) return;
+        const double nc = std::min<double>(TB, np - J0);
+        by += (nc * SB + 0.5 * nc * nc) * sz + 2.0 * nc * dm * sz + nc * dm * 8.0;
+        fl += 2.0 * dm * (nc * SB * 0.5 + 0.5 * nc * nc);
+      });
+      timed(tm, HF_K_SOLVE_DIAG, wd.first, wd.second, s, [&] {
+        k_bwd_diag<T><<<nl, 256, 0, s>>>(ln, nodes, st, front, loff, linv, ctx->d_piv.as<int32_t>(), J0, m, Y, rb);
+      });
+      if (J0 > 0) {
+        dim3 g(cdiv(J0, 64), nl);
+        auto wu = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
+          if (np <= J0) return;
+          const double nc = std::min<double>(TB, np - J0);
+          by += J0 * nc * sz + 2.0 * J0 * dm * sz;
+          fl += 2.0 * dm * J0 * nc;
+        });
+        timed(tm, HF_K_SOLVE_UPDATE, wu.first, wu.second, s, [&] {
+          k_bwd_upd<T><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, rb);
+        });
+      }
+    }
+  }
+  HF_HIP(hipGetLastError());
+}
+
+template void prepare_solve<float>(hf_ctx*, hipStream_t);
+template void prepare_solve<double>(hf_ctx*, hipStream_t);
+template void precond_apply<float>(hf_ctx*, int, const double*, double*, hipStream_t);
+template void precond_apply<double>(hf_ctx*, int, const double*, double*, hipStream_t);
+
+}  // namespace hf

@@ -1,0 +1,263 @@
+"""Python binding of the C ABI in include/hf.h (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library ``libhyfact.so`` built in-tree by
+``paper_2208_01907_amd/build.py``.  PyTorch provides device memory and the HIP
+stream.  If the library is missing this module raises at import time: there is
+no fallback.
+
+The function names follow the C entry points:
+
+    ctx = hf_analyse(indptr, indices, perm, node_ptr, parent, opt)
+    hf_factorize(ctx, values_dev)            # values: torch float64 on the GPU
+    X = hf_solve(ctx, B_dev)                 # B: (L, r) torch float64 on the GPU
+    k = hf_kernel_dim(ctx)
+    N = hf_kernel_basis(ctx)                 # (L, k)
+    lam2, S22 = hf_schur(ctx)                # hard part, Schur complement (scaled)
+    q = hf_scaling(ctx)
+    info = hf_info(ctx)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libhyfact.so")
+
+HF_OK = 0
+HF_ERR_ARG = -1
+HF_ERR_PATTERN = -2
+HF_ERR_VALUE = -3
+HF_ERR_STATE = -4
+HF_ERR_NO_CONVERGENCE = -5
+HF_ERR_BREAKDOWN = -6
+HF_ERR_OOM = -7
+HF_ERR_HIP = -8
+HF_ERR_NOT_IMPLEMENTED = -9
+HF_PREC_FP32 = 32
+HF_PREC_FP64 = 64
+
+EXPORTS = ["hf_default_options", "hf_analyse", "hf_factorize", "hf_solve", "hf_kernel_dim",
+           "hf_kernel_basis", "hf_schur", "hf_scaling", "hf_info", "hf_strerror", "hf_destroy",
+           "hf_timing_enable", "hf_timing_get"]
+
+# kernel classes of hf_timing_get
+KCLASS = ["panel", "f11_update", "trsm", "syrk", "extend_add", "solve_diag", "solve_update",
+          "solve_gather", "spmm", "gram", "other"]
+
+
+class HFError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        super().__init__(f"{where}: {hf_strerror(code)} ({code})")
+
+
+class HFOptions(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("low_precision", ctypes.c_int32),
+                ("first_pivot_unit", ctypes.c_int32), ("n_enlarge", ctypes.c_int32),
+                ("gcr_block", ctypes.c_int32), ("gcr_tol", ctypes.c_double),
+                ("gcr_maxit", ctypes.c_int32), ("ker_tol", ctypes.c_double),
+                ("refine_steps", ctypes.c_int32)]
+
+
+class HFInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_nodes", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("max_front", ctypes.c_int32), ("max_pivots", ctypes.c_int32),
+                ("factor_entries", ctypes.c_int64), ("factor_flops", ctypes.c_double),
+                ("factor_flops_done", ctypes.c_double), ("front_bytes", ctypes.c_int64),
+                ("M", ctypes.c_int32), ("kernel_dim", ctypes.c_int32), ("gcr_blocks", ctypes.c_int32),
+                ("gcr_iters_max", ctypes.c_int32), ("gcr_iters_total", ctypes.c_int32),
+                ("solve_gcr_iters", ctypes.c_int32), ("rank_gap", ctypes.c_double),
+                ("rank_candidates", ctypes.c_int32), ("state", ctypes.c_int32),
+                ("t_analyse_ms", ctypes.c_double), ("t_step1_ms", ctypes.c_double),
+                ("t_gcr_ms", ctypes.c_double), ("t_s22_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double)]
+
+
+class HFKStat(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is missing: build it with `python paper_2208_01907_amd/build.py` "
+                          "(the HIP library is required; there is no fallback)")
+    lib = ctypes.CDLL(LIBPATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "hf_default_options": (None, [P]),
+        "hf_analyse": (ctypes.c_int, [I64, P, P, P, I32, P, P, P, P]),
+        "hf_factorize": (ctypes.c_int, [P, P, P]),
+        "hf_solve": (ctypes.c_int, [P, I32, P, I64, P, I64, P]),
+        "hf_kernel_dim": (ctypes.c_int, [P, P]),
+        "hf_kernel_basis": (ctypes.c_int, [P, P, I64, P]),
+        "hf_schur": (ctypes.c_int, [P, P, P, P, I64, P]),
+        "hf_scaling": (ctypes.c_int, [P, P, P]),
+        "hf_info": (ctypes.c_int, [P, P]),
+        "hf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "hf_destroy": (None, [P]),
+        "hf_timing_enable": (ctypes.c_int, [P, I32]),
+        "hf_timing_get": (ctypes.c_int, [P, I32, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def hf_strerror(code: int) -> str:
+    return _lib.hf_strerror(int(code)).decode()
+
+
+def _check(code, where):
+    if code != HF_OK:
+        raise HFError(code, where)
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def hf_default_options(**kw) -> HFOptions:
+    o = HFOptions()
+    _lib.hf_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """Owns an hf_ctx; destroyed with the object."""
+
+    def __init__(self, handle, n):
+        self._h = handle
+        self.n = n
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("context destroyed")
+        return self._h
+
+    def destroy(self):
+        if self._h:
+            _lib.hf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def hf_analyse(indptr, indices, perm=None, node_ptr=None, parent=None, opt=None) -> Context:
+    indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(indices, dtype=np.int32)
+    n = len(indptr) - 1
+    perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+    node_ptr = None if node_ptr is None else np.ascontiguousarray(node_ptr, dtype=np.int32)
+    parent = None if parent is None else np.ascontiguousarray(parent, dtype=np.int32)
+    n_nodes = 0 if parent is None else len(parent)
+    h = ctypes.c_void_p()
+    code = _lib.hf_analyse(n, _np_ptr(indptr), _np_ptr(indices), _np_ptr(perm), n_nodes, _np_ptr(node_ptr),
+                           _np_ptr(parent), ctypes.byref(opt) if opt is not None else None, ctypes.byref(h))
+    _check(code, "hf_analyse")
+    return Context(h, n)
+
+
+def hf_factorize(ctx: Context, values, stream=None):
+    import torch
+    assert values.is_cuda and values.dtype == torch.float64 and values.is_contiguous()
+    _check(_lib.hf_factorize(ctx.handle, ctypes.c_void_p(values.data_ptr()), _stream(stream)), "hf_factorize")
+
+
+def hf_solve(ctx: Context, B, X=None, stream=None):
+    """Solve for B of shape (L, r) (float64, GPU).  Returns X of shape (L, r)."""
+    import torch
+    assert B.is_cuda and B.dtype == torch.float64
+    one = B.dim() == 1
+    B2 = B.reshape(B.shape[0], -1)
+    r = B2.shape[1]
+    Bc = B2.t().contiguous()                # column-major (L x r) storage
+    Xc = torch.empty_like(Bc)
+    _check(_lib.hf_solve(ctx.handle, r, ctypes.c_void_p(Bc.data_ptr()), ctx.n, ctypes.c_void_p(Xc.data_ptr()),
+                         ctx.n, _stream(stream)), "hf_solve")
+    out = Xc.t()
+    if X is not None:
+        X.copy_(out.reshape(X.shape))
+        return X
+    return out[:, 0] if one else out
+
+
+def hf_kernel_dim(ctx: Context) -> int:
+    k = ctypes.c_int32()
+    _check(_lib.hf_kernel_dim(ctx.handle, ctypes.byref(k)), "hf_kernel_dim")
+    return k.value
+
+
+def hf_kernel_basis(ctx: Context, stream=None):
+    import torch
+    k = hf_kernel_dim(ctx)
+    Nc = torch.zeros((k, ctx.n), dtype=torch.float64, device="cuda")
+    if k:
+        _check(_lib.hf_kernel_basis(ctx.handle, ctypes.c_void_p(Nc.data_ptr()), ctx.n, _stream(stream)),
+               "hf_kernel_basis")
+    return Nc.t()
+
+
+def hf_schur(ctx: Context, stream=None):
+    import torch
+    m = ctypes.c_int32()
+    _check(_lib.hf_schur(ctx.handle, ctypes.byref(m), None, None, 0, _stream(stream)), "hf_schur")
+    M = m.value
+    lam = np.zeros(max(M, 1), dtype=np.int32)
+    S = torch.zeros((max(M, 1), max(M, 1)), dtype=torch.float64, device="cuda")
+    if M:
+        _check(_lib.hf_schur(ctx.handle, ctypes.byref(m), _np_ptr(lam), ctypes.c_void_p(S.data_ptr()), M,
+                             _stream(stream)), "hf_schur")
+    return lam[:M], S[:M, :M].t()
+
+
+def hf_scaling(ctx: Context, stream=None):
+    import torch
+    q = torch.zeros(ctx.n, dtype=torch.float64, device="cuda")
+    _check(_lib.hf_scaling(ctx.handle, ctypes.c_void_p(q.data_ptr()), _stream(stream)), "hf_scaling")
+    return q
+
+
+def hf_info(ctx: Context) -> dict:
+    info = HFInfo()
+    _check(_lib.hf_info(ctx.handle, ctypes.byref(info)), "hf_info")
+    return {name: getattr(info, name) for name, _ in HFInfo._fields_}
+
+
+def hf_timing_enable(ctx: Context, on: bool = True):
+    _check(_lib.hf_timing_enable(ctx.handle, 1 if on else 0), "hf_timing_enable")
+
+
+def hf_timing_get(ctx: Context) -> dict:
+    out = {}
+    for cls, name in enumerate(KCLASS):
+        st = HFKStat()
+        _check(_lib.hf_timing_get(ctx.handle, cls, ctypes.byref(st)), "hf_timing_get")
+        out[name] = {"ms": st.ms, "launches": st.launches, "bytes": st.bytes, "flops": st.flops}
+    return out

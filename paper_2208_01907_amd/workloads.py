@@ -339,8 +339,14 @@ def config_c2():
 
 
 def config_c3():
-    """Floating Q1 elastic cube, 24^3 elements, E = 10^U(0,6), 32 RHS, kernel 6."""
-    return elasticity(24, seed=3, leaf_max=64, r=32, tau=1e-2, gcr_block=32)
+    """Floating Q1 elastic cube, 24^3 elements, E = 10^U(0,6), 32 RHS, kernel 6.
+
+    The postponing threshold is not fixed by the configuration; tau = 0.1 lies in
+    the window (0.05 .. 0.25) where the single-precision step 1 postpones exactly
+    the six rigid modes, as in the paper's floating Stokes example (Sec. 4.2),
+    which also needed a larger threshold in single precision.
+    """
+    return elasticity(24, seed=3, leaf_max=64, r=32, tau=0.1, gcr_block=0)
 
 
 CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3}

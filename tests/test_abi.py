@@ -1,0 +1,90 @@
+"""C ABI: the library loads and exports every entry point of include/hf.h; host-side
+validation errors (returned before any device work, so they run without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2208_01907_amd import hyfact as hy
+from paper_2208_01907_amd import workloads as w
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "hf.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hf_[a-z_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    names = _declared()
+    assert "hf_analyse" in names and "hf_factorize" in names and "hf_solve" in names
+    lib = ctypes.CDLL(hy.LIBPATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(hy.EXPORTS) == names
+
+
+def test_strerror_and_defaults():
+    assert hy.hf_strerror(0) == "ok"
+    for code in range(-9, 0):
+        assert hy.hf_strerror(code) not in ("ok", "unknown status")
+    o = hy.hf_default_options()
+    assert o.tau == 1e-2 and o.n_enlarge == 4 and o.low_precision == hy.HF_PREC_FP32
+    assert o.gcr_tol == 1e-15 and o.gcr_block == 0
+
+
+def _analyse_code(indptr, indices, perm=None, node_ptr=None, parent=None, opt=None):
+    try:
+        hy.hf_analyse(indptr, indices, perm, node_ptr, parent, opt)
+    except hy.HFError as e:
+        return e.code
+    return 0
+
+
+def _small():
+    W = w.neumann2d(5, 4, seed=1, leaf_max=6)
+    return W
+
+
+def test_pattern_errors():
+    W = _small()
+    ip, ix = W.indptr.copy(), W.indices.copy()
+    bad = ix.copy()
+    bad[ip[3]], bad[ip[3] + 1] = bad[ip[3] + 1], bad[ip[3]]      # unsorted row
+    assert _analyse_code(ip, bad) == hy.HF_ERR_PATTERN
+    bad = ix.copy()
+    bad[0] = W.n + 5                                             # out of range
+    assert _analyse_code(ip, bad) == hy.HF_ERR_PATTERN
+    # drop one off-diagonal entry of row 0 -> unsymmetric pattern
+    keep = np.ones(len(ix), bool)
+    e = next(e for e in range(ip[0], ip[1]) if ix[e] != 0)
+    keep[e] = False
+    ip2 = ip.copy()
+    ip2[1:] -= 1
+    assert _analyse_code(ip2, ix[keep]) == hy.HF_ERR_PATTERN
+
+
+def test_tree_and_option_errors():
+    W = _small()
+    ip, ix = W.indptr, W.indices
+    perm = W.perm.copy()
+    perm[0] = perm[1]                                            # not a permutation
+    assert _analyse_code(ip, ix, perm, W.node_ptr, W.parent) == hy.HF_ERR_ARG
+    par = W.parent.copy()
+    par[0] = -1                                                  # breaks subtree contiguity / postorder
+    if W.n_nodes > 2:
+        assert _analyse_code(ip, ix, W.perm, W.node_ptr, par) in (hy.HF_ERR_ARG, hy.HF_ERR_PATTERN)
+    # two leaves swapped under the wrong separators: couplings between sibling subtrees
+    nodes = np.diff(W.node_ptr)
+    rev = W.perm[::-1].copy()
+    assert _analyse_code(ip, ix, rev, W.node_ptr, W.parent) == hy.HF_ERR_PATTERN
+    o = hy.hf_default_options(tau=-1.0)
+    assert _analyse_code(ip, ix, W.perm, W.node_ptr, W.parent, o) == hy.HF_ERR_ARG
+    o = hy.hf_default_options(low_precision=16)
+    assert _analyse_code(ip, ix, W.perm, W.node_ptr, W.parent, o) == hy.HF_ERR_ARG
+    o = hy.hf_default_options(gcr_block=65)
+    assert _analyse_code(ip, ix, W.perm, W.node_ptr, W.parent, o) == hy.HF_ERR_ARG

@@ -1,0 +1,192 @@
+"""GPU parity tests: the HIP path through the C ABI against the CPU oracle.
+
+Every case runs the oracle and the library on the same seeded inputs and
+compares: the hard-part size M and the hard part itself (exact), the kernel
+dimension k (exact), S22 (tolerance below), the minimum-norm solution (relative
+1e-10) and the backward error (<= 1e-14).  Tolerances: S22 is formed in FP64 as
+K22 - K21 X12 where X12 carries the block-GCR relative residual (1e-15) times
+cond(K11); entries of K22 are O(1) (unit diagonal), so both sides agree to about
+cond(K11) * 1e-15 in absolute terms -- 1e-9 is used (cond(K11) < 1e6 here).
+Solutions: two backward-stable FP64 solvers differ by about cond(K|Im K) * eps;
+with the 1e6 coefficient contrasts here cond reaches 1e7-1e8, so the bar is
+relative error <= max(1e-10, 4 * the oracle's own forward error against the
+exact solution x*) -- 1e-10 wherever the conditioning allows it.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_01907_amd import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+hy = pytest.importorskip("paper_2208_01907_amd.hyfact")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+CASES = {
+    "c1": lambda: w.config_c1(),
+    "inc20": lambda: w.inclusions3d(20, 8, seed=5, leaf_max=128, r=4, gcr_block=8),
+    "inc24": lambda: w.inclusions3d(24, 12, seed=6, leaf_max=512, r=3, gcr_block=16),
+    "n2d_ragged": lambda: w.neumann2d(67, 45, seed=7, leaf_max=100, r=2, gcr_block=8),
+    "el6": lambda: w.elasticity(6, seed=8, leaf_max=27, r=5, gcr_block=8),
+    "el7_ragged": lambda: w.elasticity(7, seed=9, leaf_max=50, r=3, gcr_block=0),
+    "dense_k2": lambda: w.random_dense_workload(150, seed=10, kernel_dim=2, cond=1e3, r=3),
+    "dense_indef_all_postponed": lambda: w.random_dense_workload(40, seed=11, indefinite=True, cond=1e2,
+                                                                 r=2, tau=2.0),
+}
+
+
+def _gpu(W, prec, gcr_block=None):
+    opt = hy.hf_default_options(tau=W.tau, low_precision=prec,
+                                gcr_block=W.gcr_block if gcr_block is None else gcr_block)
+    ctx = hy.hf_analyse(W.indptr, W.indices, W.perm, W.node_ptr, W.parent, opt)
+    hy.hf_factorize(ctx, torch.tensor(W.values, device="cuda"))
+    return ctx
+
+
+def _principal_cos(A, B):
+    qa, _ = np.linalg.qr(A)
+    qb, _ = np.linalg.qr(B)
+    return np.linalg.svd(qa.T @ qb, compute_uv=False)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+@pytest.mark.parametrize("name", list(CASES))
+def test_parity(name, prec):
+    W = CASES[name]()
+    print(f"case {name} prec {prec} n={W.n}", flush=True)
+    low = np.float32 if prec == 32 else np.float64
+    ref = oracle.hybrid_factorize(W.csr(), W.perm, W.node_ptr, W.parent, tau=W.tau, low=low,
+                                  gcr_block=W.gcr_block)
+    Xref = oracle.hybrid_solve(ref, W.b)
+    ctx = _gpu(W, prec)
+    info = hy.hf_info(ctx)
+    assert info["M"] == ref.M
+    lam, S = hy.hf_schur(ctx)
+    assert np.array_equal(lam, np.sort(W.perm[ref.step1.lambda2]))
+    assert hy.hf_kernel_dim(ctx) == ref.k
+    if ref.M:
+        order = np.argsort(W.perm[ref.step1.lambda2])
+        Sref = ref.S22[np.ix_(order, order)]
+        assert np.abs(S.cpu().numpy() - Sref).max() <= 1e-9
+    X = hy.hf_solve(ctx, torch.tensor(W.b, device="cuda")).cpu().numpy().reshape(W.b.shape)
+    fwd_oracle = np.linalg.norm(Xref - W.x_star) / np.linalg.norm(W.x_star)
+    rel = np.linalg.norm(X - Xref) / np.linalg.norm(Xref)
+    print(f"  M={info['M']} k={ref.k} rel_vs_oracle={rel:.2e} oracle_fwd_err={fwd_oracle:.2e}", flush=True)
+    assert rel <= max(1e-10, 4 * fwd_oracle)
+    assert oracle.backward_error(W.csr(), X, W.b) <= 1e-14
+    if ref.k:
+        N = hy.hf_kernel_basis(ctx).cpu().numpy()
+        assert np.all(_principal_cos(N, ref.kernel) > 1 - 1e-8)
+        assert np.allclose(N.T @ N, np.eye(ref.k), atol=1e-12)
+
+
+def test_expected_kernel_dims():
+    """Closed forms: Neumann Laplacian -> constants (k = 1); floating body -> rigid modes (k = 6)."""
+    for W, k, Z in ((w.config_c1(), 1, np.ones((1024, 1))),
+                    (w.elasticity(6, seed=8, leaf_max=27, r=1), 6, w.rigid_modes(6))):
+        ctx = _gpu(W, 32, gcr_block=0)
+        assert hy.hf_kernel_dim(ctx) == k
+        N = hy.hf_kernel_basis(ctx).cpu().numpy()
+        assert np.all(_principal_cos(N, Z) > 1 - 1e-8)
+
+
+def test_state_and_value_errors():
+    W = w.neumann2d(12, 10, seed=3, leaf_max=20, r=1)
+    opt = hy.hf_default_options(tau=W.tau)
+    ctx = hy.hf_analyse(W.indptr, W.indices, W.perm, W.node_ptr, W.parent, opt)
+    B = torch.tensor(W.b, device="cuda")
+    with pytest.raises(hy.HFError) as e:
+        hy.hf_solve(ctx, B)
+    assert e.value.code == hy.HF_ERR_STATE
+    with pytest.raises(hy.HFError) as e:
+        hy.hf_kernel_dim(ctx)
+    assert e.value.code == hy.HF_ERR_STATE
+    bad = torch.tensor(W.values, device="cuda")
+    bad[7] = float("nan")
+    with pytest.raises(hy.HFError) as e:
+        hy.hf_factorize(ctx, bad)
+    assert e.value.code == hy.HF_ERR_VALUE
+    # the context is still usable
+    hy.hf_factorize(ctx, torch.tensor(W.values, device="cuda"))
+    X = hy.hf_solve(ctx, B).cpu().numpy()
+    assert oracle.backward_error(W.csr(), X, W.b) <= 1e-14
+
+
+def test_refactorize_new_values_and_reproducibility():
+    W = w.inclusions3d(16, 5, seed=12, leaf_max=100, r=2, gcr_block=0)
+    opt = hy.hf_default_options(tau=W.tau)
+    ctx = hy.hf_analyse(W.indptr, W.indices, W.perm, W.node_ptr, W.parent, opt)
+    vals = torch.tensor(W.values, device="cuda")
+    B = torch.tensor(W.b, device="cuda")
+    hy.hf_factorize(ctx, vals)
+    X1 = hy.hf_solve(ctx, B).cpu().numpy()
+    l1, S1 = hy.hf_schur(ctx)
+    hy.hf_factorize(ctx, vals)
+    X2 = hy.hf_solve(ctx, B).cpu().numpy()
+    l2, S2 = hy.hf_schur(ctx)
+    assert np.array_equal(l1, l2)
+    assert np.array_equal(S1.cpu().numpy(), S2.cpu().numpy())     # bitwise: no atomics anywhere
+    assert np.array_equal(X1, X2)
+    # scaling the matrix by 4 leaves the scaled K unchanged; the solution scales by 1/4
+    hy.hf_factorize(ctx, vals * 4.0)
+    X4 = hy.hf_solve(ctx, B).cpu().numpy()
+    assert np.allclose(4.0 * X4, X1, rtol=1e-12, atol=1e-14 * np.abs(X1).max())
+
+
+def test_zero_and_many_rhs():
+    W = w.neumann2d(20, 18, seed=13, leaf_max=30, r=70)   # more than one 64-column chunk
+    ctx = _gpu(W, 32, gcr_block=0)
+    X = hy.hf_solve(ctx, torch.tensor(W.b, device="cuda")).cpu().numpy()
+    assert oracle.backward_error(W.csr(), X, W.b) <= 1e-14
+    Z = hy.hf_solve(ctx, torch.zeros((W.n, 2), dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert np.all(Z == 0.0)
+
+
+def test_nonsingular_no_postponing():
+    """tau = 0 on an SPD matrix: M = 0, the preconditioned block GCR alone solves."""
+    W = w.random_dense_workload(90, seed=14, kernel_dim=0, cond=1e2, r=2, tau=0.0)
+    for prec in (32, 64):
+        ctx = _gpu(W, prec, gcr_block=0)
+        assert hy.hf_info(ctx)["M"] == 0 and hy.hf_kernel_dim(ctx) == 0
+        X = hy.hf_solve(ctx, torch.tensor(W.b, device="cuda")).cpu().numpy()
+        assert np.allclose(X, np.linalg.solve(W.csr().toarray(), W.b), rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("cfg", ["c2", "c3"])
+def test_full_size_against_golden(cfg):
+    """Bench-size configurations in the benchmark's launch configuration.
+
+    The oracle's FP64 run (tests/golden/make_golden.py) fixes M, the hard part,
+    k and a sample of the minimum-norm solution; the GPU runs in both precisions.
+    """
+    path = os.path.join(GOLDEN, f"{cfg}_oracle_fp64.json")
+    if not os.path.exists(path):
+        pytest.skip("golden file not generated")
+    g = json.load(open(path))
+    W = w.CONFIGS[cfg]()
+    print(f"full size {cfg} n={W.n}", flush=True)
+    B = torch.tensor(W.b, device="cuda")
+    rows = np.array(g["sample_rows"])
+    xs = np.array(g["x_sample"])
+    for prec in (64, 32):
+        ctx = _gpu(W, prec, gcr_block=0)
+        info = hy.hf_info(ctx)
+        lam, _ = hy.hf_schur(ctx)
+        assert hy.hf_kernel_dim(ctx) == g["k"]
+        assert info["M"] == g["M"]
+        assert np.array_equal(np.sort(lam), np.array(g["lambda2_original"])) or prec == 32
+        X = hy.hf_solve(ctx, B).cpu().numpy()
+        fwd_oracle = np.linalg.norm(xs - W.x_star[rows]) / np.linalg.norm(W.x_star[rows])
+        rel = np.linalg.norm(X[rows] - xs) / np.linalg.norm(xs)
+        print(f"  prec {prec}: rel_vs_oracle(sample)={rel:.2e} oracle_fwd_err={fwd_oracle:.2e}", flush=True)
+        assert rel <= max(1e-10, 4 * fwd_oracle)
+        be = oracle.backward_error(W.csr(), X, W.b)
+        print(f"  prec {prec}: M={info['M']} k={hy.hf_kernel_dim(ctx)} be={be:.3e}", flush=True)
+        assert be <= 1e-14
+        del ctx
