@@ -682,33 +682,33 @@ def _algorithm2(hf: HybridFactor, b):
 def hybrid_solve(hf: HybridFactor, Bbar, refine_steps=1, Kbar=None):
     """Algorithm 2, plus residual correction, with the minimum-norm choice for singular K.
 
-    b = Pi Q bbar; x = Algorithm2(b); then refine_steps times
-    x += Algorithm2(Pi Q (bbar - Kbar xbar)) with xbar = Q Pi^T x: the residual is
-    taken in the caller's variables (the scaled K has an exactly unit diagonal and
-    differs from Q Kbar Q by rounding, so its residual does not measure the
-    caller's).  The correction is not part of the paper's Algorithm 2; it is added
-    for the 1e-14 backward-error target.  Finally xbar is projected orthogonally to
-    the detected kernel (reading for singular K).  Kbar defaults to the matrix
-    given to hybrid_factorize.
+    xbar = P(Q Pi^T Algorithm2(Pi Q bbar)) where P projects orthogonally to the
+    detected kernel (reading for singular K: the minimum-norm solution); then
+    refine_steps times xbar += P(Q Pi^T Algorithm2(Pi Q (bbar - Kbar xbar))).  The
+    residual is taken in the caller's variables on the projected iterate: the
+    scaled K has an exactly unit diagonal and differs from Q Kbar Q by rounding,
+    and Kbar 1 is only zero up to rounding, so a large kernel component would
+    pollute it.  The correction is not part of the paper's Algorithm 2; it is
+    added for the 1e-14 backward-error target.  Kbar defaults to the matrix given
+    to hybrid_factorize.
     """
     Bbar = np.asarray(Bbar, dtype=np.float64)
     one = Bbar.ndim == 1
     Bbar = Bbar.reshape(hf.n, -1)
-    b = (hf.q[:, None] * Bbar)[hf.perm]
-    x = _algorithm2(hf, b)
+    Kbar = hf.Kbar if Kbar is None else sp.csr_matrix(Kbar)
 
     def to_orig(xp):
         out = np.zeros_like(xp)
         out[hf.perm] = xp
-        return hf.q[:, None] * out
+        out = hf.q[:, None] * out
+        if hf.k:
+            out = out - hf.kernel @ (hf.kernel.T @ out)
+        return out
 
-    Kbar = hf.Kbar if Kbar is None else sp.csr_matrix(Kbar)
+    xbar = to_orig(_algorithm2(hf, (hf.q[:, None] * Bbar)[hf.perm]))
     for _ in range(refine_steps):
-        rbar = Bbar - Kbar @ to_orig(x)
-        x = x + _algorithm2(hf, (hf.q[:, None] * rbar)[hf.perm])
-    xbar = to_orig(x)
-    if hf.k:
-        xbar = xbar - hf.kernel @ (hf.kernel.T @ xbar)
+        rbar = Bbar - Kbar @ xbar
+        xbar = xbar + to_orig(_algorithm2(hf, (hf.q[:, None] * rbar)[hf.perm]))
     return xbar[:, 0] if one else xbar
 
 

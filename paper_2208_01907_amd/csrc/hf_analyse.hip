@@ -309,6 +309,16 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
       for (int32_t q = 0; q < nb; ++q) ctx->blk_node.push_back(j);
     }
     ctx->linv_elems = (int64_t)ctx->blk_first[n_nodes] * 64 * 64;
+    // 256x256 step blocks (their inverses drive the triangular sweeps)
+    ctx->stp_first.assign(n_nodes + 1, 0);
+    ctx->linv2_off.assign(std::max(n_nodes, 1), 0);
+    for (int32_t j = 0; j < n_nodes; ++j) {
+      const int32_t nb = (ctx->nodes[j].p + 255) / 256;
+      ctx->linv2_off[j] = (int64_t)ctx->stp_first[j] * 256 * 256;
+      ctx->stp_first[j + 1] = ctx->stp_first[j] + nb;
+      for (int32_t q = 0; q < nb; ++q) ctx->stp_node.push_back(j);
+    }
+    ctx->linv2_elems = (int64_t)ctx->stp_first[n_nodes] * 256 * 256;
     // device copies of the pattern
     hipStream_t s = nullptr;
     upload(ctx->d_pindptr, pindptr, s);
@@ -327,6 +337,9 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
     upload(ctx->d_blk_node, ctx->blk_node, s);
     upload(ctx->d_blk_first, ctx->blk_first, s);
     upload(ctx->d_linv_off, ctx->linv_off, s);
+    upload(ctx->d_stp_node, ctx->stp_node, s);
+    upload(ctx->d_stp_first, ctx->stp_first, s);
+    upload(ctx->d_linv2_off, ctx->linv2_off, s);
     HF_HIP(hipStreamSynchronize(s));
     ctx->state = 1;
   } catch (const HipError&) {

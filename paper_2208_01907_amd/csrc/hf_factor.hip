@@ -100,11 +100,14 @@ __device__ inline void argmax_combine(T& bv, int& bid, int& bk, T v, int id, int
   if (v > bv || (v == bv && id < bid)) { bv = v; bid = id; bk = k; }
 }
 
+constexpr int PT = 512;               // threads of the panel kernel
+constexpr int PROWS = 4096 / PT;      // rows per thread (nodes hold at most 4096 indices)
+
 template <class T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(PT)
 k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, NodeState* st,
-        T* __restrict__ front, int32_t* __restrict__ piv, T* __restrict__ dval, int k0p, double tau,
-        int first_unit) {
+        T* __restrict__ front, int32_t* __restrict__ piv, int32_t* __restrict__ swaps,
+        T* __restrict__ dval, int k0p, double tau, int first_unit) {
   const int j = lnodes[blockIdx.x];
   const NodeInfo ni = nodes[j];
   const NodeState s0 = st[j];
@@ -113,17 +116,19 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   const int64_t f = ni.f;
   T* F = front + ni.front_off;
   int32_t* idx = piv + ni.start;
+  int32_t* sw = swaps + ni.start;
   T* D = dval + ni.start;
   const int tid = threadIdx.x;
+  constexpr int NW = PT / 64;
 
   extern __shared__ unsigned char smem_raw[];
   T* dg = reinterpret_cast<T*>(smem_raw);  // current diagonal of positions [k0p, p)
   __shared__ T u[PANEL_NB];
-  __shared__ T red_v[4];
-  __shared__ int red_id[4], red_k[4];
+  __shared__ T red_v[NW];
+  __shared__ int red_id[NW], red_k[NW];
   __shared__ int s_k, s_stop;
 
-  for (int k = k0p + tid; k < p; k += 256) dg[k - k0p] = F[(int64_t)k * f + k];
+  for (int k = k0p + tid; k < p; k += PT) dg[k - k0p] = F[(int64_t)k * f + k];
   double dprev = s0.dprev;
   int have_prev = (s0.npiv > 0) ? 1 : first_unit;
   const int iend = min(k0p + PANEL_NB, p);
@@ -133,7 +138,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     // workgroup argmax of |diag| over the remaining candidates
     T bv = (T)-1;
     int bid = INT_MAX, bk = -1;
-    for (int k = i + tid; k < p; k += 256) {
+    for (int k = i + tid; k < p; k += PT) {
       const T v = dg[k - k0p];
       argmax_combine(bv, bid, bk, v < (T)0 ? -v : v, idx[k], k);
     }
@@ -146,29 +151,31 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     if ((tid & 63) == 0) { red_v[tid >> 6] = bv; red_id[tid >> 6] = bid; red_k[tid >> 6] = bk; }
     __syncthreads();
     if (tid == 0) {
-      for (int w = 1; w < 4; ++w) argmax_combine(bv, bid, bk, red_v[w], red_id[w], red_k[w]);
+      for (int w = 1; w < NW; ++w) argmax_combine(bv, bid, bk, red_v[w], red_id[w], red_k[w]);
       const double dk = (double)dg[bk - k0p];
       int stop = (dk == 0.0);
       if (!stop && have_prev && fabs(dk) < tau * fabs(dprev)) stop = 1;
       s_stop = stop;
       s_k = bk;
+      if (!stop) sw[i] = bk;
     }
     __syncthreads();
     if (s_stop) break;
     const int k = s_k;
     if (k != i) {
-      // symmetric exchange of positions i < k in the lower triangle
-      for (int c = tid; c < i; c += 256) {
+      // symmetric exchange of positions i < k in the lower triangle; columns of
+      // earlier panels get their row exchanges later in one pass (k_apply_swaps)
+      for (int c = k0p + tid; c < i; c += PT) {
         const T a = F[(int64_t)c * f + i];
         F[(int64_t)c * f + i] = F[(int64_t)c * f + k];
         F[(int64_t)c * f + k] = a;
       }
-      for (int c = i + 1 + tid; c < k; c += 256) {
+      for (int c = i + 1 + tid; c < k; c += PT) {
         const T a = F[(int64_t)i * f + c];
         F[(int64_t)i * f + c] = F[(int64_t)c * f + k];
         F[(int64_t)c * f + k] = a;
       }
-      for (int64_t r = k + 1 + tid; r < f; r += 256) {
+      for (int64_t r = k + 1 + tid; r < f; r += PT) {
         const T a = F[(int64_t)i * f + r];
         F[(int64_t)i * f + r] = F[(int64_t)k * f + r];
         F[(int64_t)k * f + r] = a;
@@ -183,16 +190,34 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     }
     __syncthreads();
     const T d = dg[i - k0p];
-    for (int c = k0p + tid; c < i; c += 256) u[c - k0p] = D[c] * F[(int64_t)c * f + i];
+    for (int c = k0p + tid; c < i; c += PT) u[c - k0p] = D[c] * F[(int64_t)c * f + i];
     __syncthreads();
-    // pivot column (rows of F11 below the pivot), left-looking within the panel
+    // pivot column (rows of F11 below the pivot), left-looking within the panel;
+    // each thread keeps its rows in registers so the loads of a column overlap
+    T acc[PROWS];
+#pragma unroll
+    for (int t = 0; t < PROWS; ++t) {
+      const int r = i + 1 + tid + t * PT;
+      acc[t] = (r < p) ? F[(int64_t)i * f + r] : (T)0;
+    }
+    for (int c = k0p; c < i; ++c) {
+      const T uc = u[c - k0p];
+      const T* Fc = F + (int64_t)c * f;
+#pragma unroll
+      for (int t = 0; t < PROWS; ++t) {
+        const int r = i + 1 + tid + t * PT;
+        if (r < p) acc[t] -= Fc[r] * uc;
+      }
+    }
     const T inv = (T)1 / d;
-    for (int r = i + 1 + tid; r < p; r += 256) {
-      T v = F[(int64_t)i * f + r];
-      for (int c = k0p; c < i; ++c) v -= F[(int64_t)c * f + r] * u[c - k0p];
-      const T l = v * inv;
-      F[(int64_t)i * f + r] = l;
-      dg[r - k0p] -= l * v;
+#pragma unroll
+    for (int t = 0; t < PROWS; ++t) {
+      const int r = i + 1 + tid + t * PT;
+      if (r < p) {
+        const T l = acc[t] * inv;
+        F[(int64_t)i * f + r] = l;
+        dg[r - k0p] -= l * acc[t];
+      }
     }
     if (tid == 0) {
       F[(int64_t)i * f + i] = d;
@@ -208,6 +233,30 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     ns.dprev = dprev;
     ns.done = (i < iend || i == p) ? 1 : 0;
     st[j] = ns;
+  }
+}
+
+// Row exchanges of the panel at k0p applied to the columns of earlier panels
+// (one thread per column, exchanges in pivot order).
+template <class T>
+__global__ void k_apply_swaps(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+                              const NodeState* __restrict__ st, const int32_t* __restrict__ swaps,
+                              T* __restrict__ front, int k0p) {
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k0p || k0p >= npiv) return;
+  const int iend = min(npiv, k0p + PANEL_NB);
+  const int32_t* sw = swaps + ni.start;
+  T* Fc = front + ni.front_off + (int64_t)c * ni.f;
+  for (int i = k0p; i < iend; ++i) {
+    const int k = sw[i];
+    if (k != i) {
+      const T a = Fc[i];
+      Fc[i] = Fc[k];
+      Fc[k] = a;
+    }
   }
 }
 
@@ -432,6 +481,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
   ctx->d_front.alloc((size_t)ctx->front_elems * sizeof(T));
   ctx->d_state.alloc((size_t)ctx->n_nodes * sizeof(NodeState));
   ctx->d_piv.alloc((size_t)n * sizeof(int32_t));
+  ctx->d_swaps.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
   ctx->d_dval.alloc((size_t)n * sizeof(T));
   ctx->d_q.alloc((size_t)n * sizeof(double));
   ctx->d_kval.alloc((size_t)ctx->nnz * sizeof(double));
@@ -504,8 +554,13 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         fl += nb * nb * r;
       });
       timed(tm, HF_K_PANEL, w1.first, w1.second, s, [&] {
-        k_panel<T><<<nl, 256, shm, s>>>(lnodes, nodes, st, front, ctx->d_piv.as<int32_t>(),
-                                        ctx->d_dval.as<T>(), k0p, ctx->opt.tau, ctx->opt.first_pivot_unit);
+        k_panel<T><<<nl, PT, shm, s>>>(lnodes, nodes, st, front, ctx->d_piv.as<int32_t>(),
+                                       ctx->d_swaps.as<int32_t>(), ctx->d_dval.as<T>(), k0p, ctx->opt.tau,
+                                       ctx->opt.first_pivot_unit);
+        if (k0p > 0) {
+          dim3 gs(cdiv(k0p, 256), (unsigned)nl);
+          k_apply_swaps<T><<<gs, 256, 0, s>>>(lnodes, nodes, st, ctx->d_swaps.as<int32_t>(), front, k0p);
+        }
       });
       const int nr = maxp - (k0p + PANEL_NB);
       if (nr > 0) {

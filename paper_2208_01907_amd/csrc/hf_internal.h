@@ -168,6 +168,9 @@ struct hf_ctx {
   std::vector<int32_t> blk_node, blk_first;  // 64-row diagonal blocks of every L11
   std::vector<int64_t> linv_off;
   int64_t linv_elems = 0;
+  std::vector<int32_t> stp_node, stp_first;  // 256-column steps of every L11
+  std::vector<int64_t> linv2_off;
+  int64_t linv2_elems = 0;
   std::vector<int32_t> ea_items;
   int64_t front_elems = 0, rhs_rows = 0;
   int32_t max_front = 0, max_p = 0;
@@ -182,7 +185,10 @@ struct hf_ctx {
   hf::DBuf d_front;                // front arena (T = float or double)
   hf::DBuf d_state, d_piv, d_dval; // NodeState[n_nodes], piv_order[n], D[n] (T)
   hf::DBuf d_ipos;                 // position of each index in its node's pivot order
+  hf::DBuf d_swaps;                // row exchange of every pivot (position swapped with)
   hf::DBuf d_linv, d_linv_off, d_blk_node, d_blk_first;  // inverses of 64x64 diagonal blocks
+  hf::DBuf d_linv2, d_linv2_off, d_stp_node, d_stp_first;  // inverses of 256x256 step blocks
+  hf::DBuf d_zb_arena;             // second solve arena (step results)
   hf::DBuf d_isl2, d_flag;         // uint8 mask [n], error flags
   int32_t factor_prec = 0;         // precision of d_front
   // hard part

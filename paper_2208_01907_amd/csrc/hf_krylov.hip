@@ -48,23 +48,20 @@ __global__ void k_spmm_k11(int64_t n, const int64_t* __restrict__ ip, const int3
   Y[e] = acc;
 }
 
-// Residual of the caller's system, returned scaled: for row g (elimination
-// order) r_g = q_g (bbar_{perm g} - sum_e Kbar_e xbar_{perm c_e}) with
-// xbar = Q Pi^T x formed exactly as the solution handed back.  B is the caller's
-// column-major right-hand side block (columns c0.., leading dimension ldb).
+// Residual of the caller's system, returned scaled and in elimination order:
+// r_g = q_g (bbar_{perm g} - sum_e Kbar_e xo_{perm c_e}), xo being the current
+// solution in the caller's variables (row-major n x m, original order) and B the
+// caller's column-major right-hand side block (columns c0.., leading dimension ldb).
 __global__ void k_residual_orig(int64_t n, const int64_t* __restrict__ ip, const int32_t* __restrict__ ix,
                                 const double* __restrict__ kbar, const double* __restrict__ qp,
                                 const int32_t* __restrict__ perm, int m, const double* __restrict__ B,
-                                int64_t ldb, int c0, const double* __restrict__ X, double* __restrict__ R) {
+                                int64_t ldb, int c0, const double* __restrict__ xo, double* __restrict__ R) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t row = e / m;
   const int col = (int)(e - row * m);
   if (row >= n) return;
   double acc = B[(int64_t)(c0 + col) * ldb + perm[row]];
-  for (int64_t q = ip[row]; q < ip[row + 1]; ++q) {
-    const int32_t c = ix[q];
-    acc -= kbar[q] * (qp[c] * X[(int64_t)c * m + col]);
-  }
+  for (int64_t q = ip[row]; q < ip[row + 1]; ++q) acc -= kbar[q] * xo[(int64_t)perm[ix[q]] * m + col];
   R[e] = qp[row] * acc;
 }
 
@@ -965,34 +962,39 @@ int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, 
       const int m = std::min(MAXM, r - c0);
       BgcrWork& w = get_work(ctx, std::max(m, std::max(ctx->mb, k)));
       const int64_t nm = n * m;
-      ctx->d_rhs_b.alloc((size_t)nm * sizeof(double) * 5);
+      ctx->d_rhs_b.alloc((size_t)nm * sizeof(double) * 6);
       double* b = ctx->d_rhs_b.as<double>();
       double* b1 = b + nm;
       double* x = b1 + nm;
       double* res = x + nm;
-      double* dx = res + nm;
+      double* xo = res + nm;
+      double* dxo = xo + nm;
+      // x -> caller's variables, projected orthogonally to the detected kernel
+      auto to_orig = [&](const double* xp, double* out) {
+        k_unperm<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(), xp, out);
+        if (k > 0) {
+          double* G = w.gram.as<double>();
+          gram(ctx, n, k, ctx->d_kern.as<double>(), 0, 1, m, out, G, s);
+          k_neg<<<cdiv((int64_t)k * m, 256), 256, 0, s>>>((int64_t)k * m, G);
+          k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, k, m, out, out, 1, ctx->d_kern.as<double>(), 0, G);
+        }
+      };
       k_load_rhs<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(), B, ldb,
                                                c0, b);
       ctx->solve_iters = std::max(ctx->solve_iters, solve_core(ctx, m, b, x, b1, s));
-      // residual correction: x += Algorithm2(Q Pi (bbar - Kbar xbar)), the residual
-      // taken in the caller's variables (the scaled matrix has an exactly unit
-      // diagonal and differs from Q Kbar Q by rounding)
+      to_orig(x, xo);
+      // residual correction: xo += P(Q Pi^T Algorithm2(Pi Q (bbar - Kbar xo))); the
+      // residual is taken in the caller's variables on the projected iterate (the
+      // scaled matrix has an exactly unit diagonal and differs from Q Kbar Q by
+      // rounding; Kbar 1 vanishes only up to rounding)
       for (int it = 0; it < ctx->opt.refine_steps; ++it) {
         k_residual_orig<<<cdiv(nm, 256), 256, 0, s>>>(n, ctx->d_pindptr.as<int64_t>(),
                                                       ctx->d_pindices.as<int32_t>(), ctx->d_kbar.as<double>(),
                                                       ctx->d_q.as<double>(), ctx->d_perm.as<int32_t>(), m, B, ldb, c0,
-                                                      x, res);
-        ctx->solve_iters = std::max(ctx->solve_iters, solve_core(ctx, m, res, dx, b1, s));
-        k_add<<<cdiv(nm, 256), 256, 0, s>>>(nm, x, dx);
-      }
-      // back to original variables, projection orthogonal to the kernel
-      double* xo = b1;
-      k_unperm<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(), x, xo);
-      if (k > 0) {
-        double* G = w.gram.as<double>();
-        gram(ctx, n, k, ctx->d_kern.as<double>(), 0, 1, m, xo, G, s);
-        k_neg<<<cdiv((int64_t)k * m, 256), 256, 0, s>>>((int64_t)k * m, G);
-        k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, k, m, xo, xo, 1, ctx->d_kern.as<double>(), 0, G);
+                                                      xo, res);
+        ctx->solve_iters = std::max(ctx->solve_iters, solve_core(ctx, m, res, x, b1, s));
+        to_orig(x, dxo);
+        k_add<<<cdiv(nm, 256), 256, 0, s>>>(nm, xo, dxo);
       }
       k_store_cols<<<cdiv(nm, 256), 256, 0, s>>>(n, m, xo, X, ldx, c0);
       HF_HIP(hipGetLastError());

@@ -7,14 +7,16 @@
 //   gather   : own accepted rows from the FP64 input (cast to T), children's
 //              border blocks added (extend-add, pivot-order aware);
 //   steps of TB = 256 columns of L11:
-//     diag   : z_J = L_JJ^{-1} w_J with four 64x64 sub-blocks whose inverses
-//              were formed once after the factorization (k_inv_diag);
+//     diag   : z_J = L_JJ^{-1} w_J, a plain product with the inverse of the
+//              256x256 step block formed once after the factorization
+//              (k_inv_diag for its 64x64 diagonal blocks, k_inv_step for the
+//              rest), four workgroups per step; z goes to a second arena;
 //     update : w_rows -= L[rows, J] z_J for every row below the step (the rest
 //              of L11 and the border L21), 64-row strips, many workgroups.
 // Backward sweep, root first, per level:
 //   border   : t = D^{-1} z - L21^T x_border (column strips, x_border read from
 //              the FP64 result of the ancestors);
-//   steps from the last one: diag (L_JJ^{-T} with the same inverses, result
+//   steps from the last one: diag (x_J = L_JJ^{-T} t_J with the same inverse,
 //              scattered to FP64) and update of the columns left of the step.
 // Rows of the hard part are never written, so they stay zero in the result.
 #include <algorithm>
@@ -76,89 +78,195 @@ k_inv_diag(const int32_t* __restrict__ blk_node, const int32_t* __restrict__ blk
 }
 
 // ---------------------------------------------------------------------------
-// forward sweep
+// inverse of every 256x256 step block, assembled from the 64x64 inverses:
+// X_II = Linv_II, X_IJ = -Linv_II sum_{K=J}^{I-1} L_IK X_KJ  (I > J)
 // ---------------------------------------------------------------------------
 
 template <class T>
 __global__ void __launch_bounds__(256)
-k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-             const NodeState* __restrict__ st, const int32_t* __restrict__ piv,
-             const int32_t* __restrict__ relmap, const int32_t* __restrict__ child_list,
-             const int32_t* __restrict__ ipos, int m, const double* __restrict__ R, T* __restrict__ rb) {
-  const int j = lnodes[blockIdx.x];
+k_inv_step(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp_first,
+           const NodeInfo* __restrict__ nodes, const NodeState* __restrict__ st,
+           const T* __restrict__ front, const int64_t* __restrict__ linv_off, const T* __restrict__ linv,
+           const int64_t* __restrict__ linv2_off, T* __restrict__ linv2) {
+  const int bi = blockIdx.x;
+  const int j = stp_node[bi];
+  const int S = bi - stp_first[j];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
-  const int p = ni.p, f = ni.f;
-  T* W = rb + ni.rhs_off * m;
+  const int J0 = S * TB;
+  if (J0 >= npiv) return;
+  const int nc = min(TB, npiv - J0);
+  const int nb = (nc + SB - 1) / SB;
+  const int64_t f = ni.f;
+  const T* F = front + ni.front_off;
+  T* X = linv2 + linv2_off[j] + (int64_t)S * TB * TB;  // column-major 256x256
+  const T* L64 = linv + linv_off[j] + (int64_t)(J0 / SB) * SB * SB;
+  __shared__ T As[32][64];
+  __shared__ T Bs[32][64];
+  __shared__ T Ts[64][64];
   const int tid = threadIdx.x;
-  for (int e = tid; e < f * m; e += 256) {
-    const int r = e / m, col = e - r * m;
-    W[e] = (r < npiv) ? (T)R[(int64_t)piv[ni.start + r] * m + col] : (T)0;
-  }
+  const int tx = tid & 15, ty = tid >> 4;
+  for (int e = tid; e < TB * TB; e += 256) X[e] = (T)0;
   __syncthreads();
-  for (int ci = ni.child_begin; ci < ni.child_end; ++ci) {
-    const NodeInfo cn = nodes[child_list[ci]];
-    const T* Wc = rb + (cn.rhs_off + cn.p) * m;
-    const int32_t* rel = relmap + cn.border_off;
-    for (int e = tid; e < cn.b * m; e += 256) {
-      const int r = e / m, col = e - r * m;
-      int pr = rel[r];
-      if (pr < p) pr = ipos[ni.start + pr];  // own rows are stored in pivot order
-      W[(int64_t)pr * m + col] += Wc[e];
+  for (int I = 0; I < nb; ++I)
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int r = e & 63, c = e >> 6;
+      X[(int64_t)(SB * I + c) * TB + SB * I + r] = L64[(int64_t)I * SB * SB + (int64_t)c * SB + r];
     }
-    __syncthreads();
+  __syncthreads();
+  for (int I = 1; I < nb; ++I) {
+    for (int J = 0; J < I; ++J) {
+      T acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+      for (int K = J; K < I; ++K) {
+        for (int k0 = 0; k0 < SB; k0 += 32) {
+          for (int e = tid; e < 32 * 64; e += 256) {
+            const int r = e & 63, kq = e >> 6;
+            const int gr = SB * I + r, gc = SB * K + k0 + kq;
+            As[kq][r] = (gr < nc && gc < nc) ? F[(int64_t)(J0 + gc) * f + J0 + gr] : (T)0;
+            const int kb = e & 31, c = e >> 5;
+            Bs[kb][c] = X[(int64_t)(SB * J + c) * TB + SB * K + k0 + kb];
+          }
+          __syncthreads();
+#pragma unroll 4
+          for (int kq = 0; kq < 32; ++kq) {
+            T a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { a[q] = As[kq][ty * 4 + q]; b[q] = Bs[kq][tx * 4 + q]; }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+              for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+          }
+          __syncthreads();
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) Ts[ty * 4 + x][tx * 4 + y] = acc[x][y];
+      __syncthreads();
+      T out[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) out[a][b] = (T)0;
+      const T* Li = L64 + (int64_t)I * SB * SB;
+      for (int k0 = 0; k0 < SB; k0 += 32) {
+        for (int e = tid; e < 32 * 64; e += 256) {
+          const int r = e & 63, kq = e >> 6;
+          As[kq][r] = Li[(int64_t)(k0 + kq) * SB + r];
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kq = 0; kq < 32; ++kq) {
+          T a[4], b[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) { a[q] = As[kq][ty * 4 + q]; b[q] = Ts[k0 + kq][tx * 4 + q]; }
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) out[x][y] += a[x] * b[y];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          X[(int64_t)(SB * J + tx * 4 + y) * TB + SB * I + ty * 4 + x] = -out[x][y];
+      __syncthreads();
+    }
   }
 }
 
-// z_J = L_JJ^{-1} w_J for the step at J0 (one workgroup per front)
+// ---------------------------------------------------------------------------
+// forward sweep
+// ---------------------------------------------------------------------------
+
+// own accepted rows from the FP64 input, everything else zero
+template <class T>
+__global__ void __launch_bounds__(256)
+k_fwd_init(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+           const NodeState* __restrict__ st, const int32_t* __restrict__ piv, int m,
+           const double* __restrict__ R, T* __restrict__ rb) {
+  const NodeInfo ni = nodes[lnodes[blockIdx.y]];
+  const int npiv = st[lnodes[blockIdx.y]].npiv;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)ni.f * m) return;
+  const int r = (int)(e / m), col = (int)(e - (int64_t)r * m);
+  rb[ni.rhs_off * m + e] = (r < npiv) ? (T)R[(int64_t)piv[ni.start + r] * m + col] : (T)0;
+}
+
+// children of one rank add their border rows into the parent (pivot-order aware)
+template <class T>
+__global__ void __launch_bounds__(256)
+k_fwd_addchild(const int32_t* __restrict__ items, const NodeInfo* __restrict__ nodes,
+               const int32_t* __restrict__ relmap, const int32_t* __restrict__ ipos, int m,
+               T* __restrict__ rb) {
+  const NodeInfo cn = nodes[items[blockIdx.y]];
+  const NodeInfo pn = nodes[cn.parent];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)cn.b * m) return;
+  const int r = (int)(e / m), col = (int)(e - (int64_t)r * m);
+  int pr = relmap[cn.border_off + r];
+  if (pr < pn.p) pr = ipos[pn.start + pr];  // own rows of the parent are stored in pivot order
+  rb[(pn.rhs_off + pr) * m + col] += rb[(cn.rhs_off + cn.p) * m + e];
+}
+
+// z_J = Linv_J w_J; four workgroups (64 rows each) per front
 template <class T>
 __global__ void __launch_bounds__(256)
 k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-           const NodeState* __restrict__ st, const T* __restrict__ front,
-           const int64_t* __restrict__ linv_off, const T* __restrict__ linv, int J0, int m,
-           T* __restrict__ rb) {
-  const int j = lnodes[blockIdx.x];
+           const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
+           const T* __restrict__ linv2, int J0, int m, const T* __restrict__ rb, T* __restrict__ zb) {
+  const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
   if (J0 >= npiv) return;
   const int nc = min(TB, npiv - J0);
-  const int64_t f = ni.f;
-  const T* F = front + ni.front_off;
-  T* W = rb + ni.rhs_off * m;
-  __shared__ T Lt[SB][SB + 1];
-  __shared__ T acc[SB * 64];
+  const int I = blockIdx.x;
+  if (SB * I >= nc) return;
+  const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB;
+  const T* W = rb + (ni.rhs_off + J0) * m;
+  __shared__ T Xs[KC][64 + 1];
+  __shared__ T ws[KC * 64];
   const int tid = threadIdx.x;
-  for (int s0 = J0; s0 < J0 + nc; s0 += SB) {
-    const int ns = min(SB, J0 + nc - s0);
-    for (int e = tid; e < SB * m; e += 256) acc[e] = (e / m < ns) ? W[(int64_t)s0 * m + e] : (T)0;
+  const int row = tid & 63, cg = tid >> 6;
+  T a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) a[q] = (T)0;
+  const int cend = min(nc, SB * I + SB);
+  for (int c0 = 0; c0 < cend; c0 += KC) {
+    const int kc = min(KC, cend - c0);
+    for (int e = tid; e < KC * 64; e += 256) {
+      const int rr = e & 63, kk = e >> 6;
+      Xs[kk][rr] = (kk < kc) ? X[(int64_t)(c0 + kk) * TB + SB * I + rr] : (T)0;
+    }
+    for (int e = tid; e < kc * m; e += 256) ws[e] = W[(int64_t)c0 * m + e];
     __syncthreads();
-    for (int t0 = J0; t0 < s0; t0 += SB) {
-      for (int e = tid; e < SB * SB; e += 256) {
-        const int r = e & 63, c = e >> 6;
-        Lt[r][c] = (r < ns) ? F[(int64_t)(t0 + c) * f + s0 + r] : (T)0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = cg + 4 * q;
+      if (col < m) {
+        T v = a[q];
+        for (int kk = 0; kk < kc; ++kk) v += Xs[kk][row] * ws[kk * m + col];
+        a[q] = v;
       }
-      __syncthreads();
-      for (int e = tid; e < ns * m; e += 256) {
-        const int r = e / m, col = e - r * m;
-        T v = (T)0;
-        for (int k = 0; k < SB; ++k) v += Lt[r][k] * W[(int64_t)(t0 + k) * m + col];
-        acc[e] -= v;
-      }
-      __syncthreads();
-    }
-    const T* Li = linv + linv_off[j] + (int64_t)((s0) / SB) * SB * SB;
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int r = e & 63, c = e >> 6;
-      Lt[r][c] = Li[(int64_t)c * SB + r];
     }
     __syncthreads();
-    for (int e = tid; e < ns * m; e += 256) {
-      const int r = e / m, col = e - r * m;
-      T v = (T)0;
-      for (int k = 0; k <= r; ++k) v += Lt[r][k] * acc[k * m + col];
-      W[(int64_t)(s0 + r) * m + col] = v;
+  }
+  const int r = SB * I + row;
+  if (r < nc) {
+    T* Z = zb + (ni.rhs_off + J0 + r) * m;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = cg + 4 * q;
+      if (col < m) Z[col] = a[q];
     }
-    __syncthreads();
   }
 }
 
@@ -167,7 +275,7 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
           const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int m,
-          T* __restrict__ rb) {
+          const T* __restrict__ zb, T* __restrict__ rb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -179,6 +287,7 @@ k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
   const int64_t lf = f;
   const T* F = front + ni.front_off;
   T* W = rb + ni.rhs_off * m;
+  const T* Z = zb + ni.rhs_off * m;
   __shared__ T Lt[KC][64 + 1];
   __shared__ T zs[KC * 64];
   const int tid = threadIdx.x;
@@ -193,7 +302,7 @@ k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
       const int rr = e & 63, kk = e >> 6;
       Lt[kk][rr] = (kk < kc && rs + rr < f) ? F[(int64_t)(J0 + k0 + kk) * lf + rs + rr] : (T)0;
     }
-    for (int e = tid; e < kc * m; e += 256) zs[e] = W[(int64_t)(J0 + k0) * m + e];
+    for (int e = tid; e < kc * m; e += 256) zs[e] = Z[(int64_t)(J0 + k0) * m + e];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -225,7 +334,7 @@ __global__ void __launch_bounds__(256)
 k_bwd_border(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
              const NodeState* __restrict__ st, const T* __restrict__ front, const T* __restrict__ dval,
              const int32_t* __restrict__ border, int m, const double* __restrict__ Y,
-             T* __restrict__ rb) {
+             const T* __restrict__ zb, T* __restrict__ rb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -235,6 +344,7 @@ k_bwd_border(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
   const int64_t lf = ni.f;
   const T* F = front + ni.front_off;
   T* W = rb + ni.rhs_off * m;
+  const T* Z = zb + ni.rhs_off * m;
   __shared__ T Lt[KC][64 + 1];
   __shared__ T xs[KC * 64];
   const int tid = threadIdx.x;
@@ -270,66 +380,65 @@ k_bwd_border(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int col = cg + 4 * q;
-      if (col < m) W[(int64_t)k * m + col] = W[(int64_t)k * m + col] * dinv - a[q];
+      if (col < m) W[(int64_t)k * m + col] = Z[(int64_t)k * m + col] * dinv - a[q];
     }
   }
 }
 
-// x_J = L_JJ^{-T} t_J for the step at J0, scattered to the FP64 result
+// x_J = Linv_J^T t_J (four workgroups of 64 columns), scattered to the FP64 result
 template <class T>
 __global__ void __launch_bounds__(256)
 k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-           const NodeState* __restrict__ st, const T* __restrict__ front,
-           const int64_t* __restrict__ linv_off, const T* __restrict__ linv,
-           const int32_t* __restrict__ piv, int J0, int m, double* __restrict__ Y, T* __restrict__ rb) {
-  const int j = lnodes[blockIdx.x];
+           const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
+           const T* __restrict__ linv2, const int32_t* __restrict__ piv, int J0, int m,
+           double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb) {
+  const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
   if (J0 >= npiv) return;
   const int nc = min(TB, npiv - J0);
-  const int64_t f = ni.f;
-  const T* F = front + ni.front_off;
-  T* W = rb + ni.rhs_off * m;
-  __shared__ T Lt[SB][SB + 1];
-  __shared__ T acc[SB * 64];
+  const int I = blockIdx.x;
+  if (SB * I >= nc) return;
+  const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB;
+  const T* W = rb + (ni.rhs_off + J0) * m;
+  __shared__ T Xs[KC][64 + 1];
+  __shared__ T ts[KC * 64];
   const int tid = threadIdx.x;
-  const int nsub = (nc + SB - 1) / SB;
-  for (int si = nsub - 1; si >= 0; --si) {
-    const int s0 = J0 + si * SB;
-    const int ns = min(SB, J0 + nc - s0);
-    for (int e = tid; e < SB * m; e += 256) acc[e] = (e / m < ns) ? W[(int64_t)s0 * m + e] : (T)0;
+  const int cl = tid & 63, cg = tid >> 6;
+  T a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) a[q] = (T)0;
+  for (int r0 = SB * I; r0 < nc; r0 += KC) {
+    const int kc = min(KC, nc - r0);
+    for (int e = tid; e < KC * 64; e += 256) {
+      const int rr = e & (KC - 1), cc = e / KC;
+      Xs[rr][cc] = (rr < kc) ? X[(int64_t)(SB * I + cc) * TB + r0 + rr] : (T)0;
+    }
+    for (int e = tid; e < kc * m; e += 256) ts[e] = W[(int64_t)r0 * m + e];
     __syncthreads();
-    for (int t0 = s0 + SB; t0 < J0 + nc; t0 += SB) {
-      const int nt = min(SB, J0 + nc - t0);
-      // Lt[c][k] = L[t0 + k, s0 + c]
-      for (int e = tid; e < SB * SB; e += 256) {
-        const int kk = e & 63, c = e >> 6;
-        Lt[c][kk] = (kk < nt && c < ns) ? F[(int64_t)(s0 + c) * f + t0 + kk] : (T)0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = cg + 4 * q;
+      if (col < m) {
+        T v = a[q];
+        for (int rr = 0; rr < kc; ++rr) v += Xs[rr][cl] * ts[rr * m + col];
+        a[q] = v;
       }
-      __syncthreads();
-      for (int e = tid; e < ns * m; e += 256) {
-        const int c = e / m, col = e - c * m;
-        T v = (T)0;
-        for (int kk = 0; kk < nt; ++kk) v += Lt[c][kk] * W[(int64_t)(t0 + kk) * m + col];
-        acc[e] -= v;
+    }
+    __syncthreads();
+  }
+  const int c = SB * I + cl;
+  if (c < nc) {
+    T* Zr = zb + (ni.rhs_off + J0 + c) * m;
+    double* Yr = Y + (int64_t)piv[ni.start + J0 + c] * m;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = cg + 4 * q;
+      if (col < m) {
+        Zr[col] = a[q];
+        Yr[col] = (double)a[q];
       }
-      __syncthreads();
     }
-    const T* Li = linv + linv_off[j] + (int64_t)(s0 / SB) * SB * SB;
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int r = e & 63, c = e >> 6;
-      Lt[r][c] = Li[(int64_t)c * SB + r];  // Lt[r][c] = Linv(r, c)
-    }
-    __syncthreads();
-    // x = Linv^T acc: x_c = sum_{r >= c} Linv(r, c) acc_r
-    for (int e = tid; e < ns * m; e += 256) {
-      const int c = e / m, col = e - c * m;
-      T v = (T)0;
-      for (int r = c; r < ns; ++r) v += Lt[r][c] * acc[r * m + col];
-      W[(int64_t)(s0 + c) * m + col] = v;
-      Y[(int64_t)piv[ni.start + s0 + c] * m + col] = (double)v;
-    }
-    __syncthreads();
   }
 }
 
@@ -338,7 +447,7 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
           const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int m,
-          T* __restrict__ rb) {
+          const T* __restrict__ zb, T* __restrict__ rb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -349,6 +458,7 @@ k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
   const int64_t lf = ni.f;
   const T* F = front + ni.front_off;
   T* W = rb + ni.rhs_off * m;
+  const T* Z = zb + ni.rhs_off * m;
   __shared__ T Lt[KC][64 + 1];
   __shared__ T xs[KC * 64];
   const int tid = threadIdx.x;
@@ -362,7 +472,7 @@ k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
       const int rr = e & (KC - 1), kk = e / KC;
       Lt[rr][kk] = (rr < rc && cs + kk < J0) ? F[(int64_t)(cs + kk) * lf + J0 + r0 + rr] : (T)0;
     }
-    for (int e = tid; e < rc * m; e += 256) xs[e] = W[(int64_t)(J0 + r0) * m + e];
+    for (int e = tid; e < rc * m; e += 256) xs[e] = Z[(int64_t)(J0 + r0) * m + e];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -391,24 +501,37 @@ k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
 
 template <class T>
 void prepare_solve(hf_ctx* ctx, hipStream_t s) {
-  const int64_t nb = ctx->blk_first.empty() ? 0 : (int64_t)ctx->blk_node.size();
+  const int64_t nb = (int64_t)ctx->blk_node.size();
   ctx->d_linv.alloc((size_t)std::max<int64_t>(ctx->linv_elems, 1) * sizeof(T));
   if (nb > 0)
     k_inv_diag<T><<<(unsigned)nb, 256, 0, s>>>(ctx->d_blk_node.as<int32_t>(), ctx->d_blk_first.as<int32_t>(),
                                                ctx->d_nodes.as<NodeInfo>(), ctx->d_state.as<NodeState>(),
                                                ctx->d_front.as<T>(), ctx->d_linv_off.as<int64_t>(),
                                                ctx->d_linv.as<T>());
+  const int64_t ns = (int64_t)ctx->stp_node.size();
+  ctx->d_linv2.alloc((size_t)std::max<int64_t>(ctx->linv2_elems, 1) * sizeof(T));
+  if (ns > 0)
+    timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, [&] {
+      k_inv_step<T><<<(unsigned)ns, 256, 0, s>>>(ctx->d_stp_node.as<int32_t>(), ctx->d_stp_first.as<int32_t>(),
+                                                 ctx->d_nodes.as<NodeInfo>(), ctx->d_state.as<NodeState>(),
+                                                 ctx->d_front.as<T>(), ctx->d_linv_off.as<int64_t>(),
+                                                 ctx->d_linv.as<T>(), ctx->d_linv2_off.as<int64_t>(),
+                                                 ctx->d_linv2.as<T>());
+    });
   HF_HIP(hipGetLastError());
 }
 
 template <class T>
 void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s) {
   const int nlev = (int)ctx->level_ptr.size() - 1;
-  ctx->d_rhs_arena.alloc((size_t)std::max<int64_t>(ctx->rhs_rows, 1) * m * sizeof(T));
+  const size_t arena = (size_t)std::max<int64_t>(ctx->rhs_rows, 1) * m * sizeof(T);
+  ctx->d_rhs_arena.alloc(arena);
+  ctx->d_zb_arena.alloc(arena);
   T* rb = ctx->d_rhs_arena.as<T>();
+  T* zb = ctx->d_zb_arena.as<T>();
   const T* front = ctx->d_front.as<T>();
-  const T* linv = ctx->d_linv.as<T>();
-  const int64_t* loff = ctx->d_linv_off.as<int64_t>();
+  const T* linv2 = ctx->d_linv2.as<T>();
+  const int64_t* loff2 = ctx->d_linv2_off.as<int64_t>();
   const NodeInfo* nodes = ctx->d_nodes.as<NodeInfo>();
   const NodeState* st = ctx->d_state.as<NodeState>();
   const int32_t* lall = ctx->d_level_nodes.as<int32_t>();
@@ -425,31 +548,43 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     return std::make_pair(by, fl);
   };
   HF_HIP(hipMemsetAsync(Y, 0, (size_t)ctx->n * m * sizeof(double), s));
+  size_t ea = 0;
   for (int l = 0; l < nlev; ++l) {
     const int nl = ctx->level_ptr[l + 1] - ctx->level_ptr[l];
     const int32_t* ln = lall + ctx->level_ptr[l];
+    const int maxp = ctx->level_maxp[l], maxf = ctx->level_maxf[l];
     auto wg = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
       by += ni.f * dm * sz + np * dm * 8.0;
-      for (int32_t c = ni.child_begin; c < ni.child_end; ++c) {
-        const double bc = ctx->nodes[ctx->child_list[c]].b;
-        by += 2.0 * bc * dm * sz;
-        fl += bc * dm;
-      }
     });
     timed(tm, HF_K_SOLVE_GATHER, wg.first, wg.second, s, [&] {
-      k_fwd_gather<T><<<nl, 256, 0, s>>>(ln, nodes, st, ctx->d_piv.as<int32_t>(), ctx->d_relmap.as<int32_t>(),
-                                         ctx->d_child_list.as<int32_t>(), ctx->d_ipos.as<int32_t>(), m, R, rb);
+      dim3 g(cdiv((int64_t)maxf * m, 256), nl);
+      k_fwd_init<T><<<g, 256, 0, s>>>(ln, nodes, st, ctx->d_piv.as<int32_t>(), m, R, rb);
     });
-    const int maxp = ctx->level_maxp[l], maxf = ctx->level_maxf[l];
+    for (; ea < ctx->ea_launch.size() && ctx->ea_launch[ea].level == l; ++ea) {
+      const EaLaunch& el = ctx->ea_launch[ea];
+      double by = 0.0, fl = 0.0;
+      if (tm.on)
+        for (int q = 0; q < el.count; ++q) {
+          const double bc = ctx->nodes[ctx->ea_items[el.off + q]].b;
+          by += 3.0 * bc * dm * sz;
+          fl += bc * dm;
+        }
+      timed(tm, HF_K_SOLVE_GATHER, by, fl, s, [&] {
+        dim3 g(cdiv((int64_t)el.maxb * m, 256), (unsigned)el.count);
+        k_fwd_addchild<T><<<g, 256, 0, s>>>(ctx->d_ea_items.as<int32_t>() + el.off, nodes,
+                                            ctx->d_relmap.as<int32_t>(), ctx->d_ipos.as<int32_t>(), m, rb);
+      });
+    }
     for (int J0 = 0; J0 < maxp; J0 += TB) {
       auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
         if (np <= J0) return;
         const double nc = std::min<double>(TB, np - J0);
-        by += (nc * SB + 0.5 * nc * nc) * sz + 2.0 * nc * dm * sz;
-        fl += 2.0 * dm * (nc * SB * 0.5 + 0.5 * nc * nc);
+        by += 0.5 * nc * nc * sz + 2.0 * nc * dm * sz;
+        fl += dm * nc * nc;
       });
       timed(tm, HF_K_SOLVE_DIAG, wd.first, wd.second, s, [&] {
-        k_fwd_diag<T><<<nl, 256, 0, s>>>(ln, nodes, st, front, loff, linv, J0, m, rb);
+        dim3 g(TB / SB, nl);
+        k_fwd_diag<T><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, m, rb, zb);
       });
       const int rows = maxf - J0 - 1;
       if (rows > 0) {
@@ -463,7 +598,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           fl += 2.0 * dm * below * nc;
         });
         timed(tm, HF_K_SOLVE_UPDATE, wu.first, wu.second, s, [&] {
-          k_fwd_upd<T><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, rb);
+          k_fwd_upd<T><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
         });
       }
     }
@@ -480,17 +615,18 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     });
     timed(tm, HF_K_SOLVE_UPDATE, wb.first, wb.second, s, [&] {
       k_bwd_border<T><<<gb, 256, 0, s>>>(ln, nodes, st, front, ctx->d_dval.as<T>(), ctx->d_border.as<int32_t>(), m,
-                                         Y, rb);
+                                         Y, zb, rb);
     });
     for (int J0 = ((maxp - 1) / TB) * TB; J0 >= 0; J0 -= TB) {
       auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
         if (np <= J0) return;
         const double nc = std::min<double>(TB, np - J0);
-        by += (nc * SB + 0.5 * nc * nc) * sz + 2.0 * nc * dm * sz + nc * dm * 8.0;
-        fl += 2.0 * dm * (nc * SB * 0.5 + 0.5 * nc * nc);
+        by += 0.5 * nc * nc * sz + 2.0 * nc * dm * sz + nc * dm * 8.0;
+        fl += dm * nc * nc;
       });
       timed(tm, HF_K_SOLVE_DIAG, wd.first, wd.second, s, [&] {
-        k_bwd_diag<T><<<nl, 256, 0, s>>>(ln, nodes, st, front, loff, linv, ctx->d_piv.as<int32_t>(), J0, m, Y, rb);
+        dim3 g(TB / SB, nl);
+        k_bwd_diag<T><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, m, Y, rb, zb);
       });
       if (J0 > 0) {
         dim3 g(cdiv(J0, 64), nl);
@@ -501,7 +637,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           fl += 2.0 * dm * J0 * nc;
         });
         timed(tm, HF_K_SOLVE_UPDATE, wu.first, wu.second, s, [&] {
-          k_bwd_upd<T><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, rb);
+          k_bwd_upd<T><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
         });
       }
     }
