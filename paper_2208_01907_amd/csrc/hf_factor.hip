@@ -100,14 +100,30 @@ __device__ inline void argmax_combine(T& bv, int& bid, int& bk, T v, int id, int
   if (v > bv || (v == bv && id < bid)) { bv = v; bid = id; bk = k; }
 }
 
-constexpr int PT = 512;               // threads of the panel kernel
-constexpr int PROWS = 4096 / PT;      // rows per thread (nodes hold at most 4096 indices)
+constexpr int PT = 1024;              // threads of the panel kernel
+constexpr int PROWS = 4096 / PT;      // pivot-block rows per thread (nodes hold at most 4096 indices)
 
+// Panel width: the panel's L values of every pivot-block row stay in registers.
+template <class T>
+struct PanelWidth {
+  static constexpr int value = sizeof(T) == 4 ? 16 : 8;
+};
+
+// Panel factorization with pivot search and postponing, one workgroup per front.
+// Thread t owns the pivot-block positions q = t + PT*s (q relative to k0p); its
+// rows' panel values L[q, 0..NB) live in registers, the current diagonal and the
+// nested-dissection indices in LDS.  Per pivot: every thread reduces the wave
+// argmax results itself, the owners of the two exchanged rows swap their panel
+// rows through LDS, and one pass over global memory does the symmetric exchange
+// of the not-yet-updated part together with the new pivot column
+// (left-looking inside the panel).  Two workgroup barriers per pivot.
 template <class T>
 __global__ void __launch_bounds__(PT)
 k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, NodeState* st,
         T* __restrict__ front, int32_t* __restrict__ piv, int32_t* __restrict__ swaps,
         T* __restrict__ dval, int k0p, double tau, int first_unit) {
+  constexpr int NB = PanelWidth<T>::value;
+  constexpr int NW = PT / 64;
   const int j = lnodes[blockIdx.x];
   const NodeInfo ni = nodes[j];
   const NodeState s0 = st[j];
@@ -115,32 +131,45 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   const int p = ni.p;
   const int64_t f = ni.f;
   T* F = front + ni.front_off;
-  int32_t* idx = piv + ni.start;
+  int32_t* idx_g = piv + ni.start;
   int32_t* sw = swaps + ni.start;
   T* D = dval + ni.start;
   const int tid = threadIdx.x;
-  constexpr int NW = PT / 64;
+  const int P = p - k0p;
 
   extern __shared__ unsigned char smem_raw[];
-  T* dg = reinterpret_cast<T*>(smem_raw);  // current diagonal of positions [k0p, p)
-  __shared__ T u[PANEL_NB];
+  T* dg = reinterpret_cast<T*>(smem_raw);                     // [P]
+  int32_t* idx = reinterpret_cast<int32_t*>(dg + ((P + 1) & ~1));  // [P]
   __shared__ T red_v[NW];
   __shared__ int red_id[NW], red_k[NW];
-  __shared__ int s_k, s_stop;
+  __shared__ T bufI[NB], bufK[NB], Dl[NB];
 
-  for (int k = k0p + tid; k < p; k += PT) dg[k - k0p] = F[(int64_t)k * f + k];
+  T Lp[PROWS][NB];
+#pragma unroll
+  for (int s = 0; s < PROWS; ++s)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Lp[s][c] = (T)0;
+  for (int q = tid; q < P; q += PT) {
+    dg[q] = F[(int64_t)(k0p + q) * f + k0p + q];
+    idx[q] = idx_g[k0p + q];
+  }
   double dprev = s0.dprev;
   int have_prev = (s0.npiv > 0) ? 1 : first_unit;
-  const int iend = min(k0p + PANEL_NB, p);
+  const int iend = min(k0p + NB, p);
   __syncthreads();
   int i;
   for (i = k0p; i < iend; ++i) {
-    // workgroup argmax of |diag| over the remaining candidates
+    const int qi = i - k0p;
+    // argmax of |diag| over the remaining candidates (own rows, then the wave, then all waves)
     T bv = (T)-1;
     int bid = INT_MAX, bk = -1;
-    for (int k = i + tid; k < p; k += PT) {
-      const T v = dg[k - k0p];
-      argmax_combine(bv, bid, bk, v < (T)0 ? -v : v, idx[k], k);
+#pragma unroll
+    for (int s = 0; s < PROWS; ++s) {
+      const int q = tid + PT * s;
+      if (q >= qi && q < P) {
+        const T v = dg[q];
+        argmax_combine(bv, bid, bk, v < (T)0 ? -v : v, idx[q], q);
+      }
     }
     for (int off = 32; off > 0; off >>= 1) {
       const T ov = __shfl_xor(bv, off, 64);
@@ -149,83 +178,120 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
       argmax_combine(bv, bid, bk, ov, oid, ok);
     }
     if ((tid & 63) == 0) { red_v[tid >> 6] = bv; red_id[tid >> 6] = bid; red_k[tid >> 6] = bk; }
-    __syncthreads();
-    if (tid == 0) {
-      for (int w = 1; w < NW; ++w) argmax_combine(bv, bid, bk, red_v[w], red_id[w], red_k[w]);
-      const double dk = (double)dg[bk - k0p];
-      int stop = (dk == 0.0);
-      if (!stop && have_prev && fabs(dk) < tau * fabs(dprev)) stop = 1;
-      s_stop = stop;
-      s_k = bk;
-      if (!stop) sw[i] = bk;
-    }
-    __syncthreads();
-    if (s_stop) break;
-    const int k = s_k;
-    if (k != i) {
-      // symmetric exchange of positions i < k in the lower triangle; columns of
-      // earlier panels get their row exchanges later in one pass (k_apply_swaps)
-      for (int c = k0p + tid; c < i; c += PT) {
-        const T a = F[(int64_t)c * f + i];
-        F[(int64_t)c * f + i] = F[(int64_t)c * f + k];
-        F[(int64_t)c * f + k] = a;
-      }
-      for (int c = i + 1 + tid; c < k; c += PT) {
-        const T a = F[(int64_t)i * f + c];
-        F[(int64_t)i * f + c] = F[(int64_t)c * f + k];
-        F[(int64_t)c * f + k] = a;
-      }
-      for (int64_t r = k + 1 + tid; r < f; r += PT) {
-        const T a = F[(int64_t)i * f + r];
-        F[(int64_t)i * f + r] = F[(int64_t)k * f + r];
-        F[(int64_t)k * f + r] = a;
-      }
-      if (tid == 0) {
-        const T a = F[(int64_t)i * f + i];
-        F[(int64_t)i * f + i] = F[(int64_t)k * f + k];
-        F[(int64_t)k * f + k] = a;
-        const T dd = dg[i - k0p]; dg[i - k0p] = dg[k - k0p]; dg[k - k0p] = dd;
-        const int32_t t = idx[i]; idx[i] = idx[k]; idx[k] = t;
-      }
-    }
-    __syncthreads();
-    const T d = dg[i - k0p];
-    for (int c = k0p + tid; c < i; c += PT) u[c - k0p] = D[c] * F[(int64_t)c * f + i];
-    __syncthreads();
-    // pivot column (rows of F11 below the pivot), left-looking within the panel;
-    // each thread keeps its rows in registers so the loads of a column overlap
-    T acc[PROWS];
+    __syncthreads();  // B1
+    bv = red_v[0]; bid = red_id[0]; bk = red_k[0];
 #pragma unroll
-    for (int t = 0; t < PROWS; ++t) {
-      const int r = i + 1 + tid + t * PT;
-      acc[t] = (r < p) ? F[(int64_t)i * f + r] : (T)0;
-    }
-    for (int c = k0p; c < i; ++c) {
-      const T uc = u[c - k0p];
-      const T* Fc = F + (int64_t)c * f;
+    for (int w = 1; w < NW; ++w) argmax_combine(bv, bid, bk, red_v[w], red_id[w], red_k[w]);
+    const int qk = bk;
+    const T d = dg[qk];
+    const T dI = dg[qi];  // moves to position k with its row
+    const double dk = (double)d;
+    bool stop = (dk == 0.0);
+    if (!stop && have_prev && fabs(dk) < tau * fabs(dprev)) stop = true;
+    if (stop) break;  // uniform: every thread computed the same decision
+    const int ti = qi % PT, si = qi / PT, tk = qk % PT, sk = qk / PT;
+    // publish the panel rows of positions i and k
+    if (tid == ti) {
 #pragma unroll
-      for (int t = 0; t < PROWS; ++t) {
-        const int r = i + 1 + tid + t * PT;
-        if (r < p) acc[t] -= Fc[r] * uc;
-      }
-    }
-    const T inv = (T)1 / d;
+      for (int s = 0; s < PROWS; ++s)
+        if (s == si)
 #pragma unroll
-    for (int t = 0; t < PROWS; ++t) {
-      const int r = i + 1 + tid + t * PT;
-      if (r < p) {
-        const T l = acc[t] * inv;
-        F[(int64_t)i * f + r] = l;
-        dg[r - k0p] -= l * acc[t];
-      }
+          for (int c = 0; c < NB; ++c) bufI[c] = Lp[s][c];
+    }
+    if (tid == tk) {
+#pragma unroll
+      for (int s = 0; s < PROWS; ++s)
+        if (s == sk)
+#pragma unroll
+          for (int c = 0; c < NB; ++c) bufK[c] = Lp[s][c];
     }
     if (tid == 0) {
-      F[(int64_t)i * f + i] = d;
+      sw[i] = k0p + qk;
+      const int32_t tx = idx[qi]; idx[qi] = idx[qk]; idx[qk] = tx;
+      Dl[qi] = d;
       D[i] = d;
     }
-    dprev = (double)d;
+    __syncthreads();  // B2
+    // rows i and k exchange their panel values (and the owner of k its diagonal)
+    if (qk != qi) {
+      if (tid == tk) dg[qk] = dI;
+      if (tid == ti) {
+#pragma unroll
+        for (int s = 0; s < PROWS; ++s)
+          if (s == si)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) Lp[s][c] = bufK[c];
+      }
+      if (tid == tk) {
+#pragma unroll
+        for (int s = 0; s < PROWS; ++s)
+          if (s == sk)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) Lp[s][c] = bufI[c];
+      }
+    }
+    // u_c = D_c L[i, c] for the panel columns so far (row i after the exchange)
+    T u[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) u[c] = (c < qi) ? Dl[c] * bufK[c] : (T)0;
+    const int k = k0p + qk;
+    const T inv = (T)1 / d;
+    // pivot-block rows below the pivot: exchange + new column + eager diagonal
+#pragma unroll
+    for (int s = 0; s < PROWS; ++s) {
+      const int q = tid + PT * s;
+      const int r = k0p + q;
+      if (q > qi && q < P) {
+        T vnew;
+        if (r > k) {
+          const T oi = F[(int64_t)i * f + r], ok2 = F[(int64_t)k * f + r];
+          vnew = ok2;
+          F[(int64_t)k * f + r] = oi;
+        } else if (r < k) {
+          const T oi = F[(int64_t)i * f + r], ok2 = F[(int64_t)r * f + k];
+          vnew = ok2;
+          F[(int64_t)r * f + k] = oi;
+        } else {
+          vnew = F[(int64_t)i * f + r];  // F[k, i] is not moved by the exchange
+        }
+        T v = vnew;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) v -= Lp[s][c] * u[c];
+        const T l = v * inv;
+        F[(int64_t)i * f + r] = l;
+        dg[q] -= l * v;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c == qi) Lp[s][c] = l;
+      }
+    }
+    // border rows: exchange only (their L values come from the TRSM)
+    for (int64_t r = p + tid; r < f; r += PT) {
+      const T oi = F[(int64_t)i * f + r];
+      F[(int64_t)i * f + r] = F[(int64_t)k * f + r];
+      F[(int64_t)k * f + r] = oi;
+    }
+    if (tid == 0) {
+      if (qk != qi) F[(int64_t)k * f + k] = F[(int64_t)i * f + i];
+      F[(int64_t)i * f + i] = d;
+    }
+    dprev = dk;
     have_prev = 1;
-    __syncthreads();
+    // the next argmax reads only the thread's own rows of dg; dg[qi], dg[qk] and
+    // the panel buffers are rewritten only after the next B1
+  }
+  __syncthreads();
+  // write the panel back: rows are in their final positions
+  const int nacc = i - k0p;
+#pragma unroll
+  for (int s = 0; s < PROWS; ++s) {
+    const int q = tid + PT * s;
+    if (q < P) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c < nacc && c < q) F[(int64_t)(k0p + c) * f + k0p + q] = Lp[s][c];
+      idx_g[k0p + q] = idx[q];
+    }
   }
   if (tid == 0) {
     NodeState ns;
@@ -241,13 +307,13 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
 template <class T>
 __global__ void k_apply_swaps(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
                               const NodeState* __restrict__ st, const int32_t* __restrict__ swaps,
-                              T* __restrict__ front, int k0p) {
+                              T* __restrict__ front, int k0p, int nb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= k0p || k0p >= npiv) return;
-  const int iend = min(npiv, k0p + PANEL_NB);
+  const int iend = min(npiv, k0p + nb);
   const int32_t* sw = swaps + ni.start;
   T* Fc = front + ni.front_off + (int64_t)c * ni.f;
   for (int i = k0p; i < iend; ++i) {
@@ -270,16 +336,16 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
        const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval, int mode,
-       int k0p) {
+       int k0p, int nb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const NodeState s = st[j];
   int r0, kc0, K, nr;
   if (mode == 0) {
     if (s.done || k0p >= ni.p) return;
-    r0 = k0p + PANEL_NB;
+    r0 = k0p + nb;
     kc0 = k0p;
-    K = PANEL_NB;
+    K = nb;
     nr = ni.p - r0;
   } else {
     r0 = ni.p;
@@ -302,15 +368,16 @@ k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
   const T* Dk = dval + ni.start + kc0;
   T* C = F + (int64_t)r0 * f + r0;
 
-  __shared__ T As[16][64 + 1];
-  __shared__ T Bs[16][64 + 1];
+  __shared__ T As[16][64 + 4];
+  __shared__ T Bs[16][64 + 4];
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  T acc[4][4];
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  typename Mfma<T>::V acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+    for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::V{0, 0, 0, 0};
   const int rowA = ti * 64, rowB = tj * 64;
   for (int kk = 0; kk < K; kk += 16) {
 #pragma unroll
@@ -327,28 +394,19 @@ k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
       Bs[kq][rr] = vb;
     }
     __syncthreads();
-#pragma unroll
-    for (int kq = 0; kq < 16; ++kq) {
-      T a[4], b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) { a[q] = As[kq][ty * 4 + q]; b[q] = Bs[kq][tx * 4 + q]; }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
-    }
+    mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
     __syncthreads();
   }
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int r = rowA + ty * 4 + x;
-    if (r >= nr) continue;
+  for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
-      const int c = rowB + tx * 4 + y;
-      if (c < nr && c <= r) C[(int64_t)c * f + r] -= acc[x][y];
-    }
-  }
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = rowA + wr + bi * 16 + Mfma<T>::row(lane, t);
+        const int c = rowB + wc + bj * 16 + (lane & 15);
+        if (r < nr && c < nr && c <= r) C[(int64_t)c * f + r] -= acc[bi][bj][t];
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -358,7 +416,8 @@ k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
 template <class T>
 __global__ void __launch_bounds__(256)
 k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-       const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval) {
+       const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval,
+       const int64_t* __restrict__ linv_off, const T* __restrict__ linv) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -370,18 +429,22 @@ k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
   T* X = F + ni.p + rs;  // X(r, c) = X[c*f + r], r < 64
   const int nrow = min(64, b - rs);
   const T* Dk = dval + ni.start;
-  __shared__ T As[16][64 + 1];
-  __shared__ T Bs[16][64 + 1];
-  __shared__ T Xt[64][64 + 1];
+  const T* L64 = linv + linv_off[j];
+  __shared__ T As[16][64 + 4];
+  __shared__ T Bs[16][64 + 4];
+  __shared__ T Yt[64][64 + 4];  // Yt[c][r]: the block right-hand side, k-major for the second product
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  using V = typename Mfma<T>::V;
   for (int J0 = 0; J0 < npiv; J0 += 64) {
     const int nc = min(64, npiv - J0);
-    T acc[4][4];
+    V acc[2][2];
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = (T)0;
+      for (int bb = 0; bb < 2; ++bb) acc[a][bb] = V{0, 0, 0, 0};
+    // acc = X[:, 0:J0] L11[J0:J0+64, 0:J0]^T
     for (int kk = 0; kk < J0; kk += 16) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -392,44 +455,94 @@ k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
         Bs[kq][rr] = (rr < nc) ? F[(int64_t)kg * f + J0 + rr] : (T)0;
       }
       __syncthreads();
+      mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
+      __syncthreads();
+    }
+    // Y = F21[:, J] - acc  (stored transposed, k-major)
 #pragma unroll
-      for (int kq = 0; kq < 16; ++kq) {
-        T a[4], bb[4];
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) { a[q] = As[kq][ty * 4 + q]; bb[q] = Bs[kq][tx * 4 + q]; }
+      for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+        for (int t = 0; t < 4; ++t) {
+          const int r = wr + bi * 16 + Mfma<T>::row(lane, t);
+          const int c = wc + bj * 16 + (lane & 15);
+          Yt[c][r] = (r < nrow && c < nc) ? X[(int64_t)(J0 + c) * f + r] - acc[bi][bj][t] : (T)0;
+        }
+    __syncthreads();
+    // X_J = Y Linv_JJ^T: X[r][c] = sum_k Y[r][k] Linv[c][k]
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * bb[y];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) acc[a][bb] = V{0, 0, 0, 0};
+    const T* Li = L64 + (int64_t)(J0 / 64) * 64 * 64;  // column-major: Linv(c, k) = Li[k*64 + c]
+    for (int kk = 0; kk < 64; kk += 16) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + q * 256;
+        const int cc = e & 63, kq = e >> 6;
+        Bs[kq][cc] = Li[(int64_t)(kk + kq) * 64 + cc];
       }
+      __syncthreads();
+      mfma_tile_64<T, 16, 68>(reinterpret_cast<const T(*)[68]>(&Yt[kk][0]), Bs, acc, lane, wr, wc);
       __syncthreads();
     }
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const int r = ty * 4 + x, c = tx * 4 + y;
-        Xt[r][c] = (r < nrow && c < nc) ? X[(int64_t)(J0 + c) * f + r] - acc[x][y] : (T)0;
-      }
-    __syncthreads();
-    // unit lower triangular solve inside the block (one thread per row)
-    if (tid < nrow) {
-      for (int c = 1; c < nc; ++c) {
-        T v = Xt[tid][c];
-        for (int c2 = 0; c2 < c; ++c2) v -= Xt[tid][c2] * F[(int64_t)(J0 + c2) * f + J0 + c];
-        Xt[tid][c] = v;
-      }
-    }
-    __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int r = e & 63, c = e >> 6;
-      if (r < nrow && c < nc) X[(int64_t)(J0 + c) * f + r] = Xt[r][c];
-    }
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int r = wr + bi * 16 + Mfma<T>::row(lane, t);
+          const int c = wc + bj * 16 + (lane & 15);
+          if (r < nrow && c < nc) X[(int64_t)(J0 + c) * f + r] = acc[bi][bj][t];
+        }
     __syncthreads();
   }
   for (int e = tid; e < 64 * npiv; e += 256) {
     const int r = e & 63, c = e >> 6;
     if (r < nrow) X[(int64_t)c * f + r] /= Dk[c];
+  }
+}
+
+// inverse of every 64x64 unit-lower diagonal block of L11 (one workgroup per block)
+template <class T>
+__global__ void __launch_bounds__(256)
+k_inv_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+           const NodeState* __restrict__ st, const T* __restrict__ front,
+           const int64_t* __restrict__ linv_off, T* __restrict__ linv) {
+  const int j = lnodes[blockIdx.y];
+  const int B = blockIdx.x;
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int J0 = B * 64;
+  if (J0 >= npiv) return;
+  const int nc = min(64, npiv - J0);
+  const int64_t f = ni.f;
+  const T* F = front + ni.front_off;
+  __shared__ T Ls[64][64 + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    T v = (r == c) ? (T)1 : (T)0;
+    if (r > c && r < nc) v = F[(int64_t)(J0 + c) * f + J0 + r];
+    Ls[r][c] = v;
+  }
+  __syncthreads();
+  T* out = linv + linv_off[j] + (int64_t)B * 64 * 64;  // column-major 64x64
+  if (tid < 64) {
+    const int c = tid;
+    T x[64];
+#pragma unroll
+    for (int r = 0; r < 64; ++r) x[r] = (T)0;
+    x[c] = (T)1;
+    for (int r = c + 1; r < 64; ++r) {
+      T v = (T)0;
+      for (int t = c; t < r; ++t) v -= Ls[r][t] * x[t];
+      x[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 64; ++r) out[(int64_t)c * 64 + r] = x[r];
   }
 }
 
@@ -482,6 +595,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
   ctx->d_state.alloc((size_t)ctx->n_nodes * sizeof(NodeState));
   ctx->d_piv.alloc((size_t)n * sizeof(int32_t));
   ctx->d_swaps.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+  ctx->d_linv.alloc((size_t)std::max<int64_t>(ctx->linv_elems, 1) * sizeof(T));
   ctx->d_dval.alloc((size_t)n * sizeof(T));
   ctx->d_q.alloc((size_t)n * sizeof(double));
   ctx->d_kval.alloc((size_t)ctx->nnz * sizeof(double));
@@ -544,12 +658,13 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
       });
     }
     // F11 panels
+    constexpr int NBP = PanelWidth<T>::value;
     const int maxp = ctx->level_maxp[l];
-    const size_t shm = (size_t)std::max(maxp, 1) * sizeof(T);
-    for (int k0p = 0; k0p < maxp; k0p += PANEL_NB) {
+    const size_t shm = (size_t)std::max(maxp + 2, 2) * (sizeof(T) + sizeof(int32_t)) + 16;
+    for (int k0p = 0; k0p < maxp; k0p += NBP) {
       auto w1 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
         if (ni.p <= k0p) return;
-        const double r = ni.p - k0p, nb = std::min(PANEL_NB, ni.p - k0p);
+        const double r = ni.p - k0p, nb = std::min(NBP, ni.p - k0p);
         by += 2.0 * r * nb * sz;
         fl += nb * nb * r;
       });
@@ -559,23 +674,30 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
                                        ctx->opt.first_pivot_unit);
         if (k0p > 0) {
           dim3 gs(cdiv(k0p, 256), (unsigned)nl);
-          k_apply_swaps<T><<<gs, 256, 0, s>>>(lnodes, nodes, st, ctx->d_swaps.as<int32_t>(), front, k0p);
+          k_apply_swaps<T><<<gs, 256, 0, s>>>(lnodes, nodes, st, ctx->d_swaps.as<int32_t>(), front, k0p, NBP);
         }
       });
-      const int nr = maxp - (k0p + PANEL_NB);
+      const int nr = maxp - (k0p + NBP);
       if (nr > 0) {
         const int nt = (nr + 63) / 64;
         dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)nl);
         auto w2 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
-          const double r = ni.p - k0p - PANEL_NB;
+          const double r = ni.p - k0p - NBP;
           if (r <= 0) return;
-          by += (r * PANEL_NB + r * r) * sz;
-          fl += r * r * PANEL_NB;
+          by += (r * NBP + r * r) * sz;
+          fl += r * r * NBP;
         });
         timed(tm, HF_K_F11_UPDATE, w2.first, w2.second, s, [&] {
-          k_syrk<T><<<grid, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), 0, k0p);
+          k_syrk<T><<<grid, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), 0, k0p, NBP);
         });
       }
+    }
+    // inverses of the 64x64 diagonal blocks of the level's L11 (TRSM and sweeps)
+    if (maxp > 0) {
+      dim3 gi(cdiv(maxp, 64), (unsigned)nl);
+      timed(tm, HF_K_OTHER, 0.0, 0.0, s, [&] {
+        k_inv_diag<T><<<gi, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_linv_off.as<int64_t>(), ctx->d_linv.as<T>());
+      });
     }
     // F21, F22
     const int maxb = ctx->level_maxb[l];
@@ -587,7 +709,8 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         fl += b * p * p;
       });
       timed(tm, HF_K_TRSM, w3.first, w3.second, s, [&] {
-        k_trsm<T><<<g1, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>());
+        k_trsm<T><<<g1, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), ctx->d_linv_off.as<int64_t>(),
+                                     ctx->d_linv.as<T>());
       });
       const int nt = (maxb + 63) / 64;
       dim3 g2((unsigned)(nt * (nt + 1) / 2), (unsigned)nl);
@@ -597,7 +720,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         fl += b * b * p;
       });
       timed(tm, HF_K_SYRK, w4.first, w4.second, s, [&] {
-        k_syrk<T><<<g2, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), 1, 0);
+        k_syrk<T><<<g2, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), 1, 0, 0);
       });
     }
     HF_HIP(hipGetLastError());

@@ -189,6 +189,7 @@ struct hf_ctx {
   hf::DBuf d_linv, d_linv_off, d_blk_node, d_blk_first;  // inverses of 64x64 diagonal blocks
   hf::DBuf d_linv2, d_linv2_off, d_stp_node, d_stp_first;  // inverses of 256x256 step blocks
   hf::DBuf d_zb_arena;             // second solve arena (step results)
+  hf::DBuf d_part;                 // partial products of the backward border step
   hf::DBuf d_isl2, d_flag;         // uint8 mask [n], error flags
   int32_t factor_prec = 0;         // precision of d_front
   // hard part

@@ -29,53 +29,13 @@ namespace hf {
 constexpr int TB = 256;  // columns of L11 per sweep step
 constexpr int SB = 64;   // sub-block with an explicit inverse
 constexpr int KC = 32;   // k-chunk of the update products staged in LDS
+constexpr int RCH = 512; // border rows per partial product of the backward sweep
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
 // inverses of the 64x64 unit-lower diagonal blocks of every L11
 // ---------------------------------------------------------------------------
-
-template <class T>
-__global__ void __launch_bounds__(256)
-k_inv_diag(const int32_t* __restrict__ blk_node, const int32_t* __restrict__ blk_first,
-           const NodeInfo* __restrict__ nodes, const NodeState* __restrict__ st,
-           const T* __restrict__ front, const int64_t* __restrict__ linv_off, T* __restrict__ linv) {
-  const int bi = blockIdx.x;
-  const int j = blk_node[bi];
-  const int B = bi - blk_first[j];
-  const NodeInfo ni = nodes[j];
-  const int npiv = st[j].npiv;
-  const int J0 = B * SB;
-  if (J0 >= npiv) return;
-  const int nc = min(SB, npiv - J0);
-  const int64_t f = ni.f;
-  const T* F = front + ni.front_off;
-  __shared__ T Ls[SB][SB + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < SB * SB; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    T v = (r == c) ? (T)1 : (T)0;
-    if (r > c && r < nc) v = F[(int64_t)(J0 + c) * f + J0 + r];
-    Ls[r][c] = v;
-  }
-  __syncthreads();
-  T* out = linv + linv_off[j] + (int64_t)B * SB * SB;  // column-major 64x64
-  if (tid < SB) {
-    const int c = tid;
-    T x[SB];
-#pragma unroll
-    for (int r = 0; r < SB; ++r) x[r] = (T)0;
-    x[c] = (T)1;
-    for (int r = c + 1; r < SB; ++r) {
-      T v = (T)0;
-      for (int t = c; t < r; ++t) v -= Ls[r][t] * x[t];
-      x[r] = v;
-    }
-#pragma unroll
-    for (int r = 0; r < SB; ++r) out[(int64_t)c * SB + r] = x[r];
-  }
-}
 
 // ---------------------------------------------------------------------------
 // inverse of every 256x256 step block, assembled from the 64x64 inverses:
@@ -328,23 +288,27 @@ k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
 // backward sweep
 // ---------------------------------------------------------------------------
 
-// t_k = z_k / d_k - sum_r L21[r, k] x_border[r]   (64-column strips)
+// Partial products P_ch[k] = sum_{r in chunk ch} L21[r, k] x_border[r] over
+// chunks of RCH border rows (64-column strips x chunks x fronts); summed in a
+// fixed order by k_bwd_border_fin.
 template <class T>
 __global__ void __launch_bounds__(256)
-k_bwd_border(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-             const NodeState* __restrict__ st, const T* __restrict__ front, const T* __restrict__ dval,
-             const int32_t* __restrict__ border, int m, const double* __restrict__ Y,
-             const T* __restrict__ zb, T* __restrict__ rb) {
-  const int j = lnodes[blockIdx.y];
+k_bwd_border_part(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+                  const NodeState* __restrict__ st, const T* __restrict__ front,
+                  const int32_t* __restrict__ border, int m, const double* __restrict__ Y, int maxch, int maxp,
+                  T* __restrict__ part) {
+  const int q = blockIdx.z;
+  const int j = lnodes[q];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
   const int cs = blockIdx.x * 64;
-  if (cs >= npiv) return;
+  const int ch = blockIdx.y;
   const int p = ni.p, b = ni.b;
+  const int rlo = ch * RCH;
+  if (cs >= npiv || rlo >= b) return;
+  const int rhi = min(b, rlo + RCH);
   const int64_t lf = ni.f;
   const T* F = front + ni.front_off;
-  T* W = rb + ni.rhs_off * m;
-  const T* Z = zb + ni.rhs_off * m;
   __shared__ T Lt[KC][64 + 1];
   __shared__ T xs[KC * 64];
   const int tid = threadIdx.x;
@@ -352,9 +316,9 @@ k_bwd_border(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
   const int k = cs + kl;
   T a[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) a[q] = (T)0;
-  for (int r0 = 0; r0 < b; r0 += KC) {
-    const int rc = min(KC, b - r0);
+  for (int t = 0; t < 16; ++t) a[t] = (T)0;
+  for (int r0 = rlo; r0 < rhi; r0 += KC) {
+    const int rc = min(KC, rhi - r0);
     for (int e = tid; e < KC * 64; e += 256) {
       const int rr = e & (KC - 1), kk = e / KC;
       Lt[rr][kk] = (rr < rc && cs + kk < npiv) ? F[(int64_t)(cs + kk) * lf + p + r0 + rr] : (T)0;
@@ -365,24 +329,44 @@ k_bwd_border(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = cg + 4 * q;
+    for (int t = 0; t < 16; ++t) {
+      const int col = cg + 4 * t;
       if (col < m) {
-        T v = a[q];
+        T v = a[t];
         for (int rr = 0; rr < rc; ++rr) v += Lt[rr][kl] * xs[rr * m + col];
-        a[q] = v;
+        a[t] = v;
       }
     }
     __syncthreads();
   }
   if (k < npiv) {
-    const T dinv = (T)1 / dval[ni.start + k];
+    T* P = part + (((int64_t)q * maxch + ch) * maxp + k) * m;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = cg + 4 * q;
-      if (col < m) W[(int64_t)k * m + col] = Z[(int64_t)k * m + col] * dinv - a[q];
+    for (int t = 0; t < 16; ++t) {
+      const int col = cg + 4 * t;
+      if (col < m) P[col] = a[t];
     }
   }
+}
+
+// t_k = z_k / d_k - sum_ch P_ch[k]
+template <class T>
+__global__ void __launch_bounds__(256)
+k_bwd_border_fin(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+                 const NodeState* __restrict__ st, const T* __restrict__ dval, int m, int maxch, int maxp,
+                 const T* __restrict__ part, const T* __restrict__ zb, T* __restrict__ rb) {
+  const int q = blockIdx.y;
+  const int j = lnodes[q];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int k = (int)(e / m), col = (int)(e - (int64_t)k * m);
+  if (k >= npiv) return;
+  const int nch = (ni.b + RCH - 1) / RCH;
+  T acc = (T)0;
+  for (int ch = 0; ch < nch; ++ch) acc += part[(((int64_t)q * maxch + ch) * maxp + k) * m + col];
+  const int64_t o = (ni.rhs_off + k) * m + col;
+  rb[o] = zb[o] / dval[ni.start + k] - acc;
 }
 
 // x_J = Linv_J^T t_J (four workgroups of 64 columns), scattered to the FP64 result
@@ -501,13 +485,6 @@ k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
 
 template <class T>
 void prepare_solve(hf_ctx* ctx, hipStream_t s) {
-  const int64_t nb = (int64_t)ctx->blk_node.size();
-  ctx->d_linv.alloc((size_t)std::max<int64_t>(ctx->linv_elems, 1) * sizeof(T));
-  if (nb > 0)
-    k_inv_diag<T><<<(unsigned)nb, 256, 0, s>>>(ctx->d_blk_node.as<int32_t>(), ctx->d_blk_first.as<int32_t>(),
-                                               ctx->d_nodes.as<NodeInfo>(), ctx->d_state.as<NodeState>(),
-                                               ctx->d_front.as<T>(), ctx->d_linv_off.as<int64_t>(),
-                                               ctx->d_linv.as<T>());
   const int64_t ns = (int64_t)ctx->stp_node.size();
   ctx->d_linv2.alloc((size_t)std::max<int64_t>(ctx->linv2_elems, 1) * sizeof(T));
   if (ns > 0)
@@ -547,6 +524,15 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     }
     return std::make_pair(by, fl);
   };
+  {
+    size_t need = 1;
+    for (int l = 0; l < nlev; ++l) {
+      const size_t nl = ctx->level_ptr[l + 1] - ctx->level_ptr[l];
+      const size_t maxch = std::max<size_t>(1, cdiv(ctx->level_maxb[l], RCH));
+      need = std::max(need, nl * maxch * ctx->level_maxp[l] * m);
+    }
+    ctx->d_part.alloc(need * sizeof(T));
+  }
   HF_HIP(hipMemsetAsync(Y, 0, (size_t)ctx->n * m * sizeof(double), s));
   size_t ea = 0;
   for (int l = 0; l < nlev; ++l) {
@@ -608,14 +594,20 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     const int32_t* ln = lall + ctx->level_ptr[l];
     const int maxp = ctx->level_maxp[l];
     if (maxp == 0) continue;
-    dim3 gb(cdiv(maxp, 64), nl);
+    const int maxch = std::max(1, (int)cdiv(ctx->level_maxb[l], RCH));
+    T* part = ctx->d_part.as<T>();
     auto wb = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
       by += ni.b * np * sz + 2.0 * np * dm * sz + ni.b * dm * 8.0;
       fl += 2.0 * dm * ni.b * np;
     });
     timed(tm, HF_K_SOLVE_UPDATE, wb.first, wb.second, s, [&] {
-      k_bwd_border<T><<<gb, 256, 0, s>>>(ln, nodes, st, front, ctx->d_dval.as<T>(), ctx->d_border.as<int32_t>(), m,
-                                         Y, zb, rb);
+      if (ctx->level_maxb[l] > 0) {
+        dim3 gp(cdiv(maxp, 64), maxch, nl);
+        k_bwd_border_part<T><<<gp, 256, 0, s>>>(ln, nodes, st, front, ctx->d_border.as<int32_t>(), m, Y, maxch, maxp,
+                                                part);
+      }
+      dim3 gf(cdiv((int64_t)maxp * m, 256), nl);
+      k_bwd_border_fin<T><<<gf, 256, 0, s>>>(ln, nodes, st, ctx->d_dval.as<T>(), m, maxch, maxp, part, zb, rb);
     });
     for (int J0 = ((maxp - 1) / TB) * TB; J0 >= 0; J0 -= TB) {
       auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
