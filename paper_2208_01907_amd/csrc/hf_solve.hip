@@ -28,10 +28,69 @@ namespace hf {
 
 constexpr int TB = 256;  // columns of L11 per sweep step
 constexpr int SB = 64;   // sub-block with an explicit inverse
-constexpr int KC = 32;   // k-chunk of the update products staged in LDS
 constexpr int RCH = 512; // border rows per partial product of the backward sweep
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Staging for the 64 x (<= 64) matrix-core products of the sweeps: As[k][row]
+// holds A(row, k0 + k), Bs[k][col] holds B(k0 + k, col); 16 k per chunk.
+constexpr int MK = 16;
+constexpr int MLD = 68;
+
+// A(row, k) = src[k * ld + row]  (rows contiguous)
+template <class T>
+__device__ __forceinline__ void stage_a_rows(T (*As)[MLD], const T* src, int64_t ld, int k0, int kc, int nrows,
+                                             int tid) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    const int row = e & 63, kq = e >> 6;
+    As[kq][row] = (kq < kc && row < nrows) ? src[(int64_t)(k0 + kq) * ld + row] : (T)0;
+  }
+}
+
+// A(row, k) = src[row * ld + k]  (k contiguous)
+template <class T>
+__device__ __forceinline__ void stage_a_kcont(T (*As)[MLD], const T* src, int64_t ld, int k0, int kc, int nrows,
+                                              int tid) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    const int kq = e & 15, row = e >> 4;
+    As[kq][row] = (kq < kc && row < nrows) ? src[(int64_t)row * ld + k0 + kq] : (T)0;
+  }
+}
+
+// B(k, col) = V[(k0 + k) * m + col], zero beyond m columns
+template <class T>
+__device__ __forceinline__ void stage_b(T (*Bs)[MLD], const T* V, int m, int k0, int kc, int tid) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    const int col = e & 63, kq = e >> 6;
+    Bs[kq][col] = (kq < kc && col < m) ? V[(int64_t)(k0 + kq) * m + col] : (T)0;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void zero_acc(typename Mfma<T>::V acc[2][2]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::V{0, 0, 0, 0};
+}
+
+// visit every (row, col, value) of a 64x64 accumulator tile
+template <class T, class Fn>
+__device__ __forceinline__ void for_tile(const typename Mfma<T>::V acc[2][2], int lane, int wr, int wc, Fn&& fn) {
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        fn(wr + bi * 16 + Mfma<T>::row(lane, t), wc + bj * 16 + (lane & 15), acc[bi][bj][t]);
+}
 
 // ---------------------------------------------------------------------------
 // inverses of the 64x64 unit-lower diagonal blocks of every L11
@@ -177,7 +236,7 @@ k_fwd_addchild(const int32_t* __restrict__ items, const NodeInfo* __restrict__ n
   rb[(pn.rhs_off + pr) * m + col] += rb[(cn.rhs_off + cn.p) * m + e];
 }
 
-// z_J = Linv_J w_J; four workgroups (64 rows each) per front
+// z_J = Linv_J w_J; four workgroups (64 rows each) per front, matrix cores
 template <class T>
 __global__ void __launch_bounds__(256)
 k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
@@ -190,44 +249,28 @@ k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   const int nc = min(TB, npiv - J0);
   const int I = blockIdx.x;
   if (SB * I >= nc) return;
-  const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB;
+  const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB + SB * I;
   const T* W = rb + (ni.rhs_off + J0) * m;
-  __shared__ T Xs[KC][64 + 1];
-  __shared__ T ws[KC * 64];
-  const int tid = threadIdx.x;
-  const int row = tid & 63, cg = tid >> 6;
-  T a[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) a[q] = (T)0;
+  __shared__ T As[MK][MLD];
+  __shared__ T Bs[MK][MLD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int nrows = min(SB, nc - SB * I);
+  typename Mfma<T>::V acc[2][2];
+  zero_acc<T>(acc);
   const int cend = min(nc, SB * I + SB);
-  for (int c0 = 0; c0 < cend; c0 += KC) {
-    const int kc = min(KC, cend - c0);
-    for (int e = tid; e < KC * 64; e += 256) {
-      const int rr = e & 63, kk = e >> 6;
-      Xs[kk][rr] = (kk < kc) ? X[(int64_t)(c0 + kk) * TB + SB * I + rr] : (T)0;
-    }
-    for (int e = tid; e < kc * m; e += 256) ws[e] = W[(int64_t)c0 * m + e];
+  for (int k0 = 0; k0 < cend; k0 += MK) {
+    const int kc = min(MK, cend - k0);
+    stage_a_rows<T>(As, X, TB, k0, kc, nrows, tid);
+    stage_b<T>(Bs, W, m, k0, kc, tid);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = cg + 4 * q;
-      if (col < m) {
-        T v = a[q];
-        for (int kk = 0; kk < kc; ++kk) v += Xs[kk][row] * ws[kk * m + col];
-        a[q] = v;
-      }
-    }
+    mfma_tile_64<T, MK, MLD>(As, Bs, acc, lane, wr, wc);
     __syncthreads();
   }
-  const int r = SB * I + row;
-  if (r < nc) {
-    T* Z = zb + (ni.rhs_off + J0 + r) * m;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = cg + 4 * q;
-      if (col < m) Z[col] = a[q];
-    }
-  }
+  T* Z = zb + (ni.rhs_off + J0 + SB * I) * m;
+  for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
+    if (r < nrows && c < m) Z[(int64_t)r * m + c] = v;
+  });
 }
 
 // w_rows -= L[rows, J0:J0+nc] z_J for the rows below the step, 64-row strips
@@ -245,43 +288,28 @@ k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
   const int rs = J0 + nc + blockIdx.x * 64;
   if (rs >= f) return;
   const int64_t lf = f;
-  const T* F = front + ni.front_off;
-  T* W = rb + ni.rhs_off * m;
-  const T* Z = zb + ni.rhs_off * m;
-  __shared__ T Lt[KC][64 + 1];
-  __shared__ T zs[KC * 64];
-  const int tid = threadIdx.x;
-  const int row = tid & 63, cg = tid >> 6;
-  const int r = rs + row;
-  T a[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) a[q] = (T)0;
-  for (int k0 = 0; k0 < nc; k0 += KC) {
-    const int kc = min(KC, nc - k0);
-    for (int e = tid; e < KC * 64; e += 256) {
-      const int rr = e & 63, kk = e >> 6;
-      Lt[kk][rr] = (kk < kc && rs + rr < f) ? F[(int64_t)(J0 + k0 + kk) * lf + rs + rr] : (T)0;
-    }
-    for (int e = tid; e < kc * m; e += 256) zs[e] = Z[(int64_t)(J0 + k0) * m + e];
+  const T* A = front + ni.front_off + (int64_t)J0 * lf + rs;
+  const T* Z = zb + (ni.rhs_off + J0) * m;
+  T* W = rb + (ni.rhs_off + rs) * m;
+  __shared__ T As[MK][MLD];
+  __shared__ T Bs[MK][MLD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int nrows = min(64, f - rs);
+  typename Mfma<T>::V acc[2][2];
+  zero_acc<T>(acc);
+  for (int k0 = 0; k0 < nc; k0 += MK) {
+    const int kc = min(MK, nc - k0);
+    stage_a_rows<T>(As, A, lf, k0, kc, nrows, tid);
+    stage_b<T>(Bs, Z, m, k0, kc, tid);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = cg + 4 * q;
-      if (col < m) {
-        T v = a[q];
-        for (int kk = 0; kk < kc; ++kk) v += Lt[kk][row] * zs[kk * m + col];
-        a[q] = v;
-      }
-    }
+    mfma_tile_64<T, MK, MLD>(As, Bs, acc, lane, wr, wc);
     __syncthreads();
   }
-  if (r < f && !(r >= npiv && r < p)) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = cg + 4 * q;
-      if (col < m) W[(int64_t)r * m + col] -= a[q];
-    }
-  }
+  for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
+    const int gr = rs + r;
+    if (r < nrows && c < m && !(gr >= npiv && gr < p)) W[(int64_t)r * m + c] -= v;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -308,45 +336,32 @@ k_bwd_border_part(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict
   if (cs >= npiv || rlo >= b) return;
   const int rhi = min(b, rlo + RCH);
   const int64_t lf = ni.f;
-  const T* F = front + ni.front_off;
-  __shared__ T Lt[KC][64 + 1];
-  __shared__ T xs[KC * 64];
-  const int tid = threadIdx.x;
-  const int kl = tid & 63, cg = tid >> 6;
-  const int k = cs + kl;
-  T a[16];
+  const T* A = front + ni.front_off + (int64_t)cs * lf + p;  // A(k, r) = L21[r, cs + k]
+  const int32_t* bord = border + ni.border_off;
+  __shared__ T As[MK][MLD];
+  __shared__ T Bs[MK][MLD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int nrows = min(64, npiv - cs);
+  typename Mfma<T>::V acc[2][2];
+  zero_acc<T>(acc);
+  for (int r0 = rlo; r0 < rhi; r0 += MK) {
+    const int kc = min(MK, rhi - r0);
+    stage_a_kcont<T>(As, A, lf, r0, kc, nrows, tid);
 #pragma unroll
-  for (int t = 0; t < 16; ++t) a[t] = (T)0;
-  for (int r0 = rlo; r0 < rhi; r0 += KC) {
-    const int rc = min(KC, rhi - r0);
-    for (int e = tid; e < KC * 64; e += 256) {
-      const int rr = e & (KC - 1), kk = e / KC;
-      Lt[rr][kk] = (rr < rc && cs + kk < npiv) ? F[(int64_t)(cs + kk) * lf + p + r0 + rr] : (T)0;
-    }
-    for (int e = tid; e < rc * m; e += 256) {
-      const int rr = e / m, col = e - rr * m;
-      xs[e] = (T)Y[(int64_t)border[ni.border_off + r0 + rr] * m + col];
+    for (int qq = 0; qq < 4; ++qq) {
+      const int e = tid + 256 * qq;
+      const int col = e & 63, kq = e >> 6;
+      Bs[kq][col] = (kq < kc && col < m) ? (T)Y[(int64_t)bord[r0 + kq] * m + col] : (T)0;
     }
     __syncthreads();
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int col = cg + 4 * t;
-      if (col < m) {
-        T v = a[t];
-        for (int rr = 0; rr < rc; ++rr) v += Lt[rr][kl] * xs[rr * m + col];
-        a[t] = v;
-      }
-    }
+    mfma_tile_64<T, MK, MLD>(As, Bs, acc, lane, wr, wc);
     __syncthreads();
   }
-  if (k < npiv) {
-    T* P = part + (((int64_t)q * maxch + ch) * maxp + k) * m;
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int col = cg + 4 * t;
-      if (col < m) P[col] = a[t];
-    }
-  }
+  T* P = part + (((int64_t)q * maxch + ch) * maxp + cs) * m;
+  for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
+    if (r < nrows && c < m) P[(int64_t)r * m + c] = v;
+  });
 }
 
 // t_k = z_k / d_k - sum_ch P_ch[k]
@@ -383,47 +398,30 @@ k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   const int nc = min(TB, npiv - J0);
   const int I = blockIdx.x;
   if (SB * I >= nc) return;
-  const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB;
+  const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB + (int64_t)SB * I * TB;  // A(c, r) = X[c*TB + r]
   const T* W = rb + (ni.rhs_off + J0) * m;
-  __shared__ T Xs[KC][64 + 1];
-  __shared__ T ts[KC * 64];
-  const int tid = threadIdx.x;
-  const int cl = tid & 63, cg = tid >> 6;
-  T a[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) a[q] = (T)0;
-  for (int r0 = SB * I; r0 < nc; r0 += KC) {
-    const int kc = min(KC, nc - r0);
-    for (int e = tid; e < KC * 64; e += 256) {
-      const int rr = e & (KC - 1), cc = e / KC;
-      Xs[rr][cc] = (rr < kc) ? X[(int64_t)(SB * I + cc) * TB + r0 + rr] : (T)0;
-    }
-    for (int e = tid; e < kc * m; e += 256) ts[e] = W[(int64_t)r0 * m + e];
+  __shared__ T As[MK][MLD];
+  __shared__ T Bs[MK][MLD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int nrows = min(SB, nc - SB * I);
+  typename Mfma<T>::V acc[2][2];
+  zero_acc<T>(acc);
+  for (int r0 = SB * I; r0 < nc; r0 += MK) {
+    const int kc = min(MK, nc - r0);
+    stage_a_kcont<T>(As, X, TB, r0, kc, nrows, tid);
+    stage_b<T>(Bs, W, m, r0, kc, tid);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = cg + 4 * q;
-      if (col < m) {
-        T v = a[q];
-        for (int rr = 0; rr < kc; ++rr) v += Xs[rr][cl] * ts[rr * m + col];
-        a[q] = v;
-      }
-    }
+    mfma_tile_64<T, MK, MLD>(As, Bs, acc, lane, wr, wc);
     __syncthreads();
   }
-  const int c = SB * I + cl;
-  if (c < nc) {
-    T* Zr = zb + (ni.rhs_off + J0 + c) * m;
-    double* Yr = Y + (int64_t)piv[ni.start + J0 + c] * m;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = cg + 4 * q;
-      if (col < m) {
-        Zr[col] = a[q];
-        Yr[col] = (double)a[q];
-      }
+  const int c0 = J0 + SB * I;
+  for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
+    if (r < nrows && c < m) {
+      zb[(ni.rhs_off + c0 + r) * m + c] = v;
+      Y[(int64_t)piv[ni.start + c0 + r] * m + c] = (double)v;
     }
-  }
+  });
 }
 
 // t_k -= sum_{r in step} L[r, k] x_r for the columns k < J0 (64-column strips)
@@ -440,43 +438,27 @@ k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
   if (cs >= J0) return;
   const int nc = min(TB, npiv - J0);
   const int64_t lf = ni.f;
-  const T* F = front + ni.front_off;
-  T* W = rb + ni.rhs_off * m;
-  const T* Z = zb + ni.rhs_off * m;
-  __shared__ T Lt[KC][64 + 1];
-  __shared__ T xs[KC * 64];
-  const int tid = threadIdx.x;
-  const int kl = tid & 63, cg = tid >> 6;
-  T a[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) a[q] = (T)0;
-  for (int r0 = 0; r0 < nc; r0 += KC) {
-    const int rc = min(KC, nc - r0);
-    for (int e = tid; e < KC * 64; e += 256) {
-      const int rr = e & (KC - 1), kk = e / KC;
-      Lt[rr][kk] = (rr < rc && cs + kk < J0) ? F[(int64_t)(cs + kk) * lf + J0 + r0 + rr] : (T)0;
-    }
-    for (int e = tid; e < rc * m; e += 256) xs[e] = Z[(int64_t)(J0 + r0) * m + e];
+  const T* A = front + ni.front_off + (int64_t)cs * lf + J0;  // A(k, r) = L[J0 + r, cs + k]
+  const T* Z = zb + (ni.rhs_off + J0) * m;
+  T* W = rb + (ni.rhs_off + cs) * m;
+  __shared__ T As[MK][MLD];
+  __shared__ T Bs[MK][MLD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int nrows = min(64, J0 - cs);
+  typename Mfma<T>::V acc[2][2];
+  zero_acc<T>(acc);
+  for (int r0 = 0; r0 < nc; r0 += MK) {
+    const int kc = min(MK, nc - r0);
+    stage_a_kcont<T>(As, A, lf, r0, kc, nrows, tid);
+    stage_b<T>(Bs, Z, m, r0, kc, tid);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = cg + 4 * q;
-      if (col < m) {
-        T v = a[q];
-        for (int rr = 0; rr < rc; ++rr) v += Lt[rr][kl] * xs[rr * m + col];
-        a[q] = v;
-      }
-    }
+    mfma_tile_64<T, MK, MLD>(As, Bs, acc, lane, wr, wc);
     __syncthreads();
   }
-  const int k = cs + kl;
-  if (k < J0) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = cg + 4 * q;
-      if (col < m) W[(int64_t)k * m + col] -= a[q];
-    }
-  }
+  for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
+    if (r < nrows && c < m) W[(int64_t)r * m + c] -= v;
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -500,6 +482,7 @@ void prepare_solve(hf_ctx* ctx, hipStream_t s) {
 
 template <class T>
 void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s) {
+  if (m < 1 || m > 64) throw Status{HF_ERR_ARG};  // the sweep tiles hold at most 64 columns
   const int nlev = (int)ctx->level_ptr.size() - 1;
   const size_t arena = (size_t)std::max<int64_t>(ctx->rhs_rows, 1) * m * sizeof(T);
   ctx->d_rhs_arena.alloc(arena);
