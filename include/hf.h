@@ -120,7 +120,9 @@ void hf_default_options(hf_options* opt);
  * With node_ptr_host == NULL and parent_host == NULL the whole matrix is one
  * node (a dense front); usable only for small n.
  * Errors: HF_ERR_ARG, HF_ERR_PATTERN (includes couplings between sibling
- * subtrees), HF_ERR_OOM, HF_ERR_HIP.
+ * subtrees), HF_ERR_NOT_IMPLEMENTED (a node of more than 4096 indices, a front
+ * of 2^31 or more entries, or more than 2^31 border entries in total),
+ * HF_ERR_OOM, HF_ERR_HIP.
  */
 int hf_analyse(int64_t n, const int64_t* indptr_host, const int32_t* indices_host,
                const int32_t* perm_host, int32_t n_nodes, const int32_t* node_ptr_host,

@@ -192,6 +192,7 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
       ni.p = np[j + 1] - np[j];
       ni.b = (int32_t)(ctx->border_ptr[j + 1] - ctx->border_ptr[j]);
       ni.f = ni.p + ni.b;
+      if ((int64_t)ni.f * ni.f >= ((int64_t)1 << 31)) { delete ctx; return HF_ERR_NOT_IMPLEMENTED; }  // 32-bit front offsets
       ni.parent = par[j];
       ni.child_begin = cptr[j];
       ni.child_end = cptr[j + 1];

@@ -100,7 +100,7 @@ __device__ inline void argmax_combine(T& bv, int& bid, int& bk, T v, int id, int
   if (v > bv || (v == bv && id < bid)) { bv = v; bid = id; bk = k; }
 }
 
-constexpr int PT = 1024;              // threads of the panel kernel
+constexpr int PT = 512;               // threads of the panel kernel (2 waves per SIMD: 256 VGPRs each)
 constexpr int PROWS = 4096 / PT;      // pivot-block rows per thread (nodes hold at most 4096 indices)
 
 // Panel width: the panel's L values of every pivot-block row stay in registers.
@@ -129,7 +129,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   const NodeState s0 = st[j];
   if (s0.done || k0p >= ni.p) return;
   const int p = ni.p;
-  const int64_t f = ni.f;
+  const uint32_t f = (uint32_t)ni.f;  // fronts hold fewer than 2^31 entries (checked at analysis)
   T* F = front + ni.front_off;
   int32_t* idx_g = piv + ni.start;
   int32_t* sw = swaps + ni.start;
@@ -150,7 +150,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
 #pragma unroll
     for (int c = 0; c < NB; ++c) Lp[s][c] = (T)0;
   for (int q = tid; q < P; q += PT) {
-    dg[q] = F[(int64_t)(k0p + q) * f + k0p + q];
+    dg[q] = F[(uint32_t)(k0p + q) * f + k0p + q];
     idx[q] = idx_g[k0p + q];
   }
   double dprev = s0.dprev;
@@ -236,7 +236,23 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     for (int c = 0; c < NB; ++c) u[c] = (c < qi) ? Dl[c] * bufK[c] : (T)0;
     const int k = k0p + qk;
     const T inv = (T)1 / d;
-    // pivot-block rows below the pivot: exchange + new column + eager diagonal
+    // pivot-block rows below the pivot: exchange + new column + eager diagonal.
+    // All loads of the pivot are issued before its first store (one memory
+    // round trip per pivot).  The border rows are not exchanged here: they stay
+    // in assembly order until the node is finished (k_gather_border).
+    T vo[PROWS], vn[PROWS];
+#pragma unroll
+    for (int s = 0; s < PROWS; ++s) {
+      const int q = tid + PT * s;
+      const int r = k0p + q;
+      vo[s] = (T)0;
+      vn[s] = (T)0;
+      if (q > qi && q < P) {
+        vo[s] = F[(uint32_t)i * f + r];
+        if (r > k) vn[s] = F[(uint32_t)k * f + r];
+        else if (r < k) vn[s] = F[(uint32_t)r * f + k];
+      }
+    }
 #pragma unroll
     for (int s = 0; s < PROWS; ++s) {
       const int q = tid + PT * s;
@@ -244,36 +260,28 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
       if (q > qi && q < P) {
         T vnew;
         if (r > k) {
-          const T oi = F[(int64_t)i * f + r], ok2 = F[(int64_t)k * f + r];
-          vnew = ok2;
-          F[(int64_t)k * f + r] = oi;
+          vnew = vn[s];
+          F[(uint32_t)k * f + r] = vo[s];
         } else if (r < k) {
-          const T oi = F[(int64_t)i * f + r], ok2 = F[(int64_t)r * f + k];
-          vnew = ok2;
-          F[(int64_t)r * f + k] = oi;
+          vnew = vn[s];
+          F[(uint32_t)r * f + k] = vo[s];
         } else {
-          vnew = F[(int64_t)i * f + r];  // F[k, i] is not moved by the exchange
+          vnew = vo[s];  // F[k, i] is not moved by the exchange
         }
         T v = vnew;
 #pragma unroll
         for (int c = 0; c < NB; ++c) v -= Lp[s][c] * u[c];
         const T l = v * inv;
-        F[(int64_t)i * f + r] = l;
+        F[(uint32_t)i * f + r] = l;
         dg[q] -= l * v;
 #pragma unroll
         for (int c = 0; c < NB; ++c)
           if (c == qi) Lp[s][c] = l;
       }
     }
-    // border rows: exchange only (their L values come from the TRSM)
-    for (int64_t r = p + tid; r < f; r += PT) {
-      const T oi = F[(int64_t)i * f + r];
-      F[(int64_t)i * f + r] = F[(int64_t)k * f + r];
-      F[(int64_t)k * f + r] = oi;
-    }
     if (tid == 0) {
-      if (qk != qi) F[(int64_t)k * f + k] = F[(int64_t)i * f + i];
-      F[(int64_t)i * f + i] = d;
+      if (qk != qi) F[(uint32_t)k * f + k] = F[(uint32_t)i * f + i];
+      F[(uint32_t)i * f + i] = d;
     }
     dprev = dk;
     have_prev = 1;
@@ -289,7 +297,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     if (q < P) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        if (c < nacc && c < q) F[(int64_t)(k0p + c) * f + k0p + q] = Lp[s][c];
+        if (c < nacc && c < q) F[(uint32_t)(k0p + c) * f + k0p + q] = Lp[s][c];
       idx_g[k0p + q] = idx[q];
     }
   }
@@ -413,6 +421,43 @@ k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
 // F3: L21 = F21 L11^{-T} D^{-1}, one workgroup per 64-row strip of F21
 // ---------------------------------------------------------------------------
 
+// The panels leave the border rows of a front in assembly order.  Once the
+// node's pivots are final, the border block is gathered in pivot order and
+// transposed into the unused upper block of the front:
+// G(c, r) = F[(p + r) * f + c] = F21[r, pi(c)], pi(c) the assembly position
+// of the index pivoted at c.  The TRSM reads its right-hand side from G.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_gather_border(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+                const NodeState* __restrict__ st, const int32_t* __restrict__ piv, T* __restrict__ front) {
+  const int j = lnodes[blockIdx.z];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  if (c0 >= npiv || r0 >= ni.b) return;
+  const int64_t f = ni.f;
+  T* F = front + ni.front_off;
+  __shared__ T tile[64][65];
+  const int tid = threadIdx.x;
+  const int lr = tid & 63;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int lc = (tid >> 6) + 4 * q;
+    const int c = c0 + lc, r = r0 + lr;
+    if (c < npiv && r < ni.b) {
+      const int src = piv[ni.start + c] - ni.start;
+      tile[lc][lr] = F[(int64_t)src * f + ni.p + r];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int lrr = (tid >> 6) + 4 * q, lcc = tid & 63;
+    const int c = c0 + lcc, r = r0 + lrr;
+    if (c < npiv && r < ni.b) F[(int64_t)(ni.p + r) * f + c] = tile[lcc][lrr];
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(256)
 k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
@@ -427,6 +472,7 @@ k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
   const int64_t f = ni.f;
   T* F = front + ni.front_off;
   T* X = F + ni.p + rs;  // X(r, c) = X[c*f + r], r < 64
+  const T* G = F + (int64_t)(ni.p + rs) * f;  // right-hand side in pivot order: G(c, r) = G[r*f + c]
   const int nrow = min(64, b - rs);
   const T* Dk = dval + ni.start;
   const T* L64 = linv + linv_off[j];
@@ -467,7 +513,7 @@ k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
         for (int t = 0; t < 4; ++t) {
           const int r = wr + bi * 16 + Mfma<T>::row(lane, t);
           const int c = wc + bj * 16 + (lane & 15);
-          Yt[c][r] = (r < nrow && c < nc) ? X[(int64_t)(J0 + c) * f + r] - acc[bi][bj][t] : (T)0;
+          Yt[c][r] = (r < nrow && c < nc) ? G[(int64_t)r * f + J0 + c] - acc[bi][bj][t] : (T)0;
         }
     __syncthreads();
     // X_J = Y Linv_JJ^T: X[r][c] = sum_k Y[r][k] Linv[c][k]
@@ -705,10 +751,12 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
       dim3 g1(cdiv(maxb, 64), (unsigned)nl);
       auto w3 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
         const double b = ni.b, p = ni.p;
-        by += (2.0 * b * p + 0.5 * p * p) * sz;
+        by += (2.0 * b * p + 0.5 * p * p) * sz;  // gather + TRSM: F21 read once, L21 written once
         fl += b * p * p;
       });
       timed(tm, HF_K_TRSM, w3.first, w3.second, s, [&] {
+        dim3 gg(cdiv(maxp, 64), cdiv(maxb, 64), (unsigned)nl);
+        k_gather_border<T><<<gg, 256, 0, s>>>(lnodes, nodes, st, ctx->d_piv.as<int32_t>(), front);
         k_trsm<T><<<g1, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), ctx->d_linv_off.as<int64_t>(),
                                      ctx->d_linv.as<T>());
       });
