@@ -190,25 +190,33 @@ int hf_scaling(const hf_ctx* ctx, double* q_dev, void* stream);
 int hf_info(const hf_ctx* ctx, hf_info_t* info_host);
 
 /*
- * Per-kernel-class timing (measurement support).  When enabled, every launch of
- * an instrumented kernel is bracketed by HIP events on the caller's stream; the
+ * Per-kernel-class timing (measurement support).  Every class but
+ * HF_K_SOLVE_GATHER and HF_K_OTHER holds the launches of one kernel.  When
+ * enabled, every launch of an instrumented kernel is bracketed by HIP events on
+ * the caller's stream; the
  * elapsed times are accumulated at the end of each hf_factorize / hf_solve,
  * together with the algorithmic bytes and flops of each launch (computed on the
  * host from the sizes of the fronts involved).  Enabling resets the counters.
  */
 enum {
-  HF_K_PANEL = 0,        /* pivot search + panel of F11 (serial pivot chain) */
-  HF_K_F11_UPDATE = 1,   /* trailing update of F11 after each panel */
-  HF_K_TRSM = 2,         /* L21 = F21 L11^{-T} D^{-1} */
-  HF_K_SYRK = 3,         /* contribution block F22 -= L21 D L21^T */
-  HF_K_EXTEND_ADD = 4,   /* assembly of the children's contribution blocks */
-  HF_K_SOLVE_DIAG = 5,   /* diagonal-block steps of the triangular sweeps */
-  HF_K_SOLVE_UPDATE = 6, /* off-diagonal products of the triangular sweeps */
-  HF_K_SOLVE_GATHER = 7, /* gathers / extend-adds of the triangular sweeps */
-  HF_K_SPMM = 8,         /* FP64 CSR products with K */
-  HF_K_GRAM = 9,         /* FP64 Gram products of block GCR */
-  HF_K_OTHER = 10,       /* everything else */
-  HF_K_NCLASS = 11
+  HF_K_PANEL = 0,         /* k_panel: pivot search + panel of F11 (serial pivot chain) */
+  HF_K_SWAPS = 1,         /* k_apply_swaps: panel exchanges applied to earlier columns */
+  HF_K_F11_UPDATE = 2,    /* k_syrk: trailing update of F11 after each panel */
+  HF_K_GATHER_BORDER = 3, /* k_gather_border: F21 in pivot order before the TRSM */
+  HF_K_TRSM = 4,          /* k_trsm: L21 = F21 L11^{-T} D^{-1} */
+  HF_K_SYRK = 5,          /* k_syrk: contribution block F22 -= L21 D L21^T */
+  HF_K_EXTEND_ADD = 6,    /* k_extend_add: the children's contribution blocks */
+  HF_K_FWD_DIAG = 7,      /* k_fwd_diag: diagonal steps of the forward sweep */
+  HF_K_FWD_UPDATE = 8,    /* k_fwd_upd: off-diagonal products of the forward sweep */
+  HF_K_BWD_BORDER = 9,    /* k_bwd_border_part: border products of the backward sweep */
+  HF_K_BWD_DIAG = 10,     /* k_bwd_diag: diagonal steps of the backward sweep */
+  HF_K_BWD_UPDATE = 11,   /* k_bwd_upd: off-diagonal products of the backward sweep */
+  HF_K_SOLVE_GATHER = 12, /* gathers / extend-adds / border sums of the sweeps */
+  HF_K_SPMM = 13,         /* k_spmm_k11: FP64 CSR products with K */
+  HF_K_GRAM = 14,         /* k_gram_partial: FP64 Gram products of block GCR */
+  HF_K_COMBINE = 15,      /* k_combine: FP64 block updates X += P C of block GCR */
+  HF_K_OTHER = 16,        /* everything else */
+  HF_K_NCLASS = 17
 };
 
 typedef struct hf_kstat_t {

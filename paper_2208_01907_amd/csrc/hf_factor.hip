@@ -718,11 +718,16 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         k_panel<T><<<nl, PT, shm, s>>>(lnodes, nodes, st, front, ctx->d_piv.as<int32_t>(),
                                        ctx->d_swaps.as<int32_t>(), ctx->d_dval.as<T>(), k0p, ctx->opt.tau,
                                        ctx->opt.first_pivot_unit);
-        if (k0p > 0) {
+      });
+      if (k0p > 0) {
+        auto ws = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
+          if (ni.p > k0p) by += 4.0 * k0p * std::min(NBP, ni.p - k0p) * sz;  // two entries exchanged per swap
+        });
+        timed(tm, HF_K_SWAPS, ws.first, 0.0, s, [&] {
           dim3 gs(cdiv(k0p, 256), (unsigned)nl);
           k_apply_swaps<T><<<gs, 256, 0, s>>>(lnodes, nodes, st, ctx->d_swaps.as<int32_t>(), front, k0p, NBP);
-        }
-      });
+        });
+      }
       const int nr = maxp - (k0p + NBP);
       if (nr > 0) {
         const int nt = (nr + 63) / 64;
@@ -751,12 +756,15 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
       dim3 g1(cdiv(maxb, 64), (unsigned)nl);
       auto w3 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
         const double b = ni.b, p = ni.p;
-        by += (2.0 * b * p + 0.5 * p * p) * sz;  // gather + TRSM: F21 read once, L21 written once
+        by += (2.0 * b * p + 0.5 * p * p) * sz;  // F21 read, L21 written, L11 read
         fl += b * p * p;
       });
-      timed(tm, HF_K_TRSM, w3.first, w3.second, s, [&] {
+      auto wg = level_sum([&](const NodeInfo& ni, double& by, double& fl) { by += 2.0 * ni.b * ni.p * sz; });
+      timed(tm, HF_K_GATHER_BORDER, wg.first, 0.0, s, [&] {
         dim3 gg(cdiv(maxp, 64), cdiv(maxb, 64), (unsigned)nl);
         k_gather_border<T><<<gg, 256, 0, s>>>(lnodes, nodes, st, ctx->d_piv.as<int32_t>(), front);
+      });
+      timed(tm, HF_K_TRSM, w3.first, w3.second, s, [&] {
         k_trsm<T><<<g1, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), ctx->d_linv_off.as<int64_t>(),
                                      ctx->d_linv.as<T>());
       });

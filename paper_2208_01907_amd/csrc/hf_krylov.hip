@@ -674,6 +674,8 @@ static void gram(hf_ctx* ctx, int64_t n, int a, const double* A, int64_t sA, int
   const double by = (double)n * (a * (double)nA + b) * 8.0, fl = 2.0 * n * a * b * (double)nA;
   timed(ctx->timer, HF_K_GRAM, by, fl, s, [&] {
     k_gram_partial<<<grid, 256, 0, s>>>(n, a, A, sA, b, B, w.partial.as<double>());
+  });
+  timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, [&] {
     k_gram_reduce<<<cdiv((int64_t)nA * a * b, 256), 256, 0, s>>>(nA, a * b, w.partial.as<double>(), C);
   });
 }
@@ -685,6 +687,17 @@ static void spmm_k11(hf_ctx* ctx, int m, const double* W, double* Y, hipStream_t
   timed(ctx->timer, HF_K_SPMM, by, fl, s, [&] {
     k_spmm_k11<<<cdiv(nm, 256), 256, 0, s>>>(ctx->n, ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(),
                                              ctx->d_kval.as<double>(), ctx->d_isl2.as<uint8_t>(), m, W, Y);
+  });
+}
+
+// out (n x b) = base + sum_t V_t (n x a) C_t (a x b), row-major blocks
+static void combine(hf_ctx* ctx, int64_t n, int a, int b, double* out, const double* base, int nterms,
+                    const double* V, int64_t sV, const double* coef, hipStream_t s) {
+  if (n * b == 0) return;
+  const double by = ((double)nterms * n * a + (base ? 2.0 : 1.0) * n * b) * 8.0;
+  const double fl = 2.0 * n * a * b * (double)nterms;
+  timed(ctx->timer, HF_K_COMBINE, by, fl, s, [&] {
+    k_combine<<<cdiv(n * b, 256), 256, 0, s>>>(n, a, b, out, base, nterms, V, sV, coef);
   });
 }
 
@@ -747,9 +760,9 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, hipStream_t s) {
     gram(ctx, n, m, Qn, 0, 1, m, R, G, s);
     k_chol_solve<<<1, 64, 0, s>>>(m, m, Lc + (int64_t)it * m * m, piv + (int64_t)it * m, rank + it, G, 0,
                                   coef, 0, 1.0);
-    k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, m, m, X, X, 1, Pn, 0, coef);
+    combine(ctx, n, m, m, X, X, 1, Pn, 0, coef, s);
     k_neg<<<cdiv((int64_t)m * m, 256), 256, 0, s>>>((int64_t)m * m, coef);
-    k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, m, m, R, R, 1, Qn, 0, coef);
+    combine(ctx, n, m, m, R, R, 1, Qn, 0, coef, s);
     HF_HIP(hipGetLastError());
     if (converged(R)) return it + 1;
     if (it + 1 >= maxit) break;
@@ -764,8 +777,8 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, hipStream_t s) {
     for (int q = 0; q < nb; ++q)
       k_chol_solve<<<1, 64, 0, s>>>(m, m, Lc + (int64_t)q * m * m, piv + (int64_t)q * m, rank + q,
                                     G + (int64_t)q * m * m, 0, coef + (int64_t)q * m * m, 0, -1.0);
-    k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, m, m, Pn1, Pn1, nb, P, sv, coef);
-    k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, m, m, Qn1, Qn1, nb, Qv, sv, coef);
+    combine(ctx, n, m, m, Pn1, Pn1, nb, P, sv, coef, s);
+    combine(ctx, n, m, m, Qn1, Qn1, nb, Qv, sv, coef, s);
     gram(ctx, n, m, Qn1, 0, 1, m, Qn1, G, s);
     k_chol_piv<<<1, 64, 0, s>>>(m, G, 0, Lc + (int64_t)(it + 1) * m * m, piv + (int64_t)(it + 1) * m,
                                 rank + it + 1, rel);
@@ -879,7 +892,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
       HF_HIP(hipMemsetAsync(N2, 0, (size_t)rows * k * sizeof(double), s));
       k_s22_null<<<1, 64, 0, s>>>(M, k, Lw, sperm, N2);
       double* Nperm = w.T1.as<double>();
-      k_combine<<<cdiv(n * k, 256), 256, 0, s>>>(n, mb, k, Nperm, nullptr, ctx->nblk, X12, (int64_t)n * mb, N2);
+      combine(ctx, n, mb, k, Nperm, nullptr, ctx->nblk, X12, (int64_t)n * mb, N2, s);
       k_neg<<<cdiv(n * k, 256), 256, 0, s>>>(n * k, Nperm);
       k_set_rows<<<cdiv((int64_t)M * k, 256), 256, 0, s>>>(M, k, ctx->d_l2.as<int32_t>(), N2, Nperm);
       ctx->d_kern.alloc((size_t)n * k * sizeof(double));
@@ -894,7 +907,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
         double* dst = pass == 0 ? N : tmp;
         gram(ctx, n, k, src, 0, 1, k, src, G, s);
         k_chol_inv<<<1, 1, 0, s>>>(k, G, Ri);
-        k_combine<<<cdiv(n * k, 256), 256, 0, s>>>(n, k, k, dst, nullptr, 1, src, 0, Ri);
+        combine(ctx, n, k, k, dst, nullptr, 1, src, 0, Ri, s);
       }
       HF_HIP(hipMemcpyAsync(N, tmp, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
@@ -940,8 +953,8 @@ static int solve_core(hf_ctx* ctx, int m, const double* b, double* x, double* b1
     HF_HIP(hipMemsetAsync(x2p, 0, (size_t)ctx->nblk * mb * m * sizeof(double), s));
     HF_HIP(hipMemcpyAsync(x2p, x2, (size_t)M * m * sizeof(double), hipMemcpyDeviceToDevice, s));
     k_neg<<<cdiv((int64_t)ctx->nblk * mb * m, 256), 256, 0, s>>>((int64_t)ctx->nblk * mb * m, x2p);
-    k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, mb, m, x, x, ctx->nblk, ctx->d_X12.as<double>(), (int64_t)n * mb,
-                                            x2p);
+    combine(ctx, n, mb, m, x, x, ctx->nblk, ctx->d_X12.as<double>(), (int64_t)n * mb,
+                                            x2p, s);
     k_set_rows<<<cdiv((int64_t)M * m, 256), 256, 0, s>>>(M, m, ctx->d_l2.as<int32_t>(), x2, x);
   }
   HF_HIP(hipGetLastError());
@@ -976,7 +989,7 @@ int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, 
           double* G = w.gram.as<double>();
           gram(ctx, n, k, ctx->d_kern.as<double>(), 0, 1, m, out, G, s);
           k_neg<<<cdiv((int64_t)k * m, 256), 256, 0, s>>>((int64_t)k * m, G);
-          k_combine<<<cdiv(nm, 256), 256, 0, s>>>(n, k, m, out, out, 1, ctx->d_kern.as<double>(), 0, G);
+          combine(ctx, n, k, m, out, out, 1, ctx->d_kern.as<double>(), 0, G, s);
         }
       };
       k_load_rhs<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(), B, ldb,

@@ -551,7 +551,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         by += 0.5 * nc * nc * sz + 2.0 * nc * dm * sz;
         fl += dm * nc * nc;
       });
-      timed(tm, HF_K_SOLVE_DIAG, wd.first, wd.second, s, [&] {
+      timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s, [&] {
         dim3 g(TB / SB, nl);
         k_fwd_diag<T><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, m, rb, zb);
       });
@@ -566,7 +566,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           by += below * nc * sz + 2.0 * below * dm * sz + nc * dm * sz;
           fl += 2.0 * dm * below * nc;
         });
-        timed(tm, HF_K_SOLVE_UPDATE, wu.first, wu.second, s, [&] {
+        timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s, [&] {
           k_fwd_upd<T><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
         });
       }
@@ -583,12 +583,17 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       by += ni.b * np * sz + 2.0 * np * dm * sz + ni.b * dm * 8.0;
       fl += 2.0 * dm * ni.b * np;
     });
-    timed(tm, HF_K_SOLVE_UPDATE, wb.first, wb.second, s, [&] {
-      if (ctx->level_maxb[l] > 0) {
+    if (ctx->level_maxb[l] > 0) {
+      timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s, [&] {
         dim3 gp(cdiv(maxp, 64), maxch, nl);
         k_bwd_border_part<T><<<gp, 256, 0, s>>>(ln, nodes, st, front, ctx->d_border.as<int32_t>(), m, Y, maxch, maxp,
                                                 part);
-      }
+      });
+    }
+    auto wf = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
+      by += 3.0 * np * dm * sz;
+    });
+    timed(tm, HF_K_SOLVE_GATHER, wf.first, wf.second, s, [&] {
       dim3 gf(cdiv((int64_t)maxp * m, 256), nl);
       k_bwd_border_fin<T><<<gf, 256, 0, s>>>(ln, nodes, st, ctx->d_dval.as<T>(), m, maxch, maxp, part, zb, rb);
     });
@@ -599,7 +604,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         by += 0.5 * nc * nc * sz + 2.0 * nc * dm * sz + nc * dm * 8.0;
         fl += dm * nc * nc;
       });
-      timed(tm, HF_K_SOLVE_DIAG, wd.first, wd.second, s, [&] {
+      timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s, [&] {
         dim3 g(TB / SB, nl);
         k_bwd_diag<T><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, m, Y, rb, zb);
       });
@@ -611,7 +616,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           by += J0 * nc * sz + 2.0 * J0 * dm * sz;
           fl += 2.0 * dm * J0 * nc;
         });
-        timed(tm, HF_K_SOLVE_UPDATE, wu.first, wu.second, s, [&] {
+        timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, [&] {
           k_bwd_upd<T><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
         });
       }

@@ -44,8 +44,9 @@ EXPORTS = ["hf_default_options", "hf_analyse", "hf_factorize", "hf_solve", "hf_k
            "hf_timing_enable", "hf_timing_get"]
 
 # kernel classes of hf_timing_get
-KCLASS = ["panel", "f11_update", "trsm", "syrk", "extend_add", "solve_diag", "solve_update",
-          "solve_gather", "spmm", "gram", "other"]
+KCLASS = ["panel", "swaps", "f11_update", "gather_border", "trsm", "syrk", "extend_add", "fwd_diag",
+          "fwd_update", "bwd_border", "bwd_diag", "bwd_update", "solve_gather", "spmm", "gram", "combine",
+          "other"]
 
 
 class HFError(RuntimeError):

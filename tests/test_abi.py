@@ -28,6 +28,14 @@ def test_header_symbols_exported():
     assert sorted(hy.EXPORTS) == names
 
 
+def test_timing_classes_match_header():
+    text = open(HEADER).read()
+    enum = dict((k, int(v)) for k, v in re.findall(r"\b(HF_K_[A-Z0-9_]+)\s*=\s*(\d+)", text))
+    assert enum["HF_K_NCLASS"] == len(hy.KCLASS)
+    for i, name in enumerate(hy.KCLASS):
+        assert enum["HF_K_" + name.upper()] == i
+
+
 def test_strerror_and_defaults():
     assert hy.hf_strerror(0) == "ok"
     for code in range(-9, 0):
