@@ -51,6 +51,53 @@ __device__ __forceinline__ void mfma_tile_64(const T (*As)[LD], const T (*Bs)[LD
   }
 }
 
+// Pipelined 64 x 64 tile product over k in [kbeg, kend), 256 threads:
+// acc += A(0:64, k) B(k, 0:64).  Operands are fetched in stages of KB values of
+// k into registers, so that the loads of stage s+1 are in flight while the
+// matrix cores work on stage s (staged in LDS, As[k][row] / Bs[k][col]).
+// fa(k, row) and fb(k, col) return the operand values (0 outside the tile);
+// AKC selects the thread mapping of A's fetch: true when A is contiguous in k
+// (consecutive threads take consecutive k), false when contiguous in row.
+template <class T, int KB, int LD, bool AKC, class FA, class FB>
+__device__ __forceinline__ void tile_gemm_64(typename Mfma<T>::V acc[2][2], T (*As)[LD], T (*Bs)[LD], int kbeg,
+                                             int kend, FA&& fa, FB&& fb, int tid, int lane, int wr, int wc) {
+  constexpr int NE = KB * 64 / 256;
+  T ra[NE], rb[NE];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + 256 * q;
+      const int kq = AKC ? (e % KB) : (e >> 6);
+      const int row = AKC ? (e / KB) : (e & 63);
+      ra[q] = (k0 + kq < kend) ? fa(k0 + kq, row) : (T)0;
+      const int kb = e >> 6, col = e & 63;
+      rb[q] = (k0 + kb < kend) ? fb(k0 + kb, col) : (T)0;
+    }
+  };
+  if (kbeg >= kend) return;
+  fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += KB) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + 256 * q;
+      const int kq = AKC ? (e % KB) : (e >> 6);
+      const int row = AKC ? (e / KB) : (e & 63);
+      As[kq][row] = ra[q];
+      Bs[e >> 6][e & 63] = rb[q];
+    }
+    __syncthreads();
+    if (k0 + KB < kend) fetch(k0 + KB);
+    mfma_tile_64<T, KB, LD>(As, Bs, acc, lane, wr, wc);
+    __syncthreads();
+  }
+}
+
+// stage of the pipelined sweeps' tile products (values of k per stage)
+template <class T>
+struct SweepStage {
+  static constexpr int value = sizeof(T) == 4 ? 128 : 64;
+};
+
 template <class T>
 void step1(hf_ctx* ctx, const double* values, hipStream_t s);
 

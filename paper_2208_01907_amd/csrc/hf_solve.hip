@@ -32,45 +32,8 @@ constexpr int RCH = 512; // border rows per partial product of the backward swee
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-// Staging for the 64 x (<= 64) matrix-core products of the sweeps: As[k][row]
-// holds A(row, k0 + k), Bs[k][col] holds B(k0 + k, col); 16 k per chunk.
-constexpr int MK = 16;
+// leading dimension of the LDS stages of the sweeps' 64 x (<= 64) tile products
 constexpr int MLD = 68;
-
-// A(row, k) = src[k * ld + row]  (rows contiguous)
-template <class T>
-__device__ __forceinline__ void stage_a_rows(T (*As)[MLD], const T* src, int64_t ld, int k0, int kc, int nrows,
-                                             int tid) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + 256 * q;
-    const int row = e & 63, kq = e >> 6;
-    As[kq][row] = (kq < kc && row < nrows) ? src[(int64_t)(k0 + kq) * ld + row] : (T)0;
-  }
-}
-
-// A(row, k) = src[row * ld + k]  (k contiguous)
-template <class T>
-__device__ __forceinline__ void stage_a_kcont(T (*As)[MLD], const T* src, int64_t ld, int k0, int kc, int nrows,
-                                              int tid) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + 256 * q;
-    const int kq = e & 15, row = e >> 4;
-    As[kq][row] = (kq < kc && row < nrows) ? src[(int64_t)row * ld + k0 + kq] : (T)0;
-  }
-}
-
-// B(k, col) = V[(k0 + k) * m + col], zero beyond m columns
-template <class T>
-__device__ __forceinline__ void stage_b(T (*Bs)[MLD], const T* V, int m, int k0, int kc, int tid) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + 256 * q;
-    const int col = e & 63, kq = e >> 6;
-    Bs[kq][col] = (kq < kc && col < m) ? V[(int64_t)(k0 + kq) * m + col] : (T)0;
-  }
-}
 
 template <class T>
 __device__ __forceinline__ void zero_acc(typename Mfma<T>::V acc[2][2]) {
@@ -251,22 +214,18 @@ k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   if (SB * I >= nc) return;
   const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB + SB * I;
   const T* W = rb + (ni.rhs_off + J0) * m;
-  __shared__ T As[MK][MLD];
-  __shared__ T Bs[MK][MLD];
+  constexpr int KB = SweepStage<T>::value;
+  __shared__ T As[KB][MLD];
+  __shared__ T Bs[KB][MLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int nrows = min(SB, nc - SB * I);
   typename Mfma<T>::V acc[2][2];
   zero_acc<T>(acc);
   const int cend = min(nc, SB * I + SB);
-  for (int k0 = 0; k0 < cend; k0 += MK) {
-    const int kc = min(MK, cend - k0);
-    stage_a_rows<T>(As, X, TB, k0, kc, nrows, tid);
-    stage_b<T>(Bs, W, m, k0, kc, tid);
-    __syncthreads();
-    mfma_tile_64<T, MK, MLD>(As, Bs, acc, lane, wr, wc);
-    __syncthreads();
-  }
+  tile_gemm_64<T, KB, MLD, false>(
+      acc, As, Bs, 0, cend, [&](int k, int r) { return r < nrows ? X[(int64_t)k * TB + r] : (T)0; },
+      [&](int k, int c) { return c < m ? W[(int64_t)k * m + c] : (T)0; }, tid, lane, wr, wc);
   T* Z = zb + (ni.rhs_off + J0 + SB * I) * m;
   for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
     if (r < nrows && c < m) Z[(int64_t)r * m + c] = v;
@@ -291,21 +250,17 @@ k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
   const T* A = front + ni.front_off + (int64_t)J0 * lf + rs;
   const T* Z = zb + (ni.rhs_off + J0) * m;
   T* W = rb + (ni.rhs_off + rs) * m;
-  __shared__ T As[MK][MLD];
-  __shared__ T Bs[MK][MLD];
+  constexpr int KB = SweepStage<T>::value;
+  __shared__ T As[KB][MLD];
+  __shared__ T Bs[KB][MLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int nrows = min(64, f - rs);
   typename Mfma<T>::V acc[2][2];
   zero_acc<T>(acc);
-  for (int k0 = 0; k0 < nc; k0 += MK) {
-    const int kc = min(MK, nc - k0);
-    stage_a_rows<T>(As, A, lf, k0, kc, nrows, tid);
-    stage_b<T>(Bs, Z, m, k0, kc, tid);
-    __syncthreads();
-    mfma_tile_64<T, MK, MLD>(As, Bs, acc, lane, wr, wc);
-    __syncthreads();
-  }
+  tile_gemm_64<T, KB, MLD, false>(
+      acc, As, Bs, 0, nc, [&](int k, int r) { return r < nrows ? A[(int64_t)k * lf + r] : (T)0; },
+      [&](int k, int c) { return c < m ? Z[(int64_t)k * m + c] : (T)0; }, tid, lane, wr, wc);
   for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
     const int gr = rs + r;
     if (r < nrows && c < m && !(gr >= npiv && gr < p)) W[(int64_t)r * m + c] -= v;
@@ -338,26 +293,17 @@ k_bwd_border_part(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict
   const int64_t lf = ni.f;
   const T* A = front + ni.front_off + (int64_t)cs * lf + p;  // A(k, r) = L21[r, cs + k]
   const int32_t* bord = border + ni.border_off;
-  __shared__ T As[MK][MLD];
-  __shared__ T Bs[MK][MLD];
+  constexpr int KB = SweepStage<T>::value / 2;  // long split-K grid: keep two workgroups per CU
+  __shared__ T As[KB][MLD];
+  __shared__ T Bs[KB][MLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int nrows = min(64, npiv - cs);
   typename Mfma<T>::V acc[2][2];
   zero_acc<T>(acc);
-  for (int r0 = rlo; r0 < rhi; r0 += MK) {
-    const int kc = min(MK, rhi - r0);
-    stage_a_kcont<T>(As, A, lf, r0, kc, nrows, tid);
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-      const int e = tid + 256 * qq;
-      const int col = e & 63, kq = e >> 6;
-      Bs[kq][col] = (kq < kc && col < m) ? (T)Y[(int64_t)bord[r0 + kq] * m + col] : (T)0;
-    }
-    __syncthreads();
-    mfma_tile_64<T, MK, MLD>(As, Bs, acc, lane, wr, wc);
-    __syncthreads();
-  }
+  tile_gemm_64<T, KB, MLD, true>(
+      acc, As, Bs, rlo, rhi, [&](int k, int r) { return r < nrows ? A[(int64_t)r * lf + k] : (T)0; },
+      [&](int k, int c) { return c < m ? (T)Y[(int64_t)bord[k] * m + c] : (T)0; }, tid, lane, wr, wc);
   T* P = part + (((int64_t)q * maxch + ch) * maxp + cs) * m;
   for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
     if (r < nrows && c < m) P[(int64_t)r * m + c] = v;
@@ -400,21 +346,17 @@ k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   if (SB * I >= nc) return;
   const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB + (int64_t)SB * I * TB;  // A(c, r) = X[c*TB + r]
   const T* W = rb + (ni.rhs_off + J0) * m;
-  __shared__ T As[MK][MLD];
-  __shared__ T Bs[MK][MLD];
+  constexpr int KB = SweepStage<T>::value;
+  __shared__ T As[KB][MLD];
+  __shared__ T Bs[KB][MLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int nrows = min(SB, nc - SB * I);
   typename Mfma<T>::V acc[2][2];
   zero_acc<T>(acc);
-  for (int r0 = SB * I; r0 < nc; r0 += MK) {
-    const int kc = min(MK, nc - r0);
-    stage_a_kcont<T>(As, X, TB, r0, kc, nrows, tid);
-    stage_b<T>(Bs, W, m, r0, kc, tid);
-    __syncthreads();
-    mfma_tile_64<T, MK, MLD>(As, Bs, acc, lane, wr, wc);
-    __syncthreads();
-  }
+  tile_gemm_64<T, KB, MLD, true>(
+      acc, As, Bs, SB * I, nc, [&](int k, int r) { return r < nrows ? X[(int64_t)r * TB + k] : (T)0; },
+      [&](int k, int c) { return c < m ? W[(int64_t)k * m + c] : (T)0; }, tid, lane, wr, wc);
   const int c0 = J0 + SB * I;
   for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
     if (r < nrows && c < m) {
@@ -441,21 +383,17 @@ k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
   const T* A = front + ni.front_off + (int64_t)cs * lf + J0;  // A(k, r) = L[J0 + r, cs + k]
   const T* Z = zb + (ni.rhs_off + J0) * m;
   T* W = rb + (ni.rhs_off + cs) * m;
-  __shared__ T As[MK][MLD];
-  __shared__ T Bs[MK][MLD];
+  constexpr int KB = SweepStage<T>::value;
+  __shared__ T As[KB][MLD];
+  __shared__ T Bs[KB][MLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int nrows = min(64, J0 - cs);
   typename Mfma<T>::V acc[2][2];
   zero_acc<T>(acc);
-  for (int r0 = 0; r0 < nc; r0 += MK) {
-    const int kc = min(MK, nc - r0);
-    stage_a_kcont<T>(As, A, lf, r0, kc, nrows, tid);
-    stage_b<T>(Bs, Z, m, r0, kc, tid);
-    __syncthreads();
-    mfma_tile_64<T, MK, MLD>(As, Bs, acc, lane, wr, wc);
-    __syncthreads();
-  }
+  tile_gemm_64<T, KB, MLD, true>(
+      acc, As, Bs, 0, nc, [&](int k, int r) { return r < nrows ? A[(int64_t)r * lf + k] : (T)0; },
+      [&](int k, int c) { return c < m ? Z[(int64_t)k * m + c] : (T)0; }, tid, lane, wr, wc);
   for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
     if (r < nrows && c < m) W[(int64_t)r * m + c] -= v;
   });
