@@ -143,44 +143,39 @@ __global__ void k_y2(const int64_t* __restrict__ ip, const int32_t* __restrict__
 // Gram products C = A^T B (A: n x a, B: n x b, row-major), fixed-order sums
 // ---------------------------------------------------------------------------
 
+// One 64 x 64 (a x b) partial Gram tile per workgroup over a fixed row range,
+// FP64 matrix cores; k_gram_reduce sums the GRAM_WG partials in a fixed order.
+constexpr int GLD = 68;
 __global__ void __launch_bounds__(256)
 k_gram_partial(int64_t n, int a, const double* __restrict__ A, int64_t sA, int b,
                const double* __restrict__ B, double* __restrict__ partial) {
   const int blk = blockIdx.y;
   const double* Ab = A + (int64_t)blk * sA;
   const int64_t chunk = (n + GRAM_WG - 1) / GRAM_WG;
-  const int64_t r0 = (int64_t)blockIdx.x * chunk;
-  const int64_t r1 = min(n, r0 + chunk);
-  __shared__ double As[32 * MAXM];
-  __shared__ double Bs[32 * MAXM];
-  const int tid = threadIdx.x;
-  const int ab = a * b;
-  double acc[16];
+  const int r0 = (int)((int64_t)blockIdx.x * chunk);
+  const int r1 = (int)min(n, (int64_t)r0 + chunk);
+  __shared__ double As[64][GLD];
+  __shared__ double Bs[64][GLD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  Mfma<double>::V acc[2][2];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  for (int64_t rr = r0; rr < r1; rr += 32) {
-    const int nr = (int)min((int64_t)32, r1 - rr);
-    for (int e = tid; e < nr * a; e += 256) As[e] = Ab[rr * a + e];
-    for (int e = tid; e < nr * b; e += 256) Bs[e] = B[rr * b + e];
-    __syncthreads();
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int pidx = tid + q * 256;
-      if (pidx < ab) {
-        const int i = pidx / b, jj = pidx - (pidx / b) * b;
-        double s = acc[q];
-        for (int r = 0; r < nr; ++r) s += As[r * a + i] * Bs[r * b + jj];
-        acc[q] = s;
+    for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<double>::V{0, 0, 0, 0};
+  tile_gemm_64<double, 64, GLD, false>(
+      acc, As, Bs, r0, r1, [&](int k, int i) { return i < a ? Ab[(int64_t)k * a + i] : 0.0; },
+      [&](int k, int j) { return j < b ? B[(int64_t)k * b + j] : 0.0; }, tid, lane, wr, wc);
+  double* out = partial + ((int64_t)blk * GRAM_WG + blockIdx.x) * a * b;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = wr + bi * 16 + Mfma<double>::row(lane, t), j = wc + bj * 16 + (lane & 15);
+        if (i < a && j < b) out[i * b + j] = acc[bi][bj][t];
       }
-    }
-    __syncthreads();
-  }
-  double* out = partial + ((int64_t)blk * GRAM_WG + blockIdx.x) * ab;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int pidx = tid + q * 256;
-    if (pidx < ab) out[pidx] = acc[q];
-  }
 }
 
 __global__ void k_gram_reduce(int nblk, int ab, const double* __restrict__ partial,
@@ -281,19 +276,47 @@ __global__ void k_chol_solve(int m, int nc, const double* __restrict__ Lc, const
 
 // out[row, col] = (base ? base[row, col] : 0) + sum_t sum_k V_t[row, k] coef_t[k, col]
 // V_t = V + t*sV (n x a, row-major), coef_t = coef + t*a*b (a x b), out n x b.
-__global__ void k_combine(int64_t n, int a, int b, double* out, const double* base, int nterms,
-                          const double* __restrict__ V, int64_t sV, const double* __restrict__ coef) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t row = e / b;
-  const int col = (int)(e - row * b);
-  if (row >= n) return;
-  double acc = base ? base[e] : 0.0;
-  for (int t = 0; t < nterms; ++t) {
-    const double* v = V + (int64_t)t * sV + row * a;
-    const double* cf = coef + (int64_t)t * a * b + col;
-    for (int k = 0; k < a; ++k) acc += v[k] * cf[(int64_t)k * b];
-  }
-  out[e] = acc;
+// out (n x b) = base + sum_t V_t (n x a) C_t (a x b); V_t = V + t sV and C_t
+// = coef + t a b, all row-major; base may alias out or be null.  One 64-row
+// strip per workgroup, the nterms products concatenated along k (FP64 matrix
+// cores).
+__global__ void __launch_bounds__(256)
+k_combine(int64_t n, int a, int b, double* out, const double* base, int nterms,
+          const double* __restrict__ V, int64_t sV, const double* __restrict__ coef) {
+  const int r0 = blockIdx.x * 64;
+  const int nrows = (int)min((int64_t)64, n - r0);
+  __shared__ double As[64][GLD];
+  __shared__ double Bs[64][GLD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  Mfma<double>::V acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<double>::V{0, 0, 0, 0};
+  tile_gemm_64<double, 64, GLD, true>(
+      acc, As, Bs, 0, a * nterms,
+      [&](int k, int r) {
+        const int t = k / a, kk = k - t * a;
+        return r < nrows ? V[t * sV + (int64_t)(r0 + r) * a + kk] : 0.0;
+      },
+      [&](int k, int c) {
+        const int t = k / a, kk = k - t * a;
+        return c < b ? coef[((int64_t)t * a + kk) * b + c] : 0.0;
+      },
+      tid, lane, wr, wc);
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = wr + bi * 16 + Mfma<double>::row(lane, t), c = wc + bj * 16 + (lane & 15);
+        if (r < nrows && c < b) {
+          const int64_t e = (int64_t)(r0 + r) * b + c;
+          out[e] = (base ? base[e] : 0.0) + acc[bi][bj][t];
+        }
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -697,7 +720,7 @@ static void combine(hf_ctx* ctx, int64_t n, int a, int b, double* out, const dou
   const double by = ((double)nterms * n * a + (base ? 2.0 : 1.0) * n * b) * 8.0;
   const double fl = 2.0 * n * a * b * (double)nterms;
   timed(ctx->timer, HF_K_COMBINE, by, fl, s, [&] {
-    k_combine<<<cdiv(n * b, 256), 256, 0, s>>>(n, a, b, out, base, nterms, V, sV, coef);
+    k_combine<<<cdiv(n, 64), 256, 0, s>>>(n, a, b, out, base, nterms, V, sV, coef);
   });
 }
 
