@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"hbm_GBps": 8000.0, "fp32_TFLOPs": 157.3, "fp64_TFLOPs": 78.6}
 # classes that compute in FP64 whatever the factorization precision
 FP64_CLASSES = {"spmm", "gram", "combine"}
-KERNEL_NAME = {"panel": "k_panel", "swaps": "k_apply_swaps", "f11_update": "k_syrk (trailing F11)",
+KERNEL_NAME = {"panel": "k_panel", "permute_l11": "k_l11_gather + k_l11_back", "f11_update": "k_syrk (trailing F11)",
                "gather_border": "k_gather_border", "trsm": "k_trsm", "syrk": "k_syrk (contribution)",
                "extend_add": "k_extend_add", "fwd_diag": "k_fwd_diag", "fwd_update": "k_fwd_upd",
                "bwd_border": "k_bwd_border_part", "bwd_diag": "k_bwd_diag", "bwd_update": "k_bwd_upd",
@@ -77,7 +77,7 @@ def run_path(hy, W, vals, B, prec, steps, warmup, torch):
 
 
 # classes that hold several kernels are not priced as one kernel
-MIXED_CLASSES = {"solve_gather", "other"}
+MIXED_CLASSES = {"solve_gather", "other", "permute_l11"}
 
 
 def roofline(stats, steps, prec):

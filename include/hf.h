@@ -200,7 +200,7 @@ int hf_info(const hf_ctx* ctx, hf_info_t* info_host);
  */
 enum {
   HF_K_PANEL = 0,         /* k_panel: pivot search + panel of F11 (serial pivot chain) */
-  HF_K_SWAPS = 1,         /* k_apply_swaps: panel exchanges applied to earlier columns */
+  HF_K_PERMUTE_L11 = 1,   /* k_l11_gather + k_l11_back: L11 columns put in pivot order */
   HF_K_F11_UPDATE = 2,    /* k_syrk: trailing update of F11 after each panel */
   HF_K_GATHER_BORDER = 3, /* k_gather_border: F21 in pivot order before the TRSM */
   HF_K_TRSM = 4,          /* k_trsm: L21 = F21 L11^{-T} D^{-1} */

@@ -95,11 +95,6 @@ __global__ void k_extend_add(const int32_t* __restrict__ items, int nitems,
 // F2: panel factorization of F11 with pivot search and postponing
 // ---------------------------------------------------------------------------
 
-template <class T>
-__device__ inline void argmax_combine(T& bv, int& bid, int& bk, T v, int id, int k) {
-  if (v > bv || (v == bv && id < bid)) { bv = v; bid = id; bk = k; }
-}
-
 constexpr int PT = 512;               // threads of the panel kernel (2 waves per SIMD: 256 VGPRs each)
 constexpr int PROWS = 4096 / PT;      // pivot-block rows per thread (nodes hold at most 4096 indices)
 
@@ -110,17 +105,23 @@ struct PanelWidth {
 };
 
 // Panel factorization with pivot search and postponing, one workgroup per front.
-// Thread t owns the pivot-block positions q = t + PT*s (q relative to k0p); its
-// rows' panel values L[q, 0..NB) live in registers, the current diagonal and the
-// nested-dissection indices in LDS.  Per pivot: every thread reduces the wave
-// argmax results itself, the owners of the two exchanged rows swap their panel
-// rows through LDS, and one pass over global memory does the symmetric exchange
-// of the not-yet-updated part together with the new pivot column
-// (left-looking inside the panel).  Two workgroup barriers per pivot.
+// Thread t owns the pivot-block positions q = t + PT*s (q relative to k0p); the
+// panel values L[q, 0..NB), the current diagonal and the nested-dissection index
+// of its rows live in its registers, so that only the owner of a position ever
+// touches them.  Per pivot, one workgroup barrier: before it, every wave posts
+// its argmax candidate together with that row's panel values, and the owner of
+// position i posts row i; after it, every thread combines the wave results, the
+// two owners exchange their rows from the posted copies, and one pass over
+// global memory does the symmetric exchange of the not-yet-updated part together
+// with the new pivot column (left-looking inside the panel).  The posted copies
+// alternate between two buffers, so a buffer is rewritten only after every
+// thread has passed the next barrier.  Columns of earlier panels are not
+// exchanged here: the panel leaves a snapshot of the position -> index map,
+// from which k_l11_gather puts them in pivot order once the node is finished.
 template <class T>
 __global__ void __launch_bounds__(PT)
 k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, NodeState* st,
-        T* __restrict__ front, int32_t* __restrict__ piv, int32_t* __restrict__ swaps,
+        T* __restrict__ front, int32_t* __restrict__ piv, int32_t* __restrict__ snap,
         T* __restrict__ dval, int k0p, double tau, int first_unit) {
   constexpr int NB = PanelWidth<T>::value;
   constexpr int NW = PT / 64;
@@ -132,103 +133,123 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   const uint32_t f = (uint32_t)ni.f;  // fronts hold fewer than 2^31 entries (checked at analysis)
   T* F = front + ni.front_off;
   int32_t* idx_g = piv + ni.start;
-  int32_t* sw = swaps + ni.start;
   T* D = dval + ni.start;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int P = p - k0p;
 
-  extern __shared__ unsigned char smem_raw[];
-  T* dg = reinterpret_cast<T*>(smem_raw);                     // [P]
-  int32_t* idx = reinterpret_cast<int32_t*>(dg + ((P + 1) & ~1));  // [P]
-  __shared__ T red_v[NW];
-  __shared__ int red_id[NW], red_k[NW];
-  __shared__ T bufI[NB], bufK[NB], Dl[NB];
+  __shared__ T red_v[2][NW], red_d[2][NW];
+  __shared__ int red_id[2][NW], red_k[2][NW];
+  __shared__ T pubK[2][NW][NB];            // panel row of each wave's candidate
+  __shared__ T pubI[2][NB];                // panel row of position i
+  __shared__ T pubI_d[2];
+  __shared__ int pubI_idx[2];
+  __shared__ T Dl[NB];
 
-  T Lp[PROWS][NB];
+  T Lp[PROWS][NB], dgr[PROWS];
+  int idxr[PROWS];
 #pragma unroll
-  for (int s = 0; s < PROWS; ++s)
+  for (int s = 0; s < PROWS; ++s) {
+    const int q = tid + PT * s;
 #pragma unroll
     for (int c = 0; c < NB; ++c) Lp[s][c] = (T)0;
-  for (int q = tid; q < P; q += PT) {
-    dg[q] = F[(uint32_t)(k0p + q) * f + k0p + q];
-    idx[q] = idx_g[k0p + q];
+    dgr[s] = (T)0;
+    idxr[s] = INT_MAX;
+    if (q < P) {
+      dgr[s] = F[(uint32_t)(k0p + q) * f + k0p + q];
+      idxr[s] = idx_g[k0p + q];
+    }
   }
   double dprev = s0.dprev;
   int have_prev = (s0.npiv > 0) ? 1 : first_unit;
   const int iend = min(k0p + NB, p);
-  __syncthreads();
   int i;
   for (i = k0p; i < iend; ++i) {
     const int qi = i - k0p;
-    // argmax of |diag| over the remaining candidates (own rows, then the wave, then all waves)
-    T bv = (T)-1;
+    const int par = qi & 1;
+    const int ti = qi % PT, si = qi / PT;
+    // argmax of |diag| over the remaining candidates: own rows, then the wave
+    T bv = (T)-1, bd = (T)0;
     int bid = INT_MAX, bk = -1;
 #pragma unroll
     for (int s = 0; s < PROWS; ++s) {
       const int q = tid + PT * s;
       if (q >= qi && q < P) {
-        const T v = dg[q];
-        argmax_combine(bv, bid, bk, v < (T)0 ? -v : v, idx[q], q);
+        const T v = dgr[s];
+        const T av = v < (T)0 ? -v : v;
+        if (av > bv || (av == bv && idxr[s] < bid)) { bv = av; bd = v; bid = idxr[s]; bk = q; }
       }
     }
     for (int off = 32; off > 0; off >>= 1) {
       const T ov = __shfl_xor(bv, off, 64);
+      const T od = __shfl_xor(bd, off, 64);
       const int oid = __shfl_xor(bid, off, 64);
       const int ok = __shfl_xor(bk, off, 64);
-      argmax_combine(bv, bid, bk, ov, oid, ok);
+      if (ov > bv || (ov == bv && oid < bid)) { bv = ov; bd = od; bid = oid; bk = ok; }
     }
-    if ((tid & 63) == 0) { red_v[tid >> 6] = bv; red_id[tid >> 6] = bid; red_k[tid >> 6] = bk; }
-    __syncthreads();  // B1
-    bv = red_v[0]; bid = red_id[0]; bk = red_k[0];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) argmax_combine(bv, bid, bk, red_v[w], red_id[w], red_k[w]);
-    const int qk = bk;
-    const T d = dg[qk];
-    const T dI = dg[qi];  // moves to position k with its row
-    const double dk = (double)d;
-    bool stop = (dk == 0.0);
-    if (!stop && have_prev && fabs(dk) < tau * fabs(dprev)) stop = true;
-    if (stop) break;  // uniform: every thread computed the same decision
-    const int ti = qi % PT, si = qi / PT, tk = qk % PT, sk = qk / PT;
-    // publish the panel rows of positions i and k
-    if (tid == ti) {
-#pragma unroll
-      for (int s = 0; s < PROWS; ++s)
-        if (s == si)
-#pragma unroll
-          for (int c = 0; c < NB; ++c) bufI[c] = Lp[s][c];
-    }
-    if (tid == tk) {
+    // post the wave's candidate (its owner posts the panel row) and row i
+    if (lane == 0) { red_v[par][wv] = bv; red_d[par][wv] = bd; red_id[par][wv] = bid; red_k[par][wv] = bk; }
+    if (bk >= 0 && tid == bk % PT) {
+      const int sk = bk / PT;
 #pragma unroll
       for (int s = 0; s < PROWS; ++s)
         if (s == sk)
 #pragma unroll
-          for (int c = 0; c < NB; ++c) bufK[c] = Lp[s][c];
+          for (int c = 0; c < NB; ++c) pubK[par][wv][c] = Lp[s][c];
     }
-    if (tid == 0) {
-      sw[i] = k0p + qk;
-      const int32_t tx = idx[qi]; idx[qi] = idx[qk]; idx[qk] = tx;
-      Dl[qi] = d;
-      D[i] = d;
+    if (tid == ti) {
+#pragma unroll
+      for (int s = 0; s < PROWS; ++s)
+        if (s == si) {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) pubI[par][c] = Lp[s][c];
+          pubI_d[par] = dgr[s];
+          pubI_idx[par] = idxr[s];
+        }
     }
-    __syncthreads();  // B2
-    // rows i and k exchange their panel values (and the owner of k its diagonal)
+    __syncthreads();
+    int ww = 0;
+    bv = red_v[par][0]; bid = red_id[par][0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const T ov = red_v[par][w];
+      const int oid = red_id[par][w];
+      if (ov > bv || (ov == bv && oid < bid)) { bv = ov; bid = oid; ww = w; }
+    }
+    const int qk = red_k[par][ww];
+    const T d = red_d[par][ww];
+    const double dk = (double)d;
+    bool stop = (dk == 0.0);
+    if (!stop && have_prev && fabs(dk) < tau * fabs(dprev)) stop = true;
+    if (stop) break;  // uniform: every thread computed the same decision
+    const int tk = qk % PT, sk = qk / PT;
+    const T* bufK = pubK[par][ww];  // panel row of the pivot row (LDS)
+    // rows i and k exchange their panel values, diagonals and indices
     if (qk != qi) {
-      if (tid == tk) dg[qk] = dI;
+      if (tid == tk) {
+        const T dI = pubI_d[par];
+        const int idI = pubI_idx[par];
+#pragma unroll
+        for (int s = 0; s < PROWS; ++s)
+          if (s == sk) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) Lp[s][c] = pubI[par][c];
+            dgr[s] = dI;
+            idxr[s] = idI;
+          }
+      }
       if (tid == ti) {
 #pragma unroll
         for (int s = 0; s < PROWS; ++s)
-          if (s == si)
+          if (s == si) {
 #pragma unroll
             for (int c = 0; c < NB; ++c) Lp[s][c] = bufK[c];
+            idxr[s] = bid;
+          }
       }
-      if (tid == tk) {
-#pragma unroll
-        for (int s = 0; s < PROWS; ++s)
-          if (s == sk)
-#pragma unroll
-            for (int c = 0; c < NB; ++c) Lp[s][c] = bufI[c];
-      }
+    }
+    if (tid == 0) {
+      Dl[qi] = d;  // read from the next pivot on, after its barrier
+      D[i] = d;
     }
     // u_c = D_c L[i, c] for the panel columns so far (row i after the exchange)
     T u[NB];
@@ -273,7 +294,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
         for (int c = 0; c < NB; ++c) v -= Lp[s][c] * u[c];
         const T l = v * inv;
         F[(uint32_t)i * f + r] = l;
-        dg[q] -= l * v;
+        dgr[s] -= l * v;
 #pragma unroll
         for (int c = 0; c < NB; ++c)
           if (c == qi) Lp[s][c] = l;
@@ -285,12 +306,11 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     }
     dprev = dk;
     have_prev = 1;
-    // the next argmax reads only the thread's own rows of dg; dg[qi], dg[qk] and
-    // the panel buffers are rewritten only after the next B1
   }
-  __syncthreads();
-  // write the panel back: rows are in their final positions
+  // write the panel back (rows are in their final positions for this panel) and
+  // the snapshot of the position -> index map of positions k0p..p-1
   const int nacc = i - k0p;
+  int32_t* sn = snap + ni.snap_off + (int64_t)(k0p / NB) * p;
 #pragma unroll
   for (int s = 0; s < PROWS; ++s) {
     const int q = tid + PT * s;
@@ -298,7 +318,8 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
 #pragma unroll
       for (int c = 0; c < NB; ++c)
         if (c < nacc && c < q) F[(uint32_t)(k0p + c) * f + k0p + q] = Lp[s][c];
-      idx_g[k0p + q] = idx[q];
+      idx_g[k0p + q] = idxr[s];
+      sn[k0p + q] = idxr[s];
     }
   }
   if (tid == 0) {
@@ -310,27 +331,68 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   }
 }
 
-// Row exchanges of the panel at k0p applied to the columns of earlier panels
-// (one thread per column, exchanges in pivot order).
+// Once a node is finished, the columns of every panel are put in pivot order:
+// the L value of final row a in column c (panel jp) sits at the position that
+// the index piv[a] had when panel jp ended.  One workgroup per panel; the
+// result goes transposed into the unused upper triangle (k_l11_back copies it
+// down), so that no value is overwritten before it is read.
 template <class T>
-__global__ void k_apply_swaps(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-                              const NodeState* __restrict__ st, const int32_t* __restrict__ swaps,
-                              T* __restrict__ front, int k0p, int nb) {
+__global__ void __launch_bounds__(256)
+k_l11_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+             const NodeState* __restrict__ st, const int32_t* __restrict__ piv,
+             const int32_t* __restrict__ snap, T* __restrict__ front) {
+  constexpr int NB = PanelWidth<T>::value;
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= k0p || k0p >= npiv) return;
-  const int iend = min(npiv, k0p + nb);
-  const int32_t* sw = swaps + ni.start;
-  T* Fc = front + ni.front_off + (int64_t)c * ni.f;
-  for (int i = k0p; i < iend; ++i) {
-    const int k = sw[i];
-    if (k != i) {
-      const T a = Fc[i];
-      Fc[i] = Fc[k];
-      Fc[k] = a;
+  const int c0 = blockIdx.x * NB;
+  if (c0 >= npiv) return;
+  const int p = ni.p;
+  const uint32_t f = (uint32_t)ni.f;
+  T* F = front + ni.front_off;
+  const int32_t* sn = snap + ni.snap_off + (int64_t)blockIdx.x * p;
+  const int32_t* pv = piv + ni.start;
+  __shared__ int32_t inv[4096];
+  for (int x = c0 + threadIdx.x; x < p; x += 256) inv[sn[x] - ni.start] = x;
+  __syncthreads();
+  const int nc = min(NB, npiv - c0);
+  const int rows = npiv - c0;
+  for (int e = threadIdx.x; e < rows * NB; e += 256) {
+    const int a = c0 + e / NB, cc = e % NB;
+    const int c = c0 + cc;
+    if (cc < nc && a > c) {
+      const int x = inv[pv[a] - ni.start];
+      F[(uint32_t)a * f + c] = F[(uint32_t)c * f + x];
     }
+  }
+}
+
+// L[a, c] = U[c, a] for c < a < npiv (64 x 64 tiles through LDS)
+template <class T>
+__global__ void __launch_bounds__(256)
+k_l11_back(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+           const NodeState* __restrict__ st, T* __restrict__ front) {
+  const int j = lnodes[blockIdx.z];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int a0 = blockIdx.x * 64, c0 = blockIdx.y * 64;  // rows a, columns c of L
+  if (a0 >= npiv || c0 >= npiv || a0 + 63 < c0) return;
+  const uint32_t f = (uint32_t)ni.f;
+  T* F = front + ni.front_off;
+  __shared__ T tile[64][65];
+  const int tid = threadIdx.x, l = tid & 63;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int aa = (tid >> 6) + 4 * q;  // U[c0 + l, a0 + aa] read along c
+    const int a = a0 + aa, c = c0 + l;
+    if (a < npiv && c < a) tile[aa][l] = F[(uint32_t)a * f + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int cc = (tid >> 6) + 4 * q;  // L[a0 + l, c0 + cc] written along a
+    const int a = a0 + l, c = c0 + cc;
+    if (a < npiv && c < a) F[(uint32_t)c * f + a] = tile[l][cc];
   }
 }
 
@@ -640,7 +702,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
   ctx->d_front.alloc((size_t)ctx->front_elems * sizeof(T));
   ctx->d_state.alloc((size_t)ctx->n_nodes * sizeof(NodeState));
   ctx->d_piv.alloc((size_t)n * sizeof(int32_t));
-  ctx->d_swaps.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+  ctx->d_snap.alloc((size_t)std::max<int64_t>(ctx->snap_elems, 1) * sizeof(int32_t));
   ctx->d_linv.alloc((size_t)std::max<int64_t>(ctx->linv_elems, 1) * sizeof(T));
   ctx->d_dval.alloc((size_t)n * sizeof(T));
   ctx->d_q.alloc((size_t)n * sizeof(double));
@@ -706,7 +768,6 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
     // F11 panels
     constexpr int NBP = PanelWidth<T>::value;
     const int maxp = ctx->level_maxp[l];
-    const size_t shm = (size_t)std::max(maxp + 2, 2) * (sizeof(T) + sizeof(int32_t)) + 16;
     for (int k0p = 0; k0p < maxp; k0p += NBP) {
       auto w1 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
         if (ni.p <= k0p) return;
@@ -715,19 +776,9 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         fl += nb * nb * r;
       });
       timed(tm, HF_K_PANEL, w1.first, w1.second, s, [&] {
-        k_panel<T><<<nl, PT, shm, s>>>(lnodes, nodes, st, front, ctx->d_piv.as<int32_t>(),
-                                       ctx->d_swaps.as<int32_t>(), ctx->d_dval.as<T>(), k0p, ctx->opt.tau,
-                                       ctx->opt.first_pivot_unit);
+        k_panel<T><<<nl, PT, 0, s>>>(lnodes, nodes, st, front, ctx->d_piv.as<int32_t>(), ctx->d_snap.as<int32_t>(),
+                                     ctx->d_dval.as<T>(), k0p, ctx->opt.tau, ctx->opt.first_pivot_unit);
       });
-      if (k0p > 0) {
-        auto ws = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
-          if (ni.p > k0p) by += 4.0 * k0p * std::min(NBP, ni.p - k0p) * sz;  // two entries exchanged per swap
-        });
-        timed(tm, HF_K_SWAPS, ws.first, 0.0, s, [&] {
-          dim3 gs(cdiv(k0p, 256), (unsigned)nl);
-          k_apply_swaps<T><<<gs, 256, 0, s>>>(lnodes, nodes, st, ctx->d_swaps.as<int32_t>(), front, k0p, NBP);
-        });
-      }
       const int nr = maxp - (k0p + NBP);
       if (nr > 0) {
         const int nt = (nr + 63) / 64;
@@ -742,6 +793,17 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
           k_syrk<T><<<grid, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), 0, k0p, NBP);
         });
       }
+    }
+    // L11 columns of every panel in pivot order (row exchanges of later panels)
+    if (maxp > NBP) {
+      auto wp = level_sum([&](const NodeInfo& ni, double& by, double& fl) { by += 2.0 * ni.p * ni.p * sz; });
+      timed(tm, HF_K_PERMUTE_L11, wp.first, 0.0, s, [&] {
+        dim3 g1(cdiv(maxp, NBP), (unsigned)nl);
+        k_l11_gather<T><<<g1, 256, 0, s>>>(lnodes, nodes, st, ctx->d_piv.as<int32_t>(), ctx->d_snap.as<int32_t>(),
+                                           front);
+        dim3 g2(cdiv(maxp, 64), cdiv(maxp, 64), (unsigned)nl);
+        k_l11_back<T><<<g2, 256, 0, s>>>(lnodes, nodes, st, front);
+      });
     }
     // inverses of the 64x64 diagonal blocks of the level's L11 (TRSM and sweeps)
     if (maxp > 0) {

@@ -63,6 +63,7 @@ void upload(DBuf& d, const std::vector<T>& h, hipStream_t s) {
 struct NodeInfo {
   int64_t front_off;  // offset of the front in the arena
   int64_t rhs_off;    // offset (rows) of the node's block in the solve arena
+  int64_t snap_off;   // offset of the node's per-panel position -> index snapshots
   int32_t start;      // first position of the node in elimination order
   int32_t p;          // pivot candidates
   int32_t b;          // border size
@@ -172,7 +173,7 @@ struct hf_ctx {
   std::vector<int64_t> linv2_off;
   int64_t linv2_elems = 0;
   std::vector<int32_t> ea_items;
-  int64_t front_elems = 0, rhs_rows = 0;
+  int64_t front_elems = 0, rhs_rows = 0, snap_elems = 0;
   int32_t max_front = 0, max_p = 0;
   double flops_sym = 0.0, flops_done = 0.0;
   int64_t factor_entries = 0;
@@ -185,7 +186,7 @@ struct hf_ctx {
   hf::DBuf d_front;                // front arena (T = float or double)
   hf::DBuf d_state, d_piv, d_dval; // NodeState[n_nodes], piv_order[n], D[n] (T)
   hf::DBuf d_ipos;                 // position of each index in its node's pivot order
-  hf::DBuf d_swaps;                // row exchange of every pivot (position swapped with)
+  hf::DBuf d_snap;                 // per panel: index at every position of the node when it ended
   hf::DBuf d_linv, d_linv_off, d_blk_node, d_blk_first;  // inverses of 64x64 diagonal blocks
   hf::DBuf d_linv2, d_linv2_off, d_stp_node, d_stp_first;  // inverses of 256x256 step blocks
   hf::DBuf d_zb_arena;             // second solve arena (step results)

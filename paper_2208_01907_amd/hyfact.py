@@ -44,7 +44,7 @@ EXPORTS = ["hf_default_options", "hf_analyse", "hf_factorize", "hf_solve", "hf_k
            "hf_timing_enable", "hf_timing_get"]
 
 # kernel classes of hf_timing_get
-KCLASS = ["panel", "swaps", "f11_update", "gather_border", "trsm", "syrk", "extend_add", "fwd_diag",
+KCLASS = ["panel", "permute_l11", "f11_update", "gather_border", "trsm", "syrk", "extend_add", "fwd_diag",
           "fwd_update", "bwd_border", "bwd_diag", "bwd_update", "solve_gather", "spmm", "gram", "combine",
           "other"]
 
