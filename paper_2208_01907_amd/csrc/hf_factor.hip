@@ -104,25 +104,73 @@ struct PanelWidth {
   static constexpr int value = sizeof(T) == 4 ? 16 : 8;
 };
 
+// Wave-wide reductions with DPP row shifts and row broadcasts; the result of
+// lane 63 is returned to every lane.  Lanes without a source keep their value.
+template <int CTRL, int RM>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTRL, RM, 0xf, false);
+}
+template <class Op>
+__device__ __forceinline__ int wave_reduce_i(int x, Op op) {
+  x = op(x, dpp_i<0x111, 0xf>(x));  // row_shr:1
+  x = op(x, dpp_i<0x112, 0xf>(x));  // row_shr:2
+  x = op(x, dpp_i<0x114, 0xf>(x));  // row_shr:4
+  x = op(x, dpp_i<0x118, 0xf>(x));  // row_shr:8
+  x = op(x, dpp_i<0x142, 0xa>(x));  // row_bcast:15
+  x = op(x, dpp_i<0x143, 0xc>(x));  // row_bcast:31
+  return __builtin_amdgcn_readlane(x, 63);
+}
+__device__ __forceinline__ float wave_max(float v) {
+  return __int_as_float(wave_reduce_i(__float_as_int(v), [](int a, int b) {
+    return __float_as_int(fmaxf(__int_as_float(a), __int_as_float(b)));
+  }));
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ void dmax_step(int& lo, int& hi) {
+  const int l2 = dpp_i<CTRL, RM>(lo), h2 = dpp_i<CTRL, RM>(hi);
+  const double m = fmax(__hiloint2double(hi, lo), __hiloint2double(h2, l2));
+  lo = __double2loint(m);
+  hi = __double2hiint(m);
+}
+__device__ __forceinline__ double wave_max(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  dmax_step<0x111, 0xf>(lo, hi);
+  dmax_step<0x112, 0xf>(lo, hi);
+  dmax_step<0x114, 0xf>(lo, hi);
+  dmax_step<0x118, 0xf>(lo, hi);
+  dmax_step<0x142, 0xa>(lo, hi);
+  dmax_step<0x143, 0xc>(lo, hi);
+  return __hiloint2double(__builtin_amdgcn_readlane(hi, 63), __builtin_amdgcn_readlane(lo, 63));
+}
+__device__ __forceinline__ int wave_min(int v) {
+  return wave_reduce_i(v, [](int a, int b) { return a < b ? a : b; });
+}
+
 // Panel factorization with pivot search and postponing, one workgroup per front.
-// Thread t owns the pivot-block positions q = t + PT*s (q relative to k0p); the
-// panel values L[q, 0..NB), the current diagonal and the nested-dissection index
-// of its rows live in its registers, so that only the owner of a position ever
-// touches them.  Per pivot, one workgroup barrier: before it, every wave posts
-// its argmax candidate together with that row's panel values, and the owner of
-// position i posts row i; after it, every thread combines the wave results, the
-// two owners exchange their rows from the posted copies, and one pass over
-// global memory does the symmetric exchange of the not-yet-updated part together
-// with the new pivot column (left-looking inside the panel).  The posted copies
-// alternate between two buffers, so a buffer is rewritten only after every
-// thread has passed the next barrier.  Columns of earlier panels are not
-// exchanged here: the panel leaves a snapshot of the position -> index map,
-// from which k_l11_gather puts them in pivot order once the node is finished.
+//
+// The trailing block [k0p, p)^2 of the pivot block is stored full (both
+// triangles).  A symmetric exchange of positions i and k moves no data: every
+// position carries the storage index ("phys") of its row and column, and the
+// two positions exchange these.  Thread t owns positions q = t + PT*s (relative
+// to k0p) and keeps, in registers, their panel values L[q, 0..NB), current
+// diagonal, nested-dissection index and phys.  Per pivot: a wave-wide argmax
+// (DPP), each wave posts its candidate with that row's panel values and the
+// owner of position i posts row i; one barrier; every thread combines the wave
+// results, the two owners exchange their rows, and each thread reads its rows of
+// the pivot column (one coalesced column read) and forms the new L column
+// (left-looking inside the panel).  The posted copies alternate between two
+// buffers, so a buffer is rewritten only after every thread has passed the next
+// barrier.
+// At the end, the storage columns of the displaced trailing positions are
+// copied to a scratch (k_trail_update resolves the map from there), the panel's
+// L columns are written in position order, and a snapshot of the position ->
+// index map is kept for k_l11_gather.
 template <class T>
 __global__ void __launch_bounds__(PT)
 k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, NodeState* st,
         T* __restrict__ front, int32_t* __restrict__ piv, int32_t* __restrict__ snap,
-        T* __restrict__ dval, int k0p, double tau, int first_unit) {
+        T* __restrict__ dval, int32_t* __restrict__ physmap, int32_t* __restrict__ dslot,
+        T* __restrict__ stage, int k0p, double tau, int first_unit) {
   constexpr int NB = PanelWidth<T>::value;
   constexpr int NW = PT / 64;
   const int j = lnodes[blockIdx.x];
@@ -132,21 +180,24 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   const int p = ni.p;
   const uint32_t f = (uint32_t)ni.f;  // fronts hold fewer than 2^31 entries (checked at analysis)
   T* F = front + ni.front_off;
+  T* Fb = F + (uint32_t)k0p * f + k0p;  // trailing block: Fb[c*f + r], r, c relative to k0p
   int32_t* idx_g = piv + ni.start;
   T* D = dval + ni.start;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int P = p - k0p;
 
   __shared__ T red_v[2][NW], red_d[2][NW];
-  __shared__ int red_id[2][NW], red_k[2][NW];
-  __shared__ T pubK[2][NW][NB];            // panel row of each wave's candidate
-  __shared__ T pubI[2][NB];                // panel row of position i
+  __shared__ int red_id[2][NW], red_k[2][NW], red_ph[2][NW];
+  __shared__ T pubK[2][NW][NB];  // panel row of each wave's candidate
+  __shared__ T pubI[2][NB];      // panel row of position i
   __shared__ T pubI_d[2];
-  __shared__ int pubI_idx[2];
+  __shared__ int pubI_idx[2], pubI_ph[2];
   __shared__ T Dl[NB];
+  __shared__ int nd;
+  __shared__ int dl_ph[NB];
 
   T Lp[PROWS][NB], dgr[PROWS];
-  int idxr[PROWS];
+  int idxr[PROWS], ph[PROWS];
 #pragma unroll
   for (int s = 0; s < PROWS; ++s) {
     const int q = tid + PT * s;
@@ -154,11 +205,21 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     for (int c = 0; c < NB; ++c) Lp[s][c] = (T)0;
     dgr[s] = (T)0;
     idxr[s] = INT_MAX;
+    ph[s] = q;
     if (q < P) {
-      dgr[s] = F[(uint32_t)(k0p + q) * f + k0p + q];
+      dgr[s] = Fb[(uint32_t)q * f + q];
       idxr[s] = idx_g[k0p + q];
     }
   }
+  if (tid < 2 * NW) {  // defined contents even if a wave posted nothing
+    red_v[tid / NW][tid % NW] = (T)-1;
+    red_d[tid / NW][tid % NW] = (T)0;
+    red_id[tid / NW][tid % NW] = INT_MAX;
+    red_k[tid / NW][tid % NW] = 0;
+    red_ph[tid / NW][tid % NW] = 0;
+  }
+  if (tid == 0) nd = 0;
+  __syncthreads();
   double dprev = s0.dprev;
   int have_prev = (s0.npiv > 0) ? 1 : first_unit;
   const int iend = min(k0p + NB, p);
@@ -167,35 +228,31 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     const int qi = i - k0p;
     const int par = qi & 1;
     const int ti = qi % PT, si = qi / PT;
-    // argmax of |diag| over the remaining candidates: own rows, then the wave
-    T bv = (T)-1, bd = (T)0;
-    int bid = INT_MAX, bk = -1;
+    // own best candidate: max |diag|, ties to the smallest index
+    T av = (T)-1;
+    int aid = INT_MAX, as = -1;
 #pragma unroll
     for (int s = 0; s < PROWS; ++s) {
       const int q = tid + PT * s;
       if (q >= qi && q < P) {
-        const T v = dgr[s];
-        const T av = v < (T)0 ? -v : v;
-        if (av > bv || (av == bv && idxr[s] < bid)) { bv = av; bd = v; bid = idxr[s]; bk = q; }
+        const T v = dgr[s] < (T)0 ? -dgr[s] : dgr[s];
+        if (v > av || (v == av && idxr[s] < aid)) { av = v; aid = idxr[s]; as = s; }
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const T ov = __shfl_xor(bv, off, 64);
-      const T od = __shfl_xor(bd, off, 64);
-      const int oid = __shfl_xor(bid, off, 64);
-      const int ok = __shfl_xor(bk, off, 64);
-      if (ov > bv || (ov == bv && oid < bid)) { bv = ov; bd = od; bid = oid; bk = ok; }
-    }
-    // post the wave's candidate (its owner posts the panel row) and row i
-    if (lane == 0) { red_v[par][wv] = bv; red_d[par][wv] = bd; red_id[par][wv] = bid; red_k[par][wv] = bk; }
-    if (bk >= 0 && tid == bk % PT) {
-      const int sk = bk / PT;
+    const T wmax = wave_max(av);
+    const int wid = wave_min(av == wmax ? aid : INT_MAX);
+    if (wmax >= (T)0 && av == wmax && aid == wid) {  // the wave's winner posts its row
 #pragma unroll
       for (int s = 0; s < PROWS; ++s)
-        if (s == sk)
+        if (s == as) {
 #pragma unroll
           for (int c = 0; c < NB; ++c) pubK[par][wv][c] = Lp[s][c];
+          red_d[par][wv] = dgr[s];
+          red_k[par][wv] = tid + PT * s;
+          red_ph[par][wv] = ph[s];
+        }
     }
+    if (lane == 0) { red_v[par][wv] = wmax; red_id[par][wv] = wid; }
     if (tid == ti) {
 #pragma unroll
       for (int s = 0; s < PROWS; ++s)
@@ -204,30 +261,33 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
           for (int c = 0; c < NB; ++c) pubI[par][c] = Lp[s][c];
           pubI_d[par] = dgr[s];
           pubI_idx[par] = idxr[s];
+          pubI_ph[par] = ph[s];
         }
     }
     __syncthreads();
     int ww = 0;
-    bv = red_v[par][0]; bid = red_id[par][0];
+    T bv = red_v[par][0];
+    int bid = red_id[par][0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) {
       const T ov = red_v[par][w];
       const int oid = red_id[par][w];
       if (ov > bv || (ov == bv && oid < bid)) { bv = ov; bid = oid; ww = w; }
     }
-    const int qk = red_k[par][ww];
+    const int qk = min(max(red_k[par][ww], qi), P - 1);
     const T d = red_d[par][ww];
+    const int phK = min(max(red_ph[par][ww], 0), P - 1);
     const double dk = (double)d;
     bool stop = (dk == 0.0);
     if (!stop && have_prev && fabs(dk) < tau * fabs(dprev)) stop = true;
     if (stop) break;  // uniform: every thread computed the same decision
     const int tk = qk % PT, sk = qk / PT;
     const T* bufK = pubK[par][ww];  // panel row of the pivot row (LDS)
-    // rows i and k exchange their panel values, diagonals and indices
+    // positions i and k exchange rows, diagonals, indices and storage indices
     if (qk != qi) {
       if (tid == tk) {
         const T dI = pubI_d[par];
-        const int idI = pubI_idx[par];
+        const int idI = pubI_idx[par], phI = pubI_ph[par];
 #pragma unroll
         for (int s = 0; s < PROWS; ++s)
           if (s == sk) {
@@ -235,6 +295,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
             for (int c = 0; c < NB; ++c) Lp[s][c] = pubI[par][c];
             dgr[s] = dI;
             idxr[s] = idI;
+            ph[s] = phI;
           }
       }
       if (tid == ti) {
@@ -244,6 +305,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
 #pragma unroll
             for (int c = 0; c < NB; ++c) Lp[s][c] = bufK[c];
             idxr[s] = bid;
+            ph[s] = phK;
           }
       }
     }
@@ -255,61 +317,58 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     T u[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) u[c] = (c < qi) ? Dl[c] * bufK[c] : (T)0;
-    const int k = k0p + qk;
     const T inv = (T)1 / d;
-    // pivot-block rows below the pivot: exchange + new column + eager diagonal.
-    // All loads of the pivot are issued before its first store (one memory
-    // round trip per pivot).  The border rows are not exchanged here: they stay
-    // in assembly order until the node is finished (k_gather_border).
-    T vo[PROWS], vn[PROWS];
+    // the pivot column: storage column phK at the storage rows of the positions
+    const T* colK = Fb + (uint32_t)phK * f;
+    T vn[PROWS];
 #pragma unroll
     for (int s = 0; s < PROWS; ++s) {
       const int q = tid + PT * s;
-      const int r = k0p + q;
-      vo[s] = (T)0;
-      vn[s] = (T)0;
-      if (q > qi && q < P) {
-        vo[s] = F[(uint32_t)i * f + r];
-        if (r > k) vn[s] = F[(uint32_t)k * f + r];
-        else if (r < k) vn[s] = F[(uint32_t)r * f + k];
-      }
+      vn[s] = (q > qi && q < P) ? colK[ph[s]] : (T)0;
     }
 #pragma unroll
     for (int s = 0; s < PROWS; ++s) {
       const int q = tid + PT * s;
-      const int r = k0p + q;
       if (q > qi && q < P) {
-        T vnew;
-        if (r > k) {
-          vnew = vn[s];
-          F[(uint32_t)k * f + r] = vo[s];
-        } else if (r < k) {
-          vnew = vn[s];
-          F[(uint32_t)r * f + k] = vo[s];
-        } else {
-          vnew = vo[s];  // F[k, i] is not moved by the exchange
-        }
-        T v = vnew;
+        T v = vn[s];
 #pragma unroll
         for (int c = 0; c < NB; ++c) v -= Lp[s][c] * u[c];
         const T l = v * inv;
-        F[(uint32_t)i * f + r] = l;
         dgr[s] -= l * v;
 #pragma unroll
         for (int c = 0; c < NB; ++c)
           if (c == qi) Lp[s][c] = l;
       }
     }
-    if (tid == 0) {
-      if (qk != qi) F[(uint32_t)k * f + k] = F[(uint32_t)i * f + i];
-      F[(uint32_t)i * f + i] = d;
-    }
     dprev = dk;
     have_prev = 1;
   }
-  // write the panel back (rows are in their final positions for this panel) and
-  // the snapshot of the position -> index map of positions k0p..p-1
   const int nacc = i - k0p;
+  // displaced trailing positions: their storage columns go to the scratch
+  int32_t* pm = physmap + ni.start + k0p;
+  int32_t* dsl = dslot + ni.start + k0p;
+#pragma unroll
+  for (int s = 0; s < PROWS; ++s) {
+    const int q = tid + PT * s;
+    if (q >= nacc && q < P) {
+      int slot = -1;
+      if (ph[s] != q) {  // at most one displaced position per pivot of the panel
+        slot = min(atomicAdd(&nd, 1), NB - 1);
+        dl_ph[slot] = ph[s];
+      }
+      pm[q] = ph[s];
+      dsl[q] = slot;
+    }
+  }
+  __syncthreads();
+  T* stg = stage + (int64_t)NB * 2 * ni.start;  // up to NB columns of P values
+  const int ndisp = min(nd, NB);
+  for (int e = 0; e < ndisp; ++e) {
+    const T* src = Fb + (uint32_t)dl_ph[e] * f;
+    for (int r = tid; r < P; r += PT) stg[(int64_t)e * P + r] = src[r];
+  }
+  __syncthreads();
+  // the panel's L columns in position order, the pivots on the diagonal
   int32_t* sn = snap + ni.snap_off + (int64_t)(k0p / NB) * p;
 #pragma unroll
   for (int s = 0; s < PROWS; ++s) {
@@ -317,7 +376,8 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     if (q < P) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        if (c < nacc && c < q) F[(uint32_t)(k0p + c) * f + k0p + q] = Lp[s][c];
+        if (c < nacc && c < q) Fb[(uint32_t)c * f + q] = Lp[s][c];
+      if (q < nacc) Fb[(uint32_t)q * f + q] = Dl[q];
       idx_g[k0p + q] = idxr[s];
       sn[k0p + q] = idxr[s];
     }
@@ -329,6 +389,132 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     ns.done = (i < iend || i == p) ? 1 : 0;
     st[j] = ns;
   }
+}
+
+// Full (both triangles) storage of the pivot block before its first panel:
+// the upper triangle receives the transpose of the assembled lower triangle.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_mirror(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, T* __restrict__ front) {
+  const int j = lnodes[blockIdx.z];
+  const NodeInfo ni = nodes[j];
+  const int p = ni.p;
+  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;  // lower tile rows r0.., columns c0..
+  if (r0 >= p || c0 >= p || r0 + 63 < c0) return;
+  const uint32_t f = (uint32_t)ni.f;
+  T* F = front + ni.front_off;
+  __shared__ T tile[64][65];
+  const int tid = threadIdx.x, l = tid & 63;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int cc = (tid >> 6) + 4 * q;
+    const int r = r0 + l, c = c0 + cc;
+    if (r < p && c < r) tile[cc][l] = F[(uint32_t)c * f + r];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int rr = (tid >> 6) + 4 * q;
+    const int r = r0 + rr, c = c0 + l;
+    if (r < p && c < r) F[(uint32_t)r * f + c] = tile[l][rr];
+  }
+}
+
+// Trailing update after the panel at k0p, with the exchanges of the panel
+// resolved: T'(x, y) = A(x, y) - sum_t L[x, t] D_t L[y, t] for positions
+// x, y >= k0p + NB, A(x, y) = storage(phys x, phys y), read from the scratch
+// copy of the storage column when x or y is displaced (by symmetry a storage
+// column is also a storage row).  Lower tiles are computed; each result is
+// written to both triangles.  Reads of the storage in place touch only
+// non-displaced entries of the tile itself, so updating in place is safe.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+               const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval,
+               const int32_t* __restrict__ physmap, const int32_t* __restrict__ dslot,
+               const T* __restrict__ stage, int k0p) {
+  constexpr int NB = PanelWidth<T>::value;
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const NodeState sj = st[j];
+  if (sj.done || k0p >= ni.p) return;
+  const int r0 = NB;  // relative to k0p
+  const int P = ni.p - k0p;
+  const int nr = P - r0;
+  if (nr <= 0) return;
+  const int t = blockIdx.x;
+  int ti = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int nt = (nr + 63) / 64;
+  if (ti >= nt) return;
+  const uint32_t f = (uint32_t)ni.f;
+  T* Fb = front + ni.front_off + (uint32_t)k0p * f + k0p;
+  const T* Dk = dval + ni.start + k0p;
+  const int32_t* pm = physmap + ni.start + k0p;
+  const int32_t* dsl = dslot + ni.start + k0p;
+  const T* stg = stage + (int64_t)NB * 2 * ni.start;
+
+  __shared__ T As[16][64 + 4];
+  __shared__ T Bs[16][64 + 4];
+  __shared__ int slx[64], sly[64], phx[64], phy[64];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int rowA = r0 + ti * 64, rowB = r0 + tj * 64;
+  if (tid < 64) {
+    const int x = rowA + tid;
+    slx[tid] = x < P ? dsl[x] : -1;
+    phx[tid] = x < P ? pm[x] : x;
+  } else if (tid < 128) {
+    const int y = rowB + tid - 64;
+    sly[tid - 64] = y < P ? dsl[y] : -1;
+    phy[tid - 64] = y < P ? pm[y] : y;
+  }
+  typename Mfma<T>::V acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::V{0, 0, 0, 0};
+  for (int kk = 0; kk < NB; kk += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      const int rr = e & 63, kq = e >> 6;
+      const int kg = kk + kq;
+      T va = (T)0, vb = (T)0;
+      if (kg < NB) {
+        if (rowA + rr < P) va = Fb[(uint32_t)kg * f + rowA + rr];
+        if (rowB + rr < P) vb = Fb[(uint32_t)kg * f + rowB + rr] * Dk[kg];
+      }
+      As[kq][rr] = va;
+      Bs[kq][rr] = vb;
+    }
+    __syncthreads();
+    mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        const int lr = wr + bi * 16 + Mfma<T>::row(lane, tt);
+        const int lc = wc + bj * 16 + (lane & 15);
+        const int x = rowA + lr, y = rowB + lc;
+        if (x < P && y < P && y <= x) {
+          const int sx = slx[lr], sy = sly[lc];
+          T a;
+          if (sx >= 0) a = stg[(int64_t)sx * P + phy[lc]];
+          else if (sy >= 0) a = stg[(int64_t)sy * P + x];
+          else a = Fb[(uint32_t)y * f + x];
+          const T v = a - acc[bi][bj][tt];
+          Fb[(uint32_t)y * f + x] = v;
+          Fb[(uint32_t)x * f + y] = v;
+        }
+      }
 }
 
 // Once a node is finished, the columns of every panel are put in pivot order:
@@ -703,6 +889,9 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
   ctx->d_state.alloc((size_t)ctx->n_nodes * sizeof(NodeState));
   ctx->d_piv.alloc((size_t)n * sizeof(int32_t));
   ctx->d_snap.alloc((size_t)std::max<int64_t>(ctx->snap_elems, 1) * sizeof(int32_t));
+  ctx->d_physmap.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+  ctx->d_dslot.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+  ctx->d_stage.alloc((size_t)std::max<int64_t>(n, 1) * 2 * PanelWidth<T>::value * sizeof(T));
   ctx->d_linv.alloc((size_t)std::max<int64_t>(ctx->linv_elems, 1) * sizeof(T));
   ctx->d_dval.alloc((size_t)n * sizeof(T));
   ctx->d_q.alloc((size_t)n * sizeof(double));
@@ -768,6 +957,12 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
     // F11 panels
     constexpr int NBP = PanelWidth<T>::value;
     const int maxp = ctx->level_maxp[l];
+    if (maxp > 1) {
+      timed(tm, HF_K_OTHER, 0.0, 0.0, s, [&] {
+        dim3 gm(cdiv(maxp, 64), cdiv(maxp, 64), (unsigned)nl);
+        k_mirror<T><<<gm, 256, 0, s>>>(lnodes, nodes, front);
+      });
+    }
     for (int k0p = 0; k0p < maxp; k0p += NBP) {
       auto w1 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
         if (ni.p <= k0p) return;
@@ -777,7 +972,8 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
       });
       timed(tm, HF_K_PANEL, w1.first, w1.second, s, [&] {
         k_panel<T><<<nl, PT, 0, s>>>(lnodes, nodes, st, front, ctx->d_piv.as<int32_t>(), ctx->d_snap.as<int32_t>(),
-                                     ctx->d_dval.as<T>(), k0p, ctx->opt.tau, ctx->opt.first_pivot_unit);
+                                     ctx->d_dval.as<T>(), ctx->d_physmap.as<int32_t>(), ctx->d_dslot.as<int32_t>(),
+                                     ctx->d_stage.as<T>(), k0p, ctx->opt.tau, ctx->opt.first_pivot_unit);
       });
       const int nr = maxp - (k0p + NBP);
       if (nr > 0) {
@@ -790,7 +986,9 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
           fl += r * r * NBP;
         });
         timed(tm, HF_K_F11_UPDATE, w2.first, w2.second, s, [&] {
-          k_syrk<T><<<grid, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), 0, k0p, NBP);
+          k_trail_update<T><<<grid, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(),
+                                                 ctx->d_physmap.as<int32_t>(), ctx->d_dslot.as<int32_t>(),
+                                                 ctx->d_stage.as<T>(), k0p);
         });
       }
     }

@@ -187,6 +187,8 @@ struct hf_ctx {
   hf::DBuf d_state, d_piv, d_dval; // NodeState[n_nodes], piv_order[n], D[n] (T)
   hf::DBuf d_ipos;                 // position of each index in its node's pivot order
   hf::DBuf d_snap;                 // per panel: index at every position of the node when it ended
+  hf::DBuf d_physmap, d_dslot;     // per position: storage index / scratch slot after the last panel
+  hf::DBuf d_stage;                // per node: storage columns of displaced positions (2 NB x p)
   hf::DBuf d_linv, d_linv_off, d_blk_node, d_blk_first;  // inverses of 64x64 diagonal blocks
   hf::DBuf d_linv2, d_linv2_off, d_stp_node, d_stp_first;  // inverses of 256x256 step blocks
   hf::DBuf d_zb_arena;             // second solve arena (step results)
