@@ -70,6 +70,9 @@ typedef struct hf_options {
   int32_t refine_steps;     /* hf_solve: residual-correction passes of
                                Algorithm 2 after the first one, the residual
                                taken in the caller's variables (default 1) */
+  double refine_tol;        /* block-GCR tolerance inside a correction pass
+                               (default 1e-6): a correction only has to be
+                               accurate relative to the residual it corrects */
 } hf_options;
 
 typedef struct hf_info_t {

@@ -657,18 +657,20 @@ def hybrid_factorize(Kbar, perm, node_ptr, parent, tau=1e-2, low=np.float32, gcr
                         gcr_maxit=gcr_maxit, gcr_iters=iters, Kbar=sp.csr_matrix(Kbar))
 
 
-def _algorithm2(hf: HybridFactor, b):
+def _algorithm2(hf: HybridFactor, b, tol=None):
     """Algorithm 2 on scaled right-hand sides b in elimination order: returns x.
 
-    y1 = Algorithm 5 on K11 y1 = b1; y2 = b2 - K21 y1; x2 solves S22 x2 = y2 with
-    0 on the kernel pivots; x1 = y1 - X12 x2.
+    y1 = Algorithm 5 on K11 y1 = b1 (to relative residual tol, default the
+    factorization's gcr_tol); y2 = b2 - K21 y1; x2 solves S22 x2 = y2 with 0 on
+    the kernel pivots; x1 = y1 - X12 x2.
     """
     f1 = hf.step1
     l2 = f1.lambda2
     b1 = b.copy()
     b1[l2] = 0.0
     apply_A = _masked_ops(hf.Kp, f1.is_l2)
-    y1, info = bgcr(apply_A, lambda R: precond(f1, R), b1, tol=hf.gcr_tol, maxit=hf.gcr_maxit)
+    y1, info = bgcr(apply_A, lambda R: precond(f1, R), b1, tol=hf.gcr_tol if tol is None else tol,
+                    maxit=hf.gcr_maxit)
     y1 = y1.reshape(hf.n, -1)
     x = y1.copy()
     if len(l2):
@@ -679,7 +681,7 @@ def _algorithm2(hf: HybridFactor, b):
     return x
 
 
-def hybrid_solve(hf: HybridFactor, Bbar, refine_steps=1, Kbar=None):
+def hybrid_solve(hf: HybridFactor, Bbar, refine_steps=1, Kbar=None, refine_tol=1e-6):
     """Algorithm 2, plus residual correction, with the minimum-norm choice for singular K.
 
     xbar = P(Q Pi^T Algorithm2(Pi Q bbar)) where P projects orthogonally to the
@@ -689,8 +691,10 @@ def hybrid_solve(hf: HybridFactor, Bbar, refine_steps=1, Kbar=None):
     scaled K has an exactly unit diagonal and differs from Q Kbar Q by rounding,
     and Kbar 1 is only zero up to rounding, so a large kernel component would
     pollute it.  The correction is not part of the paper's Algorithm 2; it is
-    added for the 1e-14 backward-error target.  Kbar defaults to the matrix given
-    to hybrid_factorize.
+    added for the 1e-14 backward-error target.  A correction only has to be
+    accurate relative to the residual it corrects, so its block GCR stops at
+    relative residual refine_tol.  Kbar defaults to the matrix given to
+    hybrid_factorize.
     """
     Bbar = np.asarray(Bbar, dtype=np.float64)
     one = Bbar.ndim == 1
@@ -708,7 +712,7 @@ def hybrid_solve(hf: HybridFactor, Bbar, refine_steps=1, Kbar=None):
     xbar = to_orig(_algorithm2(hf, (hf.q[:, None] * Bbar)[hf.perm]))
     for _ in range(refine_steps):
         rbar = Bbar - Kbar @ xbar
-        xbar = xbar + to_orig(_algorithm2(hf, (hf.q[:, None] * rbar)[hf.perm]))
+        xbar = xbar + to_orig(_algorithm2(hf, (hf.q[:, None] * rbar)[hf.perm], tol=refine_tol))
     return xbar[:, 0] if one else xbar
 
 

@@ -731,7 +731,7 @@ static void precond(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t 
 
 // Algorithm 5 on A = K11 for m right-hand sides B (row-major n x m, zero on the
 // hard part); X receives the solution.  Returns the iteration count.
-static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, hipStream_t s) {
+static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipStream_t s) {
   const int64_t n = ctx->n;
   const int64_t nm = n * m;
   BgcrWork& w = get_work(ctx, m);
@@ -745,7 +745,6 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, hipStream_t s) {
   int32_t* piv = w.piv.as<int32_t>();
   int32_t* rank = w.rank.as<int32_t>();
   double* coef = w.coef.as<double>();
-  const double tol = ctx->opt.gcr_tol;
   const double rel = 1e-14;
   std::vector<double> hb(m * m), hr(m * m);
   std::vector<double> bn2(m);
@@ -864,7 +863,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
         k_gather_k12<<<nbc, 256, 0, s>>>(ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(),
                                          ctx->d_kval.as<double>(), ctx->d_isl2.as<uint8_t>(),
                                          ctx->d_l2.as<int32_t>(), c0, nbc, mb, Bk);
-        const int its = bgcr(ctx, mb, Bk, X12 + (int64_t)blk * n * mb, s);
+        const int its = bgcr(ctx, mb, Bk, X12 + (int64_t)blk * n * mb, ctx->opt.gcr_tol, s);
         ctx->gcr_iters_max = std::max(ctx->gcr_iters_max, its);
         ctx->gcr_iters_total += its;
       }
@@ -951,12 +950,12 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
 
 // Algorithm 2 on scaled right-hand sides b (row-major n x m, elimination order):
 // x receives [x1; x2].  Scratch: b1 and the block-GCR work space.
-static int solve_core(hf_ctx* ctx, int m, const double* b, double* x, double* b1, hipStream_t s) {
+static int solve_core(hf_ctx* ctx, int m, const double* b, double* x, double* b1, double tol, hipStream_t s) {
   const int64_t n = ctx->n;
   const int64_t nm = n * m;
   const int M = ctx->M, k = ctx->kdim;
   k_mask_rows<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_isl2.as<uint8_t>(), b, b1);
-  const int its = bgcr(ctx, m, b1, x, s);  // y1
+  const int its = bgcr(ctx, m, b1, x, tol, s);  // y1
   if (M > 0) {
     ctx->d_y2.alloc((size_t)M * m * sizeof(double) * 3);
     double* y2 = ctx->d_y2.as<double>();
@@ -1017,7 +1016,7 @@ int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, 
       };
       k_load_rhs<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(), B, ldb,
                                                c0, b);
-      ctx->solve_iters = std::max(ctx->solve_iters, solve_core(ctx, m, b, x, b1, s));
+      ctx->solve_iters = std::max(ctx->solve_iters, solve_core(ctx, m, b, x, b1, ctx->opt.gcr_tol, s));
       to_orig(x, xo);
       // residual correction: xo += P(Q Pi^T Algorithm2(Pi Q (bbar - Kbar xo))); the
       // residual is taken in the caller's variables on the projected iterate (the
@@ -1028,7 +1027,8 @@ int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, 
                                                       ctx->d_pindices.as<int32_t>(), ctx->d_kbar.as<double>(),
                                                       ctx->d_q.as<double>(), ctx->d_perm.as<int32_t>(), m, B, ldb, c0,
                                                       xo, res);
-        ctx->solve_iters = std::max(ctx->solve_iters, solve_core(ctx, m, res, x, b1, s));
+        ctx->solve_iters =
+            std::max(ctx->solve_iters, solve_core(ctx, m, res, x, b1, ctx->opt.refine_tol, s));
         to_orig(x, dxo);
         k_add<<<cdiv(nm, 256), 256, 0, s>>>(nm, xo, dxo);
       }

@@ -60,7 +60,7 @@ class HFOptions(ctypes.Structure):
                 ("first_pivot_unit", ctypes.c_int32), ("n_enlarge", ctypes.c_int32),
                 ("gcr_block", ctypes.c_int32), ("gcr_tol", ctypes.c_double),
                 ("gcr_maxit", ctypes.c_int32), ("ker_tol", ctypes.c_double),
-                ("refine_steps", ctypes.c_int32)]
+                ("refine_steps", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
 
 
 class HFInfo(ctypes.Structure):
