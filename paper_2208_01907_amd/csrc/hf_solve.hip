@@ -200,7 +200,7 @@ k_fwd_addchild(const int32_t* __restrict__ items, const NodeInfo* __restrict__ n
 }
 
 // z_J = Linv_J w_J; four workgroups (64 rows each) per front, matrix cores
-template <class T>
+template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
            const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
@@ -214,7 +214,6 @@ k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   if (SB * I >= nc) return;
   const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB + SB * I;
   const T* W = rb + (ni.rhs_off + J0) * m;
-  constexpr int KB = SweepStage<T>::value;
   __shared__ T As[KB][MLD];
   __shared__ T Bs[KB][MLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -233,7 +232,7 @@ k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
 }
 
 // w_rows -= L[rows, J0:J0+nc] z_J for the rows below the step, 64-row strips
-template <class T>
+template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
           const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int m,
@@ -250,7 +249,6 @@ k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
   const T* A = front + ni.front_off + (int64_t)J0 * lf + rs;
   const T* Z = zb + (ni.rhs_off + J0) * m;
   T* W = rb + (ni.rhs_off + rs) * m;
-  constexpr int KB = SweepStage<T>::value;
   __shared__ T As[KB][MLD];
   __shared__ T Bs[KB][MLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -274,12 +272,25 @@ k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
 // Partial products P_ch[k] = sum_{r in chunk ch} L21[r, k] x_border[r] over
 // chunks of RCH border rows (64-column strips x chunks x fronts); summed in a
 // fixed order by k_bwd_border_fin.
+// Border values of the backward sweep, gathered once per front from the FP64
+// result into the front's (free) border rows of the sweep slab, in T.
 template <class T>
+__global__ void __launch_bounds__(256)
+k_bwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+             const int32_t* __restrict__ border, int m, const double* __restrict__ Y, T* __restrict__ rb) {
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)ni.b * m) return;
+  const int r = (int)(e / m), c = (int)(e - (int64_t)r * m);
+  rb[(ni.rhs_off + ni.p + r) * m + c] = (T)Y[(int64_t)border[ni.border_off + r] * m + c];
+}
+
+template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_bwd_border_part(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
                   const NodeState* __restrict__ st, const T* __restrict__ front,
-                  const int32_t* __restrict__ border, int m, const double* __restrict__ Y, int maxch, int maxp,
-                  T* __restrict__ part) {
+                  const T* __restrict__ rb, int m, int maxch, int maxp, T* __restrict__ part) {
   const int q = blockIdx.z;
   const int j = lnodes[q];
   const NodeInfo ni = nodes[j];
@@ -292,8 +303,7 @@ k_bwd_border_part(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict
   const int rhi = min(b, rlo + RCH);
   const int64_t lf = ni.f;
   const T* A = front + ni.front_off + (int64_t)cs * lf + p;  // A(k, r) = L21[r, cs + k]
-  const int32_t* bord = border + ni.border_off;
-  constexpr int KB = SweepStage<T>::value / 2;  // long split-K grid: keep two workgroups per CU
+  const T* Yb = rb + (ni.rhs_off + p) * m;  // border values, gathered by k_bwd_gather
   __shared__ T As[KB][MLD];
   __shared__ T Bs[KB][MLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -303,7 +313,7 @@ k_bwd_border_part(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict
   zero_acc<T>(acc);
   tile_gemm_64<T, KB, MLD, true>(
       acc, As, Bs, rlo, rhi, [&](int k, int r) { return r < nrows ? A[(int64_t)r * lf + k] : (T)0; },
-      [&](int k, int c) { return c < m ? (T)Y[(int64_t)bord[k] * m + c] : (T)0; }, tid, lane, wr, wc);
+      [&](int k, int c) { return c < m ? Yb[(int64_t)k * m + c] : (T)0; }, tid, lane, wr, wc);
   T* P = part + (((int64_t)q * maxch + ch) * maxp + cs) * m;
   for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
     if (r < nrows && c < m) P[(int64_t)r * m + c] = v;
@@ -331,7 +341,7 @@ k_bwd_border_fin(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict_
 }
 
 // x_J = Linv_J^T t_J (four workgroups of 64 columns), scattered to the FP64 result
-template <class T>
+template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
            const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
@@ -346,7 +356,6 @@ k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   if (SB * I >= nc) return;
   const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB + (int64_t)SB * I * TB;  // A(c, r) = X[c*TB + r]
   const T* W = rb + (ni.rhs_off + J0) * m;
-  constexpr int KB = SweepStage<T>::value;
   __shared__ T As[KB][MLD];
   __shared__ T Bs[KB][MLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -367,7 +376,7 @@ k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
 }
 
 // t_k -= sum_{r in step} L[r, k] x_r for the columns k < J0 (64-column strips)
-template <class T>
+template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
           const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int m,
@@ -383,7 +392,6 @@ k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
   const T* A = front + ni.front_off + (int64_t)cs * lf + J0;  // A(k, r) = L[J0 + r, cs + k]
   const T* Z = zb + (ni.rhs_off + J0) * m;
   T* W = rb + (ni.rhs_off + cs) * m;
-  constexpr int KB = SweepStage<T>::value;
   __shared__ T As[KB][MLD];
   __shared__ T Bs[KB][MLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -421,6 +429,12 @@ void prepare_solve(hf_ctx* ctx, hipStream_t s) {
 template <class T>
 void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s) {
   if (m < 1 || m > 64) throw Status{HF_ERR_ARG};  // the sweep tiles hold at most 64 columns
+  // Stage sizes of the tile products: launches over few fronts are latency
+  // bound (one workgroup per CU, long stages, few round trips); launches over
+  // many fronts are throughput bound (short stages, several workgroups per CU).
+  constexpr int KBN = SweepStage<T>::value;
+  constexpr int KBW = SweepStage<T>::value / 4;
+  auto wide = [](const dim3& g) { return (int64_t)g.x * g.y * g.z >= 1024; };
   const int nlev = (int)ctx->level_ptr.size() - 1;
   const size_t arena = (size_t)std::max<int64_t>(ctx->rhs_rows, 1) * m * sizeof(T);
   ctx->d_rhs_arena.alloc(arena);
@@ -491,7 +505,8 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       });
       timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s, [&] {
         dim3 g(TB / SB, nl);
-        k_fwd_diag<T><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, m, rb, zb);
+        if (wide(g)) k_fwd_diag<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, m, rb, zb);
+        else k_fwd_diag<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, m, rb, zb);
       });
       const int rows = maxf - J0 - 1;
       if (rows > 0) {
@@ -505,7 +520,8 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           fl += 2.0 * dm * below * nc;
         });
         timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s, [&] {
-          k_fwd_upd<T><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
+          if (wide(g)) k_fwd_upd<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
+          else k_fwd_upd<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
         });
       }
     }
@@ -518,14 +534,21 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     const int maxch = std::max(1, (int)cdiv(ctx->level_maxb[l], RCH));
     T* part = ctx->d_part.as<T>();
     auto wb = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
-      by += ni.b * np * sz + 2.0 * np * dm * sz + ni.b * dm * 8.0;
+      by += ni.b * np * sz + np * dm * sz + ni.b * dm * sz;
       fl += 2.0 * dm * ni.b * np;
     });
     if (ctx->level_maxb[l] > 0) {
+      auto wy = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
+        by += ni.b * dm * (8.0 + sz);
+      });
+      timed(tm, HF_K_SOLVE_GATHER, wy.first, 0.0, s, [&] {
+        dim3 gy(cdiv((int64_t)ctx->level_maxb[l] * m, 256), nl);
+        k_bwd_gather<T><<<gy, 256, 0, s>>>(ln, nodes, ctx->d_border.as<int32_t>(), m, Y, rb);
+      });
       timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s, [&] {
         dim3 gp(cdiv(maxp, 64), maxch, nl);
-        k_bwd_border_part<T><<<gp, 256, 0, s>>>(ln, nodes, st, front, ctx->d_border.as<int32_t>(), m, Y, maxch, maxp,
-                                                part);
+        if (wide(gp)) k_bwd_border_part<T, KBW><<<gp, 256, 0, s>>>(ln, nodes, st, front, rb, m, maxch, maxp, part);
+        else k_bwd_border_part<T, KBN / 2><<<gp, 256, 0, s>>>(ln, nodes, st, front, rb, m, maxch, maxp, part);
       });
     }
     auto wf = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
@@ -544,7 +567,10 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       });
       timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s, [&] {
         dim3 g(TB / SB, nl);
-        k_bwd_diag<T><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, m, Y, rb, zb);
+        if (wide(g))
+          k_bwd_diag<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, m, Y, rb, zb);
+        else
+          k_bwd_diag<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, m, Y, rb, zb);
       });
       if (J0 > 0) {
         dim3 g(cdiv(J0, 64), nl);
@@ -555,7 +581,8 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           fl += 2.0 * dm * J0 * nc;
         });
         timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, [&] {
-          k_bwd_upd<T><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
+          if (wide(g)) k_bwd_upd<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
+          else k_bwd_upd<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
         });
       }
     }
