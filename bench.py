@@ -80,6 +80,16 @@ def run_path(hy, W, vals, B, prec, steps, warmup, torch):
 MIXED_CLASSES = {"solve_gather", "other", "permute_l11"}
 
 
+def rates(stats):
+    """Algorithmic GB/s and TFLOP/s of every kernel class (event times)."""
+    out = {}
+    for k, v in stats.items():
+        if v["ms"] > 0 and k not in MIXED_CLASSES:
+            out[k] = {"GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1),
+                      "TFLOP/s": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2)}
+    return out
+
+
 def roofline(stats, steps, prec):
     """Roofline of the kernel with the largest summed time: algorithmic bytes
     and flops per launch (from the front sizes) over its average event time;
@@ -189,6 +199,7 @@ def main():
         "rel_err_vs_xstar": rel_xstar, "analyse_s": t_an, "ms_per_step_with_events": dt_ev * 1e3,
         "phase_ms": {k: info[k] for k in ("t_step1_ms", "t_gcr_ms", "t_s22_ms", "t_solve_ms")},
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in stats.items()},
+        "kernel_rates": rates(stats),
         "roofline": roofline(stats, args.steps, 32),
     }
     del ctx
@@ -200,6 +211,7 @@ def main():
                           "kernel_dim": info64["kernel_dim"],
                           "backward_error": be64,
                           "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in stats64.items()},
+                          "kernel_rates": rates(stats64),
                           "roofline": roofline(stats64, args.steps, 64)}
         result["speedup_vs_fp64"] = dt64 / dt
         del ctx64

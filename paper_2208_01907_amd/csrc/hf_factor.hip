@@ -472,6 +472,27 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
     sly[tid - 64] = y < P ? dsl[y] : -1;
     phy[tid - 64] = y < P ? pm[y] : y;
   }
+  __syncthreads();
+  // the old values first (their loads overlap the product below)
+  T old[2][2][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        const int lr = wr + bi * 16 + Mfma<T>::row(lane, tt);
+        const int lc = wc + bj * 16 + (lane & 15);
+        const int x = rowA + lr, y = rowB + lc;
+        T a = (T)0;
+        if (x < P && y < P && y <= x) {
+          const int sx = slx[lr], sy = sly[lc];
+          if (sx >= 0) a = stg[(int64_t)sx * P + phy[lc]];
+          else if (sy >= 0) a = stg[(int64_t)sy * P + x];
+          else a = Fb[(uint32_t)y * f + x];
+        }
+        old[bi][bj][tt] = a;
+      }
   typename Mfma<T>::V acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -505,12 +526,7 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
         const int lc = wc + bj * 16 + (lane & 15);
         const int x = rowA + lr, y = rowB + lc;
         if (x < P && y < P && y <= x) {
-          const int sx = slx[lr], sy = sly[lc];
-          T a;
-          if (sx >= 0) a = stg[(int64_t)sx * P + phy[lc]];
-          else if (sy >= 0) a = stg[(int64_t)sy * P + x];
-          else a = Fb[(uint32_t)y * f + x];
-          const T v = a - acc[bi][bj][tt];
+          const T v = old[bi][bj][tt] - acc[bi][bj][tt];
           Fb[(uint32_t)y * f + x] = v;
           Fb[(uint32_t)x * f + y] = v;
         }
