@@ -726,13 +726,13 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
        const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval,
-       const int64_t* __restrict__ linv_off, const T* __restrict__ linv) {
+       const int64_t* __restrict__ linv_off, const T* __restrict__ linv, int c_lo, int c_hi) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
-  const int npiv = st[j].npiv;
+  const int npiv = min(st[j].npiv, c_hi);
   const int b = ni.b;
   const int rs = blockIdx.x * 64;
-  if (rs >= b || npiv == 0) return;
+  if (rs >= b || npiv <= c_lo) return;
   const int64_t f = ni.f;
   T* F = front + ni.front_off;
   T* X = F + ni.p + rs;  // X(r, c) = X[c*f + r], r < 64
@@ -747,7 +747,7 @@ k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
   const int lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   using V = typename Mfma<T>::V;
-  for (int J0 = 0; J0 < npiv; J0 += 64) {
+  for (int J0 = c_lo; J0 < npiv; J0 += 64) {
     const int nc = min(64, npiv - J0);
     V acc[2][2];
 #pragma unroll
@@ -755,7 +755,7 @@ k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
 #pragma unroll
       for (int bb = 0; bb < 2; ++bb) acc[a][bb] = V{0, 0, 0, 0};
     // acc = X[:, 0:J0] L11[J0:J0+64, 0:J0]^T
-    for (int kk = 0; kk < J0; kk += 16) {
+    for (int kk = c_lo; kk < J0; kk += 16) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int e = tid + q * 256;
@@ -809,10 +809,55 @@ k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
         }
     __syncthreads();
   }
-  for (int e = tid; e < 64 * npiv; e += 256) {
-    const int r = e & 63, c = e >> 6;
+  for (int e = tid; e < 64 * (npiv - c_lo); e += 256) {
+    const int r = e & 63, c = c_lo + (e >> 6);
     if (r < nrow) X[(int64_t)c * f + r] /= Dk[c];
   }
+}
+
+// Blocked TRSM, the part outside the current window of columns [j0, j0 + w):
+// G(c, r) -= sum_{k < j0} L21[r, k] D_k L11[c, k] for c in the window, i.e. the
+// contribution of the columns already solved (L21 final, so D is put back).
+template <class T>
+__global__ void __launch_bounds__(256)
+k_trsm_gemm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+            const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval, int j0) {
+  constexpr int KB = SweepStage<T>::value;
+  const int j = lnodes[blockIdx.z];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int rs = blockIdx.x * 64;
+  const int cs = j0 + blockIdx.y * 64;
+  if (rs >= ni.b || cs >= npiv) return;
+  const int64_t f = ni.f;
+  T* F = front + ni.front_off;
+  const T* L21 = F + ni.p + rs;   // L21(r, k) = L21[k*f + r]
+  const T* L11 = F + cs;          // L11(c, k) = L11[k*f + c]
+  const T* Dk = dval + ni.start;
+  T* G = F + (int64_t)(ni.p + rs) * f + cs;  // G(c, r) = G[r*f + c]
+  const int nrow = min(64, ni.b - rs), ncol = min(64, npiv - cs);
+  __shared__ T As[KB][68];
+  __shared__ T Bs[KB][68];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  typename Mfma<T>::V acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::V{0, 0, 0, 0};
+  tile_gemm_64<T, KB, 68, false>(
+      acc, As, Bs, 0, j0, [&](int k, int r) { return r < nrow ? L21[(int64_t)k * f + r] : (T)0; },
+      [&](int k, int c) { return c < ncol ? L11[(int64_t)k * f + c] * Dk[k] : (T)0; }, tid, lane, wr, wc);
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = wr + bi * 16 + Mfma<T>::row(lane, t);
+        const int c = wc + bj * 16 + (lane & 15);
+        if (r < nrow && c < ncol) G[(int64_t)r * f + c] -= acc[bi][bj][t];
+      }
 }
 
 // inverse of every 64x64 unit-lower diagonal block of L11 (one workgroup per block)
@@ -1040,9 +1085,18 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         dim3 gg(cdiv(maxp, 64), cdiv(maxb, 64), (unsigned)nl);
         k_gather_border<T><<<gg, 256, 0, s>>>(lnodes, nodes, st, ctx->d_piv.as<int32_t>(), front);
       });
+      // windows of TW columns: the solved columns' contribution to a window is
+      // one GEMM over the whole border, the window itself a 64-block TRSM
+      constexpr int TW = 256;
       timed(tm, HF_K_TRSM, w3.first, w3.second, s, [&] {
-        k_trsm<T><<<g1, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), ctx->d_linv_off.as<int64_t>(),
-                                     ctx->d_linv.as<T>());
+        for (int j0 = 0; j0 < maxp; j0 += TW) {
+          if (j0 > 0) {
+            dim3 gg2(cdiv(maxb, 64), TW / 64, (unsigned)nl);
+            k_trsm_gemm<T><<<gg2, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), j0);
+          }
+          k_trsm<T><<<g1, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), ctx->d_linv_off.as<int64_t>(),
+                                       ctx->d_linv.as<T>(), j0, j0 + TW);
+        }
       });
       const int nt = (maxb + 63) / 64;
       dim3 g2((unsigned)(nt * (nt + 1) / 2), (unsigned)nl);
