@@ -24,6 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBps": 8000.0, "fp32_TFLOPs": 157.3, "fp64_TFLOPs": 78.6}
+CALIB_BYTES = 256 << 20
+# measured HBM traffic of the dominant kernel (FETCH_SIZE / WRITE_SIZE passes),
+# valid while the source file that holds the kernel is unchanged
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_inclusions64_fp32.json")
 # classes that compute in FP64 whatever the factorization precision
 FP64_CLASSES = {"spmm", "gram", "combine"}
 KERNEL_NAME = {"panel": "k_panel", "permute_l11": "k_l11_gather + k_l11_back", "f11_update": "k_syrk (trailing F11)",
@@ -41,6 +45,8 @@ def parse():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one plain device copy of 256 MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -90,6 +96,28 @@ def rates(stats):
     return out
 
 
+def measured_traffic(cls, prec):
+    """HBM bytes per launch of the kernel class from the committed counter
+    summary, or None when there is none for it or its source has changed."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("class") != cls or t.get("prec") != prec:
+        return None
+    src = os.path.join(ROOT, t["source"])
+    try:
+        with open(src, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    if digest != t.get("source_sha256"):
+        return None
+    return t["bytes_per_launch"]
+
+
 def roofline(stats, steps, prec):
     """Roofline of the kernel with the largest summed time: algorithmic bytes
     and flops per launch (from the front sizes) over its average event time;
@@ -110,7 +138,7 @@ def roofline(stats, steps, prec):
         achieved = s["bytes"] / sec / 1e9 if sec > 0 else 0.0
         out = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBps"], "unit": "GB/s"}
     out["frac"] = out["achieved"] / out["peak"]
-    out["traffic"] = None
+    out["traffic"] = measured_traffic(name, prec)
     out.update({"kernel": KERNEL_NAME.get(name, name), "class": name, "launches_per_step": s["launches"] / steps,
                 "avg_launch_ms": per_launch_ms, "bytes_per_launch": s["bytes"] / launches,
                 "flops_per_launch": s["flops"] / launches})
@@ -177,6 +205,13 @@ def main():
 
     W = w.CONFIGS[args.config]()
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     vals = torch.tensor(W.values, device=dev)
     B = torch.tensor(W.b, device=dev)
     torch.cuda.synchronize()
