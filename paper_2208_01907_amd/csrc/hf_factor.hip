@@ -481,13 +481,13 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
-        const int lr = wr + bi * 16 + Mfma<T>::row(lane, tt);
-        const int lc = wc + bj * 16 + (lane & 15);
-        const int x = rowA + lr, y = rowB + lc;
+        const int ly = wr + bi * 16 + Mfma<T>::row(lane, tt);
+        const int lx = wc + bj * 16 + (lane & 15);  // lane-fast: the storage row
+        const int x = rowA + lx, y = rowB + ly;
         T a = (T)0;
         if (x < P && y < P && y <= x) {
-          const int sx = slx[lr], sy = sly[lc];
-          if (sx >= 0) a = stg[(int64_t)sx * P + phy[lc]];
+          const int sx = slx[lx], sy = sly[ly];
+          if (sx >= 0) a = stg[(int64_t)sx * P + phy[ly]];
           else if (sy >= 0) a = stg[(int64_t)sy * P + x];
           else a = Fb[(uint32_t)y * f + x];
         }
@@ -509,8 +509,8 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
         if (rowA + rr < P) va = Fb[(uint32_t)kg * f + rowA + rr];
         if (rowB + rr < P) vb = Fb[(uint32_t)kg * f + rowB + rr] * Dk[kg];
       }
-      As[kq][rr] = va;
-      Bs[kq][rr] = vb;
+      As[kq][rr] = vb;  // the product is formed transposed: rows of the tile on the lanes
+      Bs[kq][rr] = va;
     }
     __syncthreads();
     mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
@@ -522,9 +522,9 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) {
-        const int lr = wr + bi * 16 + Mfma<T>::row(lane, tt);
-        const int lc = wc + bj * 16 + (lane & 15);
-        const int x = rowA + lr, y = rowB + lc;
+        const int ly = wr + bi * 16 + Mfma<T>::row(lane, tt);
+        const int lx = wc + bj * 16 + (lane & 15);  // lane-fast: the storage row
+        const int x = rowA + lx, y = rowB + ly;
         if (x < P && y < P && y <= x) {
           const T v = old[bi][bj][tt] - acc[bi][bj][tt];
           Fb[(uint32_t)y * f + x] = v;
@@ -662,8 +662,8 @@ k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
         if (rowA + rr < nr) va = A[(int64_t)kg * f + rowA + rr];
         if (rowB + rr < nr) vb = A[(int64_t)kg * f + rowB + rr] * Dk[kg];
       }
-      As[kq][rr] = va;
-      Bs[kq][rr] = vb;
+      As[kq][rr] = vb;  // the product is formed transposed: rows of C on the lanes
+      Bs[kq][rr] = va;
     }
     __syncthreads();
     mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
@@ -675,8 +675,8 @@ k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int r = rowA + wr + bi * 16 + Mfma<T>::row(lane, t);
-        const int c = rowB + wc + bj * 16 + (lane & 15);
+        const int c = rowB + wr + bi * 16 + Mfma<T>::row(lane, t);
+        const int r = rowA + wc + bj * 16 + (lane & 15);
         if (r < nr && c < nr && c <= r) C[(int64_t)c * f + r] -= acc[bi][bj][t];
       }
 }
