@@ -186,8 +186,12 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int P = p - k0p;
 
-  __shared__ T red_v[2][NW], red_d[2][NW];
-  __shared__ int red_id[2][NW], red_k[2][NW], red_ph[2][NW];
+  // one record per wave: |d|, d, index, position, storage index of its candidate
+  struct alignas(16) WaveRec {
+    T v, d;
+    int id, k, ph;
+  };
+  __shared__ WaveRec rec[2][NW];
   __shared__ T pubK[2][NW][NB];  // panel row of each wave's candidate
   __shared__ T pubI[2][NB];      // panel row of position i
   __shared__ T pubI_d[2];
@@ -196,8 +200,10 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   __shared__ int nd;
   __shared__ int dl_ph[NB];
 
-  T Lp[PROWS][NB], dgr[PROWS];
+  T Lp[PROWS][NB], dgr[PROWS], Dlr[NB];
   int idxr[PROWS], ph[PROWS];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) Dlr[c] = (T)0;
 #pragma unroll
   for (int s = 0; s < PROWS; ++s) {
     const int q = tid + PT * s;
@@ -212,11 +218,13 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     }
   }
   if (tid < 2 * NW) {  // defined contents even if a wave posted nothing
-    red_v[tid / NW][tid % NW] = (T)-1;
-    red_d[tid / NW][tid % NW] = (T)0;
-    red_id[tid / NW][tid % NW] = INT_MAX;
-    red_k[tid / NW][tid % NW] = 0;
-    red_ph[tid / NW][tid % NW] = 0;
+    WaveRec r0;
+    r0.v = (T)-1;
+    r0.d = (T)0;
+    r0.id = INT_MAX;
+    r0.k = 0;
+    r0.ph = 0;
+    rec[tid / NW][tid % NW] = r0;
   }
   if (tid == 0) nd = 0;
   __syncthreads();
@@ -247,12 +255,24 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
         if (s == as) {
 #pragma unroll
           for (int c = 0; c < NB; ++c) pubK[par][wv][c] = Lp[s][c];
-          red_d[par][wv] = dgr[s];
-          red_k[par][wv] = tid + PT * s;
-          red_ph[par][wv] = ph[s];
+          WaveRec r1;
+          r1.v = wmax;
+          r1.d = dgr[s];
+          r1.id = wid;
+          r1.k = tid + PT * s;
+          r1.ph = ph[s];
+          rec[par][wv] = r1;
         }
     }
-    if (lane == 0) { red_v[par][wv] = wmax; red_id[par][wv] = wid; }
+    if (lane == 0 && wmax < (T)0) {  // no candidate in this wave
+      WaveRec r1;
+      r1.v = (T)-1;
+      r1.d = (T)0;
+      r1.id = INT_MAX;
+      r1.k = 0;
+      r1.ph = 0;
+      rec[par][wv] = r1;
+    }
     if (tid == ti) {
 #pragma unroll
       for (int s = 0; s < PROWS; ++s)
@@ -266,17 +286,16 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     }
     __syncthreads();
     int ww = 0;
-    T bv = red_v[par][0];
-    int bid = red_id[par][0];
+    WaveRec best = rec[par][0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) {
-      const T ov = red_v[par][w];
-      const int oid = red_id[par][w];
-      if (ov > bv || (ov == bv && oid < bid)) { bv = ov; bid = oid; ww = w; }
+      const WaveRec o = rec[par][w];
+      if (o.v > best.v || (o.v == best.v && o.id < best.id)) { best = o; ww = w; }
     }
-    const int qk = min(max(red_k[par][ww], qi), P - 1);
-    const T d = red_d[par][ww];
-    const int phK = min(max(red_ph[par][ww], 0), P - 1);
+    const int bid = best.id;
+    const int qk = min(max(best.k, qi), P - 1);
+    const T d = best.d;
+    const int phK = min(max(best.ph, 0), P - 1);
     const double dk = (double)d;
     bool stop = (dk == 0.0);
     if (!stop && have_prev && fabs(dk) < tau * fabs(dprev)) stop = true;
@@ -316,7 +335,10 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     // u_c = D_c L[i, c] for the panel columns so far (row i after the exchange)
     T u[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) u[c] = (c < qi) ? Dl[c] * bufK[c] : (T)0;
+    for (int c = 0; c < NB; ++c) {
+      if (c == qi) Dlr[c] = d;  // every thread keeps the panel's pivots
+      u[c] = (c < qi) ? Dlr[c] * bufK[c] : (T)0;
+    }
     const T inv = (T)1 / d;
     // the pivot column: storage column phK at the storage rows of the positions
     const T* colK = Fb + (uint32_t)phK * f;
