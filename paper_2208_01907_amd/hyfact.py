@@ -196,7 +196,9 @@ def hf_solve(ctx: Context, B, X=None, stream=None):
     import torch
     assert B.is_cuda and B.dtype == torch.float64
     one = B.dim() == 1
-    B2 = B.reshape(B.shape[0], -1)
+    if B.dim() not in (1, 2):
+        raise ValueError("B must be (L,) or (L, r)")
+    B2 = B.reshape(B.shape[0], 1) if one else B
     r = B2.shape[1]
     Bc = B2.t().contiguous()                # column-major (L x r) storage
     Xc = torch.empty_like(Bc)

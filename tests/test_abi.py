@@ -96,3 +96,17 @@ def test_tree_and_option_errors():
     assert _analyse_code(ip, ix, W.perm, W.node_ptr, W.parent, o) == hy.HF_ERR_ARG
     o = hy.hf_default_options(gcr_block=65)
     assert _analyse_code(ip, ix, W.perm, W.node_ptr, W.parent, o) == hy.HF_ERR_ARG
+
+
+def test_size_limits():
+    """A node of more than 4096 indices is refused before any device work."""
+    n = 4097
+    main = np.arange(n)
+    rows = np.concatenate([main, main[:-1], main[1:]])
+    cols = np.concatenate([main, main[1:], main[:-1]])
+    K = __import__("scipy.sparse", fromlist=["csr_matrix"]).csr_matrix(
+        (np.ones(len(rows)), (rows, cols)), shape=(n, n))
+    K.sort_indices()
+    perm, node_ptr, parent = w.single_node_tree(n)
+    assert _analyse_code(K.indptr.astype(np.int64), K.indices.astype(np.int32), perm, node_ptr,
+                         parent) == hy.HF_ERR_NOT_IMPLEMENTED

@@ -157,6 +157,29 @@ def test_zero_and_many_rhs():
     assert np.all(Z == 0.0)
 
 
+def test_empty_and_single_index():
+    """n = 0: every entry point succeeds and does nothing; n = 1: K = [c], x = b / c,
+    and K = [0] has a one-dimensional kernel (x = 0)."""
+    e64 = np.zeros(1, dtype=np.int64)
+    ctx = hy.hf_analyse(e64, np.zeros(0, dtype=np.int32))
+    hy.hf_factorize(ctx, torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert hy.hf_kernel_dim(ctx) == 0
+    X = hy.hf_solve(ctx, torch.zeros((0, 3), dtype=torch.float64, device="cuda"))
+    assert tuple(X.shape) == (0, 3)
+    ip = np.array([0, 1], dtype=np.int64)
+    ix = np.array([0], dtype=np.int32)
+    for prec in (32, 64):
+        ctx = hy.hf_analyse(ip, ix, opt=hy.hf_default_options(low_precision=prec))
+        hy.hf_factorize(ctx, torch.tensor([-4.0], dtype=torch.float64, device="cuda"))
+        assert hy.hf_kernel_dim(ctx) == 0
+        X = hy.hf_solve(ctx, torch.tensor([[2.0, -8.0]], dtype=torch.float64, device="cuda")).cpu().numpy()
+        assert np.allclose(X, [[-0.5, 2.0]], rtol=1e-15, atol=0)
+        hy.hf_factorize(ctx, torch.tensor([0.0], dtype=torch.float64, device="cuda"))
+        assert hy.hf_kernel_dim(ctx) == 1 and hy.hf_info(ctx)["M"] == 1
+        X = hy.hf_solve(ctx, torch.tensor([[0.0]], dtype=torch.float64, device="cuda")).cpu().numpy()
+        assert np.all(X == 0.0)
+
+
 def test_nonsingular_no_postponing():
     """tau = 0 on an SPD matrix: M = 0, the preconditioned block GCR alone solves."""
     W = w.random_dense_workload(90, seed=14, kernel_dim=0, cond=1e2, r=2, tau=0.0)
