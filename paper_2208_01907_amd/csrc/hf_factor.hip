@@ -240,12 +240,13 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     T av = (T)-1;
     int aid = INT_MAX, as = -1;
 #pragma unroll
-    for (int s = 0; s < PROWS; ++s) {
+    for (int s = 0; s < PROWS; ++s) {  // branch-free: bitwise tests and selects
       const int q = tid + PT * s;
-      if (q >= qi && q < P) {
-        const T v = dgr[s] < (T)0 ? -dgr[s] : dgr[s];
-        if (v > av || (v == av && idxr[s] < aid)) { av = v; aid = idxr[s]; as = s; }
-      }
+      const T v = (q >= qi && q < P) ? fabs(dgr[s]) : (T)-1;
+      const bool better = (v > av) | ((v == av) & (idxr[s] < aid));
+      av = better ? v : av;
+      aid = better ? idxr[s] : aid;
+      as = better ? s : as;
     }
     const T wmax = wave_max(av);
     const int wid = wave_min(av == wmax ? aid : INT_MAX);
