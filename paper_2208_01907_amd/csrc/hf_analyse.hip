@@ -313,16 +313,16 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
       for (int32_t q = 0; q < nb; ++q) ctx->blk_node.push_back(j);
     }
     ctx->linv_elems = (int64_t)ctx->blk_first[n_nodes] * 64 * 64;
-    // 256x256 step blocks (their inverses drive the triangular sweeps)
+    // step blocks of the triangular sweeps (their inverses drive them)
     ctx->stp_first.assign(n_nodes + 1, 0);
     ctx->linv2_off.assign(std::max(n_nodes, 1), 0);
     for (int32_t j = 0; j < n_nodes; ++j) {
-      const int32_t nb = (ctx->nodes[j].p + 255) / 256;
-      ctx->linv2_off[j] = (int64_t)ctx->stp_first[j] * 256 * 256;
+      const int32_t nb = (ctx->nodes[j].p + HF_SWEEP_STEP - 1) / HF_SWEEP_STEP;
+      ctx->linv2_off[j] = (int64_t)ctx->stp_first[j] * HF_SWEEP_STEP * HF_SWEEP_STEP;
       ctx->stp_first[j + 1] = ctx->stp_first[j] + nb;
       for (int32_t q = 0; q < nb; ++q) ctx->stp_node.push_back(j);
     }
-    ctx->linv2_elems = (int64_t)ctx->stp_first[n_nodes] * 256 * 256;
+    ctx->linv2_elems = (int64_t)ctx->stp_first[n_nodes] * HF_SWEEP_STEP * HF_SWEEP_STEP;
     // device copies of the pattern
     hipStream_t s = nullptr;
     upload(ctx->d_pindptr, pindptr, s);

@@ -12,6 +12,10 @@
 
 namespace hf {
 
+// columns of L11 per step of the triangular sweeps (explicit inverse per step)
+constexpr int HF_SWEEP_STEP = 512;
+
+
 struct HipError {
   hipError_t err;
 };

@@ -6,11 +6,12 @@
 // leaves first, per level:
 //   gather   : own accepted rows from the FP64 input (cast to T), children's
 //              border blocks added (extend-add, pivot-order aware);
-//   steps of TB = 256 columns of L11:
+//   steps of TB = 512 columns of L11:
 //     diag   : z_J = L_JJ^{-1} w_J, a plain product with the inverse of the
-//              256x256 step block formed once after the factorization
-//              (k_inv_diag for its 64x64 diagonal blocks, k_inv_step for the
-//              rest), four workgroups per step; z goes to a second arena;
+//              512x512 step block formed once after the factorization
+//              (k_inv_diag for its 64x64 diagonal blocks, k_inv_step for its
+//              two 256x256 halves, k_inv_merge for the block below them),
+//              eight workgroups per step; z goes to a second arena;
 //     update : w_rows -= L[rows, J] z_J for every row below the step (the rest
 //              of L11 and the border L21), 64-row strips, many workgroups.
 // Backward sweep, root first, per level:
@@ -26,7 +27,8 @@
 
 namespace hf {
 
-constexpr int TB = 256;  // columns of L11 per sweep step
+constexpr int TB = HF_SWEEP_STEP;  // columns of L11 per sweep step (512)
+constexpr int HB = TB / 2;         // half step, inverted from the 64x64 inverses
 constexpr int SB = 64;   // sub-block with an explicit inverse
 constexpr int RCH = 512; // border rows per partial product of the backward sweep
 
@@ -70,25 +72,26 @@ k_inv_step(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp
            const NodeInfo* __restrict__ nodes, const NodeState* __restrict__ st,
            const T* __restrict__ front, const int64_t* __restrict__ linv_off, const T* __restrict__ linv,
            const int64_t* __restrict__ linv2_off, T* __restrict__ linv2) {
-  const int bi = blockIdx.x;
+  const int bi = blockIdx.x >> 1, h = blockIdx.x & 1;  // step, half
   const int j = stp_node[bi];
   const int S = bi - stp_first[j];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
-  const int J0 = S * TB;
+  const int J0 = S * TB + h * HB;
   if (J0 >= npiv) return;
-  const int nc = min(TB, npiv - J0);
+  const int nc = min(HB, npiv - J0);
   const int nb = (nc + SB - 1) / SB;
   const int64_t f = ni.f;
   const T* F = front + ni.front_off;
-  T* X = linv2 + linv2_off[j] + (int64_t)S * TB * TB;  // column-major 256x256
+  T* X0 = linv2 + linv2_off[j] + (int64_t)S * TB * TB;  // column-major TB x TB step block
+  T* X = X0 + (int64_t)h * HB * TB + h * HB;             // its diagonal half, leading dimension TB
   const T* L64 = linv + linv_off[j] + (int64_t)(J0 / SB) * SB * SB;
   __shared__ T As[32][64];
   __shared__ T Bs[32][64];
   __shared__ T Ts[64][64];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  for (int e = tid; e < TB * TB; e += 256) X[e] = (T)0;
+  for (int e = tid; e < HB * TB; e += 256) X0[(int64_t)h * HB * TB + e] = (T)0;  // the half's columns
   __syncthreads();
   for (int I = 0; I < nb; ++I)
     for (int e = tid; e < SB * SB; e += 256) {
@@ -163,6 +166,66 @@ k_inv_step(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp
       __syncthreads();
     }
   }
+}
+
+// The block below the two halves of a step: X21 = -Linv_B L_BA Linv_A (A, B the
+// halves).  Pass 0 forms P = L_BA Linv_A into the unused upper-right quarter
+// (transposed: P(r, c) at quarter(c, r)); pass 1 forms X21 = -Linv_B P.  One
+// workgroup per 64x64 output tile; all steps of the tree in one launch.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_inv_merge(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp_first,
+            const NodeInfo* __restrict__ nodes, const NodeState* __restrict__ st,
+            const T* __restrict__ front, const int64_t* __restrict__ linv2_off, T* __restrict__ linv2, int pass) {
+  const int bi = blockIdx.y;
+  const int j = stp_node[bi];
+  const int S = bi - stp_first[j];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int J0 = S * TB;
+  const int nB = min(HB, npiv - J0 - HB);
+  if (nB <= 0) return;
+  const int rt = blockIdx.x >> 2, ct = blockIdx.x & 3;  // row tile (B), column tile (A)
+  if (rt * 64 >= nB) return;
+  const int64_t f = ni.f;
+  const T* F = front + ni.front_off;
+  T* X0 = linv2 + linv2_off[j] + (int64_t)S * TB * TB;
+  constexpr int KB = SweepStage<T>::value / 2;
+  __shared__ T As[KB][68];
+  __shared__ T Bs[KB][68];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int r0 = rt * 64, c0 = ct * 64;
+  const int nrow = min(64, nB - r0);
+  typename Mfma<T>::V acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = typename Mfma<T>::V{0, 0, 0, 0};
+  if (pass == 0) {
+    // P(r, c) = sum_k L[J0 + HB + r, J0 + k] Linv_A(k, c)
+    tile_gemm_64<T, KB, 68, false>(
+        acc, As, Bs, 0, HB,
+        [&](int k, int r) { return r < nrow ? F[(int64_t)(J0 + k) * f + J0 + HB + r0 + r] : (T)0; },
+        [&](int k, int c) { return X0[(int64_t)(c0 + c) * TB + k]; }, tid, lane, wr, wc);
+  } else {
+    // X21(r, c) = -sum_k Linv_B(r, k) P(k, c), P(k, c) stored at X0[(HB + k) TB + c]
+    tile_gemm_64<T, KB, 68, false>(
+        acc, As, Bs, 0, nB,
+        [&](int k, int r) { return r < nrow ? X0[(int64_t)(HB + k) * TB + HB + r0 + r] : (T)0; },
+        [&](int k, int c) { return X0[(int64_t)(HB + k) * TB + c0 + c]; }, tid, lane, wr, wc);
+  }
+#pragma unroll
+  for (int bi2 = 0; bi2 < 2; ++bi2)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = wr + bi2 * 16 + Mfma<T>::row(lane, t), c = wc + bj * 16 + (lane & 15);
+        if (r >= nrow) continue;
+        if (pass == 0) X0[(int64_t)(HB + r0 + r) * TB + c0 + c] = acc[bi2][bj][t];
+        else X0[(int64_t)(c0 + c) * TB + HB + r0 + r] = -acc[bi2][bj][t];
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -417,11 +480,16 @@ void prepare_solve(hf_ctx* ctx, hipStream_t s) {
   ctx->d_linv2.alloc((size_t)std::max<int64_t>(ctx->linv2_elems, 1) * sizeof(T));
   if (ns > 0)
     timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, [&] {
-      k_inv_step<T><<<(unsigned)ns, 256, 0, s>>>(ctx->d_stp_node.as<int32_t>(), ctx->d_stp_first.as<int32_t>(),
+      k_inv_step<T><<<(unsigned)(2 * ns), 256, 0, s>>>(ctx->d_stp_node.as<int32_t>(), ctx->d_stp_first.as<int32_t>(),
                                                  ctx->d_nodes.as<NodeInfo>(), ctx->d_state.as<NodeState>(),
                                                  ctx->d_front.as<T>(), ctx->d_linv_off.as<int64_t>(),
                                                  ctx->d_linv.as<T>(), ctx->d_linv2_off.as<int64_t>(),
                                                  ctx->d_linv2.as<T>());
+      for (int pass = 0; pass < 2; ++pass)
+        k_inv_merge<T><<<dim3(16, (unsigned)ns), 256, 0, s>>>(
+            ctx->d_stp_node.as<int32_t>(), ctx->d_stp_first.as<int32_t>(), ctx->d_nodes.as<NodeInfo>(),
+            ctx->d_state.as<NodeState>(), ctx->d_front.as<T>(), ctx->d_linv2_off.as<int64_t>(),
+            ctx->d_linv2.as<T>(), pass);
     });
   HF_HIP(hipGetLastError());
 }
