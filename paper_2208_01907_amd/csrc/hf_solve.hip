@@ -29,6 +29,14 @@ namespace hf {
 
 constexpr int TB = HF_SWEEP_STEP;  // columns of L11 per sweep step (512)
 constexpr int HB = TB / 2;         // half step, inverted from the 64x64 inverses
+
+// Inverse of the sweep step that starts at column J0 (a multiple of tb = TB or
+// HB): the TB-block, or one of its diagonal halves; leading dimension TB.
+template <class T>
+__device__ __forceinline__ const T* step_inverse(const T* linv2, int64_t off, int J0) {
+  const int h = (J0 % TB) / HB;
+  return linv2 + off + (int64_t)(J0 / TB) * TB * TB + (int64_t)h * HB * TB + h * HB;
+}
 constexpr int SB = 64;   // sub-block with an explicit inverse
 constexpr int RCH = 512; // border rows per partial product of the backward sweep
 
@@ -267,15 +275,15 @@ template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
            const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
-           const T* __restrict__ linv2, int J0, int m, const T* __restrict__ rb, T* __restrict__ zb) {
+           const T* __restrict__ linv2, int J0, int tb, int m, const T* __restrict__ rb, T* __restrict__ zb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
   if (J0 >= npiv) return;
-  const int nc = min(TB, npiv - J0);
+  const int nc = min(tb, npiv - J0);
   const int I = blockIdx.x;
   if (SB * I >= nc) return;
-  const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB + SB * I;
+  const T* X = step_inverse(linv2, linv2_off[j], J0) + SB * I;
   const T* W = rb + (ni.rhs_off + J0) * m;
   __shared__ T As[KB][MLD];
   __shared__ T Bs[KB][MLD];
@@ -298,13 +306,13 @@ k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
 template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-          const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int m,
+          const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int tb, int m,
           const T* __restrict__ zb, T* __restrict__ rb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
   if (J0 >= npiv) return;
-  const int nc = min(TB, npiv - J0);
+  const int nc = min(tb, npiv - J0);
   const int f = ni.f, p = ni.p;
   const int rs = J0 + nc + blockIdx.x * 64;
   if (rs >= f) return;
@@ -408,16 +416,16 @@ template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
            const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
-           const T* __restrict__ linv2, const int32_t* __restrict__ piv, int J0, int m,
+           const T* __restrict__ linv2, const int32_t* __restrict__ piv, int J0, int tb, int m,
            double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
   if (J0 >= npiv) return;
-  const int nc = min(TB, npiv - J0);
+  const int nc = min(tb, npiv - J0);
   const int I = blockIdx.x;
   if (SB * I >= nc) return;
-  const T* X = linv2 + linv2_off[j] + (int64_t)(J0 / TB) * TB * TB + (int64_t)SB * I * TB;  // A(c, r) = X[c*TB + r]
+  const T* X = step_inverse(linv2, linv2_off[j], J0) + (int64_t)SB * I * TB;  // A(c, r) = X[c*TB + r]
   const T* W = rb + (ni.rhs_off + J0) * m;
   __shared__ T As[KB][MLD];
   __shared__ T Bs[KB][MLD];
@@ -442,7 +450,7 @@ k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
 template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-          const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int m,
+          const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int tb, int m,
           const T* __restrict__ zb, T* __restrict__ rb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
@@ -450,7 +458,7 @@ k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
   if (J0 >= npiv) return;
   const int cs = blockIdx.x * 64;
   if (cs >= J0) return;
-  const int nc = min(TB, npiv - J0);
+  const int nc = min(tb, npiv - J0);
   const int64_t lf = ni.f;
   const T* A = front + ni.front_off + (int64_t)cs * lf + J0;  // A(k, r) = L[J0 + r, cs + k]
   const T* Z = zb + (ni.rhs_off + J0) * m;
@@ -503,6 +511,9 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   constexpr int KBN = SweepStage<T>::value;
   constexpr int KBW = SweepStage<T>::value / 4;
   auto wide = [](const dim3& g) { return (int64_t)g.x * g.y * g.z >= 1024; };
+  // step length: long steps (fewer sequential launches) over few fronts,
+  // half steps (shorter diagonal products) over many
+  auto step_of = [](int nl) { return nl < 128 ? TB : HB; };
   const int nlev = (int)ctx->level_ptr.size() - 1;
   const size_t arena = (size_t)std::max<int64_t>(ctx->rhs_rows, 1) * m * sizeof(T);
   ctx->d_rhs_arena.alloc(arena);
@@ -564,32 +575,33 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
                                             ctx->d_relmap.as<int32_t>(), ctx->d_ipos.as<int32_t>(), m, rb);
       });
     }
-    for (int J0 = 0; J0 < maxp; J0 += TB) {
+    const int tb = step_of(nl);
+    for (int J0 = 0; J0 < maxp; J0 += tb) {
       auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
         if (np <= J0) return;
-        const double nc = std::min<double>(TB, np - J0);
+        const double nc = std::min<double>(tb, np - J0);
         by += 0.5 * nc * nc * sz + 2.0 * nc * dm * sz;
         fl += dm * nc * nc;
       });
       timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s, [&] {
-        dim3 g(TB / SB, nl);
-        if (wide(g)) k_fwd_diag<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, m, rb, zb);
-        else k_fwd_diag<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, m, rb, zb);
+        dim3 g(tb / SB, nl);
+        if (wide(g)) k_fwd_diag<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, tb, m, rb, zb);
+        else k_fwd_diag<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, tb, m, rb, zb);
       });
       const int rows = maxf - J0 - 1;
       if (rows > 0) {
         dim3 g(cdiv(rows, 64), nl);
         auto wu = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
           if (np <= J0) return;
-          const double nc = std::min<double>(TB, np - J0);
+          const double nc = std::min<double>(tb, np - J0);
           const double below = ni.f - J0 - nc - (ni.p - np);
           if (below <= 0) return;
           by += below * nc * sz + 2.0 * below * dm * sz + nc * dm * sz;
           fl += 2.0 * dm * below * nc;
         });
         timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s, [&] {
-          if (wide(g)) k_fwd_upd<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
-          else k_fwd_upd<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
+          if (wide(g)) k_fwd_upd<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, tb, m, zb, rb);
+          else k_fwd_upd<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, tb, m, zb, rb);
         });
       }
     }
@@ -626,31 +638,32 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       dim3 gf(cdiv((int64_t)maxp * m, 256), nl);
       k_bwd_border_fin<T><<<gf, 256, 0, s>>>(ln, nodes, st, ctx->d_dval.as<T>(), m, maxch, maxp, part, zb, rb);
     });
-    for (int J0 = ((maxp - 1) / TB) * TB; J0 >= 0; J0 -= TB) {
+    const int tb = step_of(nl);
+    for (int J0 = ((maxp - 1) / tb) * tb; J0 >= 0; J0 -= tb) {
       auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
         if (np <= J0) return;
-        const double nc = std::min<double>(TB, np - J0);
+        const double nc = std::min<double>(tb, np - J0);
         by += 0.5 * nc * nc * sz + 2.0 * nc * dm * sz + nc * dm * 8.0;
         fl += dm * nc * nc;
       });
       timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s, [&] {
-        dim3 g(TB / SB, nl);
+        dim3 g(tb / SB, nl);
         if (wide(g))
-          k_bwd_diag<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, m, Y, rb, zb);
+          k_bwd_diag<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
         else
-          k_bwd_diag<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, m, Y, rb, zb);
+          k_bwd_diag<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
       });
       if (J0 > 0) {
         dim3 g(cdiv(J0, 64), nl);
         auto wu = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
           if (np <= J0) return;
-          const double nc = std::min<double>(TB, np - J0);
+          const double nc = std::min<double>(tb, np - J0);
           by += J0 * nc * sz + 2.0 * J0 * dm * sz;
           fl += 2.0 * dm * J0 * nc;
         });
         timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, [&] {
-          if (wide(g)) k_bwd_upd<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
-          else k_bwd_upd<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, m, zb, rb);
+          if (wide(g)) k_bwd_upd<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, tb, m, zb, rb);
+          else k_bwd_upd<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, tb, m, zb, rb);
         });
       }
     }
