@@ -195,83 +195,94 @@ __global__ void k_gram_reduce(int nblk, int ab, const double* __restrict__ parti
 
 // Pivoted Cholesky of an SPSD m x m Gram matrix (row-major), deflating pivots
 // <= rel * max diag.  Output: Lc (m x m row-major, lower), piv[m], rank.
-__global__ void k_chol_piv(int m, const double* __restrict__ Mm, int64_t sM, double* __restrict__ Lc,
-                           int32_t* __restrict__ piv, int32_t* __restrict__ rank, double rel) {
+__global__ void __launch_bounds__(64)
+k_chol_piv(int m, const double* __restrict__ Mm, int64_t sM, double* __restrict__ Lc,
+           int32_t* __restrict__ piv, int32_t* __restrict__ rank, double rel) {
   const int blk = blockIdx.x;
   const double* G = Mm + (int64_t)blk * sM;
-  double* L = Lc + (int64_t)blk * m * m;
+  double* Lg = Lc + (int64_t)blk * m * m;
   int32_t* P = piv + (int64_t)blk * m;
   __shared__ double A[MAXM * MAXM];
-  __shared__ int s_k, s_stop;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < m * m; e += blockDim.x) { A[e] = G[e]; L[e] = 0.0; }
-  for (int e = tid; e < m; e += blockDim.x) P[e] = e;
+  __shared__ double L[MAXM * MAXM];
+  __shared__ int Ps[MAXM];
+  const int tid = threadIdx.x;  // one wave
+  for (int e = tid; e < m * m; e += 64) { A[e] = G[e]; L[e] = 0.0; }
+  for (int e = tid; e < m; e += 64) Ps[e] = e;
   __syncthreads();
   double dmax = 0.0;
   for (int i = 0; i < m; ++i) dmax = fmax(dmax, A[i * m + i]);
   int i;
   for (i = 0; i < m; ++i) {
-    if (tid == 0) {
-      int k = i;
-      for (int t = i + 1; t < m; ++t)
-        if (A[t * m + t] > A[k * m + k]) k = t;
-      s_k = k;
-      s_stop = (A[k * m + k] <= rel * dmax || A[k * m + k] <= 0.0) ? 1 : 0;
+    // largest remaining diagonal, ties to the first
+    double bv = -INFINITY;
+    int bk = INT_MAX;
+    if (tid >= i && tid < m) { bv = A[tid * m + tid]; bk = tid; }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, 64);
+      const int ok = __shfl_xor(bk, off, 64);
+      if (ov > bv || (ov == bv && ok < bk)) { bv = ov; bk = ok; }
     }
-    __syncthreads();
-    if (s_stop) break;
-    const int k = s_k;
+    const int k = bk;
+    if (bv <= rel * dmax || bv <= 0.0) break;
     if (k != i) {
-      for (int t = tid; t < m; t += blockDim.x) {
+      for (int t = tid; t < m; t += 64) {
         const double x = A[i * m + t]; A[i * m + t] = A[k * m + t]; A[k * m + t] = x;
       }
       __syncthreads();
-      for (int t = tid; t < m; t += blockDim.x) {
+      for (int t = tid; t < m; t += 64) {
         const double x = A[t * m + i]; A[t * m + i] = A[t * m + k]; A[t * m + k] = x;
       }
-      for (int t = tid; t < i; t += blockDim.x) {
+      for (int t = tid; t < i; t += 64) {
         const double x = L[i * m + t]; L[i * m + t] = L[k * m + t]; L[k * m + t] = x;
       }
-      if (tid == 0) { const int32_t x = P[i]; P[i] = P[k]; P[k] = x; }
+      if (tid == 0) { const int x = Ps[i]; Ps[i] = Ps[k]; Ps[k] = x; }
       __syncthreads();
     }
     const double lii = sqrt(A[i * m + i]);
-    for (int r = i + tid; r < m; r += blockDim.x) L[r * m + i] = (r == i) ? lii : A[r * m + i] / lii;
+    for (int r = i + tid; r < m; r += 64) L[r * m + i] = (r == i) ? lii : A[r * m + i] / lii;
     __syncthreads();
-    for (int e = tid; e < (m - i - 1) * (m - i - 1); e += blockDim.x) {
+    for (int e = tid; e < (m - i - 1) * (m - i - 1); e += 64) {
       const int r = i + 1 + e / (m - i - 1), c = i + 1 + e % (m - i - 1);
       A[r * m + c] -= L[r * m + i] * L[c * m + i];
     }
     __syncthreads();
   }
+  for (int e = tid; e < m * m; e += 64) Lg[e] = L[e];
+  for (int e = tid; e < m; e += 64) P[e] = Ps[e];
   if (tid == 0) rank[blk] = i;
 }
 
 // out = sign * M^{-1} R for every batch item (R: m x nc row-major), deflated
 // directions get 0.  One thread per right-hand-side column.
-__global__ void k_chol_solve(int m, int nc, const double* __restrict__ Lc, const int32_t* __restrict__ piv,
-                             const int32_t* __restrict__ rank, const double* __restrict__ R,
-                             int64_t sR, double* __restrict__ out, int64_t sO, double sign) {
+__global__ void __launch_bounds__(64)
+k_chol_solve(int m, int nc, const double* __restrict__ Lc, const int32_t* __restrict__ piv,
+             const int32_t* __restrict__ rank, const double* __restrict__ R,
+             int64_t sR, double* __restrict__ out, int64_t sO, double sign) {
   const int blk = blockIdx.x;
   const int c = threadIdx.x;
-  if (c >= nc) return;
-  const double* L = Lc + (int64_t)blk * m * m;
+  const double* Lg = Lc + (int64_t)blk * m * m;
   const int32_t* P = piv + (int64_t)blk * m;
+  __shared__ double L[MAXM * MAXM];
+  __shared__ double z[MAXM][MAXM + 1];
+  __shared__ int Ps[MAXM];
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) L[e] = Lg[e];
+  for (int e = threadIdx.x; e < m; e += blockDim.x) Ps[e] = P[e];
+  __syncthreads();
+  if (c >= nc) return;
   const int rk = rank[blk];
   const double* Rb = R + (int64_t)blk * sR;
   double* O = out + (int64_t)blk * sO;
-  double z[MAXM];
   for (int i = 0; i < rk; ++i) {
-    double v = Rb[(int64_t)P[i] * nc + c];
-    for (int t = 0; t < i; ++t) v -= L[i * m + t] * z[t];
-    z[i] = v / L[i * m + i];
+    double v = Rb[(int64_t)Ps[i] * nc + c];
+    for (int t = 0; t < i; ++t) v -= L[i * m + t] * z[t][c];
+    z[i][c] = v / L[i * m + i];
   }
   for (int i = rk - 1; i >= 0; --i) {
-    double v = z[i];
-    for (int t = i + 1; t < rk; ++t) v -= L[t * m + i] * z[t];
-    z[i] = v / L[i * m + i];
+    double v = z[i][c];
+    for (int t = i + 1; t < rk; ++t) v -= L[t * m + i] * z[t][c];
+    z[i][c] = v / L[i * m + i];
   }
-  for (int i = 0; i < m; ++i) O[(int64_t)P[i] * nc + c] = (i < rk) ? sign * z[i] : 0.0;
+  for (int i = 0; i < m; ++i) O[(int64_t)Ps[i] * nc + c] = (i < rk) ? sign * z[i][c] : 0.0;
 }
 
 // out[row, col] = (base ? base[row, col] : 0) + sum_t sum_k V_t[row, k] coef_t[k, col]
@@ -329,14 +340,32 @@ k_combine(int64_t n, int a, int b, double* out, const double* base, int nterms,
 __device__ inline double& at(double* A, int M, int r, int c) { return A[(int64_t)c * M + r]; }
 
 __global__ void __launch_bounds__(256)
-k_s22_ldlt(int M, double* __restrict__ A, double* __restrict__ L, double* __restrict__ D,
+k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __restrict__ D,
            int32_t* __restrict__ perm, double* __restrict__ mags, int32_t* __restrict__ bsize,
            double tau, int n_enlarge, double ker_tol, double* __restrict__ info) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double alpha = (1.0 + sqrt(17.0)) / 8.0;
-  __shared__ double rv[256];
-  __shared__ int rk[256];
-  __shared__ int s_kd, s_r, s_c, s_mode;
+  __shared__ double rv[4];
+  __shared__ int rk[4];
+  __shared__ double sA[MAXM * MAXM];  // the working copy stays in LDS when it fits
+  double* A = (M <= MAXM) ? sA : Ag;
+  if (M <= MAXM)
+    for (int e = tid; e < M * M; e += 256) sA[e] = Ag[e];
+  // workgroup argmax of (v, k): largest v, ties to the smallest k; uniform result
+  auto argmax = [&](double& v, int& k) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off, 64);
+      const int ok = __shfl_xor(k, off, 64);
+      if (ov > v || (ov == v && ok < k)) { v = ov; k = ok; }
+    }
+    __syncthreads();  // rv/rk free
+    if (lane == 0) { rv[wv] = v; rk[wv] = k; }
+    __syncthreads();
+    v = rv[0];
+    k = rk[0];
+    for (int w = 1; w < 4; ++w)
+      if (rv[w] > v || (rv[w] == v && rk[w] < k)) { v = rv[w]; k = rk[w]; }
+  };
   for (int64_t e = tid; e < (int64_t)M * M; e += 256) {
     const int r = (int)(e % M), c = (int)(e / M);
     L[e] = (r == c) ? 1.0 : 0.0;
@@ -363,17 +392,9 @@ k_s22_ldlt(int M, double* __restrict__ A, double* __restrict__ L, double* __rest
       const double v = fabs(at(A, M, i + t, i + t));
       if (v > bv) { bv = v; bk = t; }
     }
-    rv[tid] = bv; rk[tid] = bk;
-    __syncthreads();
-    if (tid == 0) {
-      for (int t = 1; t < 256; ++t)
-        if (rv[t] > bv || (rv[t] == bv && rk[t] < bk)) { bv = rv[t]; bk = rk[t]; }
-      rv[0] = bv; s_kd = bk;
-    }
-    __syncthreads();
-    const double gd = rv[0];
-    const int kd = s_kd;
-    __syncthreads();
+    argmax(bv, bk);
+    const double gd = bv;
+    const int kd = bk;
     // largest |off-diagonal| (first in row-major order over the upper triangle)
     double ov = -1.0;
     int ok = INT_MAX;
@@ -383,22 +404,14 @@ k_s22_ldlt(int M, double* __restrict__ A, double* __restrict__ L, double* __rest
       const double v = fabs(at(A, M, i + r, i + c));
       if (v > ov) { ov = v; ok = (int)e; }
     }
-    rv[tid] = ov; rk[tid] = ok;
-    __syncthreads();
-    if (tid == 0) {
-      for (int t = 1; t < 256; ++t)
-        if (rv[t] > ov || (rv[t] == ov && rk[t] < ok)) { ov = rv[t]; ok = rk[t]; }
-      const double go = (w > 1) ? ov : 0.0;
-      int mode;
-      if (gd == 0.0 && go == 0.0) mode = 0;
-      else if (gd >= alpha * go) mode = 1;
-      else mode = 2;
-      s_mode = mode;
-      s_r = (w > 1) ? ok / w : 0;
-      s_c = (w > 1) ? ok % w : 0;
-    }
-    __syncthreads();
-    const int mode = s_mode;
+    argmax(ov, ok);
+    const double go = (w > 1) ? ov : 0.0;
+    int mode;
+    if (gd == 0.0 && go == 0.0) mode = 0;
+    else if (gd >= alpha * go) mode = 1;
+    else mode = 2;
+    const int s_r = (w > 1) ? ok / w : 0;
+    const int s_c = (w > 1) ? ok % w : 0;
     if (mode == 0) break;  // exactly zero remainder: zero pivots
     if (mode == 1) {
       swap(i, i + kd);
@@ -504,9 +517,14 @@ __global__ void k_s22_solve(int M, int k, const double* __restrict__ L, const do
                             const int32_t* __restrict__ perm, const int32_t* __restrict__ bsize, int nc,
                             const double* __restrict__ Y, double* __restrict__ X, double* __restrict__ work) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double Ls[MAXM * MAXM];  // L staged in LDS when it fits
+  const bool lds = M <= MAXM;
+  if (lds)
+    for (int e = threadIdx.x; e < M * M; e += blockDim.x) Ls[e] = L[e];
+  __syncthreads();
   if (c >= nc) return;
   double* z = work + (int64_t)c * M;
-  double* Lm = const_cast<double*>(L);
+  double* Lm = lds ? Ls : const_cast<double*>(L);
   double* Dm = const_cast<double*>(D);
   for (int i = 0; i < M; ++i) {
     double v = Y[(int64_t)perm[i] * nc + c];
