@@ -71,7 +71,7 @@ typedef struct hf_options {
                                Algorithm 2 after the first one, the residual
                                taken in the caller's variables (default 1) */
   double refine_tol;        /* block-GCR tolerance inside a correction pass
-                               (default 1e-6): a correction only has to be
+                               (default 1e-3): a correction only has to be
                                accurate relative to the residual it corrects */
 } hf_options;
 

@@ -681,7 +681,7 @@ def _algorithm2(hf: HybridFactor, b, tol=None):
     return x
 
 
-def hybrid_solve(hf: HybridFactor, Bbar, refine_steps=1, Kbar=None, refine_tol=1e-6):
+def hybrid_solve(hf: HybridFactor, Bbar, refine_steps=1, Kbar=None, refine_tol=1e-3):
     """Algorithm 2, plus residual correction, with the minimum-norm choice for singular K.
 
     xbar = P(Q Pi^T Algorithm2(Pi Q bbar)) where P projects orthogonally to the

@@ -18,7 +18,7 @@ void hf_default_options(hf_options* opt) {
   opt->gcr_maxit = 50;
   opt->ker_tol = 1e-10;
   opt->refine_steps = 1;
-  opt->refine_tol = 1e-6;
+  opt->refine_tol = 1e-3;
 }
 
 int hf_analyse(int64_t n, const int64_t* indptr_host, const int32_t* indices_host, const int32_t* perm_host,

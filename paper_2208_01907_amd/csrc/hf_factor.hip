@@ -539,6 +539,9 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
     mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
     __syncthreads();
   }
+  // lower triangle straight from the product layout (lanes along storage rows);
+  // the mirror goes through LDS so that its stores also run along storage rows
+  __shared__ T mt[64][65];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -548,12 +551,17 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
         const int ly = wr + bi * 16 + Mfma<T>::row(lane, tt);
         const int lx = wc + bj * 16 + (lane & 15);  // lane-fast: the storage row
         const int x = rowA + lx, y = rowB + ly;
-        if (x < P && y < P && y <= x) {
-          const T v = old[bi][bj][tt] - acc[bi][bj][tt];
-          Fb[(uint32_t)y * f + x] = v;
-          Fb[(uint32_t)x * f + y] = v;
-        }
+        const T v = old[bi][bj][tt] - acc[bi][bj][tt];
+        mt[lx][ly] = v;
+        if (x < P && y < P && y <= x) Fb[(uint32_t)y * f + x] = v;
       }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int lx = (tid >> 6) + 4 * q, ly = tid & 63;
+    const int x = rowA + lx, y = rowB + ly;
+    if (x < P && y < P && y <= x) Fb[(uint32_t)x * f + y] = mt[lx][ly];
+  }
 }
 
 // Once a node is finished, the columns of every panel are put in pivot order:

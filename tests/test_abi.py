@@ -42,7 +42,7 @@ def test_strerror_and_defaults():
         assert hy.hf_strerror(code) not in ("ok", "unknown status")
     o = hy.hf_default_options()
     assert o.tau == 1e-2 and o.n_enlarge == 4 and o.low_precision == hy.HF_PREC_FP32
-    assert o.gcr_tol == 1e-15 and o.gcr_block == 0 and o.refine_tol == 1e-6
+    assert o.gcr_tol == 1e-15 and o.gcr_block == 0 and o.refine_tol == 1e-3
 
 
 def _analyse_code(indptr, indices, perm=None, node_ptr=None, parent=None, opt=None):
