@@ -24,6 +24,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"hbm_GBps": 8000.0, "fp32_TFLOPs": 157.3, "fp64_TFLOPs": 78.6}
+WORKLOADS = {
+    "c1": "2D Neumann 5-point FV Laplacian 32x32 (L=1024), cell coefficients 10^U(-3,3), ND leaf 64, "
+          "tau=1e-2, FP32 step 1 + FP64 block GCR, 1 RHS",
+    "c2": "3D Neumann 7-point FV Laplacian 64^3 (L=262144), 200 inclusions at 1e6, ND leaf 512, tau=1e-2, "
+          "FP32 step 1 + FP64 block GCR, 16 RHS",
+    "c3": "floating Q1 elastic cube 24^3 elements (L=46875), E=10^U(0,6), nu=0.3, ND leaf 64 nodes, tau=0.1, "
+          "FP32 step 1 + FP64 block GCR, 32 RHS",
+}
 CALIB_BYTES = 256 << 20
 # measured HBM traffic of the dominant kernel (FETCH_SIZE / WRITE_SIZE passes),
 # valid while the source file that holds the kernel is unchanged
@@ -226,9 +234,7 @@ def main():
         "value": dt, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "3D Neumann 7-point FV Laplacian 64^3 (L=262144), 200 inclusions at 1e6, "
-                               "ND leaf 512, tau=1e-2, FP32 step 1 + FP64 block GCR, 16 RHS",
-                   "n": W.n, "nnz": W.nnz, "rhs": int(W.b.shape[1])},
+        "config": {"workload": WORKLOADS[args.config], "n": W.n, "nnz": W.nnz, "rhs": int(W.b.shape[1])},
         "M": info["M"], "kernel_dim": info["kernel_dim"], "gcr_iters_max": info["gcr_iters_max"],
         "solve_gcr_iters": info["solve_gcr_iters"], "backward_error": be, "gate_1e-14": bool(be <= 1e-14),
         "rel_err_vs_xstar": rel_xstar, "analyse_s": t_an, "ms_per_step_with_events": dt_ev * 1e3,

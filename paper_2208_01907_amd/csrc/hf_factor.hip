@@ -630,32 +630,17 @@ k_l11_back(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric rank-K update C -= A diag(D) A^T on the lower triangle, batched over
-// the fronts of a level.  mode 0: trailing F11 update after the panel at k0p;
-// mode 1: contribution block F22 -= L21 D L21^T.
+// Contribution block F22 -= L21 D L21^T (lower triangle), batched over the
+// fronts of a level, one 64x64 tile per workgroup.
 // ---------------------------------------------------------------------------
 
 template <class T>
 __global__ void __launch_bounds__(256)
 k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-       const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval, int mode,
-       int k0p, int nb) {
+       const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
-  const NodeState s = st[j];
-  int r0, kc0, K, nr;
-  if (mode == 0) {
-    if (s.done || k0p >= ni.p) return;
-    r0 = k0p + nb;
-    kc0 = k0p;
-    K = nb;
-    nr = ni.p - r0;
-  } else {
-    r0 = ni.p;
-    kc0 = 0;
-    K = s.npiv;
-    nr = ni.b;
-  }
+  const int r0 = ni.p, kc0 = 0, K = st[j].npiv, nr = ni.b;
   if (nr <= 0 || K <= 0) return;
   // tile (ti, tj), ti >= tj
   const int t = blockIdx.x;
@@ -1137,7 +1122,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         fl += b * b * p;
       });
       timed(tm, HF_K_SYRK, w4.first, w4.second, s, [&] {
-        k_syrk<T><<<g2, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), 1, 0, 0);
+        k_syrk<T><<<g2, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>());
       });
     }
     HF_HIP(hipGetLastError());
