@@ -183,7 +183,7 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
 
     // node records, arena offsets, cost model
     ctx->nodes.resize(n_nodes);
-    int64_t off = 0, roff = 0, soff = 0;
+    int64_t off = 0, roff = 0, soff = 0, loff = 0;
     ctx->flops_sym = 0.0;
     ctx->factor_entries = 0;
     for (int32_t j = 0; j < n_nodes; ++j) {
@@ -200,6 +200,9 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
       ni.front_off = off;
       ni.rhs_off = roff;
       ni.snap_off = soff;
+      ni.lbuf_ld = (ni.p + 3) & ~3;
+      ni.lbuf_off = loff;
+      loff += (int64_t)ni.p * ni.lbuf_ld;
       off += (int64_t)ni.f * ni.f;
       roff += ni.f;
       soff += (int64_t)((ni.p + 7) / 8) * ni.p;  // panels of at least 8 pivots
@@ -213,6 +216,7 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
     ctx->front_elems = off;
     ctx->rhs_rows = roff;
     ctx->snap_elems = soff;
+    ctx->lbuf_elems = loff;
     // border -> parent-front positions
     ctx->relmap.assign(std::max<int64_t>(ctx->border.size(), 1), 0);
     for (int32_t j = 0; j < n_nodes; ++j) {

@@ -169,8 +169,8 @@ template <class T>
 __global__ void __launch_bounds__(PT)
 k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, NodeState* st,
         T* __restrict__ front, int32_t* __restrict__ piv, int32_t* __restrict__ snap,
-        T* __restrict__ dval, int32_t* __restrict__ physmap, int32_t* __restrict__ dslot,
-        T* __restrict__ stage, int k0p, double tau, int first_unit) {
+        T* __restrict__ dval, int32_t* __restrict__ physmap, T* __restrict__ lbuf, int k0p, double tau,
+        int first_unit) {
   constexpr int NB = PanelWidth<T>::value;
   constexpr int NW = PT / 64;
   const int j = lnodes[blockIdx.x];
@@ -197,8 +197,6 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   __shared__ T pubI_d[2];
   __shared__ int pubI_idx[2], pubI_ph[2];
   __shared__ T Dl[NB];
-  __shared__ int nd;
-  __shared__ int dl_ph[NB];
 
   T Lp[PROWS][NB], dgr[PROWS], Dlr[NB];
   int idxr[PROWS], ph[PROWS];
@@ -226,7 +224,6 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     r0.ph = 0;
     rec[tid / NW][tid % NW] = r0;
   }
-  if (tid == 0) nd = 0;
   __syncthreads();
   double dprev = s0.dprev;
   int have_prev = (s0.npiv > 0) ? 1 : first_unit;
@@ -367,31 +364,17 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     have_prev = 1;
   }
   const int nacc = i - k0p;
-  // displaced trailing positions: their storage columns go to the scratch
+  // storage index of every trailing position (k_trail_update resolves the
+  // exchanges from it; the panel's storage columns keep their values until then)
   int32_t* pm = physmap + ni.start + k0p;
-  int32_t* dsl = dslot + ni.start + k0p;
 #pragma unroll
   for (int s = 0; s < PROWS; ++s) {
     const int q = tid + PT * s;
-    if (q >= nacc && q < P) {
-      int slot = -1;
-      if (ph[s] != q) {  // at most one displaced position per pivot of the panel
-        slot = min(atomicAdd(&nd, 1), NB - 1);
-        dl_ph[slot] = ph[s];
-      }
-      pm[q] = ph[s];
-      dsl[q] = slot;
-    }
+    if (q >= nacc && q < P) pm[q] = ph[s];
   }
-  __syncthreads();
-  T* stg = stage + (int64_t)NB * 2 * ni.start;  // up to NB columns of P values
-  const int ndisp = min(nd, NB);
-  for (int e = 0; e < ndisp; ++e) {
-    const T* src = Fb + (uint32_t)dl_ph[e] * f;
-    for (int r = tid; r < P; r += PT) stg[(int64_t)e * P + r] = src[r];
-  }
-  __syncthreads();
-  // the panel's L columns in position order, the pivots on the diagonal
+  // the panel's L columns, in position order, to the side buffer; the snapshot
+  // of the position -> index map
+  T* Lb = lbuf + ni.lbuf_off + (int64_t)k0p * ni.lbuf_ld + k0p;  // Lb[c*ld + q]
   int32_t* sn = snap + ni.snap_off + (int64_t)(k0p / NB) * p;
 #pragma unroll
   for (int s = 0; s < PROWS; ++s) {
@@ -399,8 +382,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     if (q < P) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        if (c < nacc && c < q) Fb[(uint32_t)c * f + q] = Lp[s][c];
-      if (q < nacc) Fb[(uint32_t)q * f + q] = Dl[q];
+        if (c < nacc && c < q) Lb[(int64_t)c * ni.lbuf_ld + q] = Lp[s][c];
       idx_g[k0p + q] = idxr[s];
       sn[k0p + q] = idxr[s];
     }
@@ -454,8 +436,7 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
                const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval,
-               const int32_t* __restrict__ physmap, const int32_t* __restrict__ dslot,
-               const T* __restrict__ stage, int k0p) {
+               const int32_t* __restrict__ physmap, const T* __restrict__ lbuf, int k0p) {
   constexpr int NB = PanelWidth<T>::value;
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
@@ -476,24 +457,22 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
   T* Fb = front + ni.front_off + (uint32_t)k0p * f + k0p;
   const T* Dk = dval + ni.start + k0p;
   const int32_t* pm = physmap + ni.start + k0p;
-  const int32_t* dsl = dslot + ni.start + k0p;
-  const T* stg = stage + (int64_t)NB * 2 * ni.start;
+  const T* Lb = lbuf + ni.lbuf_off + (int64_t)k0p * ni.lbuf_ld + k0p;  // L[q, c] = Lb[c*ld + q]
+  const int64_t ldl = ni.lbuf_ld;
 
   __shared__ T As[16][64 + 4];
   __shared__ T Bs[16][64 + 4];
-  __shared__ int slx[64], sly[64], phx[64], phy[64];
+  __shared__ int phx[64], phy[64];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int rowA = r0 + ti * 64, rowB = r0 + tj * 64;
   if (tid < 64) {
     const int x = rowA + tid;
-    slx[tid] = x < P ? dsl[x] : -1;
-    phx[tid] = x < P ? pm[x] : x;
+    phx[tid] = x < P ? pm[x] : 0;
   } else if (tid < 128) {
     const int y = rowB + tid - 64;
-    sly[tid - 64] = y < P ? dsl[y] : -1;
-    phy[tid - 64] = y < P ? pm[y] : y;
+    phy[tid - 64] = y < P ? pm[y] : 0;
   }
   __syncthreads();
   // the old values first (their loads overlap the product below)
@@ -508,12 +487,9 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
         const int lx = wc + bj * 16 + (lane & 15);  // lane-fast: the storage row
         const int x = rowA + lx, y = rowB + ly;
         T a = (T)0;
-        if (x < P && y < P && y <= x) {
-          const int sx = slx[lx], sy = sly[ly];
-          if (sx >= 0) a = stg[(int64_t)sx * P + phy[ly]];
-          else if (sy >= 0) a = stg[(int64_t)sy * P + x];
-          else a = Fb[(uint32_t)y * f + x];
-        }
+        // A(x, y) = storage(phys x, phys y): a displaced position's storage is a
+        // column of the panel, which this kernel never writes
+        if (x < P && y < P && y <= x) a = Fb[(uint32_t)phy[ly] * f + phx[lx]];
         old[bi][bj][tt] = a;
       }
   typename Mfma<T>::V acc[2][2];
@@ -529,8 +505,8 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
       const int kg = kk + kq;
       T va = (T)0, vb = (T)0;
       if (kg < NB) {
-        if (rowA + rr < P) va = Fb[(uint32_t)kg * f + rowA + rr];
-        if (rowB + rr < P) vb = Fb[(uint32_t)kg * f + rowB + rr] * Dk[kg];
+        if (rowA + rr < P) va = Lb[kg * ldl + rowA + rr];
+        if (rowB + rr < P) vb = Lb[kg * ldl + rowB + rr] * Dk[kg];
       }
       As[kq][rr] = vb;  // the product is formed transposed: rows of the tile on the lanes
       Bs[kq][rr] = va;
@@ -573,7 +549,7 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_l11_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
              const NodeState* __restrict__ st, const int32_t* __restrict__ piv,
-             const int32_t* __restrict__ snap, T* __restrict__ front) {
+             const int32_t* __restrict__ snap, const T* __restrict__ lbuf, T* __restrict__ front) {
   constexpr int NB = PanelWidth<T>::value;
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
@@ -595,7 +571,7 @@ k_l11_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
     const int c = c0 + cc;
     if (cc < nc && a > c) {
       const int x = inv[pv[a] - ni.start];
-      F[(uint32_t)a * f + c] = F[(uint32_t)c * f + x];
+      F[(uint32_t)a * f + c] = lbuf[ni.lbuf_off + (int64_t)c * ni.lbuf_ld + x];
     }
   }
 }
@@ -604,7 +580,7 @@ k_l11_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
 template <class T>
 __global__ void __launch_bounds__(256)
 k_l11_back(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-           const NodeState* __restrict__ st, T* __restrict__ front) {
+           const NodeState* __restrict__ st, const T* __restrict__ dval, T* __restrict__ front) {
   const int j = lnodes[blockIdx.z];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -626,6 +602,7 @@ k_l11_back(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
     const int cc = (tid >> 6) + 4 * q;  // L[a0 + l, c0 + cc] written along a
     const int a = a0 + l, c = c0 + cc;
     if (a < npiv && c < a) F[(uint32_t)c * f + a] = tile[l][cc];
+    if (a < npiv && c == a) F[(uint32_t)c * f + a] = dval[ni.start + a];
   }
 }
 
@@ -967,8 +944,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
   ctx->d_piv.alloc((size_t)n * sizeof(int32_t));
   ctx->d_snap.alloc((size_t)std::max<int64_t>(ctx->snap_elems, 1) * sizeof(int32_t));
   ctx->d_physmap.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
-  ctx->d_dslot.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
-  ctx->d_stage.alloc((size_t)std::max<int64_t>(n, 1) * 2 * PanelWidth<T>::value * sizeof(T));
+  ctx->d_lbuf.alloc((size_t)std::max<int64_t>(ctx->lbuf_elems, 1) * sizeof(T));
   ctx->d_linv.alloc((size_t)std::max<int64_t>(ctx->linv_elems, 1) * sizeof(T));
   ctx->d_dval.alloc((size_t)n * sizeof(T));
   ctx->d_q.alloc((size_t)n * sizeof(double));
@@ -1049,8 +1025,8 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
       });
       timed(tm, HF_K_PANEL, w1.first, w1.second, s, [&] {
         k_panel<T><<<nl, PT, 0, s>>>(lnodes, nodes, st, front, ctx->d_piv.as<int32_t>(), ctx->d_snap.as<int32_t>(),
-                                     ctx->d_dval.as<T>(), ctx->d_physmap.as<int32_t>(), ctx->d_dslot.as<int32_t>(),
-                                     ctx->d_stage.as<T>(), k0p, ctx->opt.tau, ctx->opt.first_pivot_unit);
+                                     ctx->d_dval.as<T>(), ctx->d_physmap.as<int32_t>(), ctx->d_lbuf.as<T>(), k0p,
+                                     ctx->opt.tau, ctx->opt.first_pivot_unit);
       });
       const int nr = maxp - (k0p + NBP);
       if (nr > 0) {
@@ -1064,20 +1040,20 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         });
         timed(tm, HF_K_F11_UPDATE, w2.first, w2.second, s, [&] {
           k_trail_update<T><<<grid, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(),
-                                                 ctx->d_physmap.as<int32_t>(), ctx->d_dslot.as<int32_t>(),
-                                                 ctx->d_stage.as<T>(), k0p);
+                                                 ctx->d_physmap.as<int32_t>(), ctx->d_lbuf.as<T>(), k0p);
         });
       }
     }
-    // L11 columns of every panel in pivot order (row exchanges of later panels)
-    if (maxp > NBP) {
+    // L11 columns of every panel in pivot order (row exchanges of later panels),
+    // from the side buffer into the front
+    if (maxp > 0) {
       auto wp = level_sum([&](const NodeInfo& ni, double& by, double& fl) { by += 2.0 * ni.p * ni.p * sz; });
       timed(tm, HF_K_PERMUTE_L11, wp.first, 0.0, s, [&] {
         dim3 g1(cdiv(maxp, NBP), (unsigned)nl);
         k_l11_gather<T><<<g1, 256, 0, s>>>(lnodes, nodes, st, ctx->d_piv.as<int32_t>(), ctx->d_snap.as<int32_t>(),
-                                           front);
+                                           ctx->d_lbuf.as<T>(), front);
         dim3 g2(cdiv(maxp, 64), cdiv(maxp, 64), (unsigned)nl);
-        k_l11_back<T><<<g2, 256, 0, s>>>(lnodes, nodes, st, front);
+        k_l11_back<T><<<g2, 256, 0, s>>>(lnodes, nodes, st, ctx->d_dval.as<T>(), front);
       });
     }
     // inverses of the 64x64 diagonal blocks of the level's L11 (TRSM and sweeps)

@@ -68,6 +68,7 @@ struct NodeInfo {
   int64_t front_off;  // offset of the front in the arena
   int64_t rhs_off;    // offset (rows) of the node's block in the solve arena
   int64_t snap_off;   // offset of the node's per-panel position -> index snapshots
+  int64_t lbuf_off;   // offset of the node's panel columns of L (p columns, leading dimension lbuf_ld)
   int32_t start;      // first position of the node in elimination order
   int32_t p;          // pivot candidates
   int32_t b;          // border size
@@ -76,6 +77,7 @@ struct NodeInfo {
   int32_t child_begin;  // into child_list
   int32_t child_end;
   int32_t border_off;   // into border / relmap (int32 is enough: < 2^31 entries)
+  int32_t lbuf_ld;      // p rounded up to a multiple of 4
 };
 
 // Mutable per-node factorization state on the device.
@@ -177,7 +179,7 @@ struct hf_ctx {
   std::vector<int64_t> linv2_off;
   int64_t linv2_elems = 0;
   std::vector<int32_t> ea_items;
-  int64_t front_elems = 0, rhs_rows = 0, snap_elems = 0;
+  int64_t front_elems = 0, rhs_rows = 0, snap_elems = 0, lbuf_elems = 0;
   int32_t max_front = 0, max_p = 0;
   double flops_sym = 0.0, flops_done = 0.0;
   int64_t factor_entries = 0;
@@ -191,8 +193,8 @@ struct hf_ctx {
   hf::DBuf d_state, d_piv, d_dval; // NodeState[n_nodes], piv_order[n], D[n] (T)
   hf::DBuf d_ipos;                 // position of each index in its node's pivot order
   hf::DBuf d_snap;                 // per panel: index at every position of the node when it ended
-  hf::DBuf d_physmap, d_dslot;     // per position: storage index / scratch slot after the last panel
-  hf::DBuf d_stage;                // per node: storage columns of displaced positions (2 NB x p)
+  hf::DBuf d_physmap;              // per position: storage index after the last panel
+  hf::DBuf d_lbuf;                 // per node: the panels' L columns, rows in the order of their panel
   hf::DBuf d_linv, d_linv_off, d_blk_node, d_blk_first;  // inverses of 64x64 diagonal blocks
   hf::DBuf d_linv2, d_linv2_off, d_stp_node, d_stp_first;  // inverses of 256x256 step blocks
   hf::DBuf d_zb_arena;             // second solve arena (step results)
