@@ -97,11 +97,27 @@ __global__ void k_extend_add(const int32_t* __restrict__ items, int nitems,
 
 constexpr int PT = 512;               // threads of the panel kernel (2 waves per SIMD: 256 VGPRs each)
 constexpr int PROWS = 4096 / PT;      // pivot-block rows per thread (nodes hold at most 4096 indices)
+// register slots a panel launch needs: the level's largest remaining pivot
+// block, rounded up to a power of two times PT
+inline int panel_slots(int rem) { return rem <= PT ? 1 : rem <= 2 * PT ? 2 : rem <= 4 * PT ? 4 : PROWS; }
 
 // Panel width: the panel's L values of every pivot-block row stay in registers.
 template <class T>
 struct PanelWidth {
   static constexpr int value = sizeof(T) == 4 ? 16 : 8;
+};
+// one row of panel values as a register vector: an element chosen by a
+// wave-uniform index is read or written in place (GPR index mode), with no
+// select over the whole row
+template <class T>
+struct PanelRow;
+template <>
+struct PanelRow<float> {
+  typedef float V __attribute__((ext_vector_type(16)));
+};
+template <>
+struct PanelRow<double> {
+  typedef double V __attribute__((ext_vector_type(8)));
 };
 
 // Wave-wide reductions with DPP row shifts and row broadcasts; the result of
@@ -161,11 +177,11 @@ __device__ __forceinline__ int wave_min(int v) {
 // (left-looking inside the panel).  The posted copies alternate between two
 // buffers, so a buffer is rewritten only after every thread has passed the next
 // barrier.
-// At the end, the storage columns of the displaced trailing positions are
-// copied to a scratch (k_trail_update resolves the map from there), the panel's
-// L columns are written in position order, and a snapshot of the position ->
-// index map is kept for k_l11_gather.
-template <class T>
+// At the end, the storage index of every trailing position goes to `physmap`
+// (k_trail_update reads its source tiles through it; no storage column moves),
+// the panel's L columns go to the side buffer `lbuf` in position order, and a
+// snapshot of the position -> index map is kept for k_l11_gather.
+template <class T, int PR>
 __global__ void __launch_bounds__(PT)
 k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, NodeState* st,
         T* __restrict__ front, int32_t* __restrict__ piv, int32_t* __restrict__ snap,
@@ -176,7 +192,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   const int j = lnodes[blockIdx.x];
   const NodeInfo ni = nodes[j];
   const NodeState s0 = st[j];
-  if (s0.done || k0p >= ni.p) return;
+  if (s0.done || k0p >= ni.p || ni.p - k0p > PR * PT) return;  // the launch sizes PR for the level
   const int p = ni.p;
   const uint32_t f = (uint32_t)ni.f;  // fronts hold fewer than 2^31 entries (checked at analysis)
   T* F = front + ni.front_off;
@@ -192,21 +208,20 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     int id, k, ph;
   };
   __shared__ WaveRec rec[2][NW];
-  __shared__ T pubK[2][NW][NB];  // panel row of each wave's candidate
-  __shared__ T pubI[2][NB];      // panel row of position i
+  __shared__ __align__(64) T pubK[2][NW][NB];  // panel row of each wave's candidate
+  __shared__ __align__(64) T pubI[2][NB];      // panel row of position i
   __shared__ T pubI_d[2];
   __shared__ int pubI_idx[2], pubI_ph[2];
-  __shared__ T Dl[NB];
+  using Row = typename PanelRow<T>::V;
 
-  T Lp[PROWS][NB], dgr[PROWS], Dlr[NB];
-  int idxr[PROWS], ph[PROWS];
+  Row Lp[PR];
+  Row Dlr = (Row)((T)0);
+  T dgr[PR];
+  int idxr[PR], ph[PR];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) Dlr[c] = (T)0;
-#pragma unroll
-  for (int s = 0; s < PROWS; ++s) {
+  for (int s = 0; s < PR; ++s) {
     const int q = tid + PT * s;
-#pragma unroll
-    for (int c = 0; c < NB; ++c) Lp[s][c] = (T)0;
+    Lp[s] = (Row)((T)0);
     dgr[s] = (T)0;
     idxr[s] = INT_MAX;
     ph[s] = q;
@@ -237,7 +252,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     T av = (T)-1;
     int aid = INT_MAX, as = -1;
 #pragma unroll
-    for (int s = 0; s < PROWS; ++s) {  // branch-free: bitwise tests and selects
+    for (int s = 0; s < PR; ++s) {  // branch-free: bitwise tests and selects
       const int q = tid + PT * s;
       const T v = (q >= qi && q < P) ? fabs(dgr[s]) : (T)-1;
       const bool better = (v > av) | ((v == av) & (idxr[s] < aid));
@@ -248,11 +263,11 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     const T wmax = wave_max(av);
     const int wid = wave_min(av == wmax ? aid : INT_MAX);
     if (wmax >= (T)0 && av == wmax && aid == wid) {  // the wave's winner posts its row
+      const int asu = __builtin_amdgcn_readfirstlane(as);  // one lane: uniform here
 #pragma unroll
-      for (int s = 0; s < PROWS; ++s)
-        if (s == as) {
-#pragma unroll
-          for (int c = 0; c < NB; ++c) pubK[par][wv][c] = Lp[s][c];
+      for (int s = 0; s < PR; ++s)
+        if (s == asu) {
+          *reinterpret_cast<Row*>(pubK[par][wv]) = Lp[s];
           WaveRec r1;
           r1.v = wmax;
           r1.d = dgr[s];
@@ -273,24 +288,32 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     }
     if (tid == ti) {
 #pragma unroll
-      for (int s = 0; s < PROWS; ++s)
+      for (int s = 0; s < PR; ++s)
         if (s == si) {
-#pragma unroll
-          for (int c = 0; c < NB; ++c) pubI[par][c] = Lp[s][c];
+          *reinterpret_cast<Row*>(pubI[par]) = Lp[s];
           pubI_d[par] = dgr[s];
           pubI_idx[par] = idxr[s];
           pubI_ph[par] = ph[s];
         }
     }
     __syncthreads();
+    // the wave records, read together, then combined without branches
+    WaveRec rw[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) rw[w] = rec[par][w];
     int ww = 0;
-    WaveRec best = rec[par][0];
+    T bv = rw[0].v;
+    int bid = rw[0].id;
 #pragma unroll
     for (int w = 1; w < NW; ++w) {
-      const WaveRec o = rec[par][w];
-      if (o.v > best.v || (o.v == best.v && o.id < best.id)) { best = o; ww = w; }
+      const bool g = (rw[w].v > bv) | ((rw[w].v == bv) & (rw[w].id < bid));
+      bv = g ? rw[w].v : bv;
+      bid = g ? rw[w].id : bid;
+      ww = g ? w : ww;
     }
-    const int bid = best.id;
+    ww = __builtin_amdgcn_readfirstlane(ww);
+    const WaveRec best = rec[par][ww];
+    const Row rowK = *reinterpret_cast<const Row*>(pubK[par][ww]);  // panel row of the pivot row
     const int qk = min(max(best.k, qi), P - 1);
     const T d = best.d;
     const int phK = min(max(best.ph, 0), P - 1);
@@ -299,17 +322,17 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     if (!stop && have_prev && fabs(dk) < tau * fabs(dprev)) stop = true;
     if (stop) break;  // uniform: every thread computed the same decision
     const int tk = qk % PT, sk = qk / PT;
-    const T* bufK = pubK[par][ww];  // panel row of the pivot row (LDS)
     // positions i and k exchange rows, diagonals, indices and storage indices
     if (qk != qi) {
       if (tid == tk) {
+        const Row rowI = *reinterpret_cast<const Row*>(pubI[par]);
         const T dI = pubI_d[par];
         const int idI = pubI_idx[par], phI = pubI_ph[par];
 #pragma unroll
-        for (int s = 0; s < PROWS; ++s)
+        for (int s = 0; s < PR; ++s)
           if (s == sk) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c) Lp[s][c] = pubI[par][c];
+            __asm__ volatile("");  // keeps this a branch: only one slot is written
+            Lp[s] = rowI;
             dgr[s] = dI;
             idxr[s] = idI;
             ph[s] = phI;
@@ -317,58 +340,60 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
       }
       if (tid == ti) {
 #pragma unroll
-        for (int s = 0; s < PROWS; ++s)
+        for (int s = 0; s < PR; ++s)
           if (s == si) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c) Lp[s][c] = bufK[c];
+            __asm__ volatile("");  // keeps this a branch: only one slot is written
+            Lp[s] = rowK;
             idxr[s] = bid;
             ph[s] = phK;
           }
       }
     }
-    if (tid == 0) {
-      Dl[qi] = d;  // read from the next pivot on, after its barrier
-      D[i] = d;
-    }
-    // u_c = D_c L[i, c] for the panel columns so far (row i after the exchange)
-    T u[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      if (c == qi) Dlr[c] = d;  // every thread keeps the panel's pivots
-      u[c] = (c < qi) ? Dlr[c] * bufK[c] : (T)0;
-    }
+    // u_c = D_c L[i, c] for the panel columns so far (row i after the exchange);
+    // the pivots of later columns are still zero, as are the row's later values
+    const Row u = Dlr * rowK;
+    Dlr[qi] = d;  // every thread keeps the panel's pivots
     const T inv = (T)1 / d;
     // the pivot column: storage column phK at the storage rows of the positions
     const T* colK = Fb + (uint32_t)phK * f;
-    T vn[PROWS];
+    T v[PR];
 #pragma unroll
-    for (int s = 0; s < PROWS; ++s) {
+    for (int s = 0; s < PR; ++s) {
       const int q = tid + PT * s;
-      vn[s] = (q > qi && q < P) ? colK[ph[s]] : (T)0;
+      v[s] = (q > qi && q < P) ? colK[ph[s]] : (T)0;
     }
+    // left-looking column: only the qi columns factored so far contribute
+    // (qi is uniform, so the cut is a scalar branch)
 #pragma unroll
-    for (int s = 0; s < PROWS; ++s) {
-      const int q = tid + PT * s;
-      if (q > qi && q < P) {
-        T v = vn[s];
+    for (int c = 0; c < NB; ++c) {
+      if (c < qi) {
 #pragma unroll
-        for (int c = 0; c < NB; ++c) v -= Lp[s][c] * u[c];
-        const T l = v * inv;
-        dgr[s] -= l * v;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c == qi) Lp[s][c] = l;
+        for (int s = 0; s < PR; ++s) v[s] -= Lp[s][c] * u[c];
       }
+    }
+    // rows at or before the pivot position and padding rows keep zeros in the
+    // new column; their diagonals are never read again
+#pragma unroll
+    for (int s = 0; s < PR; ++s) {
+      const int q = tid + PT * s;
+      const bool live = (q > qi) & (q < P);
+      const T l = live ? v[s] * inv : (T)0;
+      dgr[s] -= l * v[s];
+      Lp[s][qi] = l;
     }
     dprev = dk;
     have_prev = 1;
   }
   const int nacc = i - k0p;
+  // the panel's pivots
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    if (tid == c && c < nacc) D[k0p + c] = Dlr[c];
   // storage index of every trailing position (k_trail_update resolves the
   // exchanges from it; the panel's storage columns keep their values until then)
   int32_t* pm = physmap + ni.start + k0p;
 #pragma unroll
-  for (int s = 0; s < PROWS; ++s) {
+  for (int s = 0; s < PR; ++s) {
     const int q = tid + PT * s;
     if (q >= nacc && q < P) pm[q] = ph[s];
   }
@@ -377,7 +402,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   T* Lb = lbuf + ni.lbuf_off + (int64_t)k0p * ni.lbuf_ld + k0p;  // Lb[c*ld + q]
   int32_t* sn = snap + ni.snap_off + (int64_t)(k0p / NB) * p;
 #pragma unroll
-  for (int s = 0; s < PROWS; ++s) {
+  for (int s = 0; s < PR; ++s) {
     const int q = tid + PT * s;
     if (q < P) {
 #pragma unroll
@@ -1002,19 +1027,16 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
           fl += 0.5 * b * b;
         }
       dim3 grid(cdiv(el.maxb, 16), (unsigned)el.count);
-      timed(tm, HF_K_EXTEND_ADD, by, fl, s, [&] {
-        k_extend_add<T><<<grid, 256, 0, s>>>(ctx->d_ea_items.as<int32_t>() + el.off, el.count, nodes,
-                                             ctx->d_relmap.as<int32_t>(), front);
-      });
+      launch_timed(tm, HF_K_EXTEND_ADD, by, fl, s, k_extend_add<T>, grid, dim3(256),
+                   (const int32_t*)(ctx->d_ea_items.as<int32_t>() + el.off), el.count, nodes,
+                   (const int32_t*)ctx->d_relmap.as<int32_t>(), front);
     }
     // F11 panels
     constexpr int NBP = PanelWidth<T>::value;
     const int maxp = ctx->level_maxp[l];
     if (maxp > 1) {
-      timed(tm, HF_K_OTHER, 0.0, 0.0, s, [&] {
-        dim3 gm(cdiv(maxp, 64), cdiv(maxp, 64), (unsigned)nl);
-        k_mirror<T><<<gm, 256, 0, s>>>(lnodes, nodes, front);
-      });
+      dim3 gm(cdiv(maxp, 64), cdiv(maxp, 64), (unsigned)nl);
+      launch_timed(tm, HF_K_OTHER, 0.0, 0.0, s, k_mirror<T>, gm, dim3(256), lnodes, nodes, front);
     }
     for (int k0p = 0; k0p < maxp; k0p += NBP) {
       auto w1 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
@@ -1023,11 +1045,12 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         by += 2.0 * r * nb * sz;
         fl += nb * nb * r;
       });
-      timed(tm, HF_K_PANEL, w1.first, w1.second, s, [&] {
-        k_panel<T><<<nl, PT, 0, s>>>(lnodes, nodes, st, front, ctx->d_piv.as<int32_t>(), ctx->d_snap.as<int32_t>(),
-                                     ctx->d_dval.as<T>(), ctx->d_physmap.as<int32_t>(), ctx->d_lbuf.as<T>(), k0p,
-                                     ctx->opt.tau, ctx->opt.first_pivot_unit);
-      });
+      const int slots = panel_slots(maxp - k0p);
+      auto kp = slots == 1 ? k_panel<T, 1> : slots == 2 ? k_panel<T, 2> : slots == 4 ? k_panel<T, 4> : k_panel<T, PROWS>;
+      launch_timed(tm, HF_K_PANEL, w1.first, w1.second, s, kp, dim3((unsigned)nl), dim3(PT), lnodes, nodes,
+                   st, front, ctx->d_piv.as<int32_t>(), ctx->d_snap.as<int32_t>(), ctx->d_dval.as<T>(),
+                   ctx->d_physmap.as<int32_t>(), ctx->d_lbuf.as<T>(), k0p, ctx->opt.tau,
+                   (int)ctx->opt.first_pivot_unit);
       const int nr = maxp - (k0p + NBP);
       if (nr > 0) {
         const int nt = (nr + 63) / 64;
@@ -1038,10 +1061,9 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
           by += (r * NBP + r * r) * sz;
           fl += r * r * NBP;
         });
-        timed(tm, HF_K_F11_UPDATE, w2.first, w2.second, s, [&] {
-          k_trail_update<T><<<grid, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(),
-                                                 ctx->d_physmap.as<int32_t>(), ctx->d_lbuf.as<T>(), k0p);
-        });
+        launch_timed(tm, HF_K_F11_UPDATE, w2.first, w2.second, s, k_trail_update<T>, grid, dim3(256), lnodes, nodes,
+                     (const NodeState*)st, front, (const T*)ctx->d_dval.as<T>(),
+                     (const int32_t*)ctx->d_physmap.as<int32_t>(), (const T*)ctx->d_lbuf.as<T>(), k0p);
       }
     }
     // L11 columns of every panel in pivot order (row exchanges of later panels),
@@ -1059,9 +1081,8 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
     // inverses of the 64x64 diagonal blocks of the level's L11 (TRSM and sweeps)
     if (maxp > 0) {
       dim3 gi(cdiv(maxp, 64), (unsigned)nl);
-      timed(tm, HF_K_OTHER, 0.0, 0.0, s, [&] {
-        k_inv_diag<T><<<gi, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_linv_off.as<int64_t>(), ctx->d_linv.as<T>());
-      });
+      launch_timed(tm, HF_K_OTHER, 0.0, 0.0, s, k_inv_diag<T>, gi, dim3(256), lnodes, nodes, (const NodeState*)st,
+                   (const T*)front, (const int64_t*)ctx->d_linv_off.as<int64_t>(), ctx->d_linv.as<T>());
     }
     // F21, F22
     const int maxb = ctx->level_maxb[l];
@@ -1073,10 +1094,9 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         fl += b * p * p;
       });
       auto wg = level_sum([&](const NodeInfo& ni, double& by, double& fl) { by += 2.0 * ni.b * ni.p * sz; });
-      timed(tm, HF_K_GATHER_BORDER, wg.first, 0.0, s, [&] {
-        dim3 gg(cdiv(maxp, 64), cdiv(maxb, 64), (unsigned)nl);
-        k_gather_border<T><<<gg, 256, 0, s>>>(lnodes, nodes, st, ctx->d_piv.as<int32_t>(), front);
-      });
+      dim3 gg(cdiv(maxp, 64), cdiv(maxb, 64), (unsigned)nl);
+      launch_timed(tm, HF_K_GATHER_BORDER, wg.first, 0.0, s, k_gather_border<T>, gg, dim3(256), lnodes, nodes,
+                   (const NodeState*)st, (const int32_t*)ctx->d_piv.as<int32_t>(), front);
       // windows of TW columns: the solved columns' contribution to a window is
       // one GEMM over the whole border, the window itself a 64-block TRSM
       constexpr int TW = 256;
@@ -1097,9 +1117,8 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         by += (b * p + b * b) * sz;
         fl += b * b * p;
       });
-      timed(tm, HF_K_SYRK, w4.first, w4.second, s, [&] {
-        k_syrk<T><<<g2, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>());
-      });
+      launch_timed(tm, HF_K_SYRK, w4.first, w4.second, s, k_syrk<T>, g2, dim3(256), lnodes, nodes,
+                   (const NodeState*)st, front, (const T*)ctx->d_dval.as<T>());
     }
     HF_HIP(hipGetLastError());
   }

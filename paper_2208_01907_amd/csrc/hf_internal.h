@@ -1,6 +1,7 @@
 // Internal declarations of the hybrid factorization library (host side).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -151,6 +152,21 @@ inline void timed(KTimer& tm, int cls, double bytes, double flops, hipStream_t s
   launch();
   HF_HIP(hipEventRecord(b, s));
   tm.recs.push_back({cls, a, b, bytes, flops});
+}
+
+// Single-kernel launch; with timing on, the events take the start and end of
+// the kernel's own execution (dispatch profiling), not the stream positions
+// around it, so the per-kernel times exclude launch gaps.
+template <class K, class... A>
+inline void launch_timed(KTimer& tm, int cls, double bytes, double flops, hipStream_t s, K kernel, dim3 grid,
+                         dim3 block, A... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (tm.on) {
+    a = tm.next();
+    b = tm.next();
+    tm.recs.push_back({cls, a, b, bytes, flops});
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, args...);
 }
 
 }  // namespace hf

@@ -713,9 +713,8 @@ static void gram(hf_ctx* ctx, int64_t n, int a, const double* A, int64_t sA, int
   BgcrWork& w = *ctx->work;
   dim3 grid(GRAM_WG, nA);
   const double by = (double)n * (a * (double)nA + b) * 8.0, fl = 2.0 * n * a * b * (double)nA;
-  timed(ctx->timer, HF_K_GRAM, by, fl, s, [&] {
-    k_gram_partial<<<grid, 256, 0, s>>>(n, a, A, sA, b, B, w.partial.as<double>());
-  });
+  launch_timed(ctx->timer, HF_K_GRAM, by, fl, s, k_gram_partial, grid, dim3(256), n, a, A, sA, b, B,
+               w.partial.as<double>());
   timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, [&] {
     k_gram_reduce<<<cdiv((int64_t)nA * a * b, 256), 256, 0, s>>>(nA, a * b, w.partial.as<double>(), C);
   });
@@ -725,10 +724,9 @@ static void spmm_k11(hf_ctx* ctx, int m, const double* W, double* Y, hipStream_t
   const int64_t nm = ctx->n * m;
   if (nm == 0) return;
   const double by = ctx->nnz * 12.0 + ctx->n * 8.0 + 2.0 * nm * 8.0, fl = 2.0 * ctx->nnz * m;
-  timed(ctx->timer, HF_K_SPMM, by, fl, s, [&] {
-    k_spmm_k11<<<cdiv(nm, 256), 256, 0, s>>>(ctx->n, ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(),
-                                             ctx->d_kval.as<double>(), ctx->d_isl2.as<uint8_t>(), m, W, Y);
-  });
+  launch_timed(ctx->timer, HF_K_SPMM, by, fl, s, k_spmm_k11, dim3((unsigned)cdiv(nm, 256)), dim3(256), ctx->n,
+               ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(), ctx->d_kval.as<double>(),
+               ctx->d_isl2.as<uint8_t>(), m, W, Y);
 }
 
 // out (n x b) = base + sum_t V_t (n x a) C_t (a x b), row-major blocks
@@ -737,9 +735,8 @@ static void combine(hf_ctx* ctx, int64_t n, int a, int b, double* out, const dou
   if (n * b == 0) return;
   const double by = ((double)nterms * n * a + (base ? 2.0 : 1.0) * n * b) * 8.0;
   const double fl = 2.0 * n * a * b * (double)nterms;
-  timed(ctx->timer, HF_K_COMBINE, by, fl, s, [&] {
-    k_combine<<<cdiv(n, 64), 256, 0, s>>>(n, a, b, out, base, nterms, V, sV, coef);
-  });
+  launch_timed(ctx->timer, HF_K_COMBINE, by, fl, s, k_combine, dim3((unsigned)cdiv(n, 64)), dim3(256), n, a, b, out,
+               base, nterms, V, sV, coef);
 }
 
 static void precond(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s) {

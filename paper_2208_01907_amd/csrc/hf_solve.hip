@@ -583,11 +583,11 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         by += 0.5 * nc * nc * sz + 2.0 * nc * dm * sz;
         fl += dm * nc * nc;
       });
-      timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s, [&] {
+      {
         dim3 g(tb / SB, nl);
-        if (wide(g)) k_fwd_diag<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, tb, m, rb, zb);
-        else k_fwd_diag<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, J0, tb, m, rb, zb);
-      });
+        launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s, wide(g) ? k_fwd_diag<T, KBW> : k_fwd_diag<T, KBN>, g,
+                     dim3(256), ln, nodes, st, loff2, linv2, J0, tb, m, rb, zb);
+      }
       const int rows = maxf - J0 - 1;
       if (rows > 0) {
         dim3 g(cdiv(rows, 64), nl);
@@ -599,10 +599,8 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           by += below * nc * sz + 2.0 * below * dm * sz + nc * dm * sz;
           fl += 2.0 * dm * below * nc;
         });
-        timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s, [&] {
-          if (wide(g)) k_fwd_upd<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, tb, m, zb, rb);
-          else k_fwd_upd<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, tb, m, zb, rb);
-        });
+        launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s, wide(g) ? k_fwd_upd<T, KBW> : k_fwd_upd<T, KBN>, g,
+                     dim3(256), ln, nodes, st, front, J0, tb, m, zb, rb);
       }
     }
   }
@@ -625,11 +623,10 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         dim3 gy(cdiv((int64_t)ctx->level_maxb[l] * m, 256), nl);
         k_bwd_gather<T><<<gy, 256, 0, s>>>(ln, nodes, ctx->d_border.as<int32_t>(), m, Y, rb);
       });
-      timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s, [&] {
-        dim3 gp(cdiv(maxp, 64), maxch, nl);
-        if (wide(gp)) k_bwd_border_part<T, KBW><<<gp, 256, 0, s>>>(ln, nodes, st, front, rb, m, maxch, maxp, part);
-        else k_bwd_border_part<T, KBN / 2><<<gp, 256, 0, s>>>(ln, nodes, st, front, rb, m, maxch, maxp, part);
-      });
+      dim3 gp(cdiv(maxp, 64), maxch, nl);
+      launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
+                   wide(gp) ? k_bwd_border_part<T, KBW> : k_bwd_border_part<T, KBN / 2>, gp, dim3(256), ln, nodes, st,
+                   front, rb, m, maxch, maxp, part);
     }
     auto wf = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
       by += 3.0 * np * dm * sz;
@@ -646,13 +643,11 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         by += 0.5 * nc * nc * sz + 2.0 * nc * dm * sz + nc * dm * 8.0;
         fl += dm * nc * nc;
       });
-      timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s, [&] {
+      {
         dim3 g(tb / SB, nl);
-        if (wide(g))
-          k_bwd_diag<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
-        else
-          k_bwd_diag<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
-      });
+        launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s, wide(g) ? k_bwd_diag<T, KBW> : k_bwd_diag<T, KBN>, g,
+                     dim3(256), ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
+      }
       if (J0 > 0) {
         dim3 g(cdiv(J0, 64), nl);
         auto wu = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
@@ -661,10 +656,8 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           by += J0 * nc * sz + 2.0 * J0 * dm * sz;
           fl += 2.0 * dm * J0 * nc;
         });
-        timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, [&] {
-          if (wide(g)) k_bwd_upd<T, KBW><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, tb, m, zb, rb);
-          else k_bwd_upd<T, KBN><<<g, 256, 0, s>>>(ln, nodes, st, front, J0, tb, m, zb, rb);
-        });
+        launch_timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, wide(g) ? k_bwd_upd<T, KBW> : k_bwd_upd<T, KBN>, g,
+                     dim3(256), ln, nodes, st, front, J0, tb, m, zb, rb);
       }
     }
   }

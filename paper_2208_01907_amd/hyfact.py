@@ -22,6 +22,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: it ships a HIP runtime under the same soname as the system one
+# the library links; whichever loads first serves the process, and torch's own
+# device initialisation fails when it is handed the other one
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libhyfact.so")
@@ -128,7 +132,6 @@ def _np_ptr(a):
 
 def _stream(stream):
     if stream is None:
-        import torch
         return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
@@ -186,14 +189,12 @@ def hf_analyse(indptr, indices, perm=None, node_ptr=None, parent=None, opt=None)
 
 
 def hf_factorize(ctx: Context, values, stream=None):
-    import torch
     assert values.is_cuda and values.dtype == torch.float64 and values.is_contiguous()
     _check(_lib.hf_factorize(ctx.handle, ctypes.c_void_p(values.data_ptr()), _stream(stream)), "hf_factorize")
 
 
 def hf_solve(ctx: Context, B, X=None, stream=None):
     """Solve for B of shape (L, r) (float64, GPU).  Returns X of shape (L, r)."""
-    import torch
     assert B.is_cuda and B.dtype == torch.float64
     one = B.dim() == 1
     if B.dim() not in (1, 2):
@@ -218,7 +219,6 @@ def hf_kernel_dim(ctx: Context) -> int:
 
 
 def hf_kernel_basis(ctx: Context, stream=None):
-    import torch
     k = hf_kernel_dim(ctx)
     Nc = torch.zeros((k, ctx.n), dtype=torch.float64, device="cuda")
     if k:
@@ -228,7 +228,6 @@ def hf_kernel_basis(ctx: Context, stream=None):
 
 
 def hf_schur(ctx: Context, stream=None):
-    import torch
     m = ctypes.c_int32()
     _check(_lib.hf_schur(ctx.handle, ctypes.byref(m), None, None, 0, _stream(stream)), "hf_schur")
     M = m.value
@@ -241,7 +240,6 @@ def hf_schur(ctx: Context, stream=None):
 
 
 def hf_scaling(ctx: Context, stream=None):
-    import torch
     q = torch.zeros(ctx.n, dtype=torch.float64, device="cuda")
     _check(_lib.hf_scaling(ctx.handle, ctypes.c_void_p(q.data_ptr()), _stream(stream)), "hf_scaling")
     return q
