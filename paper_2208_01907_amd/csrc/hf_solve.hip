@@ -479,6 +479,186 @@ k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
 }
 
 // ---------------------------------------------------------------------------
+// narrow launches: 16-row tiles fed straight from global memory
+// ---------------------------------------------------------------------------
+// Over few fronts a launch has few 64-row tiles, and a workgroup that streams a
+// whole 64 x 512 block of L through its own CU is bound by the loads one CU
+// keeps in flight.  These kernels cut the rows into 16-row tiles (four times
+// the workgroups) and let the four waves of a workgroup take every fourth
+// round of 16 values of k: a wave issues the loads of all its rounds (operands
+// go straight into the matrix-core lane layout, no LDS staging) before its
+// first product, and the four partial tiles are summed through LDS in wave
+// order, so the result does not depend on timing.
+//
+// Rounds per wave: enough for a 512-value k range (8 rounds of 16 per wave).
+template <class T>
+struct NarrowRounds {  // rounds per batch, batches (register budget of FP64)
+  static constexpr int NR = sizeof(T) == 4 ? 8 : 4;
+  static constexpr int NBATCH = sizeof(T) == 4 ? 1 : 2;
+};
+
+// out(r, c) = sum_{kb <= k < ke} A(k, r) B(k, c) for r < 16, c < 16 NCB; the
+// lane (i, g) = (lane % 16, lane / 16) of a wave supplies, in step s of round
+// rd, the operands at k = kb + 16 rd + 4 g + s (the same k for A and B, so the
+// k order inside a round is only a relabelling of the sum).  epi(r, c, v) is
+// called once per output.
+template <class T, int NCB, class FA, class FB, class EPI>
+__device__ __forceinline__ void narrow_product(int kb, int ke, FA&& fa, FB&& fb, EPI&& epi) {
+  using V = typename Mfma<T>::V;
+  constexpr int NR = NarrowRounds<T>::NR, NBATCH = NarrowRounds<T>::NBATCH;
+  static_assert(16 * 4 * NR * NBATCH >= TB, "a wave's rounds cover a step");
+  __shared__ T red[4][NCB][4][64];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, g = lane >> 4;
+  V acc[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = V{0, 0, 0, 0};
+#pragma unroll
+  for (int bt = 0; bt < NBATCH; ++bt) {
+    T a[NR][4], b[NR][NCB][4];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int k0 = kb + 16 * (w + 4 * (bt * NR + q)) + 4 * g;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const bool ok = k0 + s < ke;
+        a[q][s] = ok ? fa(k0 + s, li) : (T)0;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[q][cb][s] = ok ? fb(k0 + s, cb * 16 + li) : (T)0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      if (kb + 16 * (w + 4 * (bt * NR + q)) >= ke) break;  // uniform in the wave
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = Mfma<T>::mma(a[q][s], b[q][cb][s], acc[cb]);
+    }
+  }
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) red[w][cb][t][lane] = acc[cb][t];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NCB; ++i) {
+    const int e = tid + 256 * i;
+    const int ln = e & 63, t = (e >> 6) & 3, cb = e >> 8;
+    const T v = red[0][cb][t][ln] + red[1][cb][t][ln] + red[2][cb][t][ln] + red[3][cb][t][ln];
+    epi(Mfma<T>::row(ln, t), cb * 16 + (ln & 15), v);
+  }
+}
+
+// z_J = Linv_J w_J, 16 rows of the step per workgroup
+template <class T, int NCB>
+__global__ void __launch_bounds__(256)
+k_fwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+             const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
+             const T* __restrict__ linv2, int J0, int tb, int m, const T* __restrict__ rb, T* __restrict__ zb) {
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  if (J0 >= npiv) return;
+  const int nc = min(tb, npiv - J0);
+  const int r0 = 16 * blockIdx.x;
+  if (r0 >= nc) return;
+  const int nrows = min(16, nc - r0);
+  const T* X = step_inverse(linv2, linv2_off[j], J0) + r0;  // A(k, r) = X[k TB + r]
+  const T* W = rb + (ni.rhs_off + J0) * m;
+  T* Z = zb + (ni.rhs_off + J0 + r0) * m;
+  narrow_product<T, NCB>(
+      0, min(nc, r0 + 16), [&](int k, int r) { return r < nrows ? X[(int64_t)k * TB + r] : (T)0; },
+      [&](int k, int c) { return c < m ? W[(int64_t)k * m + c] : (T)0; },
+      [&](int r, int c, T v) {
+        if (r < nrows && c < m) Z[(int64_t)r * m + c] = v;
+      });
+}
+
+// w_rows -= L[rows, J0:J0+nc] z_J for 16 rows below the step per workgroup
+template <class T, int NCB>
+__global__ void __launch_bounds__(256)
+k_fwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+            const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int tb, int m,
+            const T* __restrict__ zb, T* __restrict__ rb) {
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  if (J0 >= npiv) return;
+  const int nc = min(tb, npiv - J0);
+  const int f = ni.f, p = ni.p;
+  const int rs = J0 + nc + 16 * blockIdx.x;
+  if (rs >= f) return;
+  const int nrows = min(16, f - rs);
+  const int64_t lf = f;
+  const T* A = front + ni.front_off + (int64_t)J0 * lf + rs;  // A(k, r) = A[k lf + r]
+  const T* Z = zb + (ni.rhs_off + J0) * m;
+  T* W = rb + (ni.rhs_off + rs) * m;
+  narrow_product<T, NCB>(
+      0, nc, [&](int k, int r) { return r < nrows ? A[(int64_t)k * lf + r] : (T)0; },
+      [&](int k, int c) { return c < m ? Z[(int64_t)k * m + c] : (T)0; },
+      [&](int r, int c, T v) {
+        const int gr = rs + r;
+        if (r < nrows && c < m && !(gr >= npiv && gr < p)) W[(int64_t)r * m + c] -= v;
+      });
+}
+
+// x_J = Linv_J^T t_J, 16 columns of the step per workgroup, scattered to the FP64 result
+template <class T, int NCB>
+__global__ void __launch_bounds__(256)
+k_bwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+             const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
+             const T* __restrict__ linv2, const int32_t* __restrict__ piv, int J0, int tb, int m,
+             double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb) {
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  if (J0 >= npiv) return;
+  const int nc = min(tb, npiv - J0);
+  const int r0 = 16 * blockIdx.x;
+  if (r0 >= nc) return;
+  const int nrows = min(16, nc - r0);
+  const T* X = step_inverse(linv2, linv2_off[j], J0) + (int64_t)r0 * TB;  // A(k, r) = X[r TB + k]
+  const T* W = rb + (ni.rhs_off + J0) * m;
+  const int c0 = J0 + r0;
+  narrow_product<T, NCB>(
+      r0, nc, [&](int k, int r) { return r < nrows ? X[(int64_t)r * TB + k] : (T)0; },
+      [&](int k, int c) { return c < m ? W[(int64_t)k * m + c] : (T)0; },
+      [&](int r, int c, T v) {
+        if (r < nrows && c < m) {
+          zb[(ni.rhs_off + c0 + r) * m + c] = v;
+          Y[(int64_t)piv[ni.start + c0 + r] * m + c] = (double)v;
+        }
+      });
+}
+
+// t_k -= sum_{r in step} L[r, k] x_r for 16 columns k < J0 per workgroup
+template <class T, int NCB>
+__global__ void __launch_bounds__(256)
+k_bwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+            const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int tb, int m,
+            const T* __restrict__ zb, T* __restrict__ rb) {
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  if (J0 >= npiv) return;
+  const int cs = 16 * blockIdx.x;
+  if (cs >= J0) return;
+  const int nc = min(tb, npiv - J0);
+  const int nrows = min(16, J0 - cs);
+  const int64_t lf = ni.f;
+  const T* A = front + ni.front_off + (int64_t)cs * lf + J0;  // A(k, r) = L[J0 + k, cs + r]
+  const T* Z = zb + (ni.rhs_off + J0) * m;
+  T* W = rb + (ni.rhs_off + cs) * m;
+  narrow_product<T, NCB>(
+      0, nc, [&](int k, int r) { return r < nrows ? A[(int64_t)r * lf + k] : (T)0; },
+      [&](int k, int c) { return c < m ? Z[(int64_t)k * m + c] : (T)0; },
+      [&](int r, int c, T v) {
+        if (r < nrows && c < m) W[(int64_t)r * m + c] -= v;
+      });
+}
+
+// ---------------------------------------------------------------------------
 // drivers
 // ---------------------------------------------------------------------------
 
@@ -514,6 +694,10 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   // step length: long steps (fewer sequential launches) over few fronts,
   // half steps (shorter diagonal products) over many
   auto step_of = [](int nl) { return nl < 128 ? TB : HB; };
+  // narrow launches run the 16-row kernels with the fewest column blocks that
+  // hold m
+  const int ncb = m <= 16 ? 1 : m <= 32 ? 2 : 4;
+  auto pick = [&](auto k1, auto k2, auto k4) { return ncb == 1 ? k1 : ncb == 2 ? k2 : k4; };
   const int nlev = (int)ctx->level_ptr.size() - 1;
   const size_t arena = (size_t)std::max<int64_t>(ctx->rhs_rows, 1) * m * sizeof(T);
   ctx->d_rhs_arena.alloc(arena);
@@ -585,8 +769,13 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       });
       {
         dim3 g(tb / SB, nl);
-        launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s, wide(g) ? k_fwd_diag<T, KBW> : k_fwd_diag<T, KBN>, g,
-                     dim3(256), ln, nodes, st, loff2, linv2, J0, tb, m, rb, zb);
+        if (wide(g))
+          launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s, k_fwd_diag<T, KBW>, g, dim3(256), ln, nodes, st,
+                       loff2, linv2, J0, tb, m, rb, zb);
+        else
+          launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s,
+                       pick(k_fwd_diag_n<T, 1>, k_fwd_diag_n<T, 2>, k_fwd_diag_n<T, 4>), dim3(tb / 16, nl), dim3(256),
+                       ln, nodes, st, loff2, linv2, J0, tb, m, rb, zb);
       }
       const int rows = maxf - J0 - 1;
       if (rows > 0) {
@@ -599,8 +788,13 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           by += below * nc * sz + 2.0 * below * dm * sz + nc * dm * sz;
           fl += 2.0 * dm * below * nc;
         });
-        launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s, wide(g) ? k_fwd_upd<T, KBW> : k_fwd_upd<T, KBN>, g,
-                     dim3(256), ln, nodes, st, front, J0, tb, m, zb, rb);
+        if (wide(g))
+          launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s, k_fwd_upd<T, KBW>, g, dim3(256), ln, nodes, st,
+                       front, J0, tb, m, zb, rb);
+        else
+          launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s,
+                       pick(k_fwd_upd_n<T, 1>, k_fwd_upd_n<T, 2>, k_fwd_upd_n<T, 4>), dim3(cdiv(rows, 16), nl),
+                       dim3(256), ln, nodes, st, front, J0, tb, m, zb, rb);
       }
     }
   }
@@ -645,8 +839,13 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       });
       {
         dim3 g(tb / SB, nl);
-        launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s, wide(g) ? k_bwd_diag<T, KBW> : k_bwd_diag<T, KBN>, g,
-                     dim3(256), ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
+        if (wide(g))
+          launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s, k_bwd_diag<T, KBW>, g, dim3(256), ln, nodes, st,
+                       loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
+        else
+          launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s,
+                       pick(k_bwd_diag_n<T, 1>, k_bwd_diag_n<T, 2>, k_bwd_diag_n<T, 4>), dim3(tb / 16, nl), dim3(256),
+                       ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
       }
       if (J0 > 0) {
         dim3 g(cdiv(J0, 64), nl);
@@ -656,8 +855,13 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           by += J0 * nc * sz + 2.0 * J0 * dm * sz;
           fl += 2.0 * dm * J0 * nc;
         });
-        launch_timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, wide(g) ? k_bwd_upd<T, KBW> : k_bwd_upd<T, KBN>, g,
-                     dim3(256), ln, nodes, st, front, J0, tb, m, zb, rb);
+        if (wide(g))
+          launch_timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, k_bwd_upd<T, KBW>, g, dim3(256), ln, nodes, st,
+                       front, J0, tb, m, zb, rb);
+        else
+          launch_timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s,
+                       pick(k_bwd_upd_n<T, 1>, k_bwd_upd_n<T, 2>, k_bwd_upd_n<T, 4>), dim3(cdiv(J0, 16), nl),
+                       dim3(256), ln, nodes, st, front, J0, tb, m, zb, rb);
       }
     }
   }
