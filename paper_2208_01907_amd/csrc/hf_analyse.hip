@@ -318,15 +318,25 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
     }
     ctx->linv_elems = (int64_t)ctx->blk_first[n_nodes] * 64 * 64;
     // step blocks of the triangular sweeps (their inverses drive them)
+    // numbered level by level, so that the steps of one level are contiguous (their
+    // inverses are formed with the level, before its TRSM)
     ctx->stp_first.assign(n_nodes + 1, 0);
     ctx->linv2_off.assign(std::max(n_nodes, 1), 0);
-    for (int32_t j = 0; j < n_nodes; ++j) {
-      const int32_t nb = (ctx->nodes[j].p + HF_SWEEP_STEP - 1) / HF_SWEEP_STEP;
-      ctx->linv2_off[j] = (int64_t)ctx->stp_first[j] * HF_SWEEP_STEP * HF_SWEEP_STEP;
-      ctx->stp_first[j + 1] = ctx->stp_first[j] + nb;
-      for (int32_t q = 0; q < nb; ++q) ctx->stp_node.push_back(j);
+    ctx->lvl_step_ptr.assign(nlev + 1, 0);
+    int32_t nsteps = 0;
+    for (int32_t l = 0; l < nlev; ++l) {
+      for (int32_t q = ctx->level_ptr[l]; q < ctx->level_ptr[l + 1]; ++q) {
+        const int32_t j = ctx->level_nodes[q];
+        const int32_t nb = (ctx->nodes[j].p + HF_SWEEP_STEP - 1) / HF_SWEEP_STEP;
+        ctx->stp_first[j] = nsteps;
+        ctx->linv2_off[j] = (int64_t)nsteps * HF_SWEEP_STEP * HF_SWEEP_STEP;
+        for (int32_t t = 0; t < nb; ++t) ctx->stp_node.push_back(j);
+        nsteps += nb;
+      }
+      ctx->lvl_step_ptr[l + 1] = nsteps;
     }
-    ctx->linv2_elems = (int64_t)ctx->stp_first[n_nodes] * HF_SWEEP_STEP * HF_SWEEP_STEP;
+    ctx->stp_first[n_nodes] = nsteps;
+    ctx->linv2_elems = (int64_t)nsteps * HF_SWEEP_STEP * HF_SWEEP_STEP;
     // device copies of the pattern
     hipStream_t s = nullptr;
     upload(ctx->d_pindptr, pindptr, s);

@@ -13,7 +13,8 @@
 //                 columns symmetrically (this also permutes the columns of F21)
 //                 and computes the pivot column left-looking within the panel;
 //                 a tiled kernel then applies the panel to the trailing F11.
-//   F21 (b x p~): L21 = F21 L11^{-T} D^{-1}  (row-strip blocked TRSM)
+//   F21 (b x p~): L21 = F21 L11^{-T} D^{-1}  (blocked TRSM: windows of one sweep
+//                 step, each a product with the inverse of its diagonal block)
 //   F22 (b x b) : F22 -= L21 D L21^T         (the Schur complement passed to the
 //                 parent; rows of postponed indices are not part of it)
 // Nodes are processed by height levels: all fronts of a level in the same
@@ -740,96 +741,58 @@ k_gather_border(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__
   }
 }
 
+// L21 for the columns of one sweep step [j0, j0 + nc):
+// X(r, c) = sum_{k <= c} Y(r, k) Linv(c, k) / D_c, with Y the step's right-hand
+// side in G (the contribution of the columns left of the step already removed)
+// and Linv the inverse of the step's unit-lower diagonal block.  64x64 tiles of
+// (border rows, step columns); the tile goes through LDS so that the columns of
+// L21 are written along their rows.
 template <class T>
 __global__ void __launch_bounds__(256)
-k_trsm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-       const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval,
-       const int64_t* __restrict__ linv_off, const T* __restrict__ linv, int c_lo, int c_hi) {
-  const int j = lnodes[blockIdx.y];
+k_trsm_apply(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+             const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval,
+             const int64_t* __restrict__ linv2_off, const T* __restrict__ linv2, int j0) {
+  constexpr int KB = SweepStage<T>::value;
+  constexpr int TB = HF_SWEEP_STEP;
+  const int j = lnodes[blockIdx.z];
   const NodeInfo ni = nodes[j];
-  const int npiv = min(st[j].npiv, c_hi);
-  const int b = ni.b;
-  const int rs = blockIdx.x * 64;
-  if (rs >= b || npiv <= c_lo) return;
+  const int npiv = st[j].npiv;
+  const int rs = blockIdx.x * 64, cs = blockIdx.y * 64;
+  if (rs >= ni.b || j0 + cs >= npiv) return;
+  const int nc = min(TB, npiv - j0);
   const int64_t f = ni.f;
   T* F = front + ni.front_off;
-  T* X = F + ni.p + rs;  // X(r, c) = X[c*f + r], r < 64
-  const T* G = F + (int64_t)(ni.p + rs) * f;  // right-hand side in pivot order: G(c, r) = G[r*f + c]
-  const int nrow = min(64, b - rs);
-  const T* Dk = dval + ni.start;
-  const T* L64 = linv + linv_off[j];
-  __shared__ T As[16][64 + 4];
-  __shared__ T Bs[16][64 + 4];
-  __shared__ T Yt[64][64 + 4];  // Yt[c][r]: the block right-hand side, k-major for the second product
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6;
+  const T* Li = linv2 + linv2_off[j] + (int64_t)(j0 / TB) * TB * TB;  // Linv(c, k) = Li[k*TB + c]
+  const T* Y = F + (int64_t)(ni.p + rs) * f + j0;                     // Y(r, k) = Y[r*f + k]
+  const T* Dk = dval + ni.start + j0 + cs;
+  const int nrow = min(64, ni.b - rs), ncol = min(64, nc - cs);
+  __shared__ T As[KB][68];
+  __shared__ T Bs[KB][68];
+  __shared__ T Ot[64][65];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  using V = typename Mfma<T>::V;
-  for (int J0 = c_lo; J0 < npiv; J0 += 64) {
-    const int nc = min(64, npiv - J0);
-    V acc[2][2];
+  typename Mfma<T>::V acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int bb = 0; bb < 2; ++bb) acc[a][bb] = V{0, 0, 0, 0};
-    // acc = X[:, 0:J0] L11[J0:J0+64, 0:J0]^T
-    for (int kk = c_lo; kk < J0; kk += 16) {
+    for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::V{0, 0, 0, 0};
+  tile_gemm_64<T, KB, 68, true>(
+      acc, As, Bs, 0, min(nc, cs + 64), [&](int k, int r) { return r < nrow ? Y[(int64_t)r * f + k] : (T)0; },
+      [&](int k, int c) { return c < ncol ? Li[(int64_t)k * TB + cs + c] : (T)0; }, tid, lane, wr, wc);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + q * 256;
-        const int rr = e & 63, kq = e >> 6;
-        const int kg = kk + kq;
-        As[kq][rr] = (rr < nrow) ? X[(int64_t)kg * f + rr] : (T)0;
-        Bs[kq][rr] = (rr < nc) ? F[(int64_t)kg * f + J0 + rr] : (T)0;
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = wr + bi * 16 + Mfma<T>::row(lane, t);
+        const int c = wc + bj * 16 + (lane & 15);
+        Ot[c][r] = (c < ncol) ? acc[bi][bj][t] / Dk[c] : (T)0;
       }
-      __syncthreads();
-      mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
-      __syncthreads();
-    }
-    // Y = F21[:, J] - acc  (stored transposed, k-major)
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int r = wr + bi * 16 + Mfma<T>::row(lane, t);
-          const int c = wc + bj * 16 + (lane & 15);
-          Yt[c][r] = (r < nrow && c < nc) ? G[(int64_t)r * f + J0 + c] - acc[bi][bj][t] : (T)0;
-        }
-    __syncthreads();
-    // X_J = Y Linv_JJ^T: X[r][c] = sum_k Y[r][k] Linv[c][k]
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb) acc[a][bb] = V{0, 0, 0, 0};
-    const T* Li = L64 + (int64_t)(J0 / 64) * 64 * 64;  // column-major: Linv(c, k) = Li[k*64 + c]
-    for (int kk = 0; kk < 64; kk += 16) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + q * 256;
-        const int cc = e & 63, kq = e >> 6;
-        Bs[kq][cc] = Li[(int64_t)(kk + kq) * 64 + cc];
-      }
-      __syncthreads();
-      mfma_tile_64<T, 16, 68>(reinterpret_cast<const T(*)[68]>(&Yt[kk][0]), Bs, acc, lane, wr, wc);
-      __syncthreads();
-    }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int r = wr + bi * 16 + Mfma<T>::row(lane, t);
-          const int c = wc + bj * 16 + (lane & 15);
-          if (r < nrow && c < nc) X[(int64_t)(J0 + c) * f + r] = acc[bi][bj][t];
-        }
-    __syncthreads();
-  }
-  for (int e = tid; e < 64 * (npiv - c_lo); e += 256) {
-    const int r = e & 63, c = c_lo + (e >> 6);
-    if (r < nrow) X[(int64_t)c * f + r] /= Dk[c];
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int c = e >> 6, r = e & 63;
+    if (r < nrow && c < ncol) F[(int64_t)(j0 + cs + c) * f + ni.p + rs + r] = Ot[c][r];
   }
 }
 
@@ -971,6 +934,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
   ctx->d_physmap.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
   ctx->d_lbuf.alloc((size_t)std::max<int64_t>(ctx->lbuf_elems, 1) * sizeof(T));
   ctx->d_linv.alloc((size_t)std::max<int64_t>(ctx->linv_elems, 1) * sizeof(T));
+  ctx->d_linv2.alloc((size_t)std::max<int64_t>(ctx->linv2_elems, 1) * sizeof(T));
   ctx->d_dval.alloc((size_t)n * sizeof(T));
   ctx->d_q.alloc((size_t)n * sizeof(double));
   ctx->d_kval.alloc((size_t)ctx->nnz * sizeof(double));
@@ -1083,11 +1047,12 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
       dim3 gi(cdiv(maxp, 64), (unsigned)nl);
       launch_timed(tm, HF_K_OTHER, 0.0, 0.0, s, k_inv_diag<T>, gi, dim3(256), lnodes, nodes, (const NodeState*)st,
                    (const T*)front, (const int64_t*)ctx->d_linv_off.as<int64_t>(), ctx->d_linv.as<T>());
+      // and of the sweep step blocks, built from them
+      step_inverses<T>(ctx, l, s);
     }
     // F21, F22
     const int maxb = ctx->level_maxb[l];
     if (maxb > 0) {
-      dim3 g1(cdiv(maxb, 64), (unsigned)nl);
       auto w3 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
         const double b = ni.b, p = ni.p;
         by += (2.0 * b * p + 0.5 * p * p) * sz;  // F21 read, L21 written, L11 read
@@ -1097,17 +1062,16 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
       dim3 gg(cdiv(maxp, 64), cdiv(maxb, 64), (unsigned)nl);
       launch_timed(tm, HF_K_GATHER_BORDER, wg.first, 0.0, s, k_gather_border<T>, gg, dim3(256), lnodes, nodes,
                    (const NodeState*)st, (const int32_t*)ctx->d_piv.as<int32_t>(), front);
-      // windows of TW columns: the solved columns' contribution to a window is
-      // one GEMM over the whole border, the window itself a 64-block TRSM
-      constexpr int TW = 256;
+      // windows of one sweep step: the solved columns' contribution to a window
+      // is one GEMM over the whole border, the window itself one product with
+      // the inverse of its diagonal block
+      constexpr int TW = HF_SWEEP_STEP;
       timed(tm, HF_K_TRSM, w3.first, w3.second, s, [&] {
         for (int j0 = 0; j0 < maxp; j0 += TW) {
-          if (j0 > 0) {
-            dim3 gg2(cdiv(maxb, 64), TW / 64, (unsigned)nl);
-            k_trsm_gemm<T><<<gg2, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), j0);
-          }
-          k_trsm<T><<<g1, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), ctx->d_linv_off.as<int64_t>(),
-                                       ctx->d_linv.as<T>(), j0, j0 + TW);
+          dim3 gw(cdiv(maxb, 64), TW / 64, (unsigned)nl);
+          if (j0 > 0) k_trsm_gemm<T><<<gw, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), j0);
+          k_trsm_apply<T><<<gw, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(),
+                                             ctx->d_linv2_off.as<int64_t>(), ctx->d_linv2.as<T>(), j0);
         }
       });
       const int nt = (maxb + 63) / 64;
@@ -1129,7 +1093,6 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
     k_inverse_pivots<<<ctx->n_nodes, 256, 0, s>>>(ctx->n_nodes, nodes, ctx->d_piv.as<int32_t>(),
                                                   ctx->d_ipos.as<int32_t>());
   }
-  prepare_solve<T>(ctx, s);
   HF_HIP(hipGetLastError());
 }
 

@@ -191,7 +191,8 @@ struct hf_ctx {
   std::vector<int32_t> blk_node, blk_first;  // 64-row diagonal blocks of every L11
   std::vector<int64_t> linv_off;
   int64_t linv_elems = 0;
-  std::vector<int32_t> stp_node, stp_first;  // 256-column steps of every L11
+  std::vector<int32_t> stp_node, stp_first;  // sweep steps of every L11 (numbered level by level)
+  std::vector<int32_t> lvl_step_ptr;         // steps of level l: [lvl_step_ptr[l], lvl_step_ptr[l + 1])
   std::vector<int64_t> linv2_off;
   int64_t linv2_elems = 0;
   std::vector<int32_t> ea_items;
@@ -212,7 +213,7 @@ struct hf_ctx {
   hf::DBuf d_physmap;              // per position: storage index after the last panel
   hf::DBuf d_lbuf;                 // per node: the panels' L columns, rows in the order of their panel
   hf::DBuf d_linv, d_linv_off, d_blk_node, d_blk_first;  // inverses of 64x64 diagonal blocks
-  hf::DBuf d_linv2, d_linv2_off, d_stp_node, d_stp_first;  // inverses of 256x256 step blocks
+  hf::DBuf d_linv2, d_linv2_off, d_stp_node, d_stp_first;  // inverses of the sweep step blocks
   hf::DBuf d_zb_arena;             // second solve arena (step results)
   hf::DBuf d_part;                 // partial products of the backward border step
   hf::DBuf d_isl2, d_flag;         // uint8 mask [n], error flags

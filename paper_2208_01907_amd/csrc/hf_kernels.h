@@ -102,9 +102,11 @@ template <class T>
 void step1(hf_ctx* ctx, const double* values, hipStream_t s);
 
 
-// inverses of the 64x64 diagonal blocks of L11, needed by precond_apply
+// inverses of the sweep step blocks of the L11 of every node of level l (the
+// 64x64 diagonal inverses of the level formed first); they drive the TRSM of
+// the level and the triangular sweeps
 template <class T>
-void prepare_solve(hf_ctx* ctx, hipStream_t s);
+void step_inverses(hf_ctx* ctx, int l, hipStream_t s);
 
 // Q^{-1} of Sec. 3.2: Y = (L D L^T)^{-1} R on the moderate part, R and Y row-major
 // n x m in elimination order, FP64; factors in T.

@@ -8,12 +8,15 @@
 //              border blocks added (extend-add, pivot-order aware);
 //   steps of TB = 512 columns of L11:
 //     diag   : z_J = L_JJ^{-1} w_J, a plain product with the inverse of the
-//              512x512 step block formed once after the factorization
-//              (k_inv_diag for its 64x64 diagonal blocks, k_inv_step for its
-//              two 256x256 halves, k_inv_merge for the block below them),
-//              eight workgroups per step; z goes to a second arena;
+//              512x512 step block, formed with each level of the
+//              factorization (k_inv_diag for its 64x64 diagonal blocks,
+//              k_inv_step for its two 256x256 halves, k_inv_merge for the block
+//              below them; the TRSM of the level uses them too); z goes to a
+//              second arena;
 //     update : w_rows -= L[rows, J] z_J for every row below the step (the rest
-//              of L11 and the border L21), 64-row strips, many workgroups.
+//              of L11 and the border L21).
+//   Launches over many fronts use 64-row tiles staged through LDS; launches
+//   over few fronts use 16-row tiles fed straight from global memory.
 // Backward sweep, root first, per level:
 //   border   : t = D^{-1} z - L21^T x_border (column strips, x_border read from
 //              the FP64 result of the ancestors);
@@ -79,8 +82,8 @@ __global__ void __launch_bounds__(256)
 k_inv_step(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp_first,
            const NodeInfo* __restrict__ nodes, const NodeState* __restrict__ st,
            const T* __restrict__ front, const int64_t* __restrict__ linv_off, const T* __restrict__ linv,
-           const int64_t* __restrict__ linv2_off, T* __restrict__ linv2) {
-  const int bi = blockIdx.x >> 1, h = blockIdx.x & 1;  // step, half
+           const int64_t* __restrict__ linv2_off, T* __restrict__ linv2, int base) {
+  const int bi = base + (blockIdx.x >> 1), h = blockIdx.x & 1;  // step, half
   const int j = stp_node[bi];
   const int S = bi - stp_first[j];
   const NodeInfo ni = nodes[j];
@@ -179,13 +182,14 @@ k_inv_step(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp
 // The block below the two halves of a step: X21 = -Linv_B L_BA Linv_A (A, B the
 // halves).  Pass 0 forms P = L_BA Linv_A into the unused upper-right quarter
 // (transposed: P(r, c) at quarter(c, r)); pass 1 forms X21 = -Linv_B P.  One
-// workgroup per 64x64 output tile; all steps of the tree in one launch.
+// workgroup per 64x64 output tile; all steps of one level in one launch.
 template <class T>
 __global__ void __launch_bounds__(256)
 k_inv_merge(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp_first,
             const NodeInfo* __restrict__ nodes, const NodeState* __restrict__ st,
-            const T* __restrict__ front, const int64_t* __restrict__ linv2_off, T* __restrict__ linv2, int pass) {
-  const int bi = blockIdx.y;
+            const T* __restrict__ front, const int64_t* __restrict__ linv2_off, T* __restrict__ linv2, int pass,
+            int base) {
+  const int bi = base + blockIdx.y;
   const int j = stp_node[bi];
   const int S = bi - stp_first[j];
   const NodeInfo ni = nodes[j];
@@ -663,23 +667,21 @@ k_bwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
 // ---------------------------------------------------------------------------
 
 template <class T>
-void prepare_solve(hf_ctx* ctx, hipStream_t s) {
-  const int64_t ns = (int64_t)ctx->stp_node.size();
-  ctx->d_linv2.alloc((size_t)std::max<int64_t>(ctx->linv2_elems, 1) * sizeof(T));
-  if (ns > 0)
-    timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, [&] {
-      k_inv_step<T><<<(unsigned)(2 * ns), 256, 0, s>>>(ctx->d_stp_node.as<int32_t>(), ctx->d_stp_first.as<int32_t>(),
-                                                 ctx->d_nodes.as<NodeInfo>(), ctx->d_state.as<NodeState>(),
-                                                 ctx->d_front.as<T>(), ctx->d_linv_off.as<int64_t>(),
-                                                 ctx->d_linv.as<T>(), ctx->d_linv2_off.as<int64_t>(),
-                                                 ctx->d_linv2.as<T>());
-      for (int pass = 0; pass < 2; ++pass)
-        k_inv_merge<T><<<dim3(16, (unsigned)ns), 256, 0, s>>>(
-            ctx->d_stp_node.as<int32_t>(), ctx->d_stp_first.as<int32_t>(), ctx->d_nodes.as<NodeInfo>(),
-            ctx->d_state.as<NodeState>(), ctx->d_front.as<T>(), ctx->d_linv2_off.as<int64_t>(),
-            ctx->d_linv2.as<T>(), pass);
-    });
-  HF_HIP(hipGetLastError());
+void step_inverses(hf_ctx* ctx, int l, hipStream_t s) {
+  const int base = ctx->lvl_step_ptr[l], ns = ctx->lvl_step_ptr[l + 1] - base;
+  if (ns <= 0) return;
+  launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_inv_step<T>, dim3((unsigned)(2 * ns)), dim3(256),
+               (const int32_t*)ctx->d_stp_node.as<int32_t>(), (const int32_t*)ctx->d_stp_first.as<int32_t>(),
+               (const NodeInfo*)ctx->d_nodes.as<NodeInfo>(), (const NodeState*)ctx->d_state.as<NodeState>(),
+               (const T*)ctx->d_front.as<T>(), (const int64_t*)ctx->d_linv_off.as<int64_t>(),
+               (const T*)ctx->d_linv.as<T>(), (const int64_t*)ctx->d_linv2_off.as<int64_t>(), ctx->d_linv2.as<T>(),
+               base);
+  for (int pass = 0; pass < 2; ++pass)
+    launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_inv_merge<T>, dim3(16, (unsigned)ns), dim3(256),
+                 (const int32_t*)ctx->d_stp_node.as<int32_t>(), (const int32_t*)ctx->d_stp_first.as<int32_t>(),
+                 (const NodeInfo*)ctx->d_nodes.as<NodeInfo>(), (const NodeState*)ctx->d_state.as<NodeState>(),
+                 (const T*)ctx->d_front.as<T>(), (const int64_t*)ctx->d_linv2_off.as<int64_t>(), ctx->d_linv2.as<T>(),
+                 pass, base);
 }
 
 template <class T>
@@ -868,8 +870,8 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   HF_HIP(hipGetLastError());
 }
 
-template void prepare_solve<float>(hf_ctx*, hipStream_t);
-template void prepare_solve<double>(hf_ctx*, hipStream_t);
+template void step_inverses<float>(hf_ctx*, int, hipStream_t);
+template void step_inverses<double>(hf_ctx*, int, hipStream_t);
 template void precond_apply<float>(hf_ctx*, int, const double*, double*, hipStream_t);
 template void precond_apply<double>(hf_ctx*, int, const double*, double*, hipStream_t);
 
