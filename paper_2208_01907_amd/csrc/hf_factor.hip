@@ -747,12 +747,11 @@ k_gather_border(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__
 // and Linv the inverse of the step's unit-lower diagonal block.  64x64 tiles of
 // (border rows, step columns); the tile goes through LDS so that the columns of
 // L21 are written along their rows.
-template <class T>
+template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_trsm_apply(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
              const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval,
              const int64_t* __restrict__ linv2_off, const T* __restrict__ linv2, int j0) {
-  constexpr int KB = SweepStage<T>::value;
   constexpr int TB = HF_SWEEP_STEP;
   const int j = lnodes[blockIdx.z];
   const NodeInfo ni = nodes[j];
@@ -799,11 +798,10 @@ k_trsm_apply(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
 // Blocked TRSM, the part outside the current window of columns [j0, j0 + w):
 // G(c, r) -= sum_{k < j0} L21[r, k] D_k L11[c, k] for c in the window, i.e. the
 // contribution of the columns already solved (L21 final, so D is put back).
-template <class T>
+template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_trsm_gemm(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
             const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval, int j0) {
-  constexpr int KB = SweepStage<T>::value;
   const int j = lnodes[blockIdx.z];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -1067,11 +1065,18 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
       // the inverse of its diagonal block
       constexpr int TW = HF_SWEEP_STEP;
       timed(tm, HF_K_TRSM, w3.first, w3.second, s, [&] {
+        // stages of k: long over few workgroups, short (several per CU) over many
+        constexpr int KBN = SweepStage<T>::value, KBW = SweepStage<T>::value / 4;
         for (int j0 = 0; j0 < maxp; j0 += TW) {
           dim3 gw(cdiv(maxb, 64), TW / 64, (unsigned)nl);
-          if (j0 > 0) k_trsm_gemm<T><<<gw, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), j0);
-          k_trsm_apply<T><<<gw, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(),
-                                             ctx->d_linv2_off.as<int64_t>(), ctx->d_linv2.as<T>(), j0);
+          const bool wide = (int64_t)gw.x * gw.y * gw.z >= 1024;
+          if (j0 > 0) {
+            auto kg = wide ? k_trsm_gemm<T, KBW> : k_trsm_gemm<T, KBN>;
+            kg<<<gw, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), j0);
+          }
+          auto ka = wide ? k_trsm_apply<T, KBW> : k_trsm_apply<T, KBN>;
+          ka<<<gw, 256, 0, s>>>(lnodes, nodes, st, front, ctx->d_dval.as<T>(), ctx->d_linv2_off.as<int64_t>(),
+                                ctx->d_linv2.as<T>(), j0);
         }
       });
       const int nt = (maxb + 63) / 64;
