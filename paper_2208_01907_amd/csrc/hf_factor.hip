@@ -855,29 +855,27 @@ k_inv_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   const int64_t f = ni.f;
   const T* F = front + ni.front_off;
   __shared__ T Ls[64][64 + 1];
+  __shared__ T Xs[64][64 + 1];  // Xs[r][c]: column c of the inverse (one thread each)
   const int tid = threadIdx.x;
   for (int e = tid; e < 64 * 64; e += 256) {
     const int r = e & 63, c = e >> 6;
     T v = (r == c) ? (T)1 : (T)0;
     if (r > c && r < nc) v = F[(int64_t)(J0 + c) * f + J0 + r];
     Ls[r][c] = v;
+    Xs[r][c] = (r == c) ? (T)1 : (T)0;
+  }
+  __syncthreads();
+  if (tid < 64) {  // forward substitution down column c
+    const int c = tid;
+    for (int r = c + 1; r < 64; ++r) {
+      T v = (T)0;
+      for (int t = c; t < r; ++t) v -= Ls[r][t] * Xs[t][c];
+      Xs[r][c] = v;
+    }
   }
   __syncthreads();
   T* out = linv + linv_off[j] + (int64_t)B * 64 * 64;  // column-major 64x64
-  if (tid < 64) {
-    const int c = tid;
-    T x[64];
-#pragma unroll
-    for (int r = 0; r < 64; ++r) x[r] = (T)0;
-    x[c] = (T)1;
-    for (int r = c + 1; r < 64; ++r) {
-      T v = (T)0;
-      for (int t = c; t < r; ++t) v -= Ls[r][t] * x[t];
-      x[r] = v;
-    }
-#pragma unroll
-    for (int r = 0; r < 64; ++r) out[(int64_t)c * 64 + r] = x[r];
-  }
+  for (int e = tid; e < 64 * 64; e += 256) out[e] = Xs[e & 63][e >> 6];
 }
 
 // ---------------------------------------------------------------------------
