@@ -307,6 +307,30 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
         if (el.count) ctx->ea_launch.push_back(el);
       }
     }
+    // forward-sweep gather: for every front row (slot rhs_off + assembly position),
+    // the children's border rows added into it, children in rank order
+    {
+      std::vector<int64_t> cnt((size_t)ctx->rhs_rows + 1, 0);
+      for (int32_t c = 0; c < n_nodes; ++c) {
+        const NodeInfo& cn = ctx->nodes[c];
+        if (cn.parent < 0) continue;
+        const NodeInfo& pn = ctx->nodes[cn.parent];
+        for (int32_t r = 0; r < cn.b; ++r) cnt[pn.rhs_off + ctx->relmap[cn.border_off + r] + 1]++;
+      }
+      for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+      ctx->gat_ptr = cnt;
+      ctx->gat_src.assign(std::max<int64_t>(cnt.back(), 1), 0);
+      std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+      for (int32_t j = 0; j < n_nodes; ++j) {
+        const NodeInfo& pn = ctx->nodes[j];
+        for (int32_t q = pn.child_begin; q < pn.child_end; ++q) {  // rank order
+          const int32_t c = ctx->child_list[q];
+          const NodeInfo& cn = ctx->nodes[c];
+          for (int32_t r = 0; r < cn.b; ++r)
+            ctx->gat_src[fill[pn.rhs_off + ctx->relmap[cn.border_off + r]]++] = cn.rhs_off + cn.p + r;
+        }
+      }
+    }
     // 64x64 diagonal blocks of every node (inverted after each factorization)
     ctx->blk_first.assign(n_nodes + 1, 0);
     ctx->linv_off.assign(std::max(n_nodes, 1), 0);
@@ -352,6 +376,8 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
     upload(ctx->d_level_nodes, ctx->level_nodes, s);
     upload(ctx->d_child_list, ctx->child_list, s);
     upload(ctx->d_ea_items, ctx->ea_items, s);
+    upload(ctx->d_gat_ptr, ctx->gat_ptr, s);
+    upload(ctx->d_gat_src, ctx->gat_src, s);
     upload(ctx->d_blk_node, ctx->blk_node, s);
     upload(ctx->d_blk_first, ctx->blk_first, s);
     upload(ctx->d_linv_off, ctx->linv_off, s);

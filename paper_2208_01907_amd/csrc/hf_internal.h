@@ -196,6 +196,7 @@ struct hf_ctx {
   std::vector<int64_t> linv2_off;
   int64_t linv2_elems = 0;
   std::vector<int32_t> ea_items;
+  std::vector<int64_t> gat_ptr, gat_src;  // per front-row slot: the child slab rows added into it
   int64_t front_elems = 0, rhs_rows = 0, snap_elems = 0, lbuf_elems = 0;
   int32_t max_front = 0, max_p = 0;
   double flops_sym = 0.0, flops_done = 0.0;
@@ -203,6 +204,7 @@ struct hf_ctx {
   // device: pattern
   hf::DBuf d_pindptr, d_pindices, d_psrc, d_prow_orig, d_diagpos, d_asm;
   hf::DBuf d_perm, d_iperm, d_nodes, d_border, d_relmap, d_level_nodes, d_child_list, d_ea_items;
+  hf::DBuf d_gat_ptr, d_gat_src;
   // device: numeric
   hf::DBuf d_q, d_kval;            // scaling, scaled FP64 values (elimination order)
   hf::DBuf d_kbar;                 // the caller's FP64 values in elimination order

@@ -244,34 +244,27 @@ k_inv_merge(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ st
 // forward sweep
 // ---------------------------------------------------------------------------
 
-// own accepted rows from the FP64 input, everything else zero
+// The forward gather of a level in one launch: every front row takes its own
+// accepted value from the FP64 input (0 for postponed and border rows) plus the
+// border rows of the children that map onto it, in child-rank order.  Thread
+// (a, col) for assembly position a; own rows land at their pivot position.
 template <class T>
 __global__ void __launch_bounds__(256)
-k_fwd_init(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-           const NodeState* __restrict__ st, const int32_t* __restrict__ piv, int m,
-           const double* __restrict__ R, T* __restrict__ rb) {
-  const NodeInfo ni = nodes[lnodes[blockIdx.y]];
-  const int npiv = st[lnodes[blockIdx.y]].npiv;
+k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+             const NodeState* __restrict__ st, const int32_t* __restrict__ ipos,
+             const int64_t* __restrict__ gat_ptr, const int64_t* __restrict__ gat_src, int m,
+             const double* __restrict__ R, T* __restrict__ rb) {
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)ni.f * m) return;
-  const int r = (int)(e / m), col = (int)(e - (int64_t)r * m);
-  rb[ni.rhs_off * m + e] = (r < npiv) ? (T)R[(int64_t)piv[ni.start + r] * m + col] : (T)0;
-}
-
-// children of one rank add their border rows into the parent (pivot-order aware)
-template <class T>
-__global__ void __launch_bounds__(256)
-k_fwd_addchild(const int32_t* __restrict__ items, const NodeInfo* __restrict__ nodes,
-               const int32_t* __restrict__ relmap, const int32_t* __restrict__ ipos, int m,
-               T* __restrict__ rb) {
-  const NodeInfo cn = nodes[items[blockIdx.y]];
-  const NodeInfo pn = nodes[cn.parent];
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)cn.b * m) return;
-  const int r = (int)(e / m), col = (int)(e - (int64_t)r * m);
-  int pr = relmap[cn.border_off + r];
-  if (pr < pn.p) pr = ipos[pn.start + pr];  // own rows of the parent are stored in pivot order
-  rb[(pn.rhs_off + pr) * m + col] += rb[(cn.rhs_off + cn.p) * m + e];
+  const int a = (int)(e / m), col = (int)(e - (int64_t)a * m);
+  const int pr = a < ni.p ? ipos[ni.start + a] : a;
+  T v = (a < ni.p && pr < npiv) ? (T)R[(int64_t)(ni.start + a) * m + col] : (T)0;
+  const int64_t slot = ni.rhs_off + a;
+  for (int64_t i = gat_ptr[slot]; i < gat_ptr[slot + 1]; ++i) v += rb[gat_src[i] * m + col];
+  rb[(ni.rhs_off + pr) * m + col] = v;
 }
 
 // z_J = Linv_J w_J; four workgroups (64 rows each) per front, matrix cores
@@ -734,33 +727,22 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     ctx->d_part.alloc(need * sizeof(T));
   }
   HF_HIP(hipMemsetAsync(Y, 0, (size_t)ctx->n * m * sizeof(double), s));
-  size_t ea = 0;
   for (int l = 0; l < nlev; ++l) {
     const int nl = ctx->level_ptr[l + 1] - ctx->level_ptr[l];
     const int32_t* ln = lall + ctx->level_ptr[l];
     const int maxp = ctx->level_maxp[l], maxf = ctx->level_maxf[l];
     auto wg = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
       by += ni.f * dm * sz + np * dm * 8.0;
+      for (int32_t q = ni.child_begin; q < ni.child_end; ++q) {
+        const double bc = ctx->nodes[ctx->child_list[q]].b;
+        by += bc * dm * sz;
+        fl += bc * dm;
+      }
     });
-    timed(tm, HF_K_SOLVE_GATHER, wg.first, wg.second, s, [&] {
-      dim3 g(cdiv((int64_t)maxf * m, 256), nl);
-      k_fwd_init<T><<<g, 256, 0, s>>>(ln, nodes, st, ctx->d_piv.as<int32_t>(), m, R, rb);
-    });
-    for (; ea < ctx->ea_launch.size() && ctx->ea_launch[ea].level == l; ++ea) {
-      const EaLaunch& el = ctx->ea_launch[ea];
-      double by = 0.0, fl = 0.0;
-      if (tm.on)
-        for (int q = 0; q < el.count; ++q) {
-          const double bc = ctx->nodes[ctx->ea_items[el.off + q]].b;
-          by += 3.0 * bc * dm * sz;
-          fl += bc * dm;
-        }
-      timed(tm, HF_K_SOLVE_GATHER, by, fl, s, [&] {
-        dim3 g(cdiv((int64_t)el.maxb * m, 256), (unsigned)el.count);
-        k_fwd_addchild<T><<<g, 256, 0, s>>>(ctx->d_ea_items.as<int32_t>() + el.off, nodes,
-                                            ctx->d_relmap.as<int32_t>(), ctx->d_ipos.as<int32_t>(), m, rb);
-      });
-    }
+    launch_timed(tm, HF_K_SOLVE_GATHER, wg.first, wg.second, s, k_fwd_gather<T>,
+                 dim3(cdiv((int64_t)maxf * m, 256), nl), dim3(256), ln, nodes, st,
+                 (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
+                 (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, rb);
     const int tb = step_of(nl);
     for (int J0 = 0; J0 < maxp; J0 += tb) {
       auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
