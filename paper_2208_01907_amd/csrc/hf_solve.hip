@@ -753,7 +753,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       });
       {
         dim3 g(tb / SB, nl);
-        if (wide(g))
+        if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s, k_fwd_diag<T, KBW>, g, dim3(256), ln, nodes, st,
                        loff2, linv2, J0, tb, m, rb, zb);
         else
@@ -772,7 +772,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           by += below * nc * sz + 2.0 * below * dm * sz + nc * dm * sz;
           fl += 2.0 * dm * below * nc;
         });
-        if (wide(g))
+        if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s, k_fwd_upd<T, KBW>, g, dim3(256), ln, nodes, st,
                        front, J0, tb, m, zb, rb);
         else
@@ -823,7 +823,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       });
       {
         dim3 g(tb / SB, nl);
-        if (wide(g))
+        if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s, k_bwd_diag<T, KBW>, g, dim3(256), ln, nodes, st,
                        loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
         else
@@ -839,7 +839,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           by += J0 * nc * sz + 2.0 * J0 * dm * sz;
           fl += 2.0 * dm * J0 * nc;
         });
-        if (wide(g))
+        if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, k_bwd_upd<T, KBW>, g, dim3(256), ln, nodes, st,
                        front, J0, tb, m, zb, rb);
         else
