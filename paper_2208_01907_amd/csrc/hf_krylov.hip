@@ -146,6 +146,8 @@ __global__ void k_y2(const int64_t* __restrict__ ip, const int32_t* __restrict__
 // One 64 x 64 (a x b) partial Gram tile per workgroup over a fixed row range,
 // FP64 matrix cores; k_gram_reduce sums the GRAM_WG partials in a fixed order.
 constexpr int GLD = 68;
+constexpr int GKB = 64;  // k per stage of the Gram tiles
+constexpr int CKB = 16;  // k per stage of the combine tiles: small stages, several workgroups per CU
 __global__ void __launch_bounds__(256)
 k_gram_partial(int64_t n, int a, const double* __restrict__ A, int64_t sA, int b,
                const double* __restrict__ B, double* __restrict__ partial) {
@@ -154,8 +156,8 @@ k_gram_partial(int64_t n, int a, const double* __restrict__ A, int64_t sA, int b
   const int64_t chunk = (n + GRAM_WG - 1) / GRAM_WG;
   const int r0 = (int)((int64_t)blockIdx.x * chunk);
   const int r1 = (int)min(n, (int64_t)r0 + chunk);
-  __shared__ double As[64][GLD];
-  __shared__ double Bs[64][GLD];
+  __shared__ double As[GKB][GLD];
+  __shared__ double Bs[GKB][GLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   Mfma<double>::V acc[2][2];
@@ -163,7 +165,7 @@ k_gram_partial(int64_t n, int a, const double* __restrict__ A, int64_t sA, int b
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<double>::V{0, 0, 0, 0};
-  tile_gemm_64<double, 64, GLD, false>(
+  tile_gemm_64<double, GKB, GLD, false>(
       acc, As, Bs, r0, r1, [&](int k, int i) { return i < a ? Ab[(int64_t)k * a + i] : 0.0; },
       [&](int k, int j) { return j < b ? B[(int64_t)k * b + j] : 0.0; }, tid, lane, wr, wc);
   double* out = partial + ((int64_t)blk * GRAM_WG + blockIdx.x) * a * b;
@@ -296,8 +298,8 @@ k_combine(int64_t n, int a, int b, double* out, const double* base, int nterms,
           const double* __restrict__ V, int64_t sV, const double* __restrict__ coef) {
   const int r0 = blockIdx.x * 64;
   const int nrows = (int)min((int64_t)64, n - r0);
-  __shared__ double As[64][GLD];
-  __shared__ double Bs[64][GLD];
+  __shared__ double As[CKB][GLD];
+  __shared__ double Bs[CKB][GLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   Mfma<double>::V acc[2][2];
@@ -305,7 +307,7 @@ k_combine(int64_t n, int a, int b, double* out, const double* base, int nterms,
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<double>::V{0, 0, 0, 0};
-  tile_gemm_64<double, 64, GLD, true>(
+  tile_gemm_64<double, CKB, GLD, true>(
       acc, As, Bs, 0, a * nterms,
       [&](int k, int r) {
         const int t = k / a, kk = k - t * a;
