@@ -167,21 +167,23 @@ __device__ __forceinline__ int wave_min(int v) {
 //
 // The trailing block [k0p, p)^2 of the pivot block is stored full (both
 // triangles).  A symmetric exchange of positions i and k moves no data: every
-// position carries the storage index ("phys") of its row and column, and the
-// two positions exchange these.  Thread t owns positions q = t + PT*s (relative
-// to k0p) and keeps, in registers, their panel values L[q, 0..NB), current
-// diagonal, nested-dissection index and phys.  Per pivot: a wave-wide argmax
-// (DPP), each wave posts its candidate with that row's panel values and the
-// owner of position i posts row i; one barrier; every thread combines the wave
-// results, the two owners exchange their rows, and each thread reads its rows of
-// the pivot column (one coalesced column read) and forms the new L column
-// (left-looking inside the panel).  The posted copies alternate between two
-// buffers, so a buffer is rewritten only after every thread has passed the next
-// barrier.
-// At the end, the storage index of every trailing position goes to `physmap`
-// (k_trail_update reads its source tiles through it; no storage column moves),
-// the panel's L columns go to the side buffer `lbuf` in position order, and a
-// snapshot of the position -> index map is kept for k_l11_gather.
+// row keeps the storage index ("phys") of its row and column, and the rows
+// only exchange their positions.  Thread t holds rows q = t + PT*s (relative to
+// k0p, q their position when the panel starts) in registers for the whole
+// panel: their panel values L[., 0..NB), current diagonal, nested-dissection
+// index, phys and current position.  Per pivot: a wave-wide argmax (DPP) over
+// the rows not yet pivoted, each wave posts its candidate (with that row's
+// panel values); one barrier; every thread combines the wave records, the
+// winner takes position i and the row at position i takes the winner's old
+// position (two compares per row), and each thread reads its rows of the pivot
+// column (one coalesced column read) and forms the new L column (left-looking
+// inside the panel).  The posted copies alternate between two buffers, so a
+// buffer is rewritten only after every thread has passed the next barrier.
+// At the end, every row is written at its final position: the storage index of
+// every trailing position goes to `physmap` (k_trail_update reads its source
+// tiles through it; no storage column moves), the panel's L columns go to the
+// side buffer `lbuf` in position order, and a snapshot of the position -> index
+// map is kept for k_l11_gather.
 template <class T, int PR>
 __global__ void __launch_bounds__(PT)
 k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, NodeState* st,
@@ -210,15 +212,12 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   };
   __shared__ WaveRec rec[2][NW];
   __shared__ __align__(64) T pubK[2][NW][NB];  // panel row of each wave's candidate
-  __shared__ __align__(64) T pubI[2][NB];      // panel row of position i
-  __shared__ T pubI_d[2];
-  __shared__ int pubI_idx[2], pubI_ph[2];
   using Row = typename PanelRow<T>::V;
 
   Row Lp[PR];
   Row Dlr = (Row)((T)0);
   T dgr[PR];
-  int idxr[PR], ph[PR];
+  int idxr[PR], ph[PR], pos[PR];
 #pragma unroll
   for (int s = 0; s < PR; ++s) {
     const int q = tid + PT * s;
@@ -226,6 +225,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     dgr[s] = (T)0;
     idxr[s] = INT_MAX;
     ph[s] = q;
+    pos[s] = q;  // padding rows (q >= P) never move
     if (q < P) {
       dgr[s] = Fb[(uint32_t)q * f + q];
       idxr[s] = idx_g[k0p + q];
@@ -248,14 +248,12 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   for (i = k0p; i < iend; ++i) {
     const int qi = i - k0p;
     const int par = qi & 1;
-    const int ti = qi % PT, si = qi / PT;
     // own best candidate: max |diag|, ties to the smallest index
     T av = (T)-1;
     int aid = INT_MAX, as = -1;
 #pragma unroll
     for (int s = 0; s < PR; ++s) {  // branch-free: bitwise tests and selects
-      const int q = tid + PT * s;
-      const T v = (q >= qi && q < P) ? fabs(dgr[s]) : (T)-1;
+      const T v = (pos[s] >= qi && pos[s] < P) ? fabs(dgr[s]) : (T)-1;
       const bool better = (v > av) | ((v == av) & (idxr[s] < aid));
       av = better ? v : av;
       aid = better ? idxr[s] : aid;
@@ -273,7 +271,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
           r1.v = wmax;
           r1.d = dgr[s];
           r1.id = wid;
-          r1.k = tid + PT * s;
+          r1.k = pos[s];
           r1.ph = ph[s];
           rec[par][wv] = r1;
         }
@@ -286,16 +284,6 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
       r1.k = 0;
       r1.ph = 0;
       rec[par][wv] = r1;
-    }
-    if (tid == ti) {
-#pragma unroll
-      for (int s = 0; s < PR; ++s)
-        if (s == si) {
-          *reinterpret_cast<Row*>(pubI[par]) = Lp[s];
-          pubI_d[par] = dgr[s];
-          pubI_idx[par] = idxr[s];
-          pubI_ph[par] = ph[s];
-        }
     }
     __syncthreads();
     // the wave records, read together, then combined without branches
@@ -322,47 +310,20 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     bool stop = (dk == 0.0);
     if (!stop && have_prev && fabs(dk) < tau * fabs(dprev)) stop = true;
     if (stop) break;  // uniform: every thread computed the same decision
-    const int tk = qk % PT, sk = qk / PT;
-    // positions i and k exchange rows, diagonals, indices and storage indices
-    if (qk != qi) {
-      if (tid == tk) {
-        const Row rowI = *reinterpret_cast<const Row*>(pubI[par]);
-        const T dI = pubI_d[par];
-        const int idI = pubI_idx[par], phI = pubI_ph[par];
+    // positions i and k exchange their rows: the winner takes position i, the
+    // row at position i takes the winner's position
 #pragma unroll
-        for (int s = 0; s < PR; ++s)
-          if (s == sk) {
-            __asm__ volatile("");  // keeps this a branch: only one slot is written
-            Lp[s] = rowI;
-            dgr[s] = dI;
-            idxr[s] = idI;
-            ph[s] = phI;
-          }
-      }
-      if (tid == ti) {
-#pragma unroll
-        for (int s = 0; s < PR; ++s)
-          if (s == si) {
-            __asm__ volatile("");  // keeps this a branch: only one slot is written
-            Lp[s] = rowK;
-            idxr[s] = bid;
-            ph[s] = phK;
-          }
-      }
-    }
-    // u_c = D_c L[i, c] for the panel columns so far (row i after the exchange);
-    // the pivots of later columns are still zero, as are the row's later values
+    for (int s = 0; s < PR; ++s) pos[s] = (idxr[s] == bid) ? qi : (pos[s] == qi ? qk : pos[s]);
+    // u_c = D_c L[i, c] for the panel columns so far (the pivot row); the
+    // pivots of later columns are still zero, as are the row's later values
     const Row u = Dlr * rowK;
     Dlr[qi] = d;  // every thread keeps the panel's pivots
     const T inv = (T)1 / d;
-    // the pivot column: storage column phK at the storage rows of the positions
+    // the pivot column: storage column phK at the storage rows of the rows
     const T* colK = Fb + (uint32_t)phK * f;
     T v[PR];
 #pragma unroll
-    for (int s = 0; s < PR; ++s) {
-      const int q = tid + PT * s;
-      v[s] = (q > qi && q < P) ? colK[ph[s]] : (T)0;
-    }
+    for (int s = 0; s < PR; ++s) v[s] = (pos[s] > qi && pos[s] < P) ? colK[ph[s]] : (T)0;
     // left-looking column: only the qi columns factored so far contribute
     // (qi is uniform, so the cut is a scalar branch)
 #pragma unroll
@@ -376,8 +337,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     // new column; their diagonals are never read again
 #pragma unroll
     for (int s = 0; s < PR; ++s) {
-      const int q = tid + PT * s;
-      const bool live = (q > qi) & (q < P);
+      const bool live = (pos[s] > qi) & (pos[s] < P);
       const T l = live ? v[s] * inv : (T)0;
       dgr[s] -= l * v[s];
       Lp[s][qi] = l;
@@ -394,17 +354,15 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   // exchanges from it; the panel's storage columns keep their values until then)
   int32_t* pm = physmap + ni.start + k0p;
 #pragma unroll
-  for (int s = 0; s < PR; ++s) {
-    const int q = tid + PT * s;
-    if (q >= nacc && q < P) pm[q] = ph[s];
-  }
+  for (int s = 0; s < PR; ++s)
+    if (pos[s] >= nacc && pos[s] < P) pm[pos[s]] = ph[s];
   // the panel's L columns, in position order, to the side buffer; the snapshot
   // of the position -> index map
   T* Lb = lbuf + ni.lbuf_off + (int64_t)k0p * ni.lbuf_ld + k0p;  // Lb[c*ld + q]
   int32_t* sn = snap + ni.snap_off + (int64_t)(k0p / NB) * p;
 #pragma unroll
   for (int s = 0; s < PR; ++s) {
-    const int q = tid + PT * s;
+    const int q = pos[s];
     if (q < P) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
