@@ -162,6 +162,25 @@ __device__ __forceinline__ double wave_max(double v) {
 __device__ __forceinline__ int wave_min(int v) {
   return wave_reduce_i(v, [](int a, int b) { return a < b ? a : b; });
 }
+// the same for an unsigned 64-bit key held as (hi, lo)
+template <int CTRL, int RM>
+__device__ __forceinline__ void kmax_step(uint64_t& k) {
+  const uint32_t h2 = (uint32_t)dpp_i<CTRL, RM>((int)(uint32_t)(k >> 32));
+  const uint32_t l2 = (uint32_t)dpp_i<CTRL, RM>((int)(uint32_t)k);
+  const uint64_t k2 = ((uint64_t)h2 << 32) | l2;
+  k = k2 > k ? k2 : k;
+}
+__device__ __forceinline__ uint64_t wave_max_key(uint64_t k) {
+  kmax_step<0x111, 0xf>(k);
+  kmax_step<0x112, 0xf>(k);
+  kmax_step<0x114, 0xf>(k);
+  kmax_step<0x118, 0xf>(k);
+  kmax_step<0x142, 0xa>(k);
+  kmax_step<0x143, 0xc>(k);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), 63);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)k, 63);
+  return ((uint64_t)hi << 32) | lo;
+}
 
 // Panel factorization with pivot search and postponing, one workgroup per front.
 //
@@ -218,6 +237,9 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   Row Dlr = (Row)((T)0);
   T dgr[PR];
   int idxr[PR], ph[PR], pos[PR];
+  // FP32: the argmax key of a row, (bits of |d|) * 2^32 + (2^32 - 1 - index),
+  // orders rows as (larger |d|, then smaller index); 0 for rows out of the race
+  uint64_t key[PR];
 #pragma unroll
   for (int s = 0; s < PR; ++s) {
     const int q = tid + PT * s;
@@ -230,6 +252,9 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
       dgr[s] = Fb[(uint32_t)q * f + q];
       idxr[s] = idx_g[k0p + q];
     }
+    key[s] = 0;
+    if constexpr (sizeof(T) == 4)
+      if (q < P) key[s] = ((uint64_t)__float_as_uint(fabsf((float)dgr[s])) << 32) | (uint32_t)~idxr[s];
   }
   if (tid < 2 * NW) {  // defined contents even if a wave posted nothing
     WaveRec r0;
@@ -249,18 +274,33 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     const int qi = i - k0p;
     const int par = qi & 1;
     // own best candidate: max |diag|, ties to the smallest index
-    T av = (T)-1;
-    int aid = INT_MAX, as = -1;
+    T av = (T)-1, wmax;
+    int aid = INT_MAX, as = -1, wid;
+    if constexpr (sizeof(T) == 4) {  // one 64-bit key per row, one reduction
+      uint64_t bk = 0;
 #pragma unroll
-    for (int s = 0; s < PR; ++s) {  // branch-free: bitwise tests and selects
-      const T v = (pos[s] >= qi && pos[s] < P) ? fabs(dgr[s]) : (T)-1;
-      const bool better = (v > av) | ((v == av) & (idxr[s] < aid));
-      av = better ? v : av;
-      aid = better ? idxr[s] : aid;
-      as = better ? s : as;
+      for (int s = 0; s < PR; ++s) {
+        const bool better = key[s] > bk;
+        bk = better ? key[s] : bk;
+        as = better ? s : as;
+      }
+      const uint64_t wk = wave_max_key(bk);
+      wmax = wk ? (T)__uint_as_float((uint32_t)(wk >> 32)) : (T)-1;
+      wid = (int)~(uint32_t)wk;
+      av = (bk == wk && wk) ? wmax : (T)-1;
+      aid = wid;
+    } else {
+#pragma unroll
+      for (int s = 0; s < PR; ++s) {  // branch-free: bitwise tests and selects
+        const T v = (pos[s] >= qi && pos[s] < P) ? fabs(dgr[s]) : (T)-1;
+        const bool better = (v > av) | ((v == av) & (idxr[s] < aid));
+        av = better ? v : av;
+        aid = better ? idxr[s] : aid;
+        as = better ? s : as;
+      }
+      wmax = wave_max(av);
+      wid = wave_min(av == wmax ? aid : INT_MAX);
     }
-    const T wmax = wave_max(av);
-    const int wid = wave_min(av == wmax ? aid : INT_MAX);
     if (wmax >= (T)0 && av == wmax && aid == wid) {  // the wave's winner posts its row
       const int asu = __builtin_amdgcn_readfirstlane(as);  // one lane: uniform here
 #pragma unroll
@@ -341,6 +381,8 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
       const T l = live ? v[s] * inv : (T)0;
       dgr[s] -= l * v[s];
       Lp[s][qi] = l;
+      if constexpr (sizeof(T) == 4)  // the rows still in the race for the next pivot
+        key[s] = live ? ((uint64_t)__float_as_uint(fabsf((float)dgr[s])) << 32) | (uint32_t)~idxr[s] : 0;
     }
     dprev = dk;
     have_prev = 1;
