@@ -81,7 +81,7 @@ __global__ void k_extend_add(const int32_t* __restrict__ items, int nitems,
   const NodeInfo ci = nodes[items[it]];
   const NodeInfo pi = nodes[ci.parent];
   const int bc = ci.b;
-  const int t = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);  // one wave per column of the child block
   if (t >= bc) return;
   const T* C = front + ci.front_off;
   T* F = front + pi.front_off;
@@ -89,7 +89,7 @@ __global__ void k_extend_add(const int32_t* __restrict__ items, int nitems,
   const int64_t fc = ci.f, fp = pi.f;
   const int64_t ct = (int64_t)(ci.p + t) * fc + ci.p;
   const int64_t pt = (int64_t)rel[t] * fp;
-  for (int r = t + (threadIdx.x & 15); r < bc; r += 16) F[pt + rel[r]] += C[ct + r];
+  for (int r = t + (threadIdx.x & 63); r < bc; r += 64) F[pt + rel[r]] += C[ct + r];
 }
 
 // ---------------------------------------------------------------------------
@@ -986,7 +986,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
           by += 1.5 * b * b * sz;
           fl += 0.5 * b * b;
         }
-      dim3 grid(cdiv(el.maxb, 16), (unsigned)el.count);
+      dim3 grid(cdiv(el.maxb, 4), (unsigned)el.count);
       launch_timed(tm, HF_K_EXTEND_ADD, by, fl, s, k_extend_add<T>, grid, dim3(256),
                    (const int32_t*)(ctx->d_ea_items.as<int32_t>() + el.off), el.count, nodes,
                    (const int32_t*)ctx->d_relmap.as<int32_t>(), front);
