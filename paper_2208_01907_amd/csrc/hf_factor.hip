@@ -110,16 +110,14 @@ struct PanelWidth {
 // one row of panel values as a register vector: an element chosen by a
 // wave-uniform index is read or written in place (GPR index mode), with no
 // select over the whole row
-template <class T>
-struct PanelRow;
-template <>
-struct PanelRow<float> {
-  typedef float V __attribute__((ext_vector_type(16)));
+template <class T, int W>
+struct PanelRow {
+  typedef T V __attribute__((ext_vector_type(W)));
 };
-template <>
-struct PanelRow<double> {
-  typedef double V __attribute__((ext_vector_type(8)));
-};
+// Panels over small remaining blocks (one register slot per thread) take
+// twice the pivots: half the trailing updates and panel launches for a
+// few more products per pivot.
+inline int panel_pivots(int base, int slots) { return slots <= 1 ? 2 * base : base; }
 
 // Wave-wide reductions with DPP row shifts and row broadcasts; the result of
 // lane 63 is returned to every lane.  Lanes without a source keep their value.
@@ -203,13 +201,14 @@ __device__ __forceinline__ uint64_t wave_max_key(uint64_t k) {
 // tiles through it; no storage column moves), the panel's L columns go to the
 // side buffer `lbuf` in position order, and a snapshot of the position -> index
 // map is kept for k_l11_gather.
-template <class T, int PR>
+template <class T, int PR, int NB>
 __global__ void __launch_bounds__(PT)
 k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, NodeState* st,
         T* __restrict__ front, int32_t* __restrict__ piv, int32_t* __restrict__ snap,
         T* __restrict__ dval, int32_t* __restrict__ physmap, T* __restrict__ lbuf, int k0p, double tau,
         int first_unit) {
-  constexpr int NB = PanelWidth<T>::value;
+  constexpr int NB0 = PanelWidth<T>::value;  // snapshot granularity
+  static_assert(NB == NB0 || NB == 2 * NB0, "panel width");
   constexpr int NW = PT / 64;
   const int j = lnodes[blockIdx.x];
   const NodeInfo ni = nodes[j];
@@ -231,7 +230,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   };
   __shared__ WaveRec rec[2][NW];
   __shared__ __align__(64) T pubK[2][NW][NB];  // panel row of each wave's candidate
-  using Row = typename PanelRow<T>::V;
+  using Row = typename PanelRow<T, NB>::V;
 
   Row Lp[PR];
   Row Dlr = (Row)((T)0);
@@ -401,7 +400,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   // the panel's L columns, in position order, to the side buffer; the snapshot
   // of the position -> index map
   T* Lb = lbuf + ni.lbuf_off + (int64_t)k0p * ni.lbuf_ld + k0p;  // Lb[c*ld + q]
-  int32_t* sn = snap + ni.snap_off + (int64_t)(k0p / NB) * p;
+  int32_t* sn = snap + ni.snap_off + (int64_t)(k0p / NB0) * p;  // a wide panel fills two slots
 #pragma unroll
   for (int s = 0; s < PR; ++s) {
     const int q = pos[s];
@@ -411,6 +410,8 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
         if (c < nacc && c < q) Lb[(int64_t)c * ni.lbuf_ld + q] = Lp[s][c];
       idx_g[k0p + q] = idxr[s];
       sn[k0p + q] = idxr[s];
+      if constexpr (NB == 2 * NB0)  // the second half's slot, where that half has columns
+        if (k0p + NB0 < p) sn[p + k0p + q] = idxr[s];
     }
   }
   if (tid == 0) {
@@ -458,12 +459,11 @@ k_mirror(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
 // column is also a storage row).  Lower tiles are computed; each result is
 // written to both triangles.  Reads of the storage in place touch only
 // non-displaced entries of the tile itself, so updating in place is safe.
-template <class T>
+template <class T, int NB>
 __global__ void __launch_bounds__(256)
 k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
                const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval,
                const int32_t* __restrict__ physmap, const T* __restrict__ lbuf, int k0p) {
-  constexpr int NB = PanelWidth<T>::value;
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const NodeState sj = st[j];
@@ -998,30 +998,35 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
       dim3 gm(cdiv(maxp, 64), cdiv(maxp, 64), (unsigned)nl);
       launch_timed(tm, HF_K_OTHER, 0.0, 0.0, s, k_mirror<T>, gm, dim3(256), lnodes, nodes, front);
     }
-    for (int k0p = 0; k0p < maxp; k0p += NBP) {
+    for (int k0p = 0, NBL = NBP; k0p < maxp; k0p += NBL) {
+      const int slots = panel_slots(maxp - k0p);
+      NBL = panel_pivots(NBP, slots);
       auto w1 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
         if (ni.p <= k0p) return;
-        const double r = ni.p - k0p, nb = std::min(NBP, ni.p - k0p);
+        const double r = ni.p - k0p, nb = std::min(NBL, ni.p - k0p);
         by += 2.0 * r * nb * sz;
         fl += nb * nb * r;
       });
-      const int slots = panel_slots(maxp - k0p);
-      auto kp = slots == 1 ? k_panel<T, 1> : slots == 2 ? k_panel<T, 2> : slots == 4 ? k_panel<T, 4> : k_panel<T, PROWS>;
+      auto kp = slots == 1   ? k_panel<T, 1, 2 * NBP>
+                : slots == 2 ? k_panel<T, 2, NBP>
+                : slots == 4 ? k_panel<T, 4, NBP>
+                             : k_panel<T, PROWS, NBP>;
       launch_timed(tm, HF_K_PANEL, w1.first, w1.second, s, kp, dim3((unsigned)nl), dim3(PT), lnodes, nodes,
                    st, front, ctx->d_piv.as<int32_t>(), ctx->d_snap.as<int32_t>(), ctx->d_dval.as<T>(),
                    ctx->d_physmap.as<int32_t>(), ctx->d_lbuf.as<T>(), k0p, ctx->opt.tau,
                    (int)ctx->opt.first_pivot_unit);
-      const int nr = maxp - (k0p + NBP);
+      const int nr = maxp - (k0p + NBL);
       if (nr > 0) {
         const int nt = (nr + 63) / 64;
         dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)nl);
         auto w2 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
-          const double r = ni.p - k0p - NBP;
+          const double r = ni.p - k0p - NBL;
           if (r <= 0) return;
-          by += (r * NBP + r * r) * sz;
-          fl += r * r * NBP;
+          by += (r * NBL + r * r) * sz;
+          fl += r * r * NBL;
         });
-        launch_timed(tm, HF_K_F11_UPDATE, w2.first, w2.second, s, k_trail_update<T>, grid, dim3(256), lnodes, nodes,
+        launch_timed(tm, HF_K_F11_UPDATE, w2.first, w2.second, s,
+                     NBL == NBP ? k_trail_update<T, NBP> : k_trail_update<T, 2 * NBP>, grid, dim3(256), lnodes, nodes,
                      (const NodeState*)st, front, (const T*)ctx->d_dval.as<T>(),
                      (const int32_t*)ctx->d_physmap.as<int32_t>(), (const T*)ctx->d_lbuf.as<T>(), k0p);
       }
