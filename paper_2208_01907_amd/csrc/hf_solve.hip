@@ -83,7 +83,9 @@ k_inv_step(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp
            const NodeInfo* __restrict__ nodes, const NodeState* __restrict__ st,
            const T* __restrict__ front, const int64_t* __restrict__ linv_off, const T* __restrict__ linv,
            const int64_t* __restrict__ linv2_off, T* __restrict__ linv2, int base) {
-  const int bi = base + (blockIdx.x >> 1), h = blockIdx.x & 1;  // step, half
+  // one workgroup per (step, half, column block J): the block column J of the
+  // half's inverse depends only on itself and L
+  const int bi = base + (blockIdx.x >> 3), h = (blockIdx.x >> 2) & 1, J = blockIdx.x & 3;
   const int j = stp_node[bi];
   const int S = bi - stp_first[j];
   const NodeInfo ni = nodes[j];
@@ -92,6 +94,7 @@ k_inv_step(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp
   if (J0 >= npiv) return;
   const int nc = min(HB, npiv - J0);
   const int nb = (nc + SB - 1) / SB;
+  if (J >= nb) return;
   const int64_t f = ni.f;
   const T* F = front + ni.front_off;
   T* X0 = linv2 + linv2_off[j] + (int64_t)S * TB * TB;  // column-major TB x TB step block
@@ -102,16 +105,15 @@ k_inv_step(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp
   __shared__ T Ts[64][64];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
-  for (int e = tid; e < HB * TB; e += 256) X0[(int64_t)h * HB * TB + e] = (T)0;  // the half's columns
+  for (int e = tid; e < SB * TB; e += 256) X0[(int64_t)(h * HB + SB * J) * TB + e] = (T)0;  // the block's columns
   __syncthreads();
-  for (int I = 0; I < nb; ++I)
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int r = e & 63, c = e >> 6;
-      X[(int64_t)(SB * I + c) * TB + SB * I + r] = L64[(int64_t)I * SB * SB + (int64_t)c * SB + r];
-    }
+  for (int e = tid; e < SB * SB; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    X[(int64_t)(SB * J + c) * TB + SB * J + r] = L64[(int64_t)J * SB * SB + (int64_t)c * SB + r];
+  }
   __syncthreads();
-  for (int I = 1; I < nb; ++I) {
-    for (int J = 0; J < I; ++J) {
+  for (int I = J + 1; I < nb; ++I) {
+    {
       T acc[4][4];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
@@ -663,7 +665,7 @@ template <class T>
 void step_inverses(hf_ctx* ctx, int l, hipStream_t s) {
   const int base = ctx->lvl_step_ptr[l], ns = ctx->lvl_step_ptr[l + 1] - base;
   if (ns <= 0) return;
-  launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_inv_step<T>, dim3((unsigned)(2 * ns)), dim3(256),
+  launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_inv_step<T>, dim3((unsigned)(8 * ns)), dim3(256),
                (const int32_t*)ctx->d_stp_node.as<int32_t>(), (const int32_t*)ctx->d_stp_first.as<int32_t>(),
                (const NodeInfo*)ctx->d_nodes.as<NodeInfo>(), (const NodeState*)ctx->d_state.as<NodeState>(),
                (const T*)ctx->d_front.as<T>(), (const int64_t*)ctx->d_linv_off.as<int64_t>(),
