@@ -185,7 +185,7 @@ __device__ __forceinline__ uint64_t wave_max_key(uint64_t k) {
 // The trailing block [k0p, p)^2 of the pivot block is stored full (both
 // triangles).  A symmetric exchange of positions i and k moves no data: every
 // row keeps the storage index ("phys") of its row and column, and the rows
-// only exchange their positions.  Thread t holds rows q = t + PT*s (relative to
+// only exchange their positions.  Thread t holds rows q = t + NT*s (relative to
 // k0p, q their position when the panel starts) in registers for the whole
 // panel: their panel values L[., 0..NB), current diagonal, nested-dissection
 // index, phys and current position.  Per pivot: a wave-wide argmax (DPP) over
@@ -201,19 +201,19 @@ __device__ __forceinline__ uint64_t wave_max_key(uint64_t k) {
 // tiles through it; no storage column moves), the panel's L columns go to the
 // side buffer `lbuf` in position order, and a snapshot of the position -> index
 // map is kept for k_l11_gather.
-template <class T, int PR, int NB>
-__global__ void __launch_bounds__(PT)
+template <class T, int PR, int NB, int NT = PT>
+__global__ void __launch_bounds__(NT)
 k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, NodeState* st,
         T* __restrict__ front, int32_t* __restrict__ piv, int32_t* __restrict__ snap,
         T* __restrict__ dval, int32_t* __restrict__ physmap, T* __restrict__ lbuf, int k0p, double tau,
         int first_unit) {
   constexpr int NB0 = PanelWidth<T>::value;  // snapshot granularity
   static_assert(NB == NB0 || NB == 2 * NB0, "panel width");
-  constexpr int NW = PT / 64;
+  constexpr int NW = NT / 64;  // waves (NT < PT for blocks of at most NT rows)
   const int j = lnodes[blockIdx.x];
   const NodeInfo ni = nodes[j];
   const NodeState s0 = st[j];
-  if (s0.done || k0p >= ni.p || ni.p - k0p > PR * PT) return;  // the launch sizes PR for the level
+  if (s0.done || k0p >= ni.p || ni.p - k0p > PR * NT) return;  // the launch sizes PR, NT for the level
   const int p = ni.p;
   const uint32_t f = (uint32_t)ni.f;  // fronts hold fewer than 2^31 entries (checked at analysis)
   T* F = front + ni.front_off;
@@ -241,7 +241,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   uint64_t key[PR];
 #pragma unroll
   for (int s = 0; s < PR; ++s) {
-    const int q = tid + PT * s;
+    const int q = tid + NT * s;
     Lp[s] = (Row)((T)0);
     dgr[s] = (T)0;
     idxr[s] = INT_MAX;
@@ -1007,11 +1007,17 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         by += 2.0 * r * nb * sz;
         fl += nb * nb * r;
       });
-      auto kp = slots == 1   ? k_panel<T, 1, 2 * NBP>
+      // blocks of at most 256 / 128 / 64 rows: as many threads (fewer waves to combine)
+      const int rem = maxp - k0p;
+      const int nt = slots > 1 ? PT : rem <= 64 ? 64 : rem <= 128 ? 128 : rem <= 256 ? 256 : PT;
+      auto kp = slots == 1   ? (nt == 64    ? k_panel<T, 1, 2 * NBP, 64>
+                                : nt == 128 ? k_panel<T, 1, 2 * NBP, 128>
+                                : nt == 256 ? k_panel<T, 1, 2 * NBP, 256>
+                                            : k_panel<T, 1, 2 * NBP>)
                 : slots == 2 ? k_panel<T, 2, NBP>
                 : slots == 4 ? k_panel<T, 4, NBP>
                              : k_panel<T, PROWS, NBP>;
-      launch_timed(tm, HF_K_PANEL, w1.first, w1.second, s, kp, dim3((unsigned)nl), dim3(PT), lnodes, nodes,
+      launch_timed(tm, HF_K_PANEL, w1.first, w1.second, s, kp, dim3((unsigned)nl), dim3(nt), lnodes, nodes,
                    st, front, ctx->d_piv.as<int32_t>(), ctx->d_snap.as<int32_t>(), ctx->d_dval.as<T>(),
                    ctx->d_physmap.as<int32_t>(), ctx->d_lbuf.as<T>(), k0p, ctx->opt.tau,
                    (int)ctx->opt.first_pivot_unit);
