@@ -356,11 +356,15 @@ k_bwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
   rb[(ni.rhs_off + ni.p + r) * m + c] = (T)Y[(int64_t)border[ni.border_off + r] * m + c];
 }
 
-template <class T, int KB>
+// With FIN (every front of the level has one chunk) the product goes straight
+// into t_k = z_k / d_k - P[k] (rows of the pivot block; the product reads the
+// border rows).
+template <class T, int KB, bool FIN>
 __global__ void __launch_bounds__(256)
 k_bwd_border_part(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
                   const NodeState* __restrict__ st, const T* __restrict__ front,
-                  const T* __restrict__ rb, int m, int maxch, int maxp, T* __restrict__ part) {
+                  T* rb, int m, int maxch, int maxp, T* __restrict__ part, const T* __restrict__ dval,
+                  const T* __restrict__ zb) {
   const int q = blockIdx.z;
   const int j = lnodes[q];
   const NodeInfo ni = nodes[j];
@@ -384,10 +388,19 @@ k_bwd_border_part(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict
   tile_gemm_64<T, KB, MLD, true>(
       acc, As, Bs, rlo, rhi, [&](int k, int r) { return r < nrows ? A[(int64_t)r * lf + k] : (T)0; },
       [&](int k, int c) { return c < m ? Yb[(int64_t)k * m + c] : (T)0; }, tid, lane, wr, wc);
-  T* P = part + (((int64_t)q * maxch + ch) * maxp + cs) * m;
-  for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
-    if (r < nrows && c < m) P[(int64_t)r * m + c] = v;
-  });
+  if constexpr (FIN) {
+    for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
+      if (r < nrows && c < m) {
+        const int64_t o = (ni.rhs_off + cs + r) * m + c;
+        rb[o] = zb[o] / dval[ni.start + cs + r] - v;
+      }
+    });
+  } else {
+    T* P = part + (((int64_t)q * maxch + ch) * maxp + cs) * m;
+    for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
+      if (r < nrows && c < m) P[(int64_t)r * m + c] = v;
+    });
+  }
 }
 
 // t_k = z_k / d_k - sum_ch P_ch[k]
@@ -790,6 +803,10 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     const int maxp = ctx->level_maxp[l];
     if (maxp == 0) continue;
     const int maxch = std::max(1, (int)cdiv(ctx->level_maxb[l], RCH));
+    // one chunk per front and a border on every front: the product writes t itself
+    bool fused_fin = maxch == 1;
+    for (int32_t q = ctx->level_ptr[l]; fused_fin && q < ctx->level_ptr[l + 1]; ++q)
+      fused_fin = ctx->nodes[ctx->level_nodes[q]].b > 0;
     T* part = ctx->d_part.as<T>();
     auto wb = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
       by += ni.b * np * sz + np * dm * sz + ni.b * dm * sz;
@@ -804,17 +821,25 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         k_bwd_gather<T><<<gy, 256, 0, s>>>(ln, nodes, ctx->d_border.as<int32_t>(), m, Y, rb);
       });
       dim3 gp(cdiv(maxp, 64), maxch, nl);
-      launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
-                   wide(gp) ? k_bwd_border_part<T, KBW> : k_bwd_border_part<T, KBN / 2>, gp, dim3(256), ln, nodes, st,
-                   front, rb, m, maxch, maxp, part);
+      const T* dv = ctx->d_dval.as<T>();
+      if (fused_fin)
+        launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
+                     wide(gp) ? k_bwd_border_part<T, KBW, true> : k_bwd_border_part<T, KBN / 2, true>, gp, dim3(256),
+                     ln, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb);
+      else
+        launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
+                     wide(gp) ? k_bwd_border_part<T, KBW, false> : k_bwd_border_part<T, KBN / 2, false>, gp, dim3(256),
+                     ln, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb);
     }
-    auto wf = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
-      by += 3.0 * np * dm * sz;
-    });
-    timed(tm, HF_K_SOLVE_GATHER, wf.first, wf.second, s, [&] {
-      dim3 gf(cdiv((int64_t)maxp * m, 256), nl);
-      k_bwd_border_fin<T><<<gf, 256, 0, s>>>(ln, nodes, st, ctx->d_dval.as<T>(), m, maxch, maxp, part, zb, rb);
-    });
+    if (!fused_fin) {
+      auto wf = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
+        by += 3.0 * np * dm * sz;
+      });
+      timed(tm, HF_K_SOLVE_GATHER, wf.first, wf.second, s, [&] {
+        dim3 gf(cdiv((int64_t)maxp * m, 256), nl);
+        k_bwd_border_fin<T><<<gf, 256, 0, s>>>(ln, nodes, st, ctx->d_dval.as<T>(), m, maxch, maxp, part, zb, rb);
+      });
+    }
     const int tb = step_of(nl);
     for (int J0 = ((maxp - 1) / tb) * tb; J0 >= 0; J0 -= tb) {
       auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
