@@ -180,6 +180,39 @@ k_gram_partial(int64_t n, int a, const double* __restrict__ A, int64_t sA, int b
       }
 }
 
+// Squared column norms of an n x m row-major block (the convergence test needs
+// only the diagonal of R^T R): GRAM_WG row chunks, each summed by 4 row phases
+// of 64 columns and the phases added in order; k_colsq_reduce adds the chunks
+// in order.
+__global__ void __launch_bounds__(256)
+k_colsq_partial(int64_t n, int m, const double* __restrict__ R, double* __restrict__ partial) {
+  const int64_t chunk = (n + GRAM_WG - 1) / GRAM_WG;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+  const int c = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  __shared__ double red[4][64];
+  double acc = 0.0;
+  if (c < m)
+    for (int64_t r = r0 + ph; r < r1; r += 32) {  // eight rows of this phase in flight
+      double v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = (r + 4 * i < r1) ? R[(r + 4 * i) * m + c] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc += v[i] * v[i];
+    }
+  red[ph][c] = acc;
+  __syncthreads();
+  if (threadIdx.x < 64 && c < m)
+    partial[(int64_t)blockIdx.x * m + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+}
+
+__global__ void k_colsq_reduce(int m, const double* __restrict__ partial, double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= m) return;
+  double s = 0.0;
+  for (int w = 0; w < GRAM_WG; ++w) s += partial[(int64_t)w * m + c];
+  out[c] = s;
+}
+
 __global__ void k_gram_reduce(int nblk, int ab, const double* __restrict__ partial,
                               double* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -765,18 +798,24 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
   const double rel = 1e-14;
   std::vector<double> hb(m * m), hr(m * m);
   std::vector<double> bn2(m);
-  // ||b_k||^2
-  gram(ctx, n, m, B, 0, 1, m, B, G, s);
-  HF_HIP(hipMemcpyAsync(hb.data(), G, sizeof(double) * m * m, hipMemcpyDeviceToHost, s));
-  HF_HIP(hipStreamSynchronize(s));
-  for (int k = 0; k < m; ++k) bn2[k] = hb[k * m + k];
-  auto converged = [&](const double* Rd) {
-    gram(ctx, n, m, Rd, 0, 1, m, Rd, G, s);
-    HF_HIP(hipMemcpyAsync(hr.data(), G, sizeof(double) * m * m, hipMemcpyDeviceToHost, s));
+  // squared column norms, on the host
+  double* nrm = w.norms.as<double>();
+  auto colsq = [&](const double* Rd, double* out) {
+    launch_timed(ctx->timer, HF_K_GRAM, (double)n * m * 8.0, 2.0 * n * m, s, k_colsq_partial, dim3(GRAM_WG),
+                 dim3(256), n, m, Rd, w.partial.as<double>());
+    launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_colsq_reduce, dim3(1), dim3(64), m,
+                 (const double*)w.partial.as<double>(), nrm);
+    HF_HIP(hipMemcpyAsync(out, nrm, sizeof(double) * m, hipMemcpyDeviceToHost, s));
     HF_HIP(hipStreamSynchronize(s));
+  };
+  // ||b_k||^2
+  colsq(B, hb.data());
+  for (int k = 0; k < m; ++k) bn2[k] = hb[k];
+  auto converged = [&](const double* Rd) {
+    colsq(Rd, hr.data());
     for (int k = 0; k < m; ++k) {
       if (bn2[k] <= 0.0) continue;
-      const double rr = hr[k * m + k];
+      const double rr = hr[k];
       if (!(rr <= tol * tol * bn2[k])) return false;
     }
     return true;
