@@ -40,9 +40,24 @@ __global__ void k_spmm_k11(int64_t n, const int64_t* __restrict__ ip, const int3
   if (row >= n) return;
   double acc = 0.0;
   if (!isl2[row]) {
-    for (int64_t q = ip[row]; q < ip[row + 1]; ++q) {
-      const int32_t c = ix[q];
-      if (!isl2[c]) acc += kv[q] * W[(int64_t)c * m + col];
+    const int64_t q1 = ip[row + 1];
+    for (int64_t q0 = ip[row]; q0 < q1; q0 += 8) {  // eight entries' loads in flight, summed in order
+      double a[8], wv[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        a[i] = 0.0;
+        wv[i] = 0.0;
+        if (q0 + i < q1) {
+          const int32_t c = ix[q0 + i];
+          if (!isl2[c]) {
+            a[i] = kv[q0 + i];
+            wv[i] = W[(int64_t)c * m + col];
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (q0 + i < q1) acc += a[i] * wv[i];
     }
   }
   Y[e] = acc;
