@@ -119,28 +119,43 @@ k_inv_step(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ stp
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-      for (int K = J; K < I; ++K) {
-        for (int k0 = 0; k0 < SB; k0 += 32) {
-          for (int e = tid; e < 32 * 64; e += 256) {
-            const int r = e & 63, kq = e >> 6;
-            const int gr = SB * I + r, gc = SB * K + k0 + kq;
-            As[kq][r] = (gr < nc && gc < nc) ? F[(int64_t)(J0 + gc) * f + J0 + gr] : (T)0;
-            const int kb = e & 31, c = e >> 5;
-            Bs[kb][c] = X[(int64_t)(SB * J + c) * TB + SB * K + k0 + kb];
-          }
-          __syncthreads();
-#pragma unroll 4
-          for (int kq = 0; kq < 32; ++kq) {
-            T a[4], b[4];
+      // stages of 32 values of k over K = J..I-1, each stage's operands fetched
+      // into registers while the previous stage is multiplied
+      const int nst = (I - J) * (SB / 32);
+      T ra[8], rb[8];
+      auto fetch = [&](int st2) {
+        const int K = J + st2 / (SB / 32), k0 = (st2 % (SB / 32)) * 32;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) { a[q] = As[kq][ty * 4 + q]; b[q] = Bs[kq][tx * 4 + q]; }
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-              for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
-          }
-          __syncthreads();
+        for (int q = 0; q < 8; ++q) {
+          const int e = tid + 256 * q;
+          const int r = e & 63, kq = e >> 6;
+          const int gr = SB * I + r, gc = SB * K + k0 + kq;
+          ra[q] = (gr < nc && gc < nc) ? F[(int64_t)(J0 + gc) * f + J0 + gr] : (T)0;
+          const int kb = e & 31, c = e >> 5;
+          rb[q] = X[(int64_t)(SB * J + c) * TB + SB * K + k0 + kb];
         }
+      };
+      fetch(0);
+      for (int st2 = 0; st2 < nst; ++st2) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int e = tid + 256 * q;
+          As[e >> 6][e & 63] = ra[q];
+          Bs[e & 31][e >> 5] = rb[q];
+        }
+        __syncthreads();
+        if (st2 + 1 < nst) fetch(st2 + 1);
+#pragma unroll 4
+        for (int kq = 0; kq < 32; ++kq) {
+          T a[4], b[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) { a[q] = As[kq][ty * 4 + q]; b[q] = Bs[kq][tx * 4 + q]; }
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+        }
+        __syncthreads();
       }
 #pragma unroll
       for (int x = 0; x < 4; ++x)
