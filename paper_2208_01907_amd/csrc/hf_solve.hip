@@ -839,11 +839,11 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       const T* dv = ctx->d_dval.as<T>();
       if (fused_fin)
         launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
-                     wide(gp) ? k_bwd_border_part<T, KBW, true> : k_bwd_border_part<T, KBN / 2, true>, gp, dim3(256),
+                     k_bwd_border_part<T, KBN / 2, true>, gp, dim3(256),
                      ln, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb);
       else
         launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
-                     wide(gp) ? k_bwd_border_part<T, KBW, false> : k_bwd_border_part<T, KBN / 2, false>, gp, dim3(256),
+                     k_bwd_border_part<T, KBN / 2, false>, gp, dim3(256),
                      ln, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb);
     }
     if (!fused_fin) {
