@@ -37,7 +37,7 @@ CALIB_BYTES = 256 << 20
 # valid while the source file that holds the kernel is unchanged
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_inclusions64_fp32.json")
 # classes that compute in FP64 whatever the factorization precision
-FP64_CLASSES = {"spmm", "gram", "combine"}
+FP64_CLASSES = {"spmm", "gram", "combine", "value_grad"}
 KERNEL_NAME = {"panel": "k_panel", "permute_l11": "k_l11_gather + k_l11_back", "f11_update": "k_syrk (trailing F11)",
                "gather_border": "k_gather_border", "trsm": "k_trsm", "syrk": "k_syrk (contribution)",
                "extend_add": "k_extend_add", "fwd_diag": "k_fwd_diag", "fwd_update": "k_fwd_upd",
@@ -199,6 +199,34 @@ def cpu_baseline(W):
                       f"{fl_sub:.3g} of {fl_all:.3g} flops) in {dt:.2f} s; factor+solve not included"}
 
 
+def adjoint_timing(hy, ctx, X, W, steps, torch):
+    """hf_adjoint on the factors of the last step (not part of the metric): one
+    more Algorithm 2 solve for a seeded loss gradient G = dl/dX, then the value
+    gradient on the pattern, whose kernel is priced against the HBM peak."""
+    import numpy as np
+    G = torch.tensor(np.random.default_rng(2208).standard_normal(W.b.shape), device=X.device)
+    hy.hf_adjoint(ctx, X, G)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hy.hf_adjoint(ctx, X, G)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    hy.hf_timing_enable(ctx, True)
+    for _ in range(steps):
+        hy.hf_adjoint(ctx, X, G)
+    torch.cuda.synchronize()
+    st = hy.hf_timing_get(ctx)["value_grad"]
+    hy.hf_timing_enable(ctx, False)
+    ms = st["ms"] / max(1, st["launches"])
+    gbs = st["bytes"] / max(1, st["launches"]) / (ms * 1e-3) / 1e9 if ms > 0 else None
+    return {"ms_per_call": dt * 1e3, "rhs": int(W.b.shape[1]),
+            "value_grad": {"kernel": "k_value_grad", "avg_launch_ms": ms,
+                           "bytes_per_launch": st["bytes"] / max(1, st["launches"]),
+                           "achieved_GBps": gbs, "peak_GBps": PEAK["hbm_GBps"],
+                           "frac": gbs / PEAK["hbm_GBps"] if gbs else None}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -243,6 +271,7 @@ def main():
         "kernel_rates": rates(stats),
         "roofline": roofline(stats, args.steps, 32),
     }
+    result["adjoint"] = adjoint_timing(hy, ctx, X, W, args.steps, torch)
     del ctx
     if not args.no_fp64:
         ctx64, X64, dt64, dt64_ev, _, stats64, info64 = run_path(hy, W, vals, B, hy.HF_PREC_FP64, args.steps,

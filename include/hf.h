@@ -159,6 +159,34 @@ int hf_factorize(hf_ctx* ctx, const double* values_dev, void* stream);
 int hf_solve(hf_ctx* ctx, int32_t r, const double* B_dev, int64_t ldb, double* X_dev, int64_t ldx,
              void* stream);
 
+/*
+ * Adjoint of hf_solve on the current factors.  An extension, not a step of the
+ * paper: one more solve with Algorithm 2 (Sec. 3) on the factors of the last
+ * hf_factorize gives the derivatives of a loss l(X) through X = Kbar^+ B.
+ *   X_dev     float64 n x r, leading dimension ldx >= n: the solution hf_solve
+ *             returned for B
+ *   G_dev     float64 n x r, leading dimension ldg >= n: dl/dX
+ *   Lam_dev   float64 n x r, leading dimension ldl >= n, output:
+ *             Lambda = Kbar^+ P G, with P the orthogonal projector onto the range
+ *             of Kbar (orthogonal to the detected kernel); Lambda is dl/dB for
+ *             right-hand sides in the range
+ *   GV_dev    float64 [nnz] or NULL, output: dl/dvalues on the analysed pattern,
+ *             in the order of indices_host: the entry (i, j) receives
+ *             -sum_c Lambda[i, c] X[j, c]
+ * P is formed with the kernel basis of hf_kernel_basis, so P G is consistent only
+ * to the accuracy of that basis, which bounds the backward error of Lambda (about
+ * 1e-12 for a 1e6 coefficient contrast at 2.6e5 unknowns, where the basis is
+ * 4.5e-8 from the exact kernel).
+ * The value gradient is exact along perturbations of Kbar that keep its kernel
+ * (for example coefficient changes of a pure-Neumann operator); along others the
+ * pseudo-inverse is not differentiable.  Lam_dev may alias neither G_dev, X_dev
+ * nor GV_dev.  With r == 0, GV_dev (if given) is set to zero.
+ * Errors: HF_ERR_STATE (not factorized), HF_ERR_ARG, HF_ERR_NO_CONVERGENCE,
+ * HF_ERR_OOM, HF_ERR_HIP.
+ */
+int hf_adjoint(hf_ctx* ctx, int32_t r, const double* X_dev, int64_t ldx, const double* G_dev, int64_t ldg,
+               double* Lam_dev, int64_t ldl, double* GV_dev, void* stream);
+
 /* Kernel dimension k found by the rank-revealing LDL^T of S22 (Sec. 2.2, Algorithm 1 step 5).
  * Errors: HF_ERR_ARG, HF_ERR_STATE. */
 int hf_kernel_dim(const hf_ctx* ctx, int32_t* k_host);
@@ -197,7 +225,8 @@ int hf_info(const hf_ctx* ctx, hf_info_t* info_host);
  * HF_K_SOLVE_GATHER and HF_K_OTHER holds the launches of one kernel.  When
  * enabled, every launch of an instrumented kernel is bracketed by HIP events on
  * the caller's stream; the
- * elapsed times are accumulated at the end of each hf_factorize / hf_solve,
+ * elapsed times are accumulated at the end of each hf_factorize / hf_solve /
+ * hf_adjoint,
  * together with the algorithmic bytes and flops of each launch (computed on the
  * host from the sizes of the fronts involved).  Enabling resets the counters.
  */
@@ -219,7 +248,8 @@ enum {
   HF_K_GRAM = 14,         /* k_gram_partial: FP64 Gram products of block GCR */
   HF_K_COMBINE = 15,      /* k_combine: FP64 block updates X += P C of block GCR */
   HF_K_OTHER = 16,        /* everything else */
-  HF_K_NCLASS = 17
+  HF_K_VALUE_GRAD = 17,   /* k_value_grad: value gradient of hf_adjoint */
+  HF_K_NCLASS = 18
 };
 
 typedef struct hf_kstat_t {

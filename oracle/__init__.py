@@ -23,6 +23,8 @@ Pipeline (Algorithm 1 and Algorithm 2 of Sec. 3):
                       1x1 / 2x2 blocks (Bunch-Parlett)
   rank_reveal      -- second-stage postponing, n_e enlargement, kernel dimension
   hybrid_factorize / hybrid_solve -- Algorithms 1 and 2 end to end
+  adjoint_solve / value_gradient -- derivatives through the solve (an
+                      extension: one more solve, then -lam x^T on the pattern)
 """
 from __future__ import annotations
 
@@ -738,3 +740,35 @@ def backward_error(Kbar, X, B):
         be = float(np.max(np.abs(r))) / den if den > 0 else 0.0
         worst = max(worst, be)
     return worst
+
+
+# ----------------------------------------------------------------------------
+# Adjoint of the solve (an extension of Algorithm 2, not a step of the paper)
+# ----------------------------------------------------------------------------
+# x = Kbar^+ b for b in the range of Kbar.  When Kbar moves along perturbations
+# that keep its kernel, differentiating Kbar x = b gives dx = -Kbar^+ dKbar x, so a
+# loss l(x) with g = dl/dx has dl/db = Kbar^+ P g and dl/dKbar_ij = -lam_i x_j with
+# lam = Kbar^+ P g (P: orthogonal projector onto the range).
+
+def adjoint_solve(Kbar, G, kernel):
+    """lam = Kbar^+ P G, dense, for small matrices.
+
+    With an orthonormal kernel basis N of the symmetric Kbar, Kbar + N N^T is
+    non-singular and its inverse is Kbar^+ + N N^T; applied to P G (orthogonal to
+    N) it gives Kbar^+ P G.  ``kernel`` may have zero columns (non-singular Kbar).
+    """
+    A = Kbar.toarray() if sp.issparse(Kbar) else np.array(Kbar, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    N = np.asarray(kernel, dtype=np.float64).reshape(A.shape[0], -1)
+    PG = G - N @ (N.T @ G) if N.shape[1] else G
+    return np.linalg.solve(A + N @ N.T, PG)
+
+
+def value_gradient(indptr, indices, X, Lam):
+    """dl/dvalues on a CSR pattern: entry (i, j) gets -sum_c Lam[i, c] X[j, c]."""
+    X = np.asarray(X, dtype=np.float64)
+    Lam = np.asarray(Lam, dtype=np.float64)
+    X = X.reshape(X.shape[0], -1)
+    Lam = Lam.reshape(Lam.shape[0], -1)
+    rows = np.repeat(np.arange(len(indptr) - 1), np.diff(indptr))
+    return -np.sum(Lam[rows] * X[np.asarray(indices)], axis=1)

@@ -40,6 +40,14 @@ int hf_solve(hf_ctx* ctx, int32_t r, const double* B_dev, int64_t ldb, double* X
   return hf::solve_impl(ctx, r, B_dev, ldb, X_dev, ldx, static_cast<hipStream_t>(stream));
 }
 
+int hf_adjoint(hf_ctx* ctx, int32_t r, const double* X_dev, int64_t ldx, const double* G_dev, int64_t ldg,
+               double* Lam_dev, int64_t ldl, double* GV_dev, void* stream) {
+  if (!ctx) return HF_ERR_ARG;
+  if (r > 0 && Lam_dev && (Lam_dev == G_dev || Lam_dev == X_dev || (GV_dev && GV_dev == Lam_dev)))
+    return HF_ERR_ARG;
+  return hf::adjoint_impl(ctx, r, X_dev, ldx, G_dev, ldg, Lam_dev, ldl, GV_dev, static_cast<hipStream_t>(stream));
+}
+
 int hf_kernel_dim(const hf_ctx* ctx, int32_t* k_host) {
   if (!ctx || !k_host) return HF_ERR_ARG;
   if (ctx->state < 2) return HF_ERR_STATE;

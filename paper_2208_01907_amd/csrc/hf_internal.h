@@ -233,6 +233,7 @@ struct hf_ctx {
   // solve-phase scratch
   hf::DBuf d_rhs_arena;            // front RHS arena (T)
   hf::DBuf d_rhs_b, d_y2, d_x2pad; // Algorithm 2 scratch
+  hf::DBuf d_adj;                  // adjoint: right-hand sides projected onto the range
   hf::BgcrWork* work = nullptr;
   hf::KTimer timer;
   std::vector<hf::NodeState> hstate;  // node states after the last factorization
@@ -252,5 +253,7 @@ int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, 
 void free_work(hf_ctx* ctx);
 int schur_impl(const hf_ctx* ctx, int32_t* m, int32_t* lambda2, double* S, int64_t lds, hipStream_t s);
 int kernel_basis_impl(const hf_ctx* ctx, double* N, int64_t ldn, hipStream_t s);
+int adjoint_impl(hf_ctx* ctx, int32_t r, const double* X, int64_t ldx, const double* G, int64_t ldg,
+                 double* Lam, int64_t ldl, double* GV, hipStream_t s);
 int scaling_impl(const hf_ctx* ctx, double* q, hipStream_t s);
 }  // namespace hf

@@ -1119,6 +1119,100 @@ int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, 
   return HF_OK;
 }
 
+// Adjoint of the solve.  Not a step of the paper's method: the derivative of the
+// solution map of Algorithm 2, taken with one more solve on the same factors.
+// For Kbar x = b with ker Kbar fixed and b in its range, x = Kbar^+ b changes by
+// dx = -Kbar^+ dKbar x when Kbar moves along perturbations that keep the kernel.
+// A loss with gradient g = dl/dx therefore has dl/db = lambda and
+// dl/dKbar_ij = -lambda_i x_j, with lambda = Kbar^+ (g projected onto the range).
+
+// caller columns c0 .. c0+m-1 (column-major, original order) -> row-major n x m
+__global__ void k_take_cols(int64_t n, int m, const double* __restrict__ G, int64_t ldg, int c0,
+                            double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t o = e / m;
+  const int c = (int)(e - o * m);
+  if (o >= n) return;
+  out[e] = G[(int64_t)(c0 + c) * ldg + o];
+}
+
+// value gradient on the stored pattern: the entry in row i, column j (original
+// numbering) receives -sum_c lambda[i, c] x[j, c], summed over c in ascending
+// order.  One wave per row of the elimination-ordered pattern, one lane per
+// entry; psrc maps each entry to its position in the caller's CSR arrays.
+__global__ void k_value_grad(int64_t n, const int64_t* __restrict__ pindptr, const int32_t* __restrict__ pindices,
+                             const int64_t* __restrict__ psrc, const int32_t* __restrict__ perm, int r,
+                             const double* __restrict__ X, int64_t ldx, const double* __restrict__ Lam,
+                             int64_t ldl, double* __restrict__ GV) {
+  const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (g >= n) return;
+  const int64_t io = perm[g];
+  for (int64_t e = pindptr[g] + lane; e < pindptr[g + 1]; e += 64) {
+    const int64_t jo = perm[pindices[e]];
+    double acc = 0.0;
+    for (int c = 0; c < r; ++c) acc = fma(Lam[(int64_t)c * ldl + io], X[(int64_t)c * ldx + jo], acc);
+    GV[psrc[e]] = -acc;
+  }
+}
+
+int adjoint_impl(hf_ctx* ctx, int32_t r, const double* X, int64_t ldx, const double* G, int64_t ldg,
+                 double* Lam, int64_t ldl, double* GV, hipStream_t s) {
+  if (ctx->state < 2) return HF_ERR_STATE;
+  const int64_t n = ctx->n;
+  if (r < 0 || (r > 0 && n > 0 && (!X || !G || !Lam || ldx < n || ldg < n || ldl < n))) return HF_ERR_ARG;
+  if (n == 0) return HF_OK;
+  try {
+    if (r == 0) {
+      if (GV) HF_HIP(hipMemsetAsync(GV, 0, (size_t)ctx->nnz * sizeof(double), s));
+      HF_HIP(hipStreamSynchronize(s));
+      return HF_OK;
+    }
+    const int k = ctx->kdim;
+    const double* Nk = ctx->d_kern.as<double>();
+    // right-hand sides g projected onto the range of Kbar (orthogonal to the kernel)
+    ctx->d_adj.alloc((size_t)n * r * sizeof(double));
+    double* P = ctx->d_adj.as<double>();
+    for (int c0 = 0; c0 < r; c0 += MAXM) {
+      const int m = std::min(MAXM, r - c0);
+      BgcrWork& w = get_work(ctx, std::max(m, std::max(ctx->mb, k)));
+      const int64_t nm = n * m;
+      ctx->d_rhs_b.alloc((size_t)nm * sizeof(double) * 6);
+      double* t = ctx->d_rhs_b.as<double>();
+      k_take_cols<<<cdiv(nm, 256), 256, 0, s>>>(n, m, G, ldg, c0, t);
+      if (k > 0) {
+        double* C = w.gram.as<double>();
+        gram(ctx, n, k, Nk, 0, 1, m, t, C, s);
+        k_neg<<<cdiv((int64_t)k * m, 256), 256, 0, s>>>((int64_t)k * m, C);
+        combine(ctx, n, k, m, t, t, 1, Nk, 0, C, s);
+      }
+      k_store_cols<<<cdiv(nm, 256), 256, 0, s>>>(n, m, t, P, n, c0);
+      HF_HIP(hipGetLastError());
+    }
+    const int st = solve_impl(ctx, r, P, n, Lam, ldl, s);
+    if (st != HF_OK) return st;
+    if (GV) {
+      // algorithmic bytes: the pattern (row pointers, permuted indices, map to the
+      // caller's order, the output) and X and Lambda read once
+      const double by = (double)ctx->nnz * (4.0 + 8.0 + 8.0) + (double)n * (8.0 + 4.0) + 2.0 * n * r * 8.0;
+      launch_timed(ctx->timer, HF_K_VALUE_GRAD, by, 2.0 * ctx->nnz * r, s, k_value_grad,
+                   dim3((unsigned)cdiv(n, 4)), dim3(256), n, ctx->d_pindptr.as<int64_t>(),
+                   ctx->d_pindices.as<int32_t>(), ctx->d_psrc.as<int64_t>(), ctx->d_perm.as<int32_t>(), r, X, ldx,
+                   (const double*)Lam, ldl, GV);
+      HF_HIP(hipGetLastError());
+    }
+    HF_HIP(hipStreamSynchronize(s));
+    ctx->timer.flush();
+  } catch (const HipError&) {
+    return HF_ERR_HIP;
+  } catch (const Status& st) {
+    return st.code;
+  } catch (const std::bad_alloc&) {
+    return HF_ERR_OOM;
+  }
+  return HF_OK;
+}
+
 // accessors used by the C entry points
 int schur_impl(const hf_ctx* ctx, int32_t* m, int32_t* lambda2, double* S, int64_t lds, hipStream_t s) {
   if (ctx->state < 2) return HF_ERR_STATE;

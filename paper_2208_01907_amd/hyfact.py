@@ -15,6 +15,8 @@ The function names follow the C entry points:
     lam2, S22 = hf_schur(ctx)                # hard part, Schur complement (scaled)
     q = hf_scaling(ctx)
     info = hf_info(ctx)
+    Lam, GV = hf_adjoint(ctx, X, G)          # derivatives of a loss through X
+    X = solve(ctx, values, B)                # torch.autograd-aware factorize + solve
 """
 from __future__ import annotations
 
@@ -45,12 +47,12 @@ HF_PREC_FP64 = 64
 
 EXPORTS = ["hf_default_options", "hf_analyse", "hf_factorize", "hf_solve", "hf_kernel_dim",
            "hf_kernel_basis", "hf_schur", "hf_scaling", "hf_info", "hf_strerror", "hf_destroy",
-           "hf_timing_enable", "hf_timing_get"]
+           "hf_timing_enable", "hf_timing_get", "hf_adjoint"]
 
 # kernel classes of hf_timing_get
 KCLASS = ["panel", "permute_l11", "f11_update", "gather_border", "trsm", "syrk", "extend_add", "fwd_diag",
           "fwd_update", "bwd_border", "bwd_diag", "bwd_update", "solve_gather", "spmm", "gram", "combine",
-          "other"]
+          "other", "value_grad"]
 
 
 class HFError(RuntimeError):
@@ -97,6 +99,7 @@ def _load():
         "hf_analyse": (ctypes.c_int, [I64, P, P, P, I32, P, P, P, P]),
         "hf_factorize": (ctypes.c_int, [P, P, P]),
         "hf_solve": (ctypes.c_int, [P, I32, P, I64, P, I64, P]),
+        "hf_adjoint": (ctypes.c_int, [P, I32, P, I64, P, I64, P, I64, P, P]),
         "hf_kernel_dim": (ctypes.c_int, [P, P]),
         "hf_kernel_basis": (ctypes.c_int, [P, P, I64, P]),
         "hf_schur": (ctypes.c_int, [P, P, P, P, I64, P]),
@@ -151,9 +154,11 @@ def hf_default_options(**kw) -> HFOptions:
 class Context:
     """Owns an hf_ctx; destroyed with the object."""
 
-    def __init__(self, handle, n):
+    def __init__(self, handle, n, nnz=0):
         self._h = handle
         self.n = n
+        self.nnz = nnz
+        self.generation = 0     # bumped by every successful hf_factorize
 
     @property
     def handle(self):
@@ -185,12 +190,13 @@ def hf_analyse(indptr, indices, perm=None, node_ptr=None, parent=None, opt=None)
     code = _lib.hf_analyse(n, _np_ptr(indptr), _np_ptr(indices), _np_ptr(perm), n_nodes, _np_ptr(node_ptr),
                            _np_ptr(parent), ctypes.byref(opt) if opt is not None else None, ctypes.byref(h))
     _check(code, "hf_analyse")
-    return Context(h, n)
+    return Context(h, n, len(indices))
 
 
 def hf_factorize(ctx: Context, values, stream=None):
     assert values.is_cuda and values.dtype == torch.float64 and values.is_contiguous()
     _check(_lib.hf_factorize(ctx.handle, ctypes.c_void_p(values.data_ptr()), _stream(stream)), "hf_factorize")
+    ctx.generation += 1
 
 
 def hf_solve(ctx: Context, B, X=None, stream=None):
@@ -210,6 +216,66 @@ def hf_solve(ctx: Context, B, X=None, stream=None):
         X.copy_(out.reshape(X.shape))
         return X
     return out[:, 0] if one else out
+
+
+def hf_adjoint(ctx: Context, X, G, with_values=True, stream=None):
+    """Adjoint solve on the current factors (see hf_adjoint in include/hf.h).
+
+    X: the solution hf_solve returned, G = dl/dX, both (L, r) or (L,) float64 on
+    the GPU.  Returns (Lam, GV): Lam = Kbar^+ P G of the shape of G, and GV of
+    shape (nnz,) = dl/dvalues on the analysed pattern (None if not with_values).
+    """
+    assert X.is_cuda and G.is_cuda and X.dtype == torch.float64 and G.dtype == torch.float64
+    if X.shape != G.shape or X.dim() not in (1, 2):
+        raise ValueError("X and G must both be (L,) or (L, r)")
+    one = X.dim() == 1
+    X2 = X.reshape(-1, 1) if one else X
+    G2 = G.reshape(-1, 1) if one else G
+    r = X2.shape[1]
+    Xc = X2.t().contiguous()
+    Gc = G2.t().contiguous()
+    Lc = torch.empty_like(Gc)
+    GV = torch.empty(ctx.nnz, dtype=torch.float64, device=X.device) if with_values else None
+    _check(_lib.hf_adjoint(ctx.handle, r, ctypes.c_void_p(Xc.data_ptr()), ctx.n, ctypes.c_void_p(Gc.data_ptr()),
+                           ctx.n, ctypes.c_void_p(Lc.data_ptr()), ctx.n,
+                           ctypes.c_void_p(GV.data_ptr()) if GV is not None else None, _stream(stream)),
+           "hf_adjoint")
+    Lam = Lc.t()
+    return (Lam[:, 0] if one else Lam), GV
+
+
+class _HybridSolve(torch.autograd.Function):
+    """values, B -> X = Kbar(values)^+ B with the adjoint of hf_adjoint as backward."""
+
+    @staticmethod
+    def forward(fctx, values, B, ctx):
+        hf_factorize(ctx, values.detach().contiguous())
+        X = hf_solve(ctx, B.detach())
+        fctx.ctx = ctx
+        fctx.generation = ctx.generation
+        fctx.save_for_backward(X)
+        return X
+
+    @staticmethod
+    def backward(fctx, gX):
+        ctx = fctx.ctx
+        if ctx.generation != fctx.generation:
+            raise RuntimeError("the context was factorized again after this solve; its adjoint needs the "
+                               "factors the solve used")
+        (X,) = fctx.saved_tensors
+        Lam, GV = hf_adjoint(ctx, X, gX.contiguous(), with_values=fctx.needs_input_grad[0])
+        return GV, (Lam if fctx.needs_input_grad[1] else None), None
+
+
+def solve(ctx: Context, values, B):
+    """Factorize with ``values`` and solve for ``B``, differentiable in both.
+
+    Gradients: dl/dB = Kbar^+ P dl/dX (P: projector onto the range) and
+    dl/dvalues[(i, j)] = -sum_c Lam[i, c] X[j, c]; the latter is exact along value
+    perturbations that keep the kernel of Kbar.  The backward pass reuses the
+    context's factors and raises if it was factorized again in between.
+    """
+    return _HybridSolve.apply(values, B, ctx)
 
 
 def hf_kernel_dim(ctx: Context) -> int:

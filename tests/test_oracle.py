@@ -284,3 +284,69 @@ def test_backward_error_checker():
     xp = W.x_star * (1 + 1e-10)
     be = oracle.backward_error(K, xp, W.b)
     assert 1e-13 < be < 1e-9
+
+
+# --- adjoint of the solve (extension) ----------------------------------------
+# Pins of oracle.adjoint_solve / oracle.value_gradient against central finite
+# differences of solutions computed by LAPACK (numpy.linalg.solve / pinv).
+
+def _loss(X, Xs):
+    return 0.5 * float(np.sum((X - Xs) ** 2))
+
+
+def test_adjoint_entrywise_finite_differences():
+    """Non-singular K, each stored entry perturbed on its own (not symmetrically):
+    dl/dK_ij = -lam_i x_j, which tells the entry (i, j) from (j, i)."""
+    W = w.random_dense_workload(12, seed=40, kernel_dim=0, cond=10.0, r=2)
+    A = W.csr().toarray()
+    rng = np.random.default_rng(41)
+    Xs = rng.standard_normal(W.b.shape)
+    X = np.linalg.solve(A, W.b)
+    lam = oracle.adjoint_solve(A, X - Xs, np.zeros((W.n, 0)))
+    GV = oracle.value_gradient(W.indptr, W.indices, X, lam)
+    rows = np.repeat(np.arange(W.n), np.diff(W.indptr))
+    h = 1e-6
+    fd = np.empty(W.nnz)
+    for e in range(W.nnz):
+        i, j = rows[e], W.indices[e]
+        Ap, Am = A.copy(), A.copy()
+        Ap[i, j] += h
+        Am[i, j] -= h
+        fd[e] = (_loss(np.linalg.solve(Ap, W.b), Xs) - _loss(np.linalg.solve(Am, W.b), Xs)) / (2 * h)
+    assert np.allclose(GV, fd, rtol=1e-6, atol=1e-8 * np.abs(fd).max())
+    # a transposed formula (lam_j x_i) differs from the finite differences
+    GVt = -np.sum(lam[W.indices] * X[rows], axis=1)
+    assert not np.allclose(GVt, fd, rtol=1e-3, atol=1e-3 * np.abs(fd).max())
+
+
+def test_adjoint_neumann_coefficient_directional_derivative():
+    """Singular pure-Neumann FV operator: coefficient changes keep ker = constants,
+    so l(c) = 1/2 ||Kbar(c)^+ B - X*||^2 is differentiable; the adjoint's
+    directional derivatives in c and in B match finite differences of pinv."""
+    rng = np.random.default_rng(42)
+    coef = 10.0 ** rng.uniform(-1, 1, size=(6, 5))
+    n = coef.size
+    one = np.ones((n, 1)) / math.sqrt(n)
+    B = rng.standard_normal((n, 3))
+    B -= one @ (one.T @ B)
+    Xs = rng.standard_normal((n, 3))
+    K = w.fv_laplacian(coef)
+    X = np.linalg.pinv(K.toarray()) @ B
+    lam = oracle.adjoint_solve(K, X - Xs, one)
+    GV = oracle.value_gradient(K.indptr, K.indices, X, lam)
+    dc = coef * rng.uniform(-1, 1, size=coef.shape)
+    h = 1e-6
+    Kp, Km = w.fv_laplacian(coef + h * dc), w.fv_laplacian(coef - h * dc)
+    assert np.array_equal(Kp.indices, K.indices) and np.array_equal(Km.indptr, K.indptr)
+    dK = (Kp.data - Km.data) / (2 * h)
+    fd = (_loss(np.linalg.pinv(Kp.toarray()) @ B, Xs) - _loss(np.linalg.pinv(Km.toarray()) @ B, Xs)) / (2 * h)
+    assert abs(GV @ dK - fd) <= 1e-6 * abs(fd)
+    dB = rng.standard_normal(B.shape)
+    dB -= one @ (one.T @ dB)
+    pinvK = np.linalg.pinv(K.toarray())
+    fdb = (_loss(pinvK @ (B + h * dB), Xs) - _loss(pinvK @ (B - h * dB), Xs)) / (2 * h)
+    assert abs(np.sum(lam * dB) - fdb) <= 1e-6 * abs(fdb)
+    # kernel component of the loss gradient: projected away
+    lam2 = oracle.adjoint_solve(K, X - Xs + 3.0 * one, one)
+    assert np.allclose(lam2, lam, rtol=0, atol=1e-12 * np.abs(lam).max())
+    assert np.abs(one.T @ lam).max() <= 1e-10 * np.abs(lam).max()
