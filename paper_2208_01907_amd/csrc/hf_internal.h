@@ -202,7 +202,8 @@ struct hf_ctx {
   double flops_sym = 0.0, flops_done = 0.0;
   int64_t factor_entries = 0;
   // device: pattern
-  hf::DBuf d_pindptr, d_pindices, d_psrc, d_prow_orig, d_diagpos, d_asm;
+  hf::DBuf d_pindptr, d_pindices, d_psrc, d_diagpos, d_asm;
+  hf::DBuf d_orow, d_ocol;         // caller's pattern, one (row, column) per entry (adjoint)
   hf::DBuf d_perm, d_iperm, d_nodes, d_border, d_relmap, d_level_nodes, d_child_list, d_ea_items;
   hf::DBuf d_gat_ptr, d_gat_src;
   // device: numeric

@@ -1136,24 +1136,31 @@ __global__ void k_take_cols(int64_t n, int m, const double* __restrict__ G, int6
   out[e] = G[(int64_t)(c0 + c) * ldg + o];
 }
 
-// value gradient on the stored pattern: the entry in row i, column j (original
-// numbering) receives -sum_c lambda[i, c] x[j, c], summed over c in ascending
-// order.  One wave per row of the elimination-ordered pattern, one lane per
-// entry; psrc maps each entry to its position in the caller's CSR arrays.
-__global__ void k_value_grad(int64_t n, const int64_t* __restrict__ pindptr, const int32_t* __restrict__ pindices,
-                             const int64_t* __restrict__ psrc, const int32_t* __restrict__ perm, int r,
-                             const double* __restrict__ X, int64_t ldx, const double* __restrict__ Lam,
-                             int64_t ldl, double* __restrict__ GV) {
-  const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (g >= n) return;
-  const int64_t io = perm[g];
-  for (int64_t e = pindptr[g] + lane; e < pindptr[g + 1]; e += 64) {
-    const int64_t jo = perm[pindices[e]];
-    double acc = 0.0;
-    for (int c = 0; c < r; ++c) acc = fma(Lam[(int64_t)c * ldl + io], X[(int64_t)c * ldx + jo], acc);
-    GV[psrc[e]] = -acc;
+// value gradient on the caller's pattern: entry e, in row i and column j of the
+// caller's CSR arrays, receives -sum_c Lam[i, c] x[j, c], summed over c in
+// ascending order.  One thread per entry in the caller's order: the output is
+// written contiguously and neighbouring entries read neighbouring rows of the
+// column-major X and Lambda.
+__global__ void k_value_grad(int64_t nnz, const int32_t* __restrict__ orow, const int32_t* __restrict__ ocol, int r,
+                             const double* __restrict__ X, int64_t ldx, const double* __restrict__ Lam, int64_t ldl,
+                             double* __restrict__ GV) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const int64_t i = orow[e], j = ocol[e];
+  double acc = 0.0;
+  int c = 0;
+  for (; c + 8 <= r; c += 8) {
+    double a[8], x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[u] = Lam[(int64_t)(c + u) * ldl + i];
+      x[u] = X[(int64_t)(c + u) * ldx + j];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(a[u], x[u], acc);
   }
+  for (; c < r; ++c) acc = fma(Lam[(int64_t)c * ldl + i], X[(int64_t)c * ldx + j], acc);
+  GV[e] = -acc;
 }
 
 int adjoint_impl(hf_ctx* ctx, int32_t r, const double* X, int64_t ldx, const double* G, int64_t ldg,
@@ -1191,14 +1198,21 @@ int adjoint_impl(hf_ctx* ctx, int32_t r, const double* X, int64_t ldx, const dou
     }
     const int st = solve_impl(ctx, r, P, n, Lam, ldl, s);
     if (st != HF_OK) return st;
-    if (GV) {
-      // algorithmic bytes: the pattern (row pointers, permuted indices, map to the
-      // caller's order, the output) and X and Lambda read once
-      const double by = (double)ctx->nnz * (4.0 + 8.0 + 8.0) + (double)n * (8.0 + 4.0) + 2.0 * n * r * 8.0;
+    if (GV && ctx->nnz > 0) {
+      if (!ctx->d_orow.ptr) {
+        // the caller's pattern as (row, column) pairs, once per context
+        std::vector<int32_t> orow(ctx->nnz);
+        for (int64_t i = 0; i < n; ++i)
+          for (int64_t e = ctx->indptr[i]; e < ctx->indptr[i + 1]; ++e) orow[e] = (int32_t)i;
+        upload(ctx->d_orow, orow, s);
+        upload(ctx->d_ocol, ctx->indices, s);
+        HF_HIP(hipStreamSynchronize(s));
+      }
+      // algorithmic bytes: the (row, column) pairs, the output, X and Lambda once
+      const double by = (double)ctx->nnz * (4.0 + 4.0 + 8.0) + 2.0 * n * r * 8.0;
       launch_timed(ctx->timer, HF_K_VALUE_GRAD, by, 2.0 * ctx->nnz * r, s, k_value_grad,
-                   dim3((unsigned)cdiv(n, 4)), dim3(256), n, ctx->d_pindptr.as<int64_t>(),
-                   ctx->d_pindices.as<int32_t>(), ctx->d_psrc.as<int64_t>(), ctx->d_perm.as<int32_t>(), r, X, ldx,
-                   (const double*)Lam, ldl, GV);
+                   dim3((unsigned)cdiv(ctx->nnz, 256)), dim3(256), ctx->nnz, ctx->d_orow.as<int32_t>(),
+                   ctx->d_ocol.as<int32_t>(), r, X, ldx, (const double*)Lam, ldl, GV);
       HF_HIP(hipGetLastError());
     }
     HF_HIP(hipStreamSynchronize(s));
