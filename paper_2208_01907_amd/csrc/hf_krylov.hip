@@ -245,7 +245,9 @@ __global__ void k_gram_reduce(int nblk, int ab, const double* __restrict__ parti
 
 // Pivoted Cholesky of an SPSD m x m Gram matrix (row-major), deflating pivots
 // <= rel * max diag.  Output: Lc (m x m row-major, lower), piv[m], rank.
-__global__ void __launch_bounds__(64)
+// Four waves: every wave finds the pivot itself (lanes over the diagonal), the
+// trailing update runs with waves over rows and lanes over columns.
+__global__ void __launch_bounds__(256)
 k_chol_piv(int m, const double* __restrict__ Mm, int64_t sM, double* __restrict__ Lc,
            int32_t* __restrict__ piv, int32_t* __restrict__ rank, double rel) {
   const int blk = blockIdx.x;
@@ -255,9 +257,9 @@ k_chol_piv(int m, const double* __restrict__ Mm, int64_t sM, double* __restrict_
   __shared__ double A[MAXM * MAXM];
   __shared__ double L[MAXM * MAXM];
   __shared__ int Ps[MAXM];
-  const int tid = threadIdx.x;  // one wave
-  for (int e = tid; e < m * m; e += 64) { A[e] = G[e]; L[e] = 0.0; }
-  for (int e = tid; e < m; e += 64) Ps[e] = e;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < m * m; e += 256) { A[e] = G[e]; L[e] = 0.0; }
+  for (int e = tid; e < m; e += 256) Ps[e] = e;
   __syncthreads();
   double dmax = 0.0;
   for (int i = 0; i < m; ++i) dmax = fmax(dmax, A[i * m + i]);
@@ -266,7 +268,7 @@ k_chol_piv(int m, const double* __restrict__ Mm, int64_t sM, double* __restrict_
     // largest remaining diagonal, ties to the first
     double bv = -INFINITY;
     int bk = INT_MAX;
-    if (tid >= i && tid < m) { bv = A[tid * m + tid]; bk = tid; }
+    if (lane >= i && lane < m) { bv = A[lane * m + lane]; bk = lane; }
     for (int off = 32; off > 0; off >>= 1) {
       const double ov = __shfl_xor(bv, off, 64);
       const int ok = __shfl_xor(bk, off, 64);
@@ -275,30 +277,29 @@ k_chol_piv(int m, const double* __restrict__ Mm, int64_t sM, double* __restrict_
     const int k = bk;
     if (bv <= rel * dmax || bv <= 0.0) break;
     if (k != i) {
-      for (int t = tid; t < m; t += 64) {
+      for (int t = tid; t < m; t += 256) {
         const double x = A[i * m + t]; A[i * m + t] = A[k * m + t]; A[k * m + t] = x;
       }
       __syncthreads();
-      for (int t = tid; t < m; t += 64) {
+      for (int t = tid; t < m; t += 256) {
         const double x = A[t * m + i]; A[t * m + i] = A[t * m + k]; A[t * m + k] = x;
       }
-      for (int t = tid; t < i; t += 64) {
+      for (int t = tid; t < i; t += 256) {
         const double x = L[i * m + t]; L[i * m + t] = L[k * m + t]; L[k * m + t] = x;
       }
       if (tid == 0) { const int x = Ps[i]; Ps[i] = Ps[k]; Ps[k] = x; }
       __syncthreads();
     }
     const double lii = sqrt(A[i * m + i]);
-    for (int r = i + tid; r < m; r += 64) L[r * m + i] = (r == i) ? lii : A[r * m + i] / lii;
+    for (int r = i + tid; r < m; r += 256) L[r * m + i] = (r == i) ? lii : A[r * m + i] / lii;
     __syncthreads();
-    for (int e = tid; e < (m - i - 1) * (m - i - 1); e += 64) {
-      const int r = i + 1 + e / (m - i - 1), c = i + 1 + e % (m - i - 1);
-      A[r * m + c] -= L[r * m + i] * L[c * m + i];
-    }
+    const int c = i + 1 + lane;
+    if (c < m)
+      for (int r = i + 1 + w; r < m; r += 4) A[r * m + c] -= L[r * m + i] * L[c * m + i];
     __syncthreads();
   }
-  for (int e = tid; e < m * m; e += 64) Lg[e] = L[e];
-  for (int e = tid; e < m; e += 64) P[e] = Ps[e];
+  for (int e = tid; e < m * m; e += 256) Lg[e] = L[e];
+  for (int e = tid; e < m; e += 256) P[e] = Ps[e];
   if (tid == 0) rank[blk] = i;
 }
 
@@ -566,42 +567,45 @@ __global__ void k_s22_null(int M, int k, const double* __restrict__ L, const int
 __global__ void k_s22_solve(int M, int k, const double* __restrict__ L, const double* __restrict__ D,
                             const int32_t* __restrict__ perm, const int32_t* __restrict__ bsize, int nc,
                             const double* __restrict__ Y, double* __restrict__ X, double* __restrict__ work) {
+  // when M <= MAXM, L and every column's work vector live in LDS (dynamic:
+  // (M*M + M*blockDim) doubles); otherwise both stay in global memory
+  extern __shared__ double sm[];
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  __shared__ double Ls[MAXM * MAXM];  // L staged in LDS when it fits
   const bool lds = M <= MAXM;
   if (lds)
-    for (int e = threadIdx.x; e < M * M; e += blockDim.x) Ls[e] = L[e];
+    for (int e = threadIdx.x; e < M * M; e += blockDim.x) sm[e] = L[e];
   __syncthreads();
   if (c >= nc) return;
-  double* z = work + (int64_t)c * M;
-  double* Lm = lds ? Ls : const_cast<double*>(L);
+  double* z = lds ? sm + M * M + threadIdx.x : work + (int64_t)c * M;
+  const int zs = lds ? blockDim.x : 1;
+  double* Lm = lds ? sm : const_cast<double*>(L);
   double* Dm = const_cast<double*>(D);
   for (int i = 0; i < M; ++i) {
     double v = Y[(int64_t)perm[i] * nc + c];
-    for (int t = 0; t < i; ++t) v -= at(Lm, M, i, t) * z[t];
-    z[i] = v;
+    for (int t = 0; t < i; ++t) v -= at(Lm, M, i, t) * z[t * zs];
+    z[i * zs] = v;
   }
   const int r = M - k;
   for (int i = 0; i < M;) {
-    if (i >= r) { z[i] = 0.0; ++i; continue; }
+    if (i >= r) { z[i * zs] = 0.0; ++i; continue; }
     if (bsize[i] == 2 && i + 1 < r) {
       const double e11 = at(Dm, M, i, i), e12 = at(Dm, M, i + 1, i), e22 = at(Dm, M, i + 1, i + 1);
       const double det = e11 * e22 - e12 * e12;
-      const double a = z[i], b = z[i + 1];
-      z[i] = (a * e22 - b * e12) / det;
-      z[i + 1] = (b * e11 - a * e12) / det;
+      const double a = z[i * zs], b = z[(i + 1) * zs];
+      z[i * zs] = (a * e22 - b * e12) / det;
+      z[(i + 1) * zs] = (b * e11 - a * e12) / det;
       i += 2;
     } else {
-      z[i] = z[i] / at(Dm, M, i, i);
+      z[i * zs] = z[i * zs] / at(Dm, M, i, i);
       ++i;
     }
   }
   for (int i = M - 1; i >= 0; --i) {
-    double v = z[i];
-    for (int t = i + 1; t < M; ++t) v -= at(Lm, M, t, i) * z[t];
-    z[i] = v;
+    double v = z[i * zs];
+    for (int t = i + 1; t < M; ++t) v -= at(Lm, M, t, i) * z[t * zs];
+    z[i * zs] = v;
   }
-  for (int i = 0; i < M; ++i) X[(int64_t)perm[i] * nc + c] = z[i];
+  for (int i = 0; i < M; ++i) X[(int64_t)perm[i] * nc + c] = z[i * zs];
 }
 
 // unpivoted Cholesky G = R^T R of a small SPD matrix (row-major k x k); coef = R^{-1}
@@ -844,7 +848,7 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
   precond(ctx, m, R, P, s);
   spmm_k11(ctx, m, P, Qv, s);
   gram(ctx, n, m, Qv, 0, 1, m, Qv, G, s);
-  k_chol_piv<<<1, 64, 0, s>>>(m, G, 0, Lc, piv, rank, rel);
+  k_chol_piv<<<1, 256, 0, s>>>(m, G, 0, Lc, piv, rank, rel);
   const int maxit = ctx->opt.gcr_maxit;
   for (int it = 0; it < maxit; ++it) {
     double* Pn = P + it * sv;
@@ -867,13 +871,12 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
     // beta_m = -M_m^{-1} Qv_m^T Z, for m = 0..n
     const int nb = it + 1;
     gram(ctx, n, m, Qv, sv, nb, m, Qn1, G, s);
-    for (int q = 0; q < nb; ++q)
-      k_chol_solve<<<1, 64, 0, s>>>(m, m, Lc + (int64_t)q * m * m, piv + (int64_t)q * m, rank + q,
-                                    G + (int64_t)q * m * m, 0, coef + (int64_t)q * m * m, 0, -1.0);
+    // the nb coefficient solves at once, one workgroup each
+    k_chol_solve<<<nb, 64, 0, s>>>(m, m, Lc, piv, rank, G, (int64_t)m * m, coef, (int64_t)m * m, -1.0);
     combine(ctx, n, m, m, Pn1, Pn1, nb, P, sv, coef, s);
     combine(ctx, n, m, m, Qn1, Qn1, nb, Qv, sv, coef, s);
     gram(ctx, n, m, Qn1, 0, 1, m, Qn1, G, s);
-    k_chol_piv<<<1, 64, 0, s>>>(m, G, 0, Lc + (int64_t)(it + 1) * m * m, piv + (int64_t)(it + 1) * m,
+    k_chol_piv<<<1, 256, 0, s>>>(m, G, 0, Lc + (int64_t)(it + 1) * m * m, piv + (int64_t)(it + 1) * m,
                                 rank + it + 1, rel);
     HF_HIP(hipGetLastError());
   }
@@ -1038,7 +1041,8 @@ static int solve_core(hf_ctx* ctx, int m, const double* b, double* x, double* b1
     double* S = ctx->d_S22f.as<double>();
     const int64_t MM = (int64_t)M * M;
     int32_t* sperm = ctx->d_s22perm.as<int32_t>();
-    k_s22_solve<<<1, 64, 0, s>>>(M, k, S + MM, S + 2 * MM, sperm, sperm + M, m, y2, x2, wk);
+    const size_t s22_lds = M <= MAXM ? (size_t)(M * M + M * 64) * sizeof(double) : 0;
+    k_s22_solve<<<1, 64, s22_lds, s>>>(M, k, S + MM, S + 2 * MM, sperm, sperm + M, m, y2, x2, wk);
     // x1 = y1 - X12 x2 (x2 rows padded per block)
     const int mb = ctx->mb;
     ctx->d_x2pad.alloc((size_t)ctx->nblk * mb * m * sizeof(double));
