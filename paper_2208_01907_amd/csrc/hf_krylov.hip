@@ -547,18 +547,24 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
 // Null vectors of S22: N2 = P^T [-L11^{-T} L21^T; I_k]  (row-major M x k)
 __global__ void k_s22_null(int M, int k, const double* __restrict__ L, const int32_t* __restrict__ perm,
                            double* __restrict__ N2) {
+  // the backward substitution runs on a work column in LDS (dynamic, M * blockDim
+  // doubles) when M <= MAXM, else directly on the rows of N2
+  extern __shared__ double sm[];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= k) return;
   const int r = M - k;
-  // Y = L11^{-T} L21^T[:, q]; backward substitution, kept in N2 rows (scattered at the end)
-  // work in place in column q of a scratch: use N2 rows of perm order
-  for (int i = 0; i < M; ++i) N2[(int64_t)perm[i] * k + q] = 0.0;
+  const bool lds = M <= MAXM;
+  double* y = lds ? sm + threadIdx.x : nullptr;
+  const int ys = blockDim.x;
+  auto Y = [&](int i) -> double& { return lds ? y[i * ys] : N2[(int64_t)perm[i] * k + q]; };
+  // Y = L11^{-T} L21^T[:, q] by backward substitution
+  for (int i = 0; i < M; ++i) Y(i) = 0.0;
   for (int i = r - 1; i >= 0; --i) {
     double v = at(const_cast<double*>(L), M, r + q, i);
-    for (int t = i + 1; t < r; ++t) v -= at(const_cast<double*>(L), M, t, i) * N2[(int64_t)perm[t] * k + q];
-    N2[(int64_t)perm[i] * k + q] = v;
+    for (int t = i + 1; t < r; ++t) v -= at(const_cast<double*>(L), M, t, i) * Y(t);
+    Y(i) = v;
   }
-  for (int i = 0; i < r; ++i) N2[(int64_t)perm[i] * k + q] = -N2[(int64_t)perm[i] * k + q];
+  for (int i = 0; i < r; ++i) N2[(int64_t)perm[i] * k + q] = -Y(i);
   for (int t = 0; t < k; ++t) N2[(int64_t)perm[r + t] * k + q] = (t == q) ? 1.0 : 0.0;
 }
 
@@ -986,7 +992,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
       ctx->d_N2.alloc((size_t)rows * k * sizeof(double));
       double* N2 = ctx->d_N2.as<double>();
       HF_HIP(hipMemsetAsync(N2, 0, (size_t)rows * k * sizeof(double), s));
-      k_s22_null<<<1, 64, 0, s>>>(M, k, Lw, sperm, N2);
+      k_s22_null<<<1, 64, M <= MAXM ? (size_t)M * 64 * sizeof(double) : 0, s>>>(M, k, Lw, sperm, N2);
       double* Nperm = w.T1.as<double>();
       combine(ctx, n, mb, k, Nperm, nullptr, ctx->nblk, X12, (int64_t)n * mb, N2, s);
       k_neg<<<cdiv(n * k, 256), 256, 0, s>>>(n * k, Nperm);
