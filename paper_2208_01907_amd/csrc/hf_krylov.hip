@@ -449,12 +449,12 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
     // largest |off-diagonal| (first in row-major order over the upper triangle)
     double ov = -1.0;
     int ok = INT_MAX;
-    for (int64_t e = tid; e < (int64_t)w * w; e += 256) {
-      const int r = (int)(e / w), c = (int)(e % w);
-      if (c <= r) continue;
-      const double v = fabs(at(A, M, i + r, i + c));
-      if (v > ov) { ov = v; ok = (int)e; }
-    }
+    for (int r = wv; r < w; r += 4)
+      for (int c = r + 1 + lane; c < w; c += 64) {
+        const double v = fabs(at(A, M, i + r, i + c));
+        const int e = r * w + c;
+        if (v > ov || (v == ov && e < ok)) { ov = v; ok = e; }
+      }
     argmax(ov, ok);
     const double go = (w > 1) ? ov : 0.0;
     int mode;
@@ -470,10 +470,8 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
       at(D, M, i, i) = d;
       for (int r = i + 1 + tid; r < M; r += 256) at(L, M, r, i) = at(A, M, r, i) / d;
       __syncthreads();
-      for (int64_t e = tid; e < (int64_t)(w - 1) * (w - 1); e += 256) {
-        const int r = i + 1 + (int)(e % (w - 1)), c = i + 1 + (int)(e / (w - 1));
-        at(A, M, r, c) -= at(L, M, r, i) * at(A, M, i, c);
-      }
+      for (int c = i + 1 + wv; c < M; c += 4)
+        for (int r = i + 1 + lane; r < M; r += 64) at(A, M, r, c) -= at(L, M, r, i) * at(A, M, i, c);
       __syncthreads();
       for (int r = i + 1 + tid; r < M; r += 256) { at(A, M, r, i) = 0.0; at(A, M, i, r) = 0.0; }
       if (tid == 0) mags[i] = fabs(d);
@@ -492,10 +490,9 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
         at(L, M, rr, i + 1) = (c2 * e11 - c1 * e12) / det;
       }
       __syncthreads();
-      for (int64_t e = tid; e < (int64_t)(w - 2) * (w - 2); e += 256) {
-        const int rr = i + 2 + (int)(e % (w - 2)), cc = i + 2 + (int)(e / (w - 2));
-        at(A, M, rr, cc) -= at(L, M, rr, i) * at(A, M, cc, i) + at(L, M, rr, i + 1) * at(A, M, cc, i + 1);
-      }
+      for (int cc = i + 2 + wv; cc < M; cc += 4)
+        for (int rr = i + 2 + lane; rr < M; rr += 64)
+          at(A, M, rr, cc) -= at(L, M, rr, i) * at(A, M, cc, i) + at(L, M, rr, i + 1) * at(A, M, cc, i + 1);
       __syncthreads();
       for (int rr = i + 2 + tid; rr < M; rr += 256) {
         at(A, M, rr, i) = 0.0; at(A, M, i, rr) = 0.0;

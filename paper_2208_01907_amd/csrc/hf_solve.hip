@@ -707,6 +707,13 @@ void step_inverses(hf_ctx* ctx, int l, hipStream_t s) {
                  pass, base);
 }
 
+__global__ void k_zero_rows(int M, int m, const int32_t* __restrict__ rows, double* __restrict__ Y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)M * m) return;
+  const int64_t i = e / m;
+  Y[(int64_t)rows[i] * m + (e - i * m)] = 0.0;
+}
+
 template <class T>
 void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s) {
   if (m < 1 || m > 64) throw Status{HF_ERR_ARG};  // the sweep tiles hold at most 64 columns
@@ -756,7 +763,10 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     }
     ctx->d_part.alloc(need * sizeof(T));
   }
-  HF_HIP(hipMemsetAsync(Y, 0, (size_t)ctx->n * m * sizeof(double), s));
+  // the backward sweep writes every row of the moderate part; the hard part's rows
+  // (also read as border values) stay zero
+  if (ctx->M > 0)
+    k_zero_rows<<<cdiv((int64_t)ctx->M * m, 256), 256, 0, s>>>(ctx->M, m, ctx->d_l2.as<int32_t>(), Y);
   for (int l = 0; l < nlev; ++l) {
     const int nl = ctx->level_ptr[l + 1] - ctx->level_ptr[l];
     const int32_t* ln = lall + ctx->level_ptr[l];
