@@ -707,6 +707,44 @@ void step_inverses(hf_ctx* ctx, int l, hipStream_t s) {
                  pass, base);
 }
 
+// border product of the backward sweep for 16 pivot rows per workgroup (narrow
+// form of k_bwd_border_part: operands loaded straight into MFMA registers)
+template <class T, int NCB, bool FIN>
+__global__ void __launch_bounds__(256)
+k_bwd_border_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+               const NodeState* __restrict__ st, const T* __restrict__ front,
+               T* rb, int m, int maxch, int maxp, T* __restrict__ part, const T* __restrict__ dval,
+               const T* __restrict__ zb) {
+  const int q = blockIdx.z;
+  const int j = lnodes[q];
+  const NodeInfo ni = nodes[j];
+  const int npiv = st[j].npiv;
+  const int cs = blockIdx.x * 16;
+  const int ch = blockIdx.y;
+  const int p = ni.p, b = ni.b;
+  const int rlo = ch * RCH;
+  if (cs >= npiv || rlo >= b) return;
+  const int rhi = min(b, rlo + RCH);
+  const int64_t lf = ni.f;
+  const T* A = front + ni.front_off + (int64_t)cs * lf + p;  // A(k, r) = L21[k, cs + r]
+  const T* Yb = rb + (ni.rhs_off + p) * m;
+  const int nrows = min(16, npiv - cs);
+  T* P = part + (((int64_t)q * maxch + ch) * maxp + cs) * m;
+  narrow_product<T, NCB>(
+      rlo, rhi, [&](int k, int r) { return r < nrows ? A[(int64_t)r * lf + k] : (T)0; },
+      [&](int k, int c) { return c < m ? Yb[(int64_t)k * m + c] : (T)0; },
+      [&](int r, int c, T v) {
+        if (r < nrows && c < m) {
+          if constexpr (FIN) {
+            const int64_t o = (ni.rhs_off + cs + r) * m + c;
+            rb[o] = zb[o] / dval[ni.start + cs + r] - v;
+          } else {
+            P[(int64_t)r * m + c] = v;
+          }
+        }
+      });
+}
+
 __global__ void k_zero_rows(int M, int m, const int32_t* __restrict__ rows, double* __restrict__ Y) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)M * m) return;
@@ -847,14 +885,16 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       });
       dim3 gp(cdiv(maxp, 64), maxch, nl);
       const T* dv = ctx->d_dval.as<T>();
-      if (fused_fin)
+      // 16 columns or fewer: the narrow form; wider blocks: 64x64 tiles staged through LDS
+      dim3 gn(cdiv(maxp, 16), maxch, nl);
+      if (ncb == 1)
         launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
-                     k_bwd_border_part<T, KBN / 2, true>, gp, dim3(256),
-                     ln, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb);
+                     fused_fin ? k_bwd_border_n<T, 1, true> : k_bwd_border_n<T, 1, false>, gn, dim3(256), ln, nodes,
+                     st, front, rb, m, maxch, maxp, part, dv, (const T*)zb);
       else
         launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
-                     k_bwd_border_part<T, KBN / 2, false>, gp, dim3(256),
-                     ln, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb);
+                     fused_fin ? k_bwd_border_part<T, KBN / 2, true> : k_bwd_border_part<T, KBN / 2, false>, gp,
+                     dim3(256), ln, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb);
     }
     if (!fused_fin) {
       auto wf = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
