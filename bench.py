@@ -153,6 +153,26 @@ def roofline(stats, steps, prec):
     return out
 
 
+def path_roofline(stats, steps, prec, ms_per_step):
+    """Roofline of the whole step: T_roof = sum over kernel classes of
+    max(algorithmic flops / peak of the class's precision, algorithmic bytes /
+    HBM peak), per step, against the measured step time; plus each class's
+    fraction of the HBM and arithmetic peaks.  Classes that hold several kernels
+    count with whatever algorithmic work they record."""
+    t_roof = 0.0
+    per = {}
+    for k, v in stats.items():
+        if v["ms"] <= 0:
+            continue
+        pk = PEAK["fp32_TFLOPs"] if (prec == 32 and k not in FP64_CLASSES) else PEAK["fp64_TFLOPs"]
+        t_roof += max(v["flops"] / (pk * 1e12), v["bytes"] / (PEAK["hbm_GBps"] * 1e9)) / steps
+        sec = v["ms"] * 1e-3
+        per[k] = {"hbm_frac": round(v["bytes"] / sec / 1e9 / PEAK["hbm_GBps"], 4),
+                  "peak_frac": round(v["flops"] / sec / 1e12 / pk, 4)}
+    return {"t_roof_ms": t_roof * 1e3, "t_measured_ms": ms_per_step, "frac": t_roof * 1e3 / ms_per_step,
+            "per_class": per}
+
+
 def cpu_baseline(W):
     """The oracle (unchanged) on a bounded sample: its step 1 on one nested-
     dissection subtree, factored as a problem of its own, is timed in full and
@@ -270,6 +290,7 @@ def main():
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in stats.items()},
         "kernel_rates": rates(stats),
         "roofline": roofline(stats, args.steps, 32),
+        "path_roofline": path_roofline(stats, args.steps, 32, dt * 1e3),
     }
     result["adjoint"] = adjoint_timing(hy, ctx, X, W, args.steps, torch)
     del ctx
@@ -282,7 +303,8 @@ def main():
                           "backward_error": be64,
                           "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in stats64.items()},
                           "kernel_rates": rates(stats64),
-                          "roofline": roofline(stats64, args.steps, 64)}
+                          "roofline": roofline(stats64, args.steps, 64),
+                          "path_roofline": path_roofline(stats64, args.steps, 64, dt64 * 1e3)}
         result["speedup_vs_fp64"] = dt64 / dt
         del ctx64
     if not args.no_cpu_baseline:
