@@ -179,8 +179,9 @@ int hf_solve(hf_ctx* ctx, int32_t r, const double* B_dev, int64_t ldb, double* X
  * 4.5e-8 from the exact kernel).
  * The value gradient is exact along perturbations of Kbar that keep its kernel
  * (for example coefficient changes of a pure-Neumann operator); along others the
- * pseudo-inverse is not differentiable.  Lam_dev may alias neither G_dev, X_dev
- * nor GV_dev.  With r == 0, GV_dev (if given) is set to zero.
+ * pseudo-inverse is not differentiable.  Lam_dev may alias neither G_dev nor
+ * X_dev, GV_dev none of the other three.  With r == 0, GV_dev (if given) is set
+ * to zero.
  * Errors: HF_ERR_STATE (not factorized), HF_ERR_ARG, HF_ERR_NO_CONVERGENCE,
  * HF_ERR_OOM, HF_ERR_HIP.
  */

@@ -43,8 +43,8 @@ int hf_solve(hf_ctx* ctx, int32_t r, const double* B_dev, int64_t ldb, double* X
 int hf_adjoint(hf_ctx* ctx, int32_t r, const double* X_dev, int64_t ldx, const double* G_dev, int64_t ldg,
                double* Lam_dev, int64_t ldl, double* GV_dev, void* stream) {
   if (!ctx) return HF_ERR_ARG;
-  if (r > 0 && Lam_dev && (Lam_dev == G_dev || Lam_dev == X_dev || (GV_dev && GV_dev == Lam_dev)))
-    return HF_ERR_ARG;
+  if (r > 0 && Lam_dev && (Lam_dev == G_dev || Lam_dev == X_dev)) return HF_ERR_ARG;
+  if (r > 0 && GV_dev && (GV_dev == Lam_dev || GV_dev == X_dev || GV_dev == G_dev)) return HF_ERR_ARG;
   return hf::adjoint_impl(ctx, r, X_dev, ldx, G_dev, ldg, Lam_dev, ldl, GV_dev, static_cast<hipStream_t>(stream));
 }
 

@@ -158,6 +158,9 @@ def test_adjoint_errors():
     L2 = torch.empty(W.n, dtype=torch.float64, device="cuda")
     assert hy._lib.hf_adjoint(ctx.handle, 1, X.data_ptr(), W.n - 1, p, W.n, L2.data_ptr(), W.n,
                               None, None) == hy.HF_ERR_ARG
+    # the value gradient aliasing X is refused
+    assert hy._lib.hf_adjoint(ctx.handle, 1, X.data_ptr(), W.n, L2.data_ptr(), W.n, p, W.n, X.data_ptr(),
+                              None) == hy.HF_ERR_ARG
     # r = 0: the value gradient is zero
     GV = torch.full((W.nnz,), 7.0, dtype=torch.float64, device="cuda")
     assert hy._lib.hf_adjoint(ctx.handle, 0, None, 0, None, 0, None, 0, GV.data_ptr(), None) == hy.HF_OK
