@@ -251,7 +251,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this hybrid-factorization path runs on one GPU "
-              "(multi-GPU sharding by nested-dissection subtrees is described in DESIGN.md, not built).",
+              "(sharding over GPUs by nested-dissection subtrees is not built).",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
