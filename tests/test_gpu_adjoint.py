@@ -194,3 +194,26 @@ def test_adjoint_full_size_properties(cfg):
     assert be <= 1e-11
     assert gap <= 1e-12
     assert ker <= 1e-7
+
+
+def test_adjoint_many_rhs_chunked():
+    """More right-hand sides than one block of the small dense kernels (64): the
+    projection, the solve and the value gradient run in chunks."""
+    W = w.config_c1()
+    rng = np.random.default_rng(502)
+    N = W.kernel
+    Xs = rng.standard_normal((W.n, 70))
+    Xs -= N @ (N.T @ Xs)
+    B = W.csr() @ Xs
+    G = rng.standard_normal((W.n, 70))
+    Xref = oracle.adjoint_solve(W.csr(), B, N)
+    Lref = oracle.adjoint_solve(W.csr(), G, N)
+    GVref = oracle.value_gradient(W.indptr, W.indices, Xref, Lref)
+    ctx = _ctx(W, 32)
+    hy.hf_factorize(ctx, torch.tensor(W.values, device="cuda"))
+    X = hy.hf_solve(ctx, torch.tensor(B, device="cuda"))
+    Lam, GV = hy.hf_adjoint(ctx, X, torch.tensor(G, device="cuda"))
+    rl = np.linalg.norm(Lam.cpu().numpy() - Lref) / np.linalg.norm(Lref)
+    rg = np.linalg.norm(GV.cpu().numpy() - GVref) / np.linalg.norm(GVref)
+    print(f"  70 RHS: rel(Lam)={rl:.2e} rel(GV)={rg:.2e}", flush=True)
+    assert rl <= 1e-10 and rg <= 2e-10
