@@ -217,3 +217,41 @@ def test_adjoint_many_rhs_chunked():
     rg = np.linalg.norm(GV.cpu().numpy() - GVref) / np.linalg.norm(GVref)
     print(f"  70 RHS: rel(Lam)={rl:.2e} rel(GV)={rg:.2e}", flush=True)
     assert rl <= 1e-10 and rg <= 2e-10
+
+
+def test_autograd_elasticity_moduli():
+    """Floating Q1 elastic cube: the rigid modes stay the kernel for every modulus
+    field, so the value gradient chained to per-element moduli matches central
+    differences of the GPU solve (both directions drawn from their own seed)."""
+    ne = 5
+    rng = np.random.default_rng(14)
+    young = 10.0 ** rng.uniform(0, 1, size=(ne, ne, ne))
+    K = w.q1_elasticity(ne, young)
+    perm, node_ptr, parent = w.grid_nested_dissection((ne + 1,) * 3, 27, dofs_per_point=3)
+    N, _ = np.linalg.qr(w.rigid_modes(ne))
+    n = K.shape[0]
+    B = rng.standard_normal((n, 3))
+    B -= N @ (N.T @ B)
+    Xs = rng.standard_normal((n, 3))
+    dE = young * rng.uniform(-1, 1, size=young.shape)
+    opt = hy.hf_default_options(tau=1e-2, low_precision=32, gcr_block=0)
+    ctx = hy.hf_analyse(K.indptr, K.indices, perm, node_ptr, parent, opt)
+    dev = "cuda"
+    Xs_t = torch.tensor(Xs, device=dev)
+    Bt = torch.tensor(B, device=dev)
+
+    def loss(vals):
+        X = hy.solve(ctx, torch.tensor(vals, device=dev), Bt)
+        return 0.5 * float(((X - Xs_t) ** 2).sum())
+
+    v = torch.tensor(K.data, device=dev, requires_grad=True)
+    X = hy.solve(ctx, v, Bt)
+    (0.5 * ((X - Xs_t) ** 2).sum()).backward()
+    gv = v.grad.cpu().numpy()
+    h = 1e-5
+    Kp, Km = w.q1_elasticity(ne, young + h * dE), w.q1_elasticity(ne, young - h * dE)
+    assert np.array_equal(Kp.indices, K.indices) and np.array_equal(Km.indptr, K.indptr)
+    dK = (Kp.data - Km.data) / (2 * h)
+    fd = (loss(Kp.data) - loss(Km.data)) / (2 * h)
+    print(f"  elasticity: moduli {gv @ dK:.10e} vs fd {fd:.10e}", flush=True)
+    assert abs(gv @ dK - fd) <= 1e-5 * abs(fd)
