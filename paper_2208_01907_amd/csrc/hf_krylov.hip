@@ -1147,11 +1147,16 @@ __global__ void k_take_cols(int64_t n, int m, const double* __restrict__ G, int6
 // caller's CSR arrays, receives -sum_c Lam[i, c] x[j, c], summed over c in
 // ascending order.  One thread per entry in the caller's order: the output is
 // written contiguously and neighbouring entries read neighbouring rows of the
-// column-major X and Lambda.
+// column-major X and Lambda.  Workgroups are dispatched to the eight XCDs in
+// turn; the grid (a multiple of 8) is remapped so that each XCD takes one
+// contiguous eighth of the entries, and rows that share columns of X (grid
+// neighbours one plane apart) meet in the same L2.
 __global__ void k_value_grad(int64_t nnz, const int32_t* __restrict__ orow, const int32_t* __restrict__ ocol, int r,
                              const double* __restrict__ X, int64_t ldx, const double* __restrict__ Lam, int64_t ldl,
                              double* __restrict__ GV) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = gridDim.x / 8;
+  const int64_t lb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t e = lb * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
   const int64_t i = orow[e], j = ocol[e];
   double acc = 0.0;
@@ -1218,7 +1223,7 @@ int adjoint_impl(hf_ctx* ctx, int32_t r, const double* X, int64_t ldx, const dou
       // algorithmic bytes: the (row, column) pairs, the output, X and Lambda once
       const double by = (double)ctx->nnz * (4.0 + 4.0 + 8.0) + 2.0 * n * r * 8.0;
       launch_timed(ctx->timer, HF_K_VALUE_GRAD, by, 2.0 * ctx->nnz * r, s, k_value_grad,
-                   dim3((unsigned)cdiv(ctx->nnz, 256)), dim3(256), ctx->nnz, ctx->d_orow.as<int32_t>(),
+                   dim3((unsigned)(8 * cdiv(cdiv(ctx->nnz, 256), 8))), dim3(256), ctx->nnz, ctx->d_orow.as<int32_t>(),
                    ctx->d_ocol.as<int32_t>(), r, X, ldx, (const double*)Lam, ldl, GV);
       HF_HIP(hipGetLastError());
     }
