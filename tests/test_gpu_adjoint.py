@@ -217,6 +217,9 @@ def test_adjoint_many_rhs_chunked():
     rg = np.linalg.norm(GV.cpu().numpy() - GVref) / np.linalg.norm(GVref)
     print(f"  70 RHS: rel(Lam)={rl:.2e} rel(GV)={rg:.2e}", flush=True)
     assert rl <= 1e-10 and rg <= 2e-10
+    # without the value gradient: the same Lam (the same arithmetic), no GV
+    Lam2, GV2 = hy.hf_adjoint(ctx, X, torch.tensor(G, device="cuda"), with_values=False)
+    assert GV2 is None and torch.equal(Lam2, Lam)
 
 
 def test_autograd_elasticity_moduli():
