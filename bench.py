@@ -29,7 +29,7 @@ WORKLOADS = {
           "tau=1e-2, FP32 step 1 + FP64 block GCR, 1 RHS",
     "c2": "3D Neumann 7-point FV Laplacian 64^3 (L=262144), 200 inclusions at 1e6, ND leaf 512, tau=1e-2, "
           "FP32 step 1 + FP64 block GCR, 16 RHS",
-    "c3": "floating Q1 elastic cube 24^3 elements (L=46875), E=10^U(0,6), nu=0.3, ND leaf 64 nodes, tau=0.1, "
+    "c3": "floating Q1 elastic cube 24^3 elements (L=46875), E=10^U(0,6), nu=0.3, ND leaf 64 nodes, tau=0.2, "
           "FP32 step 1 + FP64 block GCR, 32 RHS",
 }
 CALIB_BYTES = 256 << 20

@@ -267,6 +267,49 @@ int hf_timing_enable(hf_ctx* ctx, int32_t on);
 /* Counters of one class (0 <= cls < HF_K_NCLASS).  Errors: HF_ERR_ARG. */
 int hf_timing_get(const hf_ctx* ctx, int32_t cls, hf_kstat_t* out_host);
 
+/*
+ * Record of the step-1 pivoting of the last hf_factorize (diagnostics of the
+ * threshold postponing of Sec. 2.2).  Every output may be NULL.
+ *   npiv_host    int32 [n_nodes]: accepted pivots of every tree node; the
+ *                node's other indices were postponed (they form Lambda_2)
+ *   d_host       float64 [n]: the accepted pivots d (factor precision, widened),
+ *                node j's at positions node_ptr[j] .. node_ptr[j]+npiv[j]-1 in
+ *                the order they were taken; 0 at the postponed positions
+ *   dstop_host   float64 [n_nodes]: diagonal value of the candidate whose ratio
+ *                test stopped the node; NaN when every index was accepted
+ *   margin_host  float64 [n_nodes]: min over the node's ratio tests of
+ *                |log10(|d| / (tau |d_ref|))| in decades, d_ref the previous
+ *                accepted pivot (1 for the first one when first_pivot_unit);
+ *                a zero candidate is no test; +inf when the node made none
+ * Errors: HF_ERR_ARG, HF_ERR_STATE (not factorized), HF_ERR_HIP.
+ */
+int hf_pivots(const hf_ctx* ctx, int32_t* npiv_host, double* d_host, double* dstop_host, double* margin_host);
+
+/*
+ * Pivot magnitudes of the FP64 LDL^T of S22 (Algorithm 1 step 5), float64 [M]
+ * on the host, in elimination order: |d| of a 1x1 pivot, the smaller |eigenvalue|
+ * of a 2x2 block for both of its positions.  Errors: HF_ERR_ARG, HF_ERR_STATE,
+ * HF_ERR_HIP.
+ */
+int hf_s22_pivots(const hf_ctx* ctx, double* mags_host);
+
+/*
+ * Residual histories of the block-GCR runs (Algorithm 5): for every run the max
+ * over the active columns of ||r_k||_2 / ||b_k||_2 (recurrence residual) after
+ * the initial guess and after each iteration.  The runs of the last
+ * hf_factorize (the column blocks of K11 X12 = K12) come first, then those of
+ * the last hf_solve or hf_adjoint (per 64-column chunk: the first pass, then
+ * each residual-correction pass).
+ *   nruns_host    receives the number of runs (required)
+ *   nfactor_host  receives how many of them belong to hf_factorize (or NULL)
+ *   run_ptr_host  int32 [nruns+1] or NULL: run r owns hist[run_ptr[r] ..
+ *                 run_ptr[r+1]-1]
+ *   hist_host     float64 [run_ptr[nruns]] or NULL
+ * Call with NULL arrays to query the sizes.  Errors: HF_ERR_ARG.
+ */
+int hf_gcr_history(const hf_ctx* ctx, int32_t* nruns_host, int32_t* nfactor_host, int32_t* run_ptr_host,
+                   double* hist_host);
+
 /* Static message for a status code (never NULL). */
 const char* hf_strerror(int status);
 

@@ -69,7 +69,7 @@ def _load():
             fn = getattr(lib, f"hfo_factor_{suf}")
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P, P, P, ctypes.c_double,
-                           ctypes.c_int32, P, P, P, P, P, P, P]
+                           ctypes.c_int32, P, P, P, P, P, P, P, P]
             fn = getattr(lib, f"hfo_precond_{suf}")
             fn.restype = None
             fn.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P, P, P, P,
@@ -164,6 +164,7 @@ class Step1:
     piv_order: np.ndarray
     npiv: np.ndarray
     margin: np.ndarray
+    dstop: np.ndarray        # per node: value of the candidate that stopped it (NaN: none)
     lambda2: np.ndarray      # postponed indices, elimination order, ascending
     is_l2: np.ndarray        # uint8 mask over elimination-order indices
 
@@ -209,6 +210,7 @@ def factor_low(Kp, node_ptr, parent, tau, dtype=np.float32, first_ref_unit=True,
     piv_order = np.zeros(max(n, 1), dtype=np.int32)
     npiv = np.zeros(max(len(p), 1), dtype=np.int32)
     margin = np.zeros(max(len(p), 1), dtype=np.float64)
+    dstop = np.zeros(max(len(p), 1), dtype=np.float64)
     indptr = np.ascontiguousarray(Kp.indptr, dtype=np.int64)
     indices = np.ascontiguousarray(Kp.indices, dtype=np.int32)
     vals = np.ascontiguousarray(Kp.data, dtype=np.float64)
@@ -216,7 +218,7 @@ def factor_low(Kp, node_ptr, parent, tau, dtype=np.float32, first_ref_unit=True,
     rc = getattr(lib, f"hfo_factor_{suf}")(
         n, _ptr(indptr), _ptr(indices), _ptr(vals), len(p), _ptr(node_ptr), _ptr(parent),
         _ptr(border_ptr), _ptr(border), float(tau), 1 if first_ref_unit else 0, _ptr(exc), _ptr(lptr),
-        _ptr(L), _ptr(d), _ptr(piv_order), _ptr(npiv), _ptr(margin))
+        _ptr(L), _ptr(d), _ptr(piv_order), _ptr(npiv), _ptr(margin), _ptr(dstop))
     if rc != 0:
         raise RuntimeError(f"oracle step 1 failed (code {rc})")
     npiv = npiv[:len(p)]
@@ -227,7 +229,67 @@ def factor_low(Kp, node_ptr, parent, tau, dtype=np.float32, first_ref_unit=True,
     lambda2 = np.nonzero(is_l2)[0].astype(np.int32)
     return Step1(dtype=dt.type, n=n, node_ptr=node_ptr, parent=parent, border_ptr=border_ptr,
                  border=border, lptr=lptr, L=L, d=d[:n], piv_order=piv_order[:n], npiv=npiv,
-                 margin=margin[:len(p)], lambda2=lambda2, is_l2=is_l2)
+                 margin=margin[:len(p)], dstop=dstop[:len(p)], lambda2=lambda2, is_l2=is_l2)
+
+
+def tested_values(f1: Step1, j):
+    """Values compared by the ratio tests of node j, in test order: the accepted
+    pivots, then the candidate that stopped the node (if any), with the indices
+    of the accepted ones (-1 for the stopping candidate)."""
+    s = int(f1.node_ptr[j])
+    n = int(f1.npiv[j])
+    vals = list(f1.d[s:s + n].astype(np.float64))
+    idx = list(f1.piv_order[s:s + n])
+    if not math.isnan(float(f1.dstop[j])):
+        vals.append(float(f1.dstop[j]))
+        idx.append(-1)
+    return np.array(vals, dtype=np.float64), np.array(idx, dtype=np.int64)
+
+
+def decided_nodes(f_lo: Step1, f_hi: Step1, tau, first_ref_unit=True, factor=4.0):
+    """Nodes whose low-precision postponing decisions do not depend on rounding.
+
+    The threshold test of Sec. 2.2 compares |v| (the next pivot candidate) with
+    tau |ref| (the previous accepted pivot, or 1 for a node's first test).  A
+    pivot that results from heavy cancellation (a near-kernel direction) is
+    dominated by the rounding of the low-precision arithmetic, and so may be the
+    outcome of the test that uses it.  The rounding error of every tested value
+    is measured against the FP64 run ``f_hi`` of the same step 1: test i of node
+    j compares v_i with ref_i in both runs (same position of the same node), and
+    its error is e_i = ||v_lo| - |v_hi|| + tau ||ref_lo| - |ref_hi||.  The test
+    is fixed when its distance from the threshold in the low-precision run,
+    ||v_lo| - tau |ref_lo||, exceeds factor * e_i: another low-precision
+    computation of the same values (a different summation order) may move each
+    of them by about the same amount again, which factor = 4 covers with room.
+    A node is decided when both runs accept the same number of pivots and all of
+    its tests are fixed.  Returns (decided mask, worst error-to-distance ratio of
+    every node's tests; +inf when the runs disagree).
+    """
+    nn = len(f_lo.npiv)
+    dec = np.zeros(nn, dtype=bool)
+    worst = np.zeros(nn)
+    for j in range(nn):
+        vl, _ = tested_values(f_lo, j)
+        vh, _ = tested_values(f_hi, j)
+        if f_lo.npiv[j] != f_hi.npiv[j] or len(vl) != len(vh):
+            worst[j] = math.inf
+            continue
+        if len(vl) == 0:
+            dec[j] = True
+            continue
+        al, ah = np.abs(vl), np.abs(vh)
+        rl = np.concatenate([[1.0], al[:-1]])
+        rh = np.concatenate([[1.0], ah[:-1]])
+        if not first_ref_unit:        # the first pivot of a node is not tested
+            al, ah, rl, rh = al[1:], ah[1:], rl[1:], rh[1:]
+        live = al != 0.0              # a zero candidate stops without a test
+        err = np.abs(al - ah) + tau * np.abs(rl - rh)
+        dist = np.abs(al - tau * rl)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            q = np.where(live, err / dist, 0.0)
+        worst[j] = float(np.max(q)) if len(q) else 0.0
+        dec[j] = bool(np.all(~live | (dist > factor * err)))
+    return dec, worst
 
 
 def precond(f1: Step1, R):
@@ -497,7 +559,9 @@ def rank_reveal(ld: LDLT, tau, n_enlarge=4, ker_tol=1e-10):
     candidates (the enlargement that keeps image entries to compare against).
     Among the candidates, the kernel consists of the trailing pivots whose
     magnitude is at most ker_tol (K has unit diagonal, so ker_tol is relative to
-    its size).  This decision rule is this implementation's own: the paper cites
+    its size).  A 2x2 block counts as one pivot: when the enlarged candidate set
+    would begin at the second half of a block, it begins at the block's first
+    half.  This decision rule is this implementation's own: the paper cites
     the kernel detection of Suzuki-Roux 2014 without describing it.
     """
     mags = ld.mags
@@ -515,6 +579,10 @@ def rank_reveal(ld: LDLT, tau, n_enlarge=4, ker_tol=1e-10):
     accepted = t
     e = min(n_enlarge, accepted) if postponed > 0 else 0
     start = t - e
+    # a 2x2 pivot block is one pivot: the candidate set starts at a block boundary,
+    # so the kernel count never takes half of a block
+    if any(b0 + 1 == start for b0, bs in ld.blocks if bs == 2):
+        start -= 1
     k = 0
     for i in range(m - 1, start - 1, -1):
         if mags[i] <= ker_tol:

@@ -67,7 +67,9 @@ static void FN(sym_swap)(REAL* F, int64_t f, int64_t i, int64_t k) {
  *             postponed (k >= npiv[j]);
  *   npiv    : number of accepted pivots per node;
  *   margin  : per node, min |log10(|d_k0| / (tau |d_prev|))| over its tests
- *             (+inf when no test was made).
+ *             (+inf when no test was made);
+ *   dstop   : per node, the diagonal value of the candidate that stopped the
+ *             node (NaN when every candidate was accepted).
  *   exclude : optional mask over global indices; masked indices are never
  *             pivot candidates and end up with the postponed ones (used to build
  *             a factorization of K11 for a given split).
@@ -79,7 +81,7 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
                     const int64_t* border_ptr, const int32_t* border, double tau,
                     int32_t first_ref_unit, const uint8_t* exclude, const int64_t* lptr,
                     REAL* Lstore, REAL* dstore, int32_t* piv_order, int32_t* npiv,
-                    double* margin) {
+                    double* margin, double* dstop) {
   int rc = 0;
   int32_t* loc = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
   REAL** contrib = (REAL**)calloc((size_t)(n_nodes > 0 ? n_nodes : 1), sizeof(REAL*));
@@ -141,6 +143,7 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
     double dprev = 1.0;
     int have_prev = first_ref_unit ? 1 : 0;
     double mmin = INFINITY;
+    double stopv = NAN;
     int64_t i;
     for (i = 0; i < p; ++i) {
       int64_t k0 = -1;
@@ -152,12 +155,12 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
       }
       if (k0 < 0) break;                     /* only excluded indices remain */
       const double dk = (double)AT(F, f, k0, k0);
-      if (dk == 0.0) break;
+      if (dk == 0.0) { stopv = 0.0; break; }
       if (have_prev) {
         const double ratio = fabs(dk) / (tau * fabs(dprev));
         const double m = fabs(log10(ratio));
         if (m < mmin) mmin = m;
-        if (fabs(dk) < tau * fabs(dprev)) break;
+        if (fabs(dk) < tau * fabs(dprev)) { stopv = dk; break; }
       }
       FN(sym_swap)(F, f, i, k0);
       { int32_t t = idx[i]; idx[i] = idx[k0]; idx[k0] = t; }
@@ -177,6 +180,7 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
     }
     npiv[j] = (int32_t)i;
     margin[j] = mmin;
+    dstop[j] = stopv;
     for (int64_t k = 0; k < p; ++k) piv_order[s + k] = idx[k];
     /* the panel (all rows, p columns) goes to the factor store */
     memcpy(Lstore + lptr[j], F, sizeof(REAL) * (size_t)(f * p));

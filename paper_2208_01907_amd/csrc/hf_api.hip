@@ -1,4 +1,6 @@
 // C entry points of include/hf.h.
+#include <algorithm>
+#include <cmath>
 #include <new>
 
 #include "hf_internal.h"
@@ -99,6 +101,69 @@ int hf_info(const hf_ctx* ctx, hf_info_t* info) {
   o.t_s22_ms = ctx->t_s22;
   o.t_solve_ms = ctx->t_solve;
   *info = o;
+  return HF_OK;
+}
+
+int hf_pivots(const hf_ctx* ctx, int32_t* npiv_host, double* d_host, double* dstop_host, double* margin_host) {
+  if (!ctx) return HF_ERR_ARG;
+  if (ctx->state < 2) return HF_ERR_STATE;
+  const int32_t nn = ctx->n_nodes;
+  if ((int32_t)ctx->hstate.size() != nn) return HF_ERR_STATE;
+  std::vector<double> d(ctx->n, 0.0);
+  if ((d_host || margin_host) && ctx->n > 0) {
+    if (ctx->factor_prec == HF_PREC_FP32) {
+      std::vector<float> t(ctx->n);
+      if (hipMemcpy(t.data(), ctx->d_dval.ptr, sizeof(float) * ctx->n, hipMemcpyDeviceToHost) != hipSuccess)
+        return HF_ERR_HIP;
+      for (int64_t i = 0; i < ctx->n; ++i) d[i] = t[i];
+    } else if (hipMemcpy(d.data(), ctx->d_dval.ptr, sizeof(double) * ctx->n, hipMemcpyDeviceToHost) != hipSuccess) {
+      return HF_ERR_HIP;
+    }
+  }
+  const double tau = ctx->opt.tau;
+  for (int32_t j = 0; j < nn; ++j) {
+    const hf::NodeState& st = ctx->hstate[j];
+    const int32_t s0 = ctx->nodes[j].start, p = ctx->nodes[j].p;
+    for (int32_t k = st.npiv; k < p; ++k) d[s0 + k] = 0.0;  // postponed positions
+    if (npiv_host) npiv_host[j] = st.npiv;
+    if (dstop_host) dstop_host[j] = st.dstop;
+    if (margin_host) {
+      // the node's ratio tests: every accepted pivot against its reference, then
+      // the candidate that stopped the node (a zero candidate is not a test)
+      double m = INFINITY, ref = 1.0;
+      bool have = ctx->opt.first_pivot_unit != 0;
+      for (int32_t k = 0; k < st.npiv; ++k) {
+        const double dk = d[s0 + k];
+        if (have) m = std::min(m, std::fabs(std::log10(std::fabs(dk) / (tau * std::fabs(ref)))));
+        ref = dk;
+        have = true;
+      }
+      if (have && st.dstop == st.dstop && st.dstop != 0.0)
+        m = std::min(m, std::fabs(std::log10(std::fabs(st.dstop) / (tau * std::fabs(ref)))));
+      margin_host[j] = m;
+    }
+  }
+  if (d_host) std::copy(d.begin(), d.end(), d_host);
+  return HF_OK;
+}
+
+int hf_s22_pivots(const hf_ctx* ctx, double* mags_host) {
+  if (!ctx || !mags_host) return HF_ERR_ARG;
+  if (ctx->state < 2) return HF_ERR_STATE;
+  if (ctx->M == 0) return HF_OK;
+  if (hipMemcpy(mags_host, ctx->d_s22mag.ptr, sizeof(double) * ctx->M, hipMemcpyDeviceToHost) != hipSuccess)
+    return HF_ERR_HIP;
+  return HF_OK;
+}
+
+int hf_gcr_history(const hf_ctx* ctx, int32_t* nruns_host, int32_t* nfactor_host, int32_t* run_ptr_host,
+                   double* hist_host) {
+  if (!ctx || !nruns_host) return HF_ERR_ARG;
+  const int32_t nr = (int32_t)ctx->hist_ptr.size() - 1;
+  *nruns_host = nr;
+  if (nfactor_host) *nfactor_host = ctx->hist_factor_runs;
+  if (run_ptr_host) std::copy(ctx->hist_ptr.begin(), ctx->hist_ptr.end(), run_ptr_host);
+  if (hist_host) std::copy(ctx->hist.begin(), ctx->hist.end(), hist_host);
   return HF_OK;
 }
 

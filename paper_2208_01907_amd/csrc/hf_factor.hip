@@ -266,6 +266,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
   }
   __syncthreads();
   double dprev = s0.dprev;
+  double dstop = s0.dstop;
   int have_prev = (s0.npiv > 0) ? 1 : first_unit;
   const int iend = min(k0p + NB, p);
   int i;
@@ -348,7 +349,10 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     const double dk = (double)d;
     bool stop = (dk == 0.0);
     if (!stop && have_prev && fabs(dk) < tau * fabs(dprev)) stop = true;
-    if (stop) break;  // uniform: every thread computed the same decision
+    if (stop) {  // uniform: every thread computed the same decision
+      dstop = dk;
+      break;
+    }
     // positions i and k exchange their rows: the winner takes position i, the
     // row at position i takes the winner's position
 #pragma unroll
@@ -418,6 +422,7 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     NodeState ns;
     ns.npiv = i;
     ns.dprev = dprev;
+    ns.dstop = dstop;
     ns.done = (i < iend || i == p) ? 1 : 0;
     st[j] = ns;
   }
@@ -906,6 +911,7 @@ __global__ void k_init_state(int32_t n_nodes, NodeState* st) {
   s.npiv = 0;
   s.done = 0;
   s.dprev = 1.0;
+  s.dstop = __builtin_nan("");
   st[j] = s;
 }
 

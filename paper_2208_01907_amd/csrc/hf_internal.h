@@ -86,6 +86,7 @@ struct NodeState {
   int32_t npiv;   // accepted pivots so far
   int32_t done;   // 1 when the node's pivot block is finished
   double dprev;   // last accepted pivot (ratio reference)
+  double dstop;   // diagonal value of the candidate that stopped the node (NaN: none did)
 };
 
 // One extend-add launch: the children of rank `rank` of the nodes of a level.
@@ -238,6 +239,12 @@ struct hf_ctx {
   hf::BgcrWork* work = nullptr;
   hf::KTimer timer;
   std::vector<hf::NodeState> hstate;  // node states after the last factorization
+  // block-GCR residual histories (max relative recurrence residual over the
+  // active columns, after X0 and after every iteration): the Schur-complement
+  // runs of the last hf_factorize, then the runs of the last hf_solve
+  std::vector<int32_t> hist_ptr{0};
+  std::vector<double> hist;
+  int32_t hist_factor_runs = 0;
   // statistics
   int32_t gcr_blocks = 0, gcr_iters_max = 0, gcr_iters_total = 0, solve_iters = 0;
   double t_analyse = 0, t_step1 = 0, t_gcr = 0, t_s22 = 0, t_solve = 0;

@@ -521,7 +521,10 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
     }
     const int postponed = M - t;
     const int e = postponed > 0 ? min(n_enlarge, t) : 0;
-    const int start = t - e;
+    int start = t - e;
+    // a 2x2 block is one pivot: the candidates start at a block boundary, so the
+    // kernel count (and the rank M - k) never splits a block
+    if (start > 0 && start < M && bsize[start] == 0) --start;
     int k = 0;
     for (int q = M - 1; q >= start; --q) {
       if (mags[q] <= ker_tol) ++k;
@@ -833,14 +836,23 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
   // ||b_k||^2
   colsq(B, hb.data());
   for (int k = 0; k < m; ++k) bn2[k] = hb[k];
+  // the run's residual history (max relative residual over the active columns)
+  struct HistEnd {
+    hf_ctx* c;
+    ~HistEnd() { c->hist_ptr.push_back((int32_t)c->hist.size()); }
+  } hist_end{ctx};
   auto converged = [&](const double* Rd) {
     colsq(Rd, hr.data());
+    bool ok = true;
+    double worst = 0.0;
     for (int k = 0; k < m; ++k) {
       if (bn2[k] <= 0.0) continue;
       const double rr = hr[k];
-      if (!(rr <= tol * tol * bn2[k])) return false;
+      if (!(rr <= tol * tol * bn2[k])) ok = false;
+      worst = std::max(worst, std::sqrt(rr / bn2[k]));
     }
-    return true;
+    ctx->hist.push_back(worst);
+    return ok;
   };
   // X0 = Q^{-1} B, R0 = B - A X0
   precond(ctx, m, B, X, s);
@@ -897,6 +909,9 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
   try {
     ctx->state = 1;
     auto t0 = std::chrono::steady_clock::now();
+    ctx->hist.clear();
+    ctx->hist_ptr.assign(1, 0);
+    ctx->hist_factor_runs = 0;
     ctx->factor_prec = ctx->opt.low_precision;
     if (ctx->factor_prec == HF_PREC_FP32) step1<float>(ctx, values, s);
     else step1<double>(ctx, values, s);
@@ -945,6 +960,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
         ctx->gcr_iters_total += its;
       }
     }
+    ctx->hist_factor_runs = (int32_t)ctx->hist_ptr.size() - 1;
     ctx->t_gcr = ms_since(t0);
     // step 4: S22 = K22 - K21 X12 (symmetrized); step 5: its LDL^T and kernel
     t0 = std::chrono::steady_clock::now();
@@ -1071,6 +1087,8 @@ int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, 
     auto t0 = std::chrono::steady_clock::now();
     const int k = ctx->kdim;
     ctx->solve_iters = 0;
+    ctx->hist_ptr.resize(ctx->hist_factor_runs + 1);
+    ctx->hist.resize(ctx->hist_ptr.back());
     for (int c0 = 0; c0 < r; c0 += MAXM) {
       const int m = std::min(MAXM, r - c0);
       BgcrWork& w = get_work(ctx, std::max(m, std::max(ctx->mb, k)));

@@ -15,6 +15,9 @@ The function names follow the C entry points:
     lam2, S22 = hf_schur(ctx)                # hard part, Schur complement (scaled)
     q = hf_scaling(ctx)
     info = hf_info(ctx)
+    piv = hf_pivots(ctx)                     # step-1 pivots, postponing margins
+    mags = hf_s22_pivots(ctx)                # pivot magnitudes of the LDL^T of S22
+    runs, nfac = hf_gcr_history(ctx)         # block-GCR residual histories
     Lam, GV = hf_adjoint(ctx, X, G)          # derivatives of a loss through X
     X = solve(ctx, values, B)                # torch.autograd-aware factorize + solve
 """
@@ -47,7 +50,7 @@ HF_PREC_FP64 = 64
 
 EXPORTS = ["hf_default_options", "hf_analyse", "hf_factorize", "hf_solve", "hf_kernel_dim",
            "hf_kernel_basis", "hf_schur", "hf_scaling", "hf_info", "hf_strerror", "hf_destroy",
-           "hf_timing_enable", "hf_timing_get", "hf_adjoint"]
+           "hf_timing_enable", "hf_timing_get", "hf_adjoint", "hf_pivots", "hf_s22_pivots", "hf_gcr_history"]
 
 # kernel classes of hf_timing_get
 KCLASS = ["panel", "permute_l11", "f11_update", "gather_border", "trsm", "syrk", "extend_add", "fwd_diag",
@@ -109,6 +112,9 @@ def _load():
         "hf_destroy": (None, [P]),
         "hf_timing_enable": (ctypes.c_int, [P, I32]),
         "hf_timing_get": (ctypes.c_int, [P, I32, P]),
+        "hf_pivots": (ctypes.c_int, [P, P, P, P, P]),
+        "hf_s22_pivots": (ctypes.c_int, [P, P]),
+        "hf_gcr_history": (ctypes.c_int, [P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -315,6 +321,36 @@ def hf_info(ctx: Context) -> dict:
     info = HFInfo()
     _check(_lib.hf_info(ctx.handle, ctypes.byref(info)), "hf_info")
     return {name: getattr(info, name) for name, _ in HFInfo._fields_}
+
+
+def hf_pivots(ctx: Context) -> dict:
+    """Step-1 pivot record: per-node accepted counts, the pivots (elimination
+    positions), the candidate that stopped each node and the postponing margins."""
+    n_nodes = int(hf_info(ctx)["n_nodes"])
+    npiv = np.zeros(max(n_nodes, 1), dtype=np.int32)
+    d = np.zeros(max(ctx.n, 1), dtype=np.float64)
+    dstop = np.zeros(max(n_nodes, 1), dtype=np.float64)
+    margin = np.zeros(max(n_nodes, 1), dtype=np.float64)
+    _check(_lib.hf_pivots(ctx.handle, _np_ptr(npiv), _np_ptr(d), _np_ptr(dstop), _np_ptr(margin)), "hf_pivots")
+    return {"npiv": npiv[:n_nodes], "d": d[:ctx.n], "dstop": dstop[:n_nodes], "margin": margin[:n_nodes]}
+
+
+def hf_s22_pivots(ctx: Context) -> np.ndarray:
+    M = int(hf_info(ctx)["M"])
+    mags = np.zeros(max(M, 1), dtype=np.float64)
+    _check(_lib.hf_s22_pivots(ctx.handle, _np_ptr(mags)), "hf_s22_pivots")
+    return mags[:M]
+
+
+def hf_gcr_history(ctx: Context):
+    """Residual histories of the block-GCR runs: (list of arrays, number of runs of hf_factorize)."""
+    nr, nf = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.hf_gcr_history(ctx.handle, ctypes.byref(nr), ctypes.byref(nf), None, None), "hf_gcr_history")
+    ptr = np.zeros(nr.value + 1, dtype=np.int32)
+    _check(_lib.hf_gcr_history(ctx.handle, ctypes.byref(nr), None, _np_ptr(ptr), None), "hf_gcr_history")
+    hist = np.zeros(max(int(ptr[-1]), 1), dtype=np.float64)
+    _check(_lib.hf_gcr_history(ctx.handle, ctypes.byref(nr), None, None, _np_ptr(hist)), "hf_gcr_history")
+    return [hist[ptr[r]:ptr[r + 1]].copy() for r in range(nr.value)], nf.value
 
 
 def hf_timing_enable(ctx: Context, on: bool = True):

@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "hf
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hf_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(hf_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_symbols_exported():
@@ -110,3 +110,13 @@ def test_size_limits():
     perm, node_ptr, parent = w.single_node_tree(n)
     assert _analyse_code(K.indptr.astype(np.int64), K.indices.astype(np.int32), perm, node_ptr,
                          parent) == hy.HF_ERR_NOT_IMPLEMENTED
+
+
+def test_diagnostics_reject_null_context():
+    """hf_pivots, hf_s22_pivots and hf_gcr_history validate their arguments on the
+    host (no device work)."""
+    lib = hy._lib
+    n = ctypes.c_int32()
+    assert lib.hf_pivots(None, None, None, None, None) == hy.HF_ERR_ARG
+    assert lib.hf_s22_pivots(None, None) == hy.HF_ERR_ARG
+    assert lib.hf_gcr_history(None, ctypes.byref(n), None, None, None) == hy.HF_ERR_ARG

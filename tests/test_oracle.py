@@ -233,6 +233,62 @@ def test_ldlt_pivoted_reconstructs_and_keeps_inertia():
             assert any(k == 2 for _, k in ld.blocks)
 
 
+def test_kernel_count_never_splits_a_2x2_block():
+    """Zero diagonal: only 2x2 pivots.  With n_enlarge = 3 the enlarged candidate
+    set of the second stage would begin at the second half of a block; it begins
+    at the block instead, so the kernel dimension counts whole blocks and equals
+    the number of singular values at or below ker_tol (SVD)."""
+    bv = [10.0 ** -i for i in range(10)] + [5e-11, 3e-11, 1e-16]
+    W = w.paired_blocks_workload(bv, seed=50, n_tiny=3)
+    sv = np.linalg.svd(W.csr().toarray(), compute_uv=False)
+    for ne in (3, 4):
+        hf = oracle.hybrid_factorize(W.csr(), W.perm, W.node_ptr, W.parent, tau=1e-2, gcr_block=0, n_enlarge=ne)
+        assert hf.M == W.n and all(bs == 2 for _, bs in hf.ldl.blocks)
+        assert hf.k == 6 == int((sv <= 1e-10).sum())
+        assert (hf.M - hf.k) % 2 == 0                     # the rank cut is a block boundary
+        X = oracle.hybrid_solve(hf, W.b)
+        assert np.allclose(X, W.x_star, rtol=0, atol=1e-14 * np.abs(W.x_star).max())
+
+
+def test_elasticity_cube_tau_rule():
+    """The threshold of the 24^3 elastic cube follows its stated rule: at
+    tau = 0.2 the FP32 and the FP64 step 1 both postpone exactly the six rigid
+    modes (closed-form kernel dimension); at the grid value below (0.1) the FP32
+    step 1 postpones fewer than six, so 0.2 is the smallest such grid value."""
+    W = w.config_c3()
+    assert W.tau == 0.2 and w.C3_TAU_GRID[w.C3_TAU_GRID.index(W.tau) - 1] == 0.1
+    q, K = oracle.scale(W.csr())
+    Kp = oracle.permute(K, W.perm)
+    bd = oracle.symbolic(Kp, W.node_ptr, W.parent)
+    f32 = oracle.factor_low(Kp, W.node_ptr, W.parent, 0.2, dtype=np.float32, borders=bd)
+    f64 = oracle.factor_low(Kp, W.node_ptr, W.parent, 0.2, dtype=np.float64, borders=bd)
+    assert f32.M == f64.M == 6
+    assert oracle.factor_low(Kp, W.node_ptr, W.parent, 0.1, dtype=np.float32, borders=bd).M < 6
+
+
+def test_decided_nodes_rule():
+    """The rounding-independence rule: identical runs decide every node; a
+    planted change of one tested value in the low-precision record (a near-tau
+    pivot moved across the threshold) makes exactly that node undecided."""
+    W = w.elasticity(5, seed=31, leaf_max=27, r=1, tau=0.3)
+    q, K = oracle.scale(W.csr())
+    Kp = oracle.permute(K, W.perm)
+    f64 = oracle.factor_low(Kp, W.node_ptr, W.parent, W.tau, dtype=np.float64)
+    dec, worst = oracle.decided_nodes(f64, f64, W.tau)
+    assert dec.all() and np.all(worst == 0.0)
+    f32 = oracle.factor_low(Kp, W.node_ptr, W.parent, W.tau, dtype=np.float32)
+    dec32, worst32 = oracle.decided_nodes(f32, f64, W.tau)
+    assert np.all(dec32 == ((f32.npiv == f64.npiv) & (worst32 < 0.25)))
+    # move the second pivot of the last node to just above tau times the first
+    j = len(W.parent) - 1
+    s = f64.node_ptr[j]
+    import copy
+    g = copy.deepcopy(f64)
+    g.d[s + 1] = np.float64(W.tau * abs(g.d[s]) * 1.001) * np.sign(g.d[s + 1])
+    dec2, _ = oracle.decided_nodes(g, f64, W.tau)
+    assert not dec2[j] and dec2[:j].all()
+
+
 @pytest.mark.parametrize("kdim", [0, 1, 3])
 def test_kernel_dimension_random_planted(kdim):
     W = w.random_dense_workload(24, seed=30 + kdim, kernel_dim=kdim, cond=1e3)
