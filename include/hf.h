@@ -213,6 +213,20 @@ int hf_schur(const hf_ctx* ctx, int32_t* m_host, int32_t* lambda2_host, double* 
              void* stream);
 
 /*
+ * hf_schur without any allocation, for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it).
+ * Same arguments, outputs and errors as hf_schur; lambda2_host is sorted in
+ * place and the permutation of S22 is staged in a fixed device array of the
+ * library (one per GPU, kept until the process ends) instead of memory
+ * allocated per call.  The hard part may hold at most 16384 indices:
+ * HF_ERR_NOT_IMPLEMENTED beyond (the size query with NULL buffers still
+ * succeeds).  Calls on one GPU share that array, so calls that overlap on one
+ * GPU (different streams or threads) race; calls in sequence do not.
+ */
+int hf_schur_noalloc(const hf_ctx* ctx, int32_t* m_host, int32_t* lambda2_host, double* S22_dev, int64_t lds,
+                     void* stream);
+
+/*
  * Diagonal scaling Q (Sec. 2) as float64 [n] on the device: K = Q Kbar Q.
  * Errors: HF_ERR_ARG, HF_ERR_STATE, HF_ERR_HIP.
  */

@@ -50,7 +50,8 @@ HF_PREC_FP64 = 64
 
 EXPORTS = ["hf_default_options", "hf_analyse", "hf_factorize", "hf_solve", "hf_kernel_dim",
            "hf_kernel_basis", "hf_schur", "hf_scaling", "hf_info", "hf_strerror", "hf_destroy",
-           "hf_timing_enable", "hf_timing_get", "hf_adjoint", "hf_pivots", "hf_s22_pivots", "hf_gcr_history"]
+           "hf_timing_enable", "hf_timing_get", "hf_adjoint", "hf_pivots", "hf_s22_pivots", "hf_gcr_history",
+           "hf_schur_noalloc"]
 
 # kernel classes of hf_timing_get
 KCLASS = ["panel", "permute_l11", "f11_update", "gather_border", "trsm", "syrk", "extend_add", "fwd_diag",
@@ -115,6 +116,7 @@ def _load():
         "hf_pivots": (ctypes.c_int, [P, P, P, P, P]),
         "hf_s22_pivots": (ctypes.c_int, [P, P]),
         "hf_gcr_history": (ctypes.c_int, [P, P, P, P, P]),
+        "hf_schur_noalloc": (ctypes.c_int, [P, P, P, P, I64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -308,6 +310,22 @@ def hf_schur(ctx: Context, stream=None):
     if M:
         _check(_lib.hf_schur(ctx.handle, ctypes.byref(m), _np_ptr(lam), ctypes.c_void_p(S.data_ptr()), M,
                              _stream(stream)), "hf_schur")
+    return lam[:M], S[:M, :M].t()
+
+
+def hf_schur_noalloc(ctx: Context, S_out=None, stream=None):
+    """hf_schur through the allocation-free entry point.  S_out (an (M, M) float64
+    CUDA tensor, column-major storage: its transpose is returned) may be given
+    so that the call itself allocates nothing; the Python side allocates it
+    otherwise."""
+    m = ctypes.c_int32()
+    _check(_lib.hf_schur_noalloc(ctx.handle, ctypes.byref(m), None, None, 0, _stream(stream)), "hf_schur_noalloc")
+    M = m.value
+    lam = np.zeros(max(M, 1), dtype=np.int32)
+    S = S_out if S_out is not None else torch.zeros((max(M, 1), max(M, 1)), dtype=torch.float64, device="cuda")
+    if M:
+        _check(_lib.hf_schur_noalloc(ctx.handle, ctypes.byref(m), _np_ptr(lam), ctypes.c_void_p(S.data_ptr()), M,
+                                     _stream(stream)), "hf_schur_noalloc")
     return lam[:M], S[:M, :M].t()
 
 
