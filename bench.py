@@ -31,6 +31,8 @@ WORKLOADS = {
           "FP32 step 1 + FP64 block GCR, 16 RHS",
     "c3": "floating Q1 elastic cube 24^3 elements (L=46875), E=10^U(0,6), nu=0.3, ND leaf 64 nodes, tau=0.2, "
           "FP32 step 1 + FP64 block GCR, 32 RHS",
+    "c4": "enclosed MAC Stokes saddle point 32^3 cells (95232 face velocities + 32768 pressures, L=128000), "
+          "viscosity 10^U(-2,2), staggered ND leaf 512, tau=1e-2, FP32 step 1 + FP64 block GCR, 32 RHS",
 }
 CALIB_BYTES = 256 << 20
 # measured HBM traffic of the dominant kernel (FETCH_SIZE / WRITE_SIZE passes),
@@ -52,6 +54,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain device copy of 256 MiB (calibrates HBM byte counters)")
@@ -173,50 +176,100 @@ def path_roofline(stats, steps, prec, ms_per_step):
             "per_class": per}
 
 
-def cpu_baseline(W):
-    """The oracle (unchanged) on a bounded sample: its step 1 on one nested-
-    dissection subtree, factored as a problem of its own, is timed in full and
-    its per-flop rate applied to the whole factorization's symbolic flop count.
-    The oracle's Krylov and solve phases are not included, so the figure is a
-    lower bound on the oracle's factor+solve time."""
+def _subtree_sample(W, frac):
+    """The nested-dissection subtree whose size is closest to frac * n, as a
+    problem of its own (rows and columns of the permuted scaled matrix)."""
     import numpy as np
     import oracle
     q, K = oracle.scale(W.csr())
     Kp = oracle.permute(K, W.perm)
-    borders = oracle.symbolic(Kp, W.node_ptr, W.parent)
-    # sample: the larger subtree below the root separator (half the unknowns),
-    # factored as a problem of its own: about 5-10 s of oracle time on 16 cores
     n_nodes = len(W.parent)
-    sizes = np.diff(W.node_ptr).astype(float)
-    fronts = sizes + np.diff(borders[0])
-    node_fl = sizes * fronts * fronts - sizes * sizes * fronts + sizes ** 3 / 3
-    fl_all = float(np.sum(node_fl))
     first = np.arange(n_nodes)
     for j in range(n_nodes):
         pj = W.parent[j]
         if pj >= 0:
             first[pj] = min(first[pj], first[j])
     sub_n = np.array([W.node_ptr[j + 1] - W.node_ptr[first[j]] for j in range(n_nodes)])
-    j = int(np.argmin(np.abs(sub_n - W.n / 2)))
+    j = int(np.argmin(np.abs(sub_n - frac * W.n)))
     lo, hi = first[j], j + 1
     s0, s1 = W.node_ptr[lo], W.node_ptr[hi]
     Ksub = Kp[s0:s1, s0:s1].tocsr()
-    nptr = W.node_ptr[lo:hi + 1] - s0
+    nptr = (W.node_ptr[lo:hi + 1] - s0).astype(np.int32)
     par = np.array([p - lo if (p >= 0 and p < hi) else -1 for p in W.parent[lo:hi]], dtype=np.int32)
-    bp, bo = oracle.symbolic(Ksub, nptr, par)
-    p = np.diff(nptr).astype(float)
-    f = p + np.diff(bp)
-    fl_sub = float(np.sum(p * f * f - p * p * f + p ** 3 / 3))
+    return j, Ksub, nptr, par
+
+
+SAMPLE_SCRIPT = """
+import sys, time, numpy as np, scipy.sparse as sp
+sys.path.insert(0, {root!r})
+import oracle
+d = np.load({path!r})
+K = sp.csr_matrix((d['data'], d['indices'], d['indptr']), shape=tuple(d['shape']))
+bd = oracle.symbolic(K, d['nptr'], d['par'])
+t0 = time.perf_counter()
+oracle.factor_low(K, d['nptr'], d['par'], float(d['tau']), dtype=np.float32, borders=bd)
+print(time.perf_counter() - t0)
+"""
+
+
+def cpu_baseline(W):
+    """The oracle (unchanged), timed on the host: its whole factor+solve with the
+    FP32 step 1 on this workload (Algorithm 1, then Algorithm 2 with the
+    residual-correction pass), split by phase, with OpenMP over all host cores;
+    and, as a bounded sample, its step 1 on a subtree of about 1/8 of the
+    unknowns run with one thread and with all threads (the whole run with one
+    thread would take tens of minutes)."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    oracle.factor_low(Ksub, nptr, par, W.tau, dtype=np.float32, borders=(bp, bo))
-    dt = time.perf_counter() - t0
-    est = dt * fl_all / fl_sub
-    return {"value": est, "unit": "s (step-1 factorization, extrapolated by flops; lower bound)",
-            "cores": threads,
-            "kind": "oracle",
-            "sample": f"oracle FP32 step 1 on the subtree of node {j} ({s1 - s0} unknowns, "
-                      f"{fl_sub:.3g} of {fl_all:.3g} flops) in {dt:.2f} s; factor+solve not included"}
+    hf = oracle.hybrid_factorize(W.csr(), W.perm, W.node_ptr, W.parent, tau=W.tau, low=np.float32, gcr_block=0)
+    t1 = time.perf_counter()
+    oracle.hybrid_solve(hf, W.b)
+    t2 = time.perf_counter()
+    phases = {"step1_s": hf.seconds["step1"], "gcr_s": hf.seconds["gcr"], "s22_s": hf.seconds["s22"],
+              "solve_s": t2 - t1}
+    sample = {}
+    try:
+        j, Ksub, nptr, par = _subtree_sample(W, 0.125)
+        with tempfile.TemporaryDirectory() as td:
+            path = os.path.join(td, "sub.npz")
+            np.savez(path, data=Ksub.data, indices=Ksub.indices, indptr=Ksub.indptr, shape=np.array(Ksub.shape),
+                     nptr=nptr, par=par, tau=W.tau)
+            code = SAMPLE_SCRIPT.format(root=ROOT, path=path)
+            for nt in (1, threads):
+                env = dict(os.environ, OMP_NUM_THREADS=str(nt))
+                out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                                     timeout=600, check=True)
+                sample[f"step1_s_{nt}_threads"] = float(out.stdout.strip().splitlines()[-1])
+        sample["subtree"] = f"node {j}, {Ksub.shape[0]} unknowns"
+    except (OSError, subprocess.SubprocessError, ValueError) as e:
+        sample["error"] = str(e)
+    return {"value": t2 - t0, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": "the whole workload: oracle FP32 step 1 + FP64 block GCR + S22 + solve with one "
+                      "correction pass, OpenMP over all host cores (the C step 1 and preconditioner; NumPy/SciPy "
+                      "for the rest)",
+            "phases": phases, "M": int(hf.M), "kernel_dim": int(hf.k),
+            "one_thread_sample": sample}
+
+
+def golden_rel(cfg, X):
+    """Relative difference between X and the oracle's FP64 minimum-norm solution
+    stored for this workload (tests/golden, written by the oracle), over the
+    stored sample of rows; None when no stored solution exists."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{cfg}_oracle_fp64.json")
+    try:
+        with open(path) as fh:
+            g = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rows = np.array(g["sample_rows"])
+    xs = np.array(g["x_sample"])
+    return {"value": float(np.linalg.norm(X[rows] - xs) / np.linalg.norm(xs)), "rows": int(len(rows)),
+            "reference": f"oracle FP64 solution (tests/golden/{cfg}_oracle_fp64.json)"}
 
 
 def adjoint_timing(hy, ctx, X, W, steps, torch):
@@ -277,6 +330,7 @@ def main():
     from paper_2208_01907_amd.metrics import backward_error
     be = backward_error(W.csr(), Xh, W.b)
     rel_xstar = float(np.linalg.norm(Xh - W.x_star) / np.linalg.norm(W.x_star))
+    rel_oracle = golden_rel(args.config, Xh)
     result = {
         "metric": "factor+solve s at backward err <=1e-14, mixed vs FP64 LDL^T; % HBM/MFMA peak",
         "value": dt, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -285,7 +339,8 @@ def main():
         "config": {"workload": WORKLOADS[args.config], "n": W.n, "nnz": W.nnz, "rhs": int(W.b.shape[1])},
         "M": info["M"], "kernel_dim": info["kernel_dim"], "gcr_iters_max": info["gcr_iters_max"],
         "solve_gcr_iters": info["solve_gcr_iters"], "backward_error": be, "gate_1e-14": bool(be <= 1e-14),
-        "rel_err_vs_xstar": rel_xstar, "analyse_s": t_an, "ms_per_step_with_events": dt_ev * 1e3,
+        "rel_err_vs_xstar": rel_xstar, "rel_vs_oracle": rel_oracle, "gate_rel_1e-10": (
+            None if rel_oracle is None else bool(rel_oracle["value"] <= 1e-10)), "analyse_s": t_an, "ms_per_step_with_events": dt_ev * 1e3,
         "phase_ms": {k: info[k] for k in ("t_step1_ms", "t_gcr_ms", "t_s22_ms", "t_solve_ms")},
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in stats.items()},
         "kernel_rates": rates(stats),
@@ -297,16 +352,41 @@ def main():
     if not args.no_fp64:
         ctx64, X64, dt64, dt64_ev, _, stats64, info64 = run_path(hy, W, vals, B, hy.HF_PREC_FP64, args.steps,
                                                                  args.warmup, torch)
-        be64 = backward_error(W.csr(), X64.cpu().numpy(), W.b)
+        X64h = X64.cpu().numpy()
+        be64 = backward_error(W.csr(), X64h, W.b)
         result["fp64"] = {"s_per_step": dt64, "s_per_step_with_events": dt64_ev, "M": info64["M"],
                           "kernel_dim": info64["kernel_dim"],
-                          "backward_error": be64,
+                          "backward_error": be64, "rel_vs_oracle": golden_rel(args.config, X64h),
                           "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in stats64.items()},
                           "kernel_rates": rates(stats64),
                           "roofline": roofline(stats64, args.steps, 64),
                           "path_roofline": path_roofline(stats64, args.steps, 64, dt64 * 1e3)}
         result["speedup_vs_fp64"] = dt64 / dt
         del ctx64
+    if not args.no_fp16:
+        result["fp16_updates"] = {}
+        for key, prec, what in (
+                ("pair", hy.HF_PREC_FP16_PAIR, "FP32 fronts; trailing and contribution updates on the FP16 matrix "
+                 "cores with operands as FP16 pairs (three products), per-tile 2^k scaling, FP32 accumulation"),
+                ("single", hy.HF_PREC_FP16, "as pair, operands rounded to single FP16 numbers (one product)")):
+            try:
+                ctx16, X16, dt16, dt16_ev, _, stats16, info16 = run_path(hy, W, vals, B, prec, args.steps,
+                                                                         args.warmup, torch)
+            except hy.HFError as e:
+                result["fp16_updates"][key] = {"what": what, "error": str(e)}
+                continue
+            X16h = X16.cpu().numpy()
+            runs16, nfac16 = hy.hf_gcr_history(ctx16)
+            result["fp16_updates"][key] = {
+                "what": what, "s_per_step": dt16, "speedup_vs_fp32_updates": dt / dt16, "M": info16["M"],
+                "kernel_dim": info16["kernel_dim"], "gcr_iters_max": info16["gcr_iters_max"],
+                "solve_gcr_iters": info16["solve_gcr_iters"],
+                "gcr_histories": [[float(x) for x in r] for r in runs16],
+                "backward_error": backward_error(W.csr(), X16h, W.b),
+                "rel_vs_oracle": golden_rel(args.config, X16h),
+                "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in stats16.items()},
+                "kernel_rates": rates(stats16)}
+            del ctx16
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(result))

@@ -48,14 +48,23 @@ enum {
   HF_ERR_NOT_IMPLEMENTED = -9
 };
 
-/* precision of the step-1 factorization (the preconditioner) */
-enum { HF_PREC_FP32 = 32, HF_PREC_FP64 = 64 };
+/* precision of the step-1 factorization (the preconditioner).  HF_PREC_FP16 and
+   HF_PREC_FP16_PAIR: FP32 fronts and factor, with the two front updates (the
+   trailing update of the pivot block after each panel and the contribution
+   block) multiplied on the FP16 matrix cores: each 64 x 16 operand tile is
+   scaled by a power of two that brings its largest magnitude just below 2^14,
+   and the products are accumulated and unscaled in FP32.  HF_PREC_FP16 casts
+   every scaled operand to FP16 (11 significant bits); HF_PREC_FP16_PAIR carries
+   it as a pair of FP16 numbers (hi + lo, about 22 bits) and forms three products
+   per tile (hi*hi, hi*lo, lo*hi) */
+enum { HF_PREC_FP16 = 16, HF_PREC_FP16_PAIR = 17, HF_PREC_FP32 = 32, HF_PREC_FP64 = 64 };
 
 typedef struct hf_ctx hf_ctx;
 
 typedef struct hf_options {
   double tau;               /* postponing threshold of Sec. 2.2 (default 1e-2) */
-  int32_t low_precision;    /* HF_PREC_FP32 (mixed, default) or HF_PREC_FP64 */
+  int32_t low_precision;    /* HF_PREC_FP32 (mixed, default), HF_PREC_FP16,
+                               HF_PREC_FP16_PAIR or HF_PREC_FP64 */
   int32_t first_pivot_unit; /* 1 (default): the first pivot of a node is compared
                                with 1, the unit diagonal of the scaled matrix;
                                0: it is accepted whenever nonzero */

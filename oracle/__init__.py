@@ -33,6 +33,7 @@ import dataclasses
 import math
 import os
 import subprocess
+import time
 
 import numpy as np
 import scipy.sparse as sp
@@ -69,7 +70,7 @@ def _load():
             fn = getattr(lib, f"hfo_factor_{suf}")
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.c_int64, P, P, P, ctypes.c_int32, P, P, P, P, ctypes.c_double,
-                           ctypes.c_int32, P, P, P, P, P, P, P, P]
+                           ctypes.c_int32, P, P, P, P, P, P, P, P, P]
             fn = getattr(lib, f"hfo_precond_{suf}")
             fn.restype = None
             fn.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P, P, P, P,
@@ -165,6 +166,7 @@ class Step1:
     npiv: np.ndarray
     margin: np.ndarray
     dstop: np.ndarray        # per node: value of the candidate that stopped it (NaN: none)
+    tiegap: np.ndarray       # per node: smallest relative lead of an accepted pivot over its rival
     lambda2: np.ndarray      # postponed indices, elimination order, ascending
     is_l2: np.ndarray        # uint8 mask over elimination-order indices
 
@@ -211,6 +213,7 @@ def factor_low(Kp, node_ptr, parent, tau, dtype=np.float32, first_ref_unit=True,
     npiv = np.zeros(max(len(p), 1), dtype=np.int32)
     margin = np.zeros(max(len(p), 1), dtype=np.float64)
     dstop = np.zeros(max(len(p), 1), dtype=np.float64)
+    tiegap = np.zeros(max(len(p), 1), dtype=np.float64)
     indptr = np.ascontiguousarray(Kp.indptr, dtype=np.int64)
     indices = np.ascontiguousarray(Kp.indices, dtype=np.int32)
     vals = np.ascontiguousarray(Kp.data, dtype=np.float64)
@@ -218,7 +221,7 @@ def factor_low(Kp, node_ptr, parent, tau, dtype=np.float32, first_ref_unit=True,
     rc = getattr(lib, f"hfo_factor_{suf}")(
         n, _ptr(indptr), _ptr(indices), _ptr(vals), len(p), _ptr(node_ptr), _ptr(parent),
         _ptr(border_ptr), _ptr(border), float(tau), 1 if first_ref_unit else 0, _ptr(exc), _ptr(lptr),
-        _ptr(L), _ptr(d), _ptr(piv_order), _ptr(npiv), _ptr(margin), _ptr(dstop))
+        _ptr(L), _ptr(d), _ptr(piv_order), _ptr(npiv), _ptr(margin), _ptr(dstop), _ptr(tiegap))
     if rc != 0:
         raise RuntimeError(f"oracle step 1 failed (code {rc})")
     npiv = npiv[:len(p)]
@@ -229,7 +232,8 @@ def factor_low(Kp, node_ptr, parent, tau, dtype=np.float32, first_ref_unit=True,
     lambda2 = np.nonzero(is_l2)[0].astype(np.int32)
     return Step1(dtype=dt.type, n=n, node_ptr=node_ptr, parent=parent, border_ptr=border_ptr,
                  border=border, lptr=lptr, L=L, d=d[:n], piv_order=piv_order[:n], npiv=npiv,
-                 margin=margin[:len(p)], dstop=dstop[:len(p)], lambda2=lambda2, is_l2=is_l2)
+                 margin=margin[:len(p)], dstop=dstop[:len(p)], tiegap=tiegap[:len(p)], lambda2=lambda2,
+                 is_l2=is_l2)
 
 
 def tested_values(f1: Step1, j):
@@ -647,6 +651,7 @@ class HybridFactor:
     gcr_maxit: int
     gcr_iters: list
     Kbar: sp.csr_matrix = None   # the caller's matrix (residual correction of the solve)
+    seconds: dict = None         # wall time of steps 1, 3 (block GCR) and 4-5 (S22, rank)
 
     @property
     def M(self):
@@ -680,10 +685,12 @@ def hybrid_factorize(Kbar, perm, node_ptr, parent, tau=1e-2, low=np.float32, gcr
     4. S22 = K22 - K21 X12 in FP64, symmetrized;
     5. FP64 pivoted LDL^T of S22 and its kernel.
     """
+    t0 = time.perf_counter()
     q, K = scale(Kbar)
     Kp = permute(K, perm)
     n = Kp.shape[0]
     f1 = factor_low(Kp, node_ptr, parent, tau, dtype=low, first_ref_unit=first_ref_unit)
+    t1 = time.perf_counter()
     l2 = f1.lambda2
     M = len(l2)
     apply_A = _masked_ops(Kp, f1.is_l2)
@@ -705,6 +712,8 @@ def hybrid_factorize(Kbar, perm, node_ptr, parent, tau=1e-2, low=np.float32, gcr
                 raise RuntimeError("block GCR did not converge")
             X12[:, c0:c0 + mb] = Xb
             iters.append(info.iterations)
+    t2 = time.perf_counter()
+    if M:
         W = -X12
         W[l2, np.arange(M)] = 1.0
         S22 = (Kp @ W)[l2]
@@ -722,9 +731,11 @@ def hybrid_factorize(Kbar, perm, node_ptr, parent, tau=1e-2, low=np.float32, gcr
         nb[perm] = kern                   # back to original ordering
         nb = q[:, None] * nb              # Kbar (Q n) = 0 when K n = 0
         kern, _ = np.linalg.qr(nb)
+    t3 = time.perf_counter()
     return HybridFactor(n=n, q=q, perm=np.asarray(perm), Kp=Kp, step1=f1, lambda1_mask=keep, X12=X12,
                         S22=S22, ldl=ld, rank=rk, kernel=kern, gcr_block=gcr_block, gcr_tol=gcr_tol,
-                        gcr_maxit=gcr_maxit, gcr_iters=iters, Kbar=sp.csr_matrix(Kbar))
+                        gcr_maxit=gcr_maxit, gcr_iters=iters, Kbar=sp.csr_matrix(Kbar),
+                        seconds={"step1": t1 - t0, "gcr": t2 - t1, "s22": t3 - t2})
 
 
 def _algorithm2(hf: HybridFactor, b, tol=None):
@@ -763,8 +774,13 @@ def hybrid_solve(hf: HybridFactor, Bbar, refine_steps=1, Kbar=None, refine_tol=1
     pollute it.  The correction is not part of the paper's Algorithm 2; it is
     added for the 1e-14 backward-error target.  A correction only has to be
     accurate relative to the residual it corrects, so its block GCR stops at
-    relative residual refine_tol.  Kbar defaults to the matrix given to
-    hybrid_factorize.
+    relative residual refine_tol.  The residual is accumulated in extended
+    precision and rounded once: in FP64 its rounding error would be about
+    eps |Kbar| |xbar|, as large as the residual of a backward-stable solution,
+    and the correction could not reduce the forward error below cond * eps; with
+    an accurate residual it converges to the solution of Kbar x = bbar itself
+    (mixed-precision iterative refinement).  Kbar defaults to the matrix given
+    to hybrid_factorize.
     """
     Bbar = np.asarray(Bbar, dtype=np.float64)
     one = Bbar.ndim == 1
@@ -780,8 +796,11 @@ def hybrid_solve(hf: HybridFactor, Bbar, refine_steps=1, Kbar=None, refine_tol=1
         return out
 
     xbar = to_orig(_algorithm2(hf, (hf.q[:, None] * Bbar)[hf.perm]))
+    Kl = Kbar.astype(np.longdouble) if refine_steps else None
     for _ in range(refine_steps):
-        rbar = Bbar - Kbar @ xbar
+        # residual in extended precision (x86 long double, 64-bit significand),
+        # rounded to FP64 once
+        rbar = np.asarray(Bbar.astype(np.longdouble) - Kl @ xbar.astype(np.longdouble), dtype=np.float64)
         xbar = xbar + to_orig(_algorithm2(hf, (hf.q[:, None] * rbar)[hf.perm], tol=refine_tol))
     return xbar[:, 0] if one else xbar
 

@@ -69,7 +69,13 @@ static void FN(sym_swap)(REAL* F, int64_t f, int64_t i, int64_t k) {
  *   margin  : per node, min |log10(|d_k0| / (tau |d_prev|))| over its tests
  *             (+inf when no test was made);
  *   dstop   : per node, the diagonal value of the candidate that stopped the
- *             node (NaN when every candidate was accepted).
+ *             node (NaN when every candidate was accepted);
+ *   tiegap  : per node, min over its accepted pivots of (|d| - r) / |d|, r the
+ *             largest |diagonal| among the other candidates of that selection,
+ *             over the selections where the winner or that rival is a computed
+ *             value (changed by an extend-add or an elimination; two untouched
+ *             entries of K tie identically in any arithmetic); +inf when no
+ *             such selection had a rival.
  *   exclude : optional mask over global indices; masked indices are never
  *             pivot candidates and end up with the postponed ones (used to build
  *             a factorization of K11 for a given split).
@@ -81,7 +87,7 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
                     const int64_t* border_ptr, const int32_t* border, double tau,
                     int32_t first_ref_unit, const uint8_t* exclude, const int64_t* lptr,
                     REAL* Lstore, REAL* dstore, int32_t* piv_order, int32_t* npiv,
-                    double* margin, double* dstop) {
+                    double* margin, double* dstop, double* tiegap) {
   int rc = 0;
   int32_t* loc = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
   REAL** contrib = (REAL**)calloc((size_t)(n_nodes > 0 ? n_nodes : 1), sizeof(REAL*));
@@ -104,7 +110,8 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
     REAL* F = (REAL*)calloc((size_t)(f * f > 0 ? f * f : 1), sizeof(REAL));
     int32_t* idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(f > 0 ? f : 1));
     REAL* w = (REAL*)malloc(sizeof(REAL) * (size_t)(f > 0 ? f : 1));
-    if (!F || !idx || !w) { free(F); free(idx); free(w); rc = -2; goto done; }
+    uint8_t* tch = (uint8_t*)calloc((size_t)(f > 0 ? f : 1), 1);   /* diagonal is a computed value */
+    if (!F || !idx || !w || !tch) { free(F); free(idx); free(w); free(tch); rc = -2; goto done; }
     for (int64_t k = 0; k < p; ++k) { loc[s + k] = (int32_t)k; idx[k] = (int32_t)(s + k); }
     for (int64_t k = 0; k < b; ++k) { loc[bj[k]] = (int32_t)(p + k); idx[p + k] = bj[k]; }
 
@@ -115,7 +122,7 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
         const int64_t c = indices[e];
         if (c < s) continue;                 /* assembled in a descendant front */
         const int32_t lc = loc[c];
-        if (lc < 0) { free(F); free(idx); free(w); rc = -1; goto done; }
+        if (lc < 0) { free(F); free(idx); free(w); free(tch); rc = -1; goto done; }
         const int64_t r0 = lc > k ? lc : k, c0 = lc > k ? k : lc;
         AT(F, f, r0, c0) = (REAL)vals[e];
       }
@@ -130,9 +137,10 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
         const int32_t lt = loc[bcl[t]];
         for (int64_t r = t; r < bc; ++r) {
           const int32_t lr = loc[bcl[r]];
-          if (lr < 0 || lt < 0) { free(F); free(idx); free(w); rc = -1; goto done; }
+          if (lr < 0 || lt < 0) { free(F); free(idx); free(w); free(tch); rc = -1; goto done; }
           const int32_t r0 = lr > lt ? lr : lt, c0 = lr > lt ? lt : lr;
           AT(F, f, r0, c0) += AT(C, bc, r, t);
+          if (r0 == c0) tch[r0] = 1;
         }
       }
       free(C);
@@ -144,6 +152,7 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
     int have_prev = first_ref_unit ? 1 : 0;
     double mmin = INFINITY;
     double stopv = NAN;
+    double gmin = INFINITY;
     int64_t i;
     for (i = 0; i < p; ++i) {
       int64_t k0 = -1;
@@ -152,6 +161,13 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
         if (exclude && exclude[idx[k]]) continue;
         const double v = fabs((double)AT(F, f, k, k));
         if (v > best || (v == best && idx[k] < idx[k0])) { best = v; k0 = k; }
+      }
+      double rival = -1.0;                   /* largest rival that can tie in another arithmetic */
+      for (int64_t k = i; k < p && k0 >= 0; ++k) {
+        if (k == k0 || (exclude && exclude[idx[k]])) continue;
+        if (!tch[k] && !tch[k0]) continue;
+        const double v = fabs((double)AT(F, f, k, k));
+        if (v > rival) rival = v;
       }
       if (k0 < 0) break;                     /* only excluded indices remain */
       const double dk = (double)AT(F, f, k0, k0);
@@ -162,8 +178,11 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
         if (m < mmin) mmin = m;
         if (fabs(dk) < tau * fabs(dprev)) { stopv = dk; break; }
       }
+      if (rival >= 0.0 && (best - rival) / best < gmin) gmin = (best - rival) / best;
       FN(sym_swap)(F, f, i, k0);
       { int32_t t = idx[i]; idx[i] = idx[k0]; idx[k0] = t; }
+      { uint8_t t = tch[i]; tch[i] = tch[k0]; tch[k0] = t; }
+      for (int64_t r = i + 1; r < p; ++r) if (AT(F, f, r, i) != (REAL)0) tch[r] = 1;
       const REAL d = AT(F, f, i, i);
       for (int64_t r = i + 1; r < f; ++r) w[r] = AT(F, f, r, i);
       /* eq. (2): S' = K'_22 - col d^{-1} row, lower triangle only */
@@ -181,19 +200,20 @@ int FN(hfo_factor_)(int64_t n, const int64_t* indptr, const int32_t* indices, co
     npiv[j] = (int32_t)i;
     margin[j] = mmin;
     dstop[j] = stopv;
+    tiegap[j] = gmin;
     for (int64_t k = 0; k < p; ++k) piv_order[s + k] = idx[k];
     /* the panel (all rows, p columns) goes to the factor store */
     memcpy(Lstore + lptr[j], F, sizeof(REAL) * (size_t)(f * p));
     /* Schur-complement block of the border for the parent (postponed rows dropped) */
     if (b > 0 && parent[j] >= 0) {
       REAL* C = (REAL*)malloc(sizeof(REAL) * (size_t)(b * b));
-      if (!C) { free(F); free(idx); free(w); rc = -2; goto done; }
+      if (!C) { free(F); free(idx); free(w); free(tch); rc = -2; goto done; }
       for (int64_t c = 0; c < b; ++c)
         for (int64_t r = 0; r < b; ++r) AT(C, b, r, c) = AT(F, f, p + r, p + c);
       contrib[j] = C;
     }
     for (int64_t k = 0; k < f; ++k) loc[idx[k]] = -1;
-    free(F); free(idx); free(w);
+    free(F); free(idx); free(w); free(tch);
   }
 done:
   if (contrib) for (int32_t j = 0; j < n_nodes; ++j) free(contrib[j]);

@@ -58,7 +58,9 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
   hf_default_options(&o);
   if (opt) o = *opt;
   if (!(o.tau >= 0.0) || !std::isfinite(o.tau)) return HF_ERR_ARG;
-  if (o.low_precision != HF_PREC_FP32 && o.low_precision != HF_PREC_FP64) return HF_ERR_ARG;
+  if (o.low_precision != HF_PREC_FP16 && o.low_precision != HF_PREC_FP16_PAIR && o.low_precision != HF_PREC_FP32 &&
+      o.low_precision != HF_PREC_FP64)
+    return HF_ERR_ARG;
   if (o.n_enlarge < 0 || o.gcr_block < 0 || o.gcr_block > 64 || o.gcr_maxit < 1 || !(o.gcr_tol > 0) ||
       !(o.ker_tol >= 0) || o.refine_steps < 0 || o.refine_steps > 8 || !(o.refine_tol > 0))
     return HF_ERR_ARG;

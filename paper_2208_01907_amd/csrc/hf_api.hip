@@ -85,7 +85,7 @@ int hf_info(const hf_ctx* ctx, hf_info_t* info) {
   o.factor_entries = ctx->factor_entries;
   o.factor_flops = ctx->flops_sym;
   o.factor_flops_done = ctx->flops_done;
-  o.front_bytes = ctx->front_elems * (ctx->opt.low_precision == HF_PREC_FP32 ? 4 : 8);
+  o.front_bytes = ctx->front_elems * (ctx->opt.low_precision == HF_PREC_FP64 ? 8 : 4);
   o.M = ctx->M;
   o.kernel_dim = ctx->kdim;
   o.gcr_blocks = ctx->gcr_blocks;

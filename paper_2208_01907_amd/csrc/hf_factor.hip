@@ -464,7 +464,7 @@ k_mirror(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
 // column is also a storage row).  Lower tiles are computed; each result is
 // written to both triangles.  Reads of the storage in place touch only
 // non-displaced entries of the tile itself, so updating in place is safe.
-template <class T, int NB>
+template <class T, int NB, int H16 = 0>
 __global__ void __launch_bounds__(256)
 k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
                const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval,
@@ -528,7 +528,9 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::V{0, 0, 0, 0};
+  __shared__ float smx[2][4];  // FP16 products: per-stage operand maxima of the four waves
   for (int kk = 0; kk < NB; kk += 16) {
+    float ma = 0.f, mb = 0.f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + q * 256;
@@ -541,9 +543,21 @@ k_trail_update(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
       }
       As[kq][rr] = vb;  // the product is formed transposed: rows of the tile on the lanes
       Bs[kq][rr] = va;
+      if constexpr (H16 > 0) {
+        ma = fmaxf(ma, fabsf((float)vb));
+        mb = fmaxf(mb, fabsf((float)va));
+      }
+    }
+    if constexpr (H16 > 0) {
+      stage_max_post(ma, smx[0], lane, w);
+      stage_max_post(mb, smx[1], lane, w);
     }
     __syncthreads();
-    mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
+    if constexpr (H16 > 0)
+      mfma_tile_64_h16<68, H16 == 2>(As, Bs, acc, lane, wr, wc, fp16_scale(stage_max_read(smx[0])),
+                                     fp16_scale(stage_max_read(smx[1])));
+    else
+      mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
     __syncthreads();
   }
   // lower triangle straight from the product layout (lanes along storage rows);
@@ -642,7 +656,7 @@ k_l11_back(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
 // fronts of a level, one 64x64 tile per workgroup.
 // ---------------------------------------------------------------------------
 
-template <class T>
+template <class T, int H16 = 0>
 __global__ void __launch_bounds__(256)
 k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
        const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval) {
@@ -675,7 +689,9 @@ k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = typename Mfma<T>::V{0, 0, 0, 0};
   const int rowA = ti * 64, rowB = tj * 64;
+  __shared__ float smx[2][4];  // FP16 products: per-stage operand maxima of the four waves
   for (int kk = 0; kk < K; kk += 16) {
+    float ma = 0.f, mb = 0.f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + q * 256;
@@ -688,9 +704,21 @@ k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
       }
       As[kq][rr] = vb;  // the product is formed transposed: rows of C on the lanes
       Bs[kq][rr] = va;
+      if constexpr (H16 > 0) {
+        ma = fmaxf(ma, fabsf((float)vb));
+        mb = fmaxf(mb, fabsf((float)va));
+      }
+    }
+    if constexpr (H16 > 0) {
+      stage_max_post(ma, smx[0], lane, w);
+      stage_max_post(mb, smx[1], lane, w);
     }
     __syncthreads();
-    mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
+    if constexpr (H16 > 0)
+      mfma_tile_64_h16<68, H16 == 2>(As, Bs, acc, lane, wr, wc, fp16_scale(stage_max_read(smx[0])),
+                                     fp16_scale(stage_max_read(smx[1])));
+    else
+      mfma_tile_64<T, 16, 68>(As, Bs, acc, lane, wr, wc);
     __syncthreads();
   }
 #pragma unroll
@@ -929,6 +957,11 @@ static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1
 template <class T>
 void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
   const int64_t n = ctx->n;
+  // FP32 fronts whose two update products run on the FP16 matrix cores: single
+  // FP16 operands (1) or FP16 pairs (2)
+  const int h16 = sizeof(T) != 4 ? 0
+                  : ctx->opt.low_precision == HF_PREC_FP16 ? 1
+                  : ctx->opt.low_precision == HF_PREC_FP16_PAIR ? 2 : 0;
   ctx->d_front.alloc((size_t)ctx->front_elems * sizeof(T));
   ctx->d_state.alloc((size_t)ctx->n_nodes * sizeof(NodeState));
   ctx->d_piv.alloc((size_t)n * sizeof(int32_t));
@@ -1037,8 +1070,12 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
           by += (r * NBL + r * r) * sz;
           fl += r * r * NBL;
         });
-        launch_timed(tm, HF_K_F11_UPDATE, w2.first, w2.second, s,
-                     NBL == NBP ? k_trail_update<T, NBP> : k_trail_update<T, 2 * NBP>, grid, dim3(256), lnodes, nodes,
+        constexpr int H1 = sizeof(T) == 4 ? 1 : 0, H2 = sizeof(T) == 4 ? 2 : 0;
+        auto ku = NBL == NBP ? (h16 == 1 ? k_trail_update<T, NBP, H1>
+                                : h16 == 2 ? k_trail_update<T, NBP, H2> : k_trail_update<T, NBP>)
+                             : (h16 == 1 ? k_trail_update<T, 2 * NBP, H1>
+                                : h16 == 2 ? k_trail_update<T, 2 * NBP, H2> : k_trail_update<T, 2 * NBP>);
+        launch_timed(tm, HF_K_F11_UPDATE, w2.first, w2.second, s, ku, grid, dim3(256), lnodes, nodes,
                      (const NodeState*)st, front, (const T*)ctx->d_dval.as<T>(),
                      (const int32_t*)ctx->d_physmap.as<int32_t>(), (const T*)ctx->d_lbuf.as<T>(), k0p);
       }
@@ -1101,7 +1138,9 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
         by += (b * p + b * b) * sz;
         fl += b * b * p;
       });
-      launch_timed(tm, HF_K_SYRK, w4.first, w4.second, s, k_syrk<T>, g2, dim3(256), lnodes, nodes,
+      constexpr int S1 = sizeof(T) == 4 ? 1 : 0, S2 = sizeof(T) == 4 ? 2 : 0;
+      launch_timed(tm, HF_K_SYRK, w4.first, w4.second, s,
+                   h16 == 1 ? k_syrk<T, S1> : h16 == 2 ? k_syrk<T, S2> : k_syrk<T>, g2, dim3(256), lnodes, nodes,
                    (const NodeState*)st, front, (const T*)ctx->d_dval.as<T>());
     }
     HF_HIP(hipGetLastError());

@@ -51,6 +51,77 @@ __device__ __forceinline__ void mfma_tile_64(const T (*As)[LD], const T (*Bs)[LD
   }
 }
 
+// FP16 operands for the matrix cores: 16x16x16 products with FP32 accumulation.
+// Lane l supplies A[l % 16][4 (l / 16) + i] and B[4 (l / 16) + i][l % 16], i < 4;
+// the accumulator layout is the one of the FP32 16x16x4 product.
+typedef _Float16 hf_h4 __attribute__((ext_vector_type(4)));
+
+// Power of two s with max|x| * s < 2^14 (FP16's largest finite value is 65504):
+// multiplying by s is exact, so the only rounding of a scaled operand is its cast.
+__device__ __forceinline__ float fp16_scale(float mx) {
+  if (!(mx > 0.f) || !(mx < 3.0e38f)) return 1.f;
+  int e;
+  (void)frexpf(mx, &e);  // mx = m 2^e, 0.5 <= m < 1
+  return ldexpf(1.f, 14 - e);
+}
+
+// acc += (As scaled by sa)^T-staged A (64 x 16) times (Bs scaled by sb) (16 x 64)
+// on the FP16 matrix cores, unscaled into the FP32 accumulator: one stage of 16
+// values of k, staged in LDS as FP32 ([k][row] / [k][col]) like mfma_tile_64.
+// SPLIT = false: every scaled operand is rounded to FP16 (11 significant bits).
+// SPLIT = true: every scaled operand x is carried as the FP16 pair h + l,
+// h = fp16(x), l = fp16(x - h) (about 22 significant bits), and the product as
+// h_a h_b + h_a l_b + l_a h_b, three 16x16x16 products (the l_a l_b term is
+// below the pair's own rounding).
+template <int LD, bool SPLIT>
+__device__ __forceinline__ void mfma_tile_64_h16(const float (*As)[LD], const float (*Bs)[LD], hf_f4 acc[2][2],
+                                                 int lane, int wr, int wc, float sa, float sb) {
+  const int k0 = 4 * (lane >> 4);
+  hf_h4 a[2], b[2], al[2], bl[2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float x = As[k0 + i][wr + bi * 16 + (lane & 15)] * sa;
+      a[bi][i] = (_Float16)x;
+      if constexpr (SPLIT) al[bi][i] = (_Float16)(x - (float)a[bi][i]);
+    }
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float x = Bs[k0 + i][wc + bj * 16 + (lane & 15)] * sb;
+      b[bj][i] = (_Float16)x;
+      if constexpr (SPLIT) bl[bj][i] = (_Float16)(x - (float)b[bj][i]);
+    }
+  const float un = 1.f / (sa * sb);  // a power of two: exact
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      hf_f4 p = {0.f, 0.f, 0.f, 0.f};
+      if constexpr (SPLIT) {
+        p = __builtin_amdgcn_mfma_f32_16x16x16f16(a[bi], bl[bj], p, 0, 0, 0);
+        p = __builtin_amdgcn_mfma_f32_16x16x16f16(al[bi], b[bj], p, 0, 0, 0);
+      }
+      p = __builtin_amdgcn_mfma_f32_16x16x16f16(a[bi], b[bj], p, 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[bi][bj][t] += p[t] * un;
+    }
+}
+
+// Largest |value| of a staged 64 x 16 operand tile, from the four values each of
+// the 256 threads staged: wave maxima through shuffles, then the four waves'
+// maxima through `slot` (4 floats in LDS, read after the next barrier).
+__device__ __forceinline__ void stage_max_post(float v, float* slot, int lane, int wave) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  if (lane == 0) slot[wave] = v;
+}
+__device__ __forceinline__ float stage_max_read(const float* slot) {
+  return fmaxf(fmaxf(slot[0], slot[1]), fmaxf(slot[2], slot[3]));
+}
+
 // Pipelined 64 x 64 tile product over k in [kbeg, kend), 256 threads:
 // acc += A(0:64, k) B(k, 0:64).  Operands are fetched in stages of KB values of
 // k into registers, so that the loads of stage s+1 are in flight while the

@@ -67,17 +67,33 @@ __global__ void k_spmm_k11(int64_t n, const int64_t* __restrict__ ip, const int3
 // r_g = q_g (bbar_{perm g} - sum_e Kbar_e xo_{perm c_e}), xo being the current
 // solution in the caller's variables (row-major n x m, original order) and B the
 // caller's column-major right-hand side block (columns c0.., leading dimension ldb).
+// The sum is carried in double-double: every product is split exactly into a
+// rounded part and its error (fused multiply-add) and every addition into its
+// sum and error (two-sum), the errors being accumulated on the side (compensated
+// dot product of Ogita, Rump and Oishi).  The residual is then accurate to a few
+// units of its own size, not of |Kbar| |xo|, so a correction pass can reduce the
+// forward error below the conditioning limit of an FP64 residual.
 __global__ void k_residual_orig(int64_t n, const int64_t* __restrict__ ip, const int32_t* __restrict__ ix,
                                 const double* __restrict__ kbar, const double* __restrict__ qp,
                                 const int32_t* __restrict__ perm, int m, const double* __restrict__ B,
                                 int64_t ldb, int c0, const double* __restrict__ xo, double* __restrict__ R) {
+#pragma clang fp contract(off)
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t row = e / m;
   const int col = (int)(e - row * m);
   if (row >= n) return;
-  double acc = B[(int64_t)(c0 + col) * ldb + perm[row]];
-  for (int64_t q = ip[row]; q < ip[row + 1]; ++q) acc -= kbar[q] * xo[(int64_t)perm[ix[q]] * m + col];
-  R[e] = qp[row] * acc;
+  double sh = B[(int64_t)(c0 + col) * ldb + perm[row]], sl = 0.0;
+  for (int64_t q = ip[row]; q < ip[row + 1]; ++q) {
+    const double a = kbar[q], x = xo[(int64_t)perm[ix[q]] * m + col];
+    const double p = a * x;
+    const double pe = fma(a, x, -p);  // a x = p + pe exactly
+    const double t = sh - p;          // sh - p = t + te exactly
+    const double z = t - sh;
+    const double te = (sh - (t - z)) - (p + z);
+    sh = t;
+    sl += te - pe;
+  }
+  R[e] = qp[row] * (sh + sl);
 }
 
 __global__ void k_add(int64_t nm, double* __restrict__ x, const double* __restrict__ d) {
@@ -614,30 +630,33 @@ __global__ void k_s22_solve(int M, int k, const double* __restrict__ L, const do
   for (int i = 0; i < M; ++i) X[(int64_t)perm[i] * nc + c] = z[i * zs];
 }
 
-// unpivoted Cholesky G = R^T R of a small SPD matrix (row-major k x k); coef = R^{-1}
-__global__ void k_chol_inv(int k, const double* __restrict__ G, double* __restrict__ Rinv) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double R[MAXM * MAXM];
-  for (int e = 0; e < k * k; ++e) R[e] = 0.0;
+// unpivoted Cholesky G = R^T R of a small SPD matrix (row-major k x k, k <= 64);
+// coef = R^{-1}.  One wave: lane c owns column c of R (row j of R is formed
+// after row j-1, one lane per entry) and then column c of R^{-1} (back
+// substitution); R stays in LDS.
+__global__ void __launch_bounds__(64) k_chol_inv(int k, const double* __restrict__ G, double* __restrict__ Rinv) {
+  __shared__ double R[MAXM * MAXM];
+  const int c = threadIdx.x;
+  for (int e = c; e < k * k; e += 64) R[e] = 0.0;
+  __syncthreads();
   for (int j = 0; j < k; ++j) {
     double s = G[j * k + j];
     for (int t = 0; t < j; ++t) s -= R[t * k + j] * R[t * k + j];
     s = sqrt(fmax(s, 0.0));
-    R[j * k + j] = s;
-    for (int c = j + 1; c < k; ++c) {
+    if (c > j && c < k) {
       double v = G[j * k + c];
       for (int t = 0; t < j; ++t) v -= R[t * k + j] * R[t * k + c];
       R[j * k + c] = s > 0.0 ? v / s : 0.0;
     }
+    if (c == j) R[j * k + j] = s;
+    __syncthreads();
   }
-  // invert the upper-triangular R
-  for (int e = 0; e < k * k; ++e) Rinv[e] = 0.0;
-  for (int c = 0; c < k; ++c) {
-    for (int i = c; i >= 0; --i) {
-      double v = (i == c) ? 1.0 : 0.0;
-      for (int t = i + 1; t <= c; ++t) v -= R[i * k + t] * Rinv[t * k + c];
-      Rinv[i * k + c] = R[i * k + i] > 0.0 ? v / R[i * k + i] : 0.0;
-    }
+  if (c >= k) return;
+  for (int i = k - 1; i > c; --i) Rinv[i * k + c] = 0.0;
+  for (int i = c; i >= 0; --i) {
+    double v = (i == c) ? 1.0 : 0.0;
+    for (int t = i + 1; t <= c; ++t) v -= R[i * k + t] * Rinv[t * k + c];
+    Rinv[i * k + c] = R[i * k + i] > 0.0 ? v / R[i * k + i] : 0.0;
   }
 }
 
@@ -912,7 +931,8 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
     ctx->hist.clear();
     ctx->hist_ptr.assign(1, 0);
     ctx->hist_factor_runs = 0;
-    ctx->factor_prec = ctx->opt.low_precision;
+    // storage precision of the fronts and factor (FP32 also for FP16 products)
+    ctx->factor_prec = ctx->opt.low_precision == HF_PREC_FP64 ? HF_PREC_FP64 : HF_PREC_FP32;
     if (ctx->factor_prec == HF_PREC_FP32) step1<float>(ctx, values, s);
     else step1<double>(ctx, values, s);
     // step 2: the split
@@ -1021,7 +1041,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
         double* src = pass == 0 ? tmp : N;
         double* dst = pass == 0 ? N : tmp;
         gram(ctx, n, k, src, 0, 1, k, src, G, s);
-        k_chol_inv<<<1, 1, 0, s>>>(k, G, Ri);
+        k_chol_inv<<<1, 64, 0, s>>>(k, G, Ri);
         combine(ctx, n, k, k, dst, nullptr, 1, src, 0, Ri, s);
       }
       HF_HIP(hipMemcpyAsync(N, tmp, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));

@@ -45,6 +45,8 @@ HF_ERR_BREAKDOWN = -6
 HF_ERR_OOM = -7
 HF_ERR_HIP = -8
 HF_ERR_NOT_IMPLEMENTED = -9
+HF_PREC_FP16 = 16
+HF_PREC_FP16_PAIR = 17
 HF_PREC_FP32 = 32
 HF_PREC_FP64 = 64
 

@@ -98,6 +98,58 @@ def grid_nested_dissection(shape, leaf_max, dofs_per_point=1):
     return perm, node_ptr, np.array(parents, dtype=np.int32)
 
 
+def staggered_nested_dissection(n, leaf_max):
+    """Geometric nested dissection of the unknowns of a MAC grid of n^3 cells.
+
+    Every unknown is a point of the doubled grid {0 .. 2n}^3: the pressure of
+    cell (i, j, k) sits at (2i+1, 2j+1, 2k+1), the x-velocity on the face
+    between cells (i-1, j, k) and (i, j, k) at (2i, 2j+1, 2k+1), and likewise
+    for y and z.  The Stokes operator couples points at most 2 apart along one
+    axis, so a separator two planes thick splits a box: [lo, hi) is cut along
+    its longest axis (ties x, y, z) into [lo, mid), the separator [mid, mid+2)
+    and [mid+2, hi), mid = lo + ext // 2; recursion stops at <= leaf_max
+    unknowns or an extent below 6.  Postorder (left, right, separator); inside
+    a node, lexicographic order of the points (x fastest).  Unknowns are
+    numbered as in ``mac_stokes`` (x-, y-, z-velocities, then pressures).
+    Returns (perm, node_ptr, parent).
+    """
+    pts = mac_points(n)
+    m = 2 * n + 1
+    key = pts[:, 0] + m * (pts[:, 1] + m * pts[:, 2])
+    nodes, parents = [], []
+
+    def rec(sel, lo, hi):
+        if len(sel) == 0:
+            return None
+        ext = [hi[a] - lo[a] for a in range(3)]
+        if len(sel) <= leaf_max or max(ext) < 6:
+            nodes.append(sel[np.argsort(key[sel], kind="stable")])
+            parents.append(-1)
+            return len(nodes) - 1
+        axis = int(np.argmax(ext))
+        mid = lo[axis] + ext[axis] // 2
+        c = pts[sel, axis]
+        lhi = list(hi); lhi[axis] = mid
+        rlo = list(lo); rlo[axis] = mid + 2
+        c1 = rec(sel[c < mid], list(lo), lhi)
+        c2 = rec(sel[c >= mid + 2], rlo, list(hi))
+        sep = sel[(c >= mid) & (c < mid + 2)]
+        nodes.append(sep[np.argsort(key[sep], kind="stable")])
+        parents.append(-1)
+        me = len(nodes) - 1
+        for ch in (c1, c2):
+            if ch is not None:
+                parents[ch] = me
+        return me
+
+    rec(np.arange(len(pts), dtype=np.int64), [0, 0, 0], [m, m, m])
+    sizes = np.array([len(x) for x in nodes], dtype=np.int64)
+    node_ptr = np.zeros(len(nodes) + 1, dtype=np.int32)
+    node_ptr[1:] = np.cumsum(sizes)
+    perm = np.concatenate(nodes).astype(np.int32)
+    return perm, node_ptr, np.array(parents, dtype=np.int32)
+
+
 # ----------------------------------------------------------------------------
 # matrices
 # ----------------------------------------------------------------------------
@@ -135,6 +187,139 @@ def fv_laplacian(cell_coef):
         np.add.at(diag, b, face)
     rows.append(np.arange(n)); cols.append(np.arange(n)); vals.append(diag)
     return _to_csr(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), n)
+
+
+def _mac_face_ids(n):
+    """Global numbers of the velocity unknowns: for each component d an integer
+    array of shape (n+1 along axis d, n along the others), indexed [x, y, z],
+    holding the unknown's number on interior faces and -1 on the walls (normal
+    velocity 0).  x-, y-, then z-velocities, each numbered x fastest."""
+    ids, off = [], 0
+    for d in range(3):
+        shape = [n, n, n]
+        shape[d] = n + 1
+        a = -np.ones(shape, dtype=np.int64)
+        sl = [slice(None)] * 3
+        sl[d] = slice(1, n)
+        inner = [n, n, n]
+        inner[d] = n - 1
+        cnt = int(np.prod(inner))
+        a[tuple(sl)] = off + np.arange(cnt, dtype=np.int64).reshape(inner, order="F")
+        ids.append(a)
+        off += cnt
+    return ids, off
+
+
+def mac_points(n):
+    """Doubled-grid point (x, y, z) of every unknown of the n^3 MAC grid, in the
+    numbering of ``mac_stokes``."""
+    ids, nv = _mac_face_ids(n)
+    pts = np.zeros((nv + n ** 3, 3), dtype=np.int64)
+    for d in range(3):
+        g = np.indices(ids[d].shape)
+        m = ids[d] >= 0
+        for a in range(3):
+            pts[ids[d][m], a] = 2 * g[a][m] + (0 if a == d else 1)
+    g = np.indices((n, n, n))
+    pid = nv + np.arange(n ** 3).reshape((n, n, n), order="F")
+    for a in range(3):
+        pts[pid.ravel(), a] = (2 * g[a] + 1).ravel()
+    return pts
+
+
+def mac_stokes(mu):
+    """3D MAC-staggered Stokes saddle point [[A, B^T], [B, 0]] on the unit cube.
+
+    mu: per-cell viscosity, shape (n, n, n) indexed [x, y, z]; h = 1/n.
+    A: for every velocity component, -div(mu grad u) with the flux between two
+    neighbouring faces weighted by the viscosity where the flux lives: the cell
+    between two faces along the component's own axis, the edge between two
+    faces across it, with the arithmetic mean of the four cells around the edge.
+    Walls: normal velocity 0 (those faces are not unknowns; the flux to them
+    enters the diagonal), tangential free slip (no flux through the wall).
+    B: the forward-difference divergence of every cell.  Enclosed flow, so the
+    constant pressure spans the kernel (B^T 1 = 0).  The pressure block is zero
+    and its diagonal is stored explicitly.  Unknowns: x-, y-, z-velocities on
+    the interior faces, then the n^3 pressures (all numbered x fastest).
+    Returns (K, number of velocity unknowns).
+    """
+    mu = np.asarray(mu, dtype=np.float64)
+    n = mu.shape[0]
+    h = 1.0 / n
+    ids, nv = _mac_face_ids(n)
+    N = nv + n ** 3
+    rows, cols, vals = [], [], []
+    diag = np.zeros(N)
+
+    def flux(a, b, wgt):
+        # coupling of unknowns a, b (either may be -1: a wall face with value 0)
+        a, b, wgt = a.ravel(), b.ravel(), wgt.ravel()
+        both = (a >= 0) & (b >= 0)
+        rows.extend([a[both], b[both]])
+        cols.extend([b[both], a[both]])
+        vals.extend([-wgt[both], -wgt[both]])
+        for x in (a, b):
+            k = x >= 0
+            np.add.at(diag, x[k], wgt[k])
+
+    for d in range(3):
+        f = ids[d]
+        for e in range(3):
+            if e == d:
+                # faces i and i+1 along d enclose cell i
+                a = np.take(f, np.arange(n), axis=d)
+                b = np.take(f, np.arange(1, n + 1), axis=d)
+                flux(a, b, mu / h ** 2)
+            else:
+                # faces j and j+1 along e meet at an edge; on face plane i (along d)
+                # the edge touches cells i-1, i along d and j, j+1 along e
+                a = np.take(f, np.arange(n - 1), axis=e)
+                b = np.take(f, np.arange(1, n), axis=e)
+                mpad = np.concatenate([np.take(mu, [0], axis=d), mu, np.take(mu, [n - 1], axis=d)], axis=d)
+                lo = np.take(mpad, np.arange(n + 1), axis=d)       # cell i-1 (padded at the walls)
+                hi = np.take(mpad, np.arange(1, n + 2), axis=d)    # cell i
+                m4 = (np.take(lo, np.arange(n - 1), axis=e) + np.take(lo, np.arange(1, n), axis=e)
+                      + np.take(hi, np.arange(n - 1), axis=e) + np.take(hi, np.arange(1, n), axis=e)) / 4.0
+                flux(a, b, m4 / h ** 2)
+    # divergence: B[p(c), u_d(face i+1)] = 1/h, B[p(c), u_d(face i)] = -1/h
+    pid = nv + np.arange(n ** 3, dtype=np.int64).reshape((n, n, n), order="F")
+    for d in range(3):
+        f = ids[d]
+        for side, sgn in ((np.arange(1, n + 1), 1.0), (np.arange(n), -1.0)):
+            u = np.take(f, side, axis=d).ravel()
+            p = pid.ravel()
+            k = u >= 0
+            rows.extend([p[k], u[k]])
+            cols.extend([u[k], p[k]])
+            vals.extend([np.full(k.sum(), sgn / h), np.full(k.sum(), sgn / h)])
+    rows.append(np.arange(N)); cols.append(np.arange(N)); vals.append(diag)
+    K = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N)).tocsr()
+    K.sum_duplicates()
+    K.sort_indices()
+    return K, nv
+
+
+def mac_viscosity_jacobian(n):
+    """values(mu) = v0 + J mu for ``mac_stokes`` (the operator is affine in the
+    per-cell viscosity: A is linear in it, B does not depend on it).  Returns
+    (J, v0): J a sparse (nnz x n^3) matrix, v0 the values at mu = 0 (the
+    divergence entries), both in the entry order of the CSR matrix that
+    ``mac_stokes`` returns (its pattern does not depend on mu).  Built from the
+    operator's response to every unit cell viscosity."""
+    K0, _ = mac_stokes(np.zeros((n, n, n)))
+    rows, cols, vals = [], [], []
+    for c in range(n ** 3):
+        e = np.zeros(n ** 3)
+        e[c] = 1.0
+        Kc, _ = mac_stokes(e.reshape((n, n, n), order="F"))
+        if not (np.array_equal(Kc.indices, K0.indices) and np.array_equal(Kc.indptr, K0.indptr)):
+            raise RuntimeError("pattern depends on the viscosity")
+        dv = Kc.data - K0.data
+        nz = np.nonzero(dv)[0]
+        rows.append(nz); cols.append(np.full(len(nz), c)); vals.append(dv[nz])
+    J = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(K0.nnz, n ** 3))
+    return J, K0.data.copy()
 
 
 def q1_element_stiffness(h, nu):
@@ -328,6 +513,23 @@ def elasticity(ne, seed, lo=0.0, hi=6.0, leaf_max=64, r=32, tau=1e-2, gcr_block=
 
 # The three single-GPU configurations of the benchmark, with the paper-derived
 # settings: tau = 1e-2, block width = RHS count.
+def stokes_mac(n, seed, lo=-2.0, hi=2.0, leaf_max=512, r=32, tau=1e-2, gcr_block=0):
+    """Enclosed 3D MAC Stokes flow on n^3 cells, per-cell viscosity 10^U(lo,hi).
+
+    Kernel: the constant pressure (velocities 0).  Right-hand sides b = K x*
+    with x* ~ N(0,1) orthogonal to the kernel.  The viscosity field is kept in
+    meta["mu"] (indexed [x, y, z]).
+    """
+    rng = np.random.default_rng(seed)
+    mu = 10.0 ** rng.uniform(lo, hi, size=(n, n, n))
+    K, nv = mac_stokes(mu)
+    perm, node_ptr, parent = staggered_nested_dissection(n, leaf_max)
+    kernel = np.zeros((K.shape[0], 1))
+    kernel[nv:, 0] = 1.0
+    return _finish(f"stokes_mac_{n}", K, perm, node_ptr, parent, kernel, r, seed, tau, gcr_block,
+                   {"cells": (n, n, n), "velocities": nv, "leaf_max": leaf_max, "seed": seed, "mu": mu})
+
+
 def config_c1():
     """2D Neumann 32x32, coefficients 10^U(-3,3), tau 1e-2, 1 RHS, kernel 1."""
     return neumann2d(32, 32, seed=1, leaf_max=64, r=1, tau=1e-2, gcr_block=0)
@@ -356,7 +558,15 @@ def config_c3():
     return elasticity(24, seed=3, leaf_max=64, r=32, tau=0.2, gcr_block=0)
 
 
-CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3}
+def config_c4():
+    """Enclosed MAC Stokes flow on 32^3 cells (95,232 face velocities + 32,768
+    pressures), viscosity 10^U(-2,2) per cell, 32 RHS, tau 1e-2 (as the other
+    configurations), kernel = constant pressure.  The differentiation workload:
+    gradients with respect to the per-cell viscosity through the adjoint."""
+    return stokes_mac(32, seed=4, leaf_max=512, r=32, tau=1e-2, gcr_block=0)
+
+
+CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4}
 
 
 def single_node_tree(n):

@@ -82,6 +82,7 @@ def nodes(name):
         "npiv_fp32": [int(x) for x in f32.npiv], "npiv_fp64": [int(x) for x in f64.npiv],
         "M_fp32": int(f32.M), "M_fp64": int(f64.M),
         "decided": [bool(x) for x in dec],
+        "tiegap_fp64": [float(x) if np.isfinite(x) else 1e300 for x in f64.tiegap],
         "worst_error_to_distance": [None if not np.isfinite(x) else float(x) for x in worst],
         "root": {"node": root, "fp32": tail(f32), "fp64": tail(f64)},
         "seconds": time.time() - t0,

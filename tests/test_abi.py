@@ -92,7 +92,7 @@ def test_tree_and_option_errors():
     assert _analyse_code(ip, ix, rev, W.node_ptr, W.parent) == hy.HF_ERR_PATTERN
     o = hy.hf_default_options(tau=-1.0)
     assert _analyse_code(ip, ix, W.perm, W.node_ptr, W.parent, o) == hy.HF_ERR_ARG
-    o = hy.hf_default_options(low_precision=16)
+    o = hy.hf_default_options(low_precision=8)
     assert _analyse_code(ip, ix, W.perm, W.node_ptr, W.parent, o) == hy.HF_ERR_ARG
     o = hy.hf_default_options(gcr_block=65)
     assert _analyse_code(ip, ix, W.perm, W.node_ptr, W.parent, o) == hy.HF_ERR_ARG
@@ -120,3 +120,17 @@ def test_diagnostics_reject_null_context():
     assert lib.hf_pivots(None, None, None, None, None) == hy.HF_ERR_ARG
     assert lib.hf_s22_pivots(None, None) == hy.HF_ERR_ARG
     assert lib.hf_gcr_history(None, ctypes.byref(n), None, None, None) == hy.HF_ERR_ARG
+
+
+def test_node_above_4096_indices_is_refused():
+    """The pivot block of a node lives in the registers of one workgroup (at most
+    4096 rows).  A 65^3 grid has a root separator of 65^2 = 4225 indices:
+    hf_analyse refuses it with HF_ERR_NOT_IMPLEMENTED before any device work,
+    as it does a single-node matrix of more than 4096 indices."""
+    W = w.inclusions3d(65, 0, seed=1, leaf_max=512, r=1)
+    assert int(np.max(np.diff(W.node_ptr))) == 65 * 65
+    assert _analyse_code(W.indptr, W.indices, W.perm, W.node_ptr, W.parent) == hy.HF_ERR_NOT_IMPLEMENTED
+    n = 4097
+    indptr = np.arange(n + 1, dtype=np.int64)
+    indices = np.arange(n, dtype=np.int32)
+    assert _analyse_code(indptr, indices) == hy.HF_ERR_NOT_IMPLEMENTED

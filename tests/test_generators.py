@@ -103,3 +103,39 @@ def test_fig1_block_pattern():
             want.add(tuple(sorted((a, b))))
     assert off == want
     assert {p for p in pairs if p[0] == p[1]} == {(i, i) for i in range(1, 8)}
+
+
+def test_mac_stokes_structure():
+    """MAC Stokes saddle point: sizes (32^3: 95,232 face velocities + 32,768
+    pressures), symmetry, an explicitly stored zero pressure diagonal, the
+    constant pressure as the only kernel direction and the inertia of a
+    saddle point (as many negative eigenvalues as pressures minus one) on a
+    small grid, and a valid nested dissection of the staggered unknowns."""
+    ids, nv = w._mac_face_ids(32)
+    assert nv == 95232
+    K, nv4 = w.mac_stokes(10.0 ** np.random.default_rng(1).uniform(-2, 2, size=(4, 4, 4)))
+    assert nv4 == 3 * 3 * 16 and K.shape[0] == nv4 + 64
+    assert abs(K - K.T).max() == 0.0
+    assert np.all(K.diagonal()[nv4:] == 0.0)
+    assert all(i in K.indices[K.indptr[i]:K.indptr[i + 1]] for i in range(K.shape[0]))
+    one = np.zeros(K.shape[0])
+    one[nv4:] = 1.0
+    assert np.abs(K @ one).max() == 0.0
+    ev = np.linalg.eigvalsh(K.toarray())
+    tol = 1e-10 * np.abs(ev).max()
+    assert (np.abs(ev) <= tol).sum() == 1 and (ev < -tol).sum() == 63 and (ev > tol).sum() == nv4
+    W = w.stokes_mac(8, seed=4, leaf_max=64, r=2)
+    _check_nd(W)
+    assert sorted(W.perm.tolist()) == list(range(W.n))
+
+
+def test_mac_viscosity_jacobian():
+    """values(mu) = v0 + J mu entry by entry (A is linear in the viscosity, the
+    divergence entries +-1/h do not depend on it)."""
+    n = 4
+    mu = 10.0 ** np.random.default_rng(2).uniform(-2, 2, size=(n, n, n))
+    K, nv = w.mac_stokes(mu)
+    J, v0 = w.mac_viscosity_jacobian(n)
+    vals = v0 + J @ mu.reshape(-1, order="F")
+    assert np.allclose(vals, K.data, rtol=1e-14, atol=0)
+    assert set(np.abs(v0[v0 != 0.0]).tolist()) == {float(n)}

@@ -7,10 +7,11 @@ dimension k (exact), S22 (tolerance below), the minimum-norm solution (relative
 K22 - K21 X12 where X12 carries the block-GCR relative residual (1e-15) times
 cond(K11); entries of K22 are O(1) (unit diagonal), so both sides agree to about
 cond(K11) * 1e-15 in absolute terms -- 1e-9 is used (cond(K11) < 1e6 here).
-Solutions: two backward-stable FP64 solvers differ by about cond(K|Im K) * eps;
-with the 1e6 coefficient contrasts here cond reaches 1e7-1e8, so the bar is
-relative error <= max(1e-10, 4 * the oracle's own forward error against the
-exact solution x*) -- 1e-10 wherever the conditioning allows it.
+Solutions: both sides end with a correction pass whose residual is accumulated
+beyond FP64 (double-double on the GPU, long double in the oracle), so both
+converge to the solution of the stored system and agree to far better than the
+cond * eps64 (up to 5e-10 here) that two FP64-residual solvers would differ by;
+the bar is 1e-10.
 """
 import json
 import os
@@ -36,6 +37,9 @@ CASES = {
     "el6_tau09": lambda: w.elasticity(6, seed=8, leaf_max=27, r=3, tau=0.9, gcr_block=0),
     # zero diagonal, 2x2 pivots only; n_enlarge = 3 makes the candidate set start
     # inside a 2x2 block, which the kernel count must not split
+    # MAC Stokes saddle point: zero pressure diagonal, indefinite pivots
+    "stokes8": lambda: w.stokes_mac(8, seed=4, leaf_max=64, r=4),
+    "stokes12_blocks2": lambda: w.stokes_mac(12, seed=5, leaf_max=128, r=3, gcr_block=2),
     "paired_ne3": lambda: _with(w.paired_blocks_workload([10.0 ** -i for i in range(10)] + [5e-11, 3e-11, 1e-16],
                                                          seed=50, n_tiny=3), n_enlarge=3),
     "inc20": lambda: w.inclusions3d(20, 8, seed=5, leaf_max=128, r=4, gcr_block=8),
@@ -90,6 +94,24 @@ def check_node_counts(npiv_gpu, f32, f64, tau, prec, label=""):
     return und
 
 
+def check_hard_part(W, lam, lam_ref, tiegap):
+    """FP64: the postponed indices of every node equal the oracle's, except at
+    nodes where an accepted pivot of the oracle was tied (relative lead at most
+    1e-10, oracle.Step1.tiegap) with a rival computed value: which of two tied
+    candidates is eliminated is fixed by rounding there, and only the count (checked
+    separately) is unique.  Returns whether the whole hard parts are equal."""
+    iperm = np.empty(W.n, dtype=np.int64)
+    iperm[W.perm] = np.arange(W.n)
+    node_of = np.repeat(np.arange(W.n_nodes), np.diff(W.node_ptr))
+    ng, nr = node_of[iperm[lam]], node_of[iperm[lam_ref]]
+    for j in np.union1d(ng, nr):
+        a, b = np.sort(lam[ng == j]), np.sort(lam_ref[nr == j])
+        if not np.array_equal(a, b):
+            assert tiegap[j] <= 1e-10, (int(j), a.tolist(), b.tolist(), float(tiegap[j]))
+            print(f"  node {j}: tied pivots, hard part {a.tolist()} vs oracle {b.tolist()}", flush=True)
+    return np.array_equal(np.sort(lam), np.sort(lam_ref))
+
+
 @pytest.mark.parametrize("prec", [32, 64])
 @pytest.mark.parametrize("name", list(CASES))
 def test_parity(name, prec):
@@ -112,8 +134,7 @@ def test_parity(name, prec):
     lam_ref = np.sort(W.perm[ref.step1.lambda2])
     # which of several candidates tied at rounding level gets postponed is not
     # unique in FP32, so the sets themselves are compared in FP64
-    same = np.array_equal(lam, lam_ref)
-    assert same or prec == 32
+    same = check_hard_part(W, lam, lam_ref, ref.step1.tiegap) if prec == 64 else np.array_equal(lam, lam_ref)
     assert hy.hf_kernel_dim(ctx) == ref.k
     if ref.M and same:
         order = np.argsort(W.perm[ref.step1.lambda2])
@@ -133,12 +154,51 @@ def test_parity(name, prec):
     fwd_oracle = np.linalg.norm(Xref - W.x_star) / np.linalg.norm(W.x_star)
     rel = np.linalg.norm(X - Xref) / np.linalg.norm(Xref)
     print(f"  M={info['M']} k={ref.k} rel_vs_oracle={rel:.2e} oracle_fwd_err={fwd_oracle:.2e}", flush=True)
-    assert rel <= max(1e-10, 4 * fwd_oracle)
+    assert rel <= 1e-10
     assert oracle.backward_error(W.csr(), X, W.b) <= 1e-14
     if ref.k:
         N = hy.hf_kernel_basis(ctx).cpu().numpy()
         assert np.all(_principal_cos(N, ref.kernel) > 1 - 1e-8)
         assert np.allclose(N.T @ N, np.eye(ref.k), atol=1e-12)
+
+
+FP16_CASES = ["c1", "inc20", "n2d_ragged", "el6", "stokes8", "dense_k2"]
+
+
+@pytest.mark.parametrize("name,prec", [(n, 17) for n in FP16_CASES] + [("stokes8", 16)])
+def test_fp16_products(name, prec):
+    """FP32 fronts with the two front updates on the FP16 matrix cores (per-tile
+    power-of-two scaling, FP32 accumulation), operands as FP16 pairs (prec 17)
+    or single FP16 numbers (prec 16; block GCR converges with them only where
+    the contrast is mild, here the Stokes flow).  Checked against the FP64
+    oracle: hard-part size and kernel dimension, and, block GCR winning back the
+    accuracy, the solution to 1e-10 and backward error 1e-14.  The step-1
+    pivots agree with the FP32 path's to the rounding of the products (a check
+    of the operand layout of the 16x16x16 products as well)."""
+    W = CASES[name]()
+    print(f"case {name} fp16 variant {prec} n={W.n}", flush=True)
+    ref = oracle.hybrid_factorize(W.csr(), W.perm, W.node_ptr, W.parent, tau=W.tau, low=np.float64,
+                                  gcr_block=W.gcr_block)
+    Xref = oracle.hybrid_solve(ref, W.b)
+    ctx = _gpu(W, prec)
+    ctx32 = _gpu(W, 32)
+    info = hy.hf_info(ctx)
+    p16, p32 = hy.hf_pivots(ctx)["d"], hy.hf_pivots(ctx32)["d"]
+    both = (p16 != 0) & (p32 != 0)
+    dev = np.abs(p16[both] - p32[both]) / np.abs(p32[both])
+    X = hy.hf_solve(ctx, torch.tensor(W.b, device="cuda")).cpu().numpy().reshape(W.b.shape)
+    rel = np.linalg.norm(X - Xref) / np.linalg.norm(Xref)
+    be = oracle.backward_error(W.csr(), X, W.b)
+    runs, nfac = hy.hf_gcr_history(ctx)
+    runs32, _ = hy.hf_gcr_history(ctx32)
+    print(f"  M={info['M']} (oracle fp64 {ref.M}) k={hy.hf_kernel_dim(ctx)} rel_vs_oracle={rel:.2e} be={be:.2e} "
+          f"pivots vs fp32: median {np.median(dev):.1e} max {dev.max():.1e}; block GCR iterations fp16 "
+          f"{[len(r) - 1 for r in runs]} fp32 {[len(r) - 1 for r in runs32]}", flush=True)
+    assert np.median(dev) <= (1e-5 if prec == hy.HF_PREC_FP16_PAIR else 1e-2)
+    assert info["M"] == ref.M
+    assert hy.hf_kernel_dim(ctx) == ref.k
+    assert rel <= 1e-10
+    assert be <= 1e-14
 
 
 def test_expected_kernel_dims():
@@ -236,7 +296,7 @@ def test_nonsingular_no_postponing():
         assert np.allclose(X, np.linalg.solve(W.csr().toarray(), W.b), rtol=1e-10, atol=1e-12)
 
 
-@pytest.mark.parametrize("cfg", ["c2", "c3"])
+@pytest.mark.parametrize("cfg", ["c2", "c3", "c4"])
 def test_full_size_against_golden(cfg):
     """Bench-size configurations in the benchmark's launch configuration.
 
@@ -261,16 +321,22 @@ def test_full_size_against_golden(cfg):
     dec = np.array(gn["decided"])
     n32, n64 = np.array(gn["npiv_fp32"]), np.array(gn["npiv_fp64"])
     root = gn["root"]["node"]
-    for prec in (64, 32):
+    for prec in (64, 32, hy.HF_PREC_FP16_PAIR):
         ctx = _gpu(W, prec, gcr_block=0)
         info = hy.hf_info(ctx)
         lam, _ = hy.hf_schur(ctx)
         piv = hy.hf_pivots(ctx)
         assert hy.hf_kernel_dim(ctx) == g["k"]
-        if prec == 64:
+        if prec == hy.HF_PREC_FP16_PAIR:
+            # FP16-pair products: reported against both oracle precisions
+            diff = np.nonzero(piv["npiv"] != n64)[0]
+            print(f"  fp16: M gpu {info['M']}, oracle fp64 {g['M']}; nodes differing from the FP64 oracle "
+                  f"(gpu, fp64, fp32): {[(int(j), int(piv['npiv'][j]), int(n64[j]), int(n32[j])) for j in diff]}",
+                  flush=True)
+        elif prec == 64:
             assert np.array_equal(piv["npiv"], n64)
             assert info["M"] == g["M"]
-            assert np.array_equal(np.sort(lam), np.array(g["lambda2_original"]))
+            check_hard_part(W, lam, np.array(g["lambda2_original"]), np.array(gn["tiegap_fp64"]))
         else:
             bad = np.nonzero(dec & (piv["npiv"] != n32))[0]
             assert len(bad) == 0, [(int(j), int(piv["npiv"][j]), int(n32[j])) for j in bad[:8]]
@@ -289,7 +355,7 @@ def test_full_size_against_golden(cfg):
         fwd_oracle = np.linalg.norm(xs - W.x_star[rows]) / np.linalg.norm(W.x_star[rows])
         rel = np.linalg.norm(X[rows] - xs) / np.linalg.norm(xs)
         print(f"  prec {prec}: rel_vs_oracle(sample)={rel:.2e} oracle_fwd_err={fwd_oracle:.2e}", flush=True)
-        assert rel <= max(1e-10, 4 * fwd_oracle)
+        assert rel <= 1e-10
         be = oracle.backward_error(W.csr(), X, W.b)
         print(f"  prec {prec}: M={info['M']} k={hy.hf_kernel_dim(ctx)} be={be:.3e}", flush=True)
         assert be <= 1e-14

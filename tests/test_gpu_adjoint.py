@@ -35,6 +35,7 @@ CASES = {
     "n2d_ragged": lambda: w.neumann2d(67, 45, seed=7, leaf_max=100, r=2, gcr_block=8),
     "el6": lambda: w.elasticity(6, seed=8, leaf_max=27, r=5, gcr_block=8),
     "dense_k2": lambda: w.random_dense_workload(150, seed=10, kernel_dim=2, cond=1e3, r=3),
+    "stokes8": lambda: w.stokes_mac(8, seed=4, leaf_max=64, r=4),
 }
 
 
@@ -167,7 +168,7 @@ def test_adjoint_errors():
     assert float(GV.abs().max()) == 0.0
 
 
-@pytest.mark.parametrize("cfg", ["c2", "c3"])
+@pytest.mark.parametrize("cfg", ["c2", "c3", "c4"])
 def test_adjoint_full_size_properties(cfg):
     """Benchmark-size configurations (launch configuration of the benchmark): the
     backward error of Lam against P G and sum(GV * values) = -trace(Lam^T B)."""
@@ -258,3 +259,48 @@ def test_autograd_elasticity_moduli():
     fd = (loss(Kp.data) - loss(Km.data)) / (2 * h)
     print(f"  elasticity: moduli {gv @ dK:.10e} vs fd {fd:.10e}", flush=True)
     assert abs(gv @ dK - fd) <= 1e-5 * abs(fd)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_autograd_stokes_viscosity(prec):
+    """Enclosed MAC Stokes flow (zero pressure diagonal, saddle point): b is made
+    at a reference viscosity field, the loss 0.5 ||x - x*||^2 is evaluated at
+    another field.  The constant pressure stays the kernel for every viscosity,
+    so the value gradient of hyfact.solve (through torch.autograd) chained to the
+    per-cell viscosity (values = v0 + J mu) matches central differences of the
+    GPU solve (h = 1e-6) and the oracle's gradient (dense adjoint)."""
+    n = 8
+    W = w.stokes_mac(n, seed=4, leaf_max=64, r=4)
+    rng = np.random.default_rng(15)
+    mu = W.meta["mu"] * np.exp(rng.uniform(-0.5, 0.5, size=W.meta["mu"].shape))
+    J, v0 = w.mac_viscosity_jacobian(n)
+    vals = v0 + J @ mu.reshape(-1, order="F")
+    opt = hy.hf_default_options(tau=W.tau, low_precision=prec, gcr_block=0)
+    ctx = hy.hf_analyse(W.indptr, W.indices, W.perm, W.node_ptr, W.parent, opt)
+    dev = "cuda"
+    Xs_t = torch.tensor(W.x_star, device=dev)
+    Bt = torch.tensor(W.b, device=dev)
+
+    def loss(m):
+        v = v0 + J @ m.reshape(-1, order="F")
+        X = hy.solve(ctx, torch.tensor(v, device=dev), Bt)
+        return 0.5 * float(((X - Xs_t) ** 2).sum())
+
+    v = torch.tensor(vals, device=dev, requires_grad=True)
+    X = hy.solve(ctx, v, Bt)
+    (0.5 * ((X - Xs_t) ** 2).sum()).backward()
+    grad = J.T @ v.grad.cpu().numpy()
+    d = mu * rng.uniform(-1, 1, size=mu.shape)
+    h = 1e-6
+    fd = (loss(mu + h * d) - loss(mu - h * d)) / (2 * h)
+    an = float(grad @ d.reshape(-1, order="F"))
+    # the oracle's gradient: dense adjoint on the same matrix
+    import scipy.sparse as sp
+    K = sp.csr_matrix((vals, W.indices, W.indptr), shape=(W.n, W.n))
+    x = oracle.adjoint_solve(K, W.b, W.kernel)
+    lam = oracle.adjoint_solve(K, x - W.x_star, W.kernel)
+    gref = J.T @ oracle.value_gradient(W.indptr, W.indices, x, lam)
+    rg = np.linalg.norm(grad - gref) / np.linalg.norm(gref)
+    print(f"  prec {prec}: viscosity {an:.10e} vs fd {fd:.10e}; rel vs oracle gradient {rg:.2e}", flush=True)
+    assert abs(an - fd) <= 1e-5 * abs(fd)
+    assert rg <= 1e-9

@@ -323,6 +323,34 @@ def test_solve_is_minimum_norm_solution(low):
     assert oracle.backward_error(W.csr(), X, W.b) <= 1e-14
 
 
+def test_solve_reaches_exact_solution_beyond_fp64_conditioning():
+    """With the correction residual in extended precision the solve converges to
+    the minimum-norm solution of the stored system itself, well below the
+    cond * eps64 limit of an FP64 residual (the limit becomes cond * 2^-64 of the
+    long-double residual).  Reference: dense LAPACK solves of Kbar + N N^T (N the
+    orthonormal kernel), refined with residuals of Kbar x + N N^T x in long
+    double (Kbar itself, not the rounded sum Kbar + N N^T).  Without the
+    correction pass the error is larger."""
+    W = w.neumann2d(16, 14, seed=34, lo=-4.0, hi=4.0, leaf_max=20, r=2)
+    K = W.csr().toarray()
+    N = W.kernel
+    A = K + N @ N.T
+    x = np.linalg.solve(A, W.b)
+    Kl, Nl = K.astype(np.longdouble), N.astype(np.longdouble)
+    for _ in range(5):
+        xl = x.astype(np.longdouble)
+        r = np.asarray(W.b.astype(np.longdouble) - Kl @ xl - Nl @ (Nl.T @ xl), dtype=np.float64)
+        x = x + np.linalg.solve(A, r)
+    cond = np.linalg.cond(A)
+    limit64 = cond * 2.0 ** -52
+    assert limit64 > 5e-9
+    for low in (np.float32, np.float64):
+        hf = oracle.hybrid_factorize(W.csr(), W.perm, W.node_ptr, W.parent, tau=W.tau, low=low, gcr_block=0)
+        e1 = np.linalg.norm(oracle.hybrid_solve(hf, W.b) - x) / np.linalg.norm(x)
+        e0 = np.linalg.norm(oracle.hybrid_solve(hf, W.b, refine_steps=0) - x) / np.linalg.norm(x)
+        assert e1 <= 1e-3 * limit64 and e1 < e0
+
+
 def test_solve_nonsingular_and_all_postponed():
     W = w.random_dense_workload(20, seed=33, kernel_dim=0, indefinite=True, cond=1e2, r=2)
     ref = np.linalg.solve(W.csr().toarray(), W.b)
@@ -406,3 +434,38 @@ def test_adjoint_neumann_coefficient_directional_derivative():
     lam2 = oracle.adjoint_solve(K, X - Xs + 3.0 * one, one)
     assert np.allclose(lam2, lam, rtol=0, atol=1e-12 * np.abs(lam).max())
     assert np.abs(one.T @ lam).max() <= 1e-10 * np.abs(lam).max()
+
+
+def test_adjoint_stokes_viscosity_gradient():
+    """Enclosed MAC Stokes flow: the kernel (constant pressure) does not depend on
+    the viscosity, so the gradient of l(mu) = 0.5 ||Kbar(mu)^+ b - x*||^2 (b made
+    at a reference field, evaluated at another) is lam x^T on the pattern chained
+    through d values / d mu.  Pinned by central differences (h = 1e-6) of
+    solutions computed with LAPACK's pinv, along a seeded direction."""
+    n = 3
+    rng = np.random.default_rng(41)
+    mu_ref = 10.0 ** rng.uniform(-2, 2, size=(n, n, n))
+    mu = mu_ref * np.exp(rng.uniform(-0.5, 0.5, size=mu_ref.shape))
+    K0, nv = w.mac_stokes(mu_ref)
+    N = np.zeros((K0.shape[0], 1))
+    N[nv:, 0] = 1.0 / np.sqrt(n ** 3)
+    xs = rng.standard_normal((K0.shape[0], 2))
+    xs -= N @ (N.T @ xs)
+    b = K0 @ xs
+
+    def loss(m):
+        K, _ = w.mac_stokes(m)
+        x = np.linalg.pinv(K.toarray()) @ b
+        return 0.5 * float(np.sum((x - xs) ** 2))
+
+    K, _ = w.mac_stokes(mu)
+    x = oracle.adjoint_solve(K, b, N)
+    lam = oracle.adjoint_solve(K, x - xs, N)
+    gv = oracle.value_gradient(K.indptr, K.indices, x, lam)
+    J, _ = w.mac_viscosity_jacobian(n)
+    grad = J.T @ gv
+    d = mu * rng.uniform(-1, 1, size=mu.shape)
+    h = 1e-6
+    fd = (loss(mu + h * d) - loss(mu - h * d)) / (2 * h)
+    an = float(grad @ d.reshape(-1, order="F"))
+    assert abs(an - fd) <= 1e-6 * abs(fd)
