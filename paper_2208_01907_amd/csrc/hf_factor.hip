@@ -330,18 +330,22 @@ k_panel(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes, 
     WaveRec rw[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) rw[w] = rec[par][w];
+    // the winner's fields are selected in registers along the way (no second
+    // LDS round trip for them)
     int ww = 0;
-    T bv = rw[0].v;
-    int bid = rw[0].id;
+    WaveRec best = rw[0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) {
-      const bool g = (rw[w].v > bv) | ((rw[w].v == bv) & (rw[w].id < bid));
-      bv = g ? rw[w].v : bv;
-      bid = g ? rw[w].id : bid;
+      const bool g = (rw[w].v > best.v) | ((rw[w].v == best.v) & (rw[w].id < best.id));
+      best.v = g ? rw[w].v : best.v;
+      best.d = g ? rw[w].d : best.d;
+      best.id = g ? rw[w].id : best.id;
+      best.k = g ? rw[w].k : best.k;
+      best.ph = g ? rw[w].ph : best.ph;
       ww = g ? w : ww;
     }
     ww = __builtin_amdgcn_readfirstlane(ww);
-    const WaveRec best = rec[par][ww];
+    const int bid = best.id;
     const Row rowK = *reinterpret_cast<const Row*>(pubK[par][ww]);  // panel row of the pivot row
     const int qk = min(max(best.k, qi), P - 1);
     const T d = best.d;

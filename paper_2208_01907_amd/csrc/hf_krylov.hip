@@ -236,28 +236,50 @@ k_colsq_partial(int64_t n, int m, const double* __restrict__ R, double* __restri
     partial[(int64_t)blockIdx.x * m + c] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
 }
 
-__global__ void k_colsq_reduce(int m, const double* __restrict__ partial, double* __restrict__ out) {
-  const int c = threadIdx.x;
-  if (c >= m) return;
+// Fixed-order sums of GRAM_WG partials (bitwise reproducible): 1024 threads per
+// 64 consecutive entries; wave ph adds partials ph, ph + 16, ph + 32, ... in
+// order, then the 16 wave sums are added in order.
+constexpr int RED_WAVES = 16;
+__device__ __forceinline__ double fixed_order_sum(const double* __restrict__ P, int64_t stride, bool ok) {
+  __shared__ double red[RED_WAVES][64];
+  const int lane = threadIdx.x & 63, ph = threadIdx.x >> 6;
   double s = 0.0;
-  for (int w = 0; w < GRAM_WG; ++w) s += partial[(int64_t)w * m + c];
-  out[c] = s;
+  if (ok)
+    for (int w = ph; w < GRAM_WG; w += RED_WAVES) s += P[(int64_t)w * stride];
+  red[ph][lane] = s;
+  __syncthreads();
+  double t = 0.0;
+  if (ph == 0)
+    for (int q = 0; q < RED_WAVES; ++q) t += red[q][lane];
+  return t;
 }
 
-__global__ void k_gram_reduce(int nblk, int ab, const double* __restrict__ partial,
-                              double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nblk * ab) return;
-  const int blk = e / ab, pidx = e - (e / ab) * ab;
-  double s = 0.0;
-  const double* P = partial + (int64_t)blk * GRAM_WG * ab + pidx;
-  for (int w = 0; w < GRAM_WG; ++w) s += P[(int64_t)w * ab];
-  out[e] = s;
+__global__ void __launch_bounds__(1024) k_colsq_reduce(int m, const double* __restrict__ partial,
+                                                       double* __restrict__ out) {
+  const int c = threadIdx.x & 63;
+  const double s = fixed_order_sum(partial + c, m, c < m);
+  if ((threadIdx.x >> 6) == 0 && c < m) out[c] = s;
+}
+
+__global__ void __launch_bounds__(1024) k_gram_reduce(int nblk, int ab, const double* __restrict__ partial,
+                                                      double* __restrict__ out) {
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  const bool ok = e < nblk * ab;
+  const int blk = ok ? e / ab : 0, pidx = ok ? e - blk * ab : 0;
+  const double s = fixed_order_sum(partial + (int64_t)blk * GRAM_WG * ab + pidx, ab, ok);
+  if ((threadIdx.x >> 6) == 0 && ok) out[e] = s;
 }
 
 // ---------------------------------------------------------------------------
 // small dense FP64 kernels (one workgroup per matrix)
 // ---------------------------------------------------------------------------
+
+// value of lane t (wave-uniform t) in every lane, through scalar registers
+__device__ __forceinline__ double lane_bcast(double v, int t) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), t);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), t);
+  return __hiloint2double(hi, lo);
+}
 
 // Pivoted Cholesky of an SPSD m x m Gram matrix (row-major), deflating pivots
 // <= rel * max diag.  Output: Lc (m x m row-major, lower), piv[m], rank.
@@ -272,6 +294,7 @@ k_chol_piv(int m, const double* __restrict__ Mm, int64_t sM, double* __restrict_
   int32_t* P = piv + (int64_t)blk * m;
   __shared__ double A[MAXM * MAXM];
   __shared__ double L[MAXM * MAXM];
+  __shared__ double Lt[MAXM * MAXM];  // column i of L for the trailing update, lanes consecutive
   __shared__ int Ps[MAXM];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int e = tid; e < m * m; e += 256) { A[e] = G[e]; L[e] = 0.0; }
@@ -307,11 +330,15 @@ k_chol_piv(int m, const double* __restrict__ Mm, int64_t sM, double* __restrict_
       __syncthreads();
     }
     const double lii = sqrt(A[i * m + i]);
-    for (int r = i + tid; r < m; r += 256) L[r * m + i] = (r == i) ? lii : A[r * m + i] / lii;
+    for (int r = i + tid; r < m; r += 256) {
+      const double x = (r == i) ? lii : A[r * m + i] / lii;
+      L[r * m + i] = x;
+      Lt[i * m + r] = x;
+    }
     __syncthreads();
     const int c = i + 1 + lane;
     if (c < m)
-      for (int r = i + 1 + w; r < m; r += 4) A[r * m + c] -= L[r * m + i] * L[c * m + i];
+      for (int r = i + 1 + w; r < m; r += 4) A[r * m + c] -= L[r * m + i] * Lt[i * m + c];
     __syncthreads();
   }
   for (int e = tid; e < m * m; e += 256) Lg[e] = L[e];
@@ -320,36 +347,49 @@ k_chol_piv(int m, const double* __restrict__ Mm, int64_t sM, double* __restrict_
 }
 
 // out = sign * M^{-1} R for every batch item (R: m x nc row-major), deflated
-// directions get 0.  One thread per right-hand-side column.
-__global__ void __launch_bounds__(64)
+// directions get 0.  One workgroup per batch item; each wave takes columns of R
+// in turn and holds one column in its lanes (lane i: row i), so the two
+// triangular sweeps are lane-parallel: after row t is final it is broadcast and
+// every later row subtracts its multiple (for row i the forward subtractions
+// run in the same order t = 0 .. i-1 as a row-by-row substitution).
+__global__ void __launch_bounds__(1024)
 k_chol_solve(int m, int nc, const double* __restrict__ Lc, const int32_t* __restrict__ piv,
              const int32_t* __restrict__ rank, const double* __restrict__ R,
              int64_t sR, double* __restrict__ out, int64_t sO, double sign) {
   const int blk = blockIdx.x;
-  const int c = threadIdx.x;
   const double* Lg = Lc + (int64_t)blk * m * m;
   const int32_t* P = piv + (int64_t)blk * m;
-  __shared__ double L[MAXM * MAXM];
-  __shared__ double z[MAXM][MAXM + 1];
+  __shared__ double L[MAXM * MAXM];   // row-major, as in global memory
+  __shared__ double Lt[MAXM * MAXM];  // its transpose: lanes read consecutive words
   __shared__ int Ps[MAXM];
-  for (int e = threadIdx.x; e < m * m; e += blockDim.x) L[e] = Lg[e];
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const double x = Lg[e];
+    L[e] = x;
+    Lt[(e % m) * m + e / m] = x;
+  }
   for (int e = threadIdx.x; e < m; e += blockDim.x) Ps[e] = P[e];
   __syncthreads();
-  if (c >= nc) return;
   const int rk = rank[blk];
   const double* Rb = R + (int64_t)blk * sR;
   double* O = out + (int64_t)blk * sO;
-  for (int i = 0; i < rk; ++i) {
-    double v = Rb[(int64_t)Ps[i] * nc + c];
-    for (int t = 0; t < i; ++t) v -= L[i * m + t] * z[t][c];
-    z[i][c] = v / L[i * m + i];
+  const int i = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const double lii = (i < rk) ? L[i * m + i] : 1.0;
+  for (int c = threadIdx.x >> 6; c < nc; c += nw) {
+    double z = (i < rk) ? Rb[(int64_t)Ps[i] * nc + c] : 0.0;
+    // forward: L z = R
+    for (int t = 0; t < rk; ++t) {
+      if (i == t) z = z / lii;
+      const double zt = lane_bcast(z, t);
+      if (i > t && i < rk) z -= Lt[t * m + i] * zt;
+    }
+    // backward: L^T z = z
+    for (int t = rk - 1; t >= 0; --t) {
+      if (i == t) z = z / lii;
+      const double zt = lane_bcast(z, t);
+      if (i < t) z -= L[t * m + i] * zt;
+    }
+    if (i < m) O[(int64_t)Ps[i] * nc + c] = (i < rk) ? sign * z : 0.0;
   }
-  for (int i = rk - 1; i >= 0; --i) {
-    double v = z[i][c];
-    for (int t = i + 1; t < rk; ++t) v -= L[t * m + i] * z[t][c];
-    z[i][c] = v / L[i * m + i];
-  }
-  for (int i = 0; i < m; ++i) O[(int64_t)Ps[i] * nc + c] = (i < rk) ? sign * z[i][c] : 0.0;
 }
 
 // out[row, col] = (base ? base[row, col] : 0) + sum_t sum_k V_t[row, k] coef_t[k, col]
@@ -630,6 +670,61 @@ __global__ void k_s22_solve(int M, int k, const double* __restrict__ L, const do
   for (int i = 0; i < M; ++i) X[(int64_t)perm[i] * nc + c] = z[i * zs];
 }
 
+// The same for M <= 64: one workgroup, each wave takes columns in turn and holds
+// one column in its lanes (lane i: position i of the LDL^T), L in LDS.  The
+// forward substitution subtracts in the same order as row-by-row substitution;
+// the backward one broadcasts each final position and subtracts its multiple
+// from the earlier ones (last position first).  The 1x1 / 2x2 pivot solves are
+// those of k_s22_solve, lane-parallel (the partner value of a 2x2 block comes
+// from the neighbouring lane).
+__global__ void __launch_bounds__(1024)
+k_s22_solve_w(int M, int k, const double* __restrict__ L, const double* __restrict__ D,
+              const int32_t* __restrict__ perm, const int32_t* __restrict__ bsize, int nc,
+              const double* __restrict__ Y, double* __restrict__ X) {
+  __shared__ double Ls[MAXM * MAXM];   // column-major, as in global memory
+  __shared__ double Lst[MAXM * MAXM];  // its transpose: lanes read consecutive words
+  for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
+    const double x = L[e];
+    Ls[e] = x;
+    Lst[(e % M) * M + e / M] = x;
+  }
+  __syncthreads();
+  const int i = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int r = M - k;
+  // this lane's pivot: 1x1, first or second half of a 2x2 block, or a kernel pivot
+  int kind = 0;  // 0: kernel / outside, 1: 1x1, 2: first of a 2x2, 3: second of a 2x2
+  double e11 = 0.0, e12 = 0.0, e22 = 0.0;
+  if (i < r) {
+    if (bsize[i] == 2 && i + 1 < r) kind = 2;
+    else if (i > 0 && bsize[i - 1] == 2 && i < r) kind = 3;
+    else kind = 1;
+    const int b0 = kind == 3 ? i - 1 : i;
+    e11 = D[(int64_t)b0 * M + b0];
+    if (kind >= 2) {
+      e12 = D[(int64_t)b0 * M + b0 + 1];
+      e22 = D[(int64_t)(b0 + 1) * M + b0 + 1];
+    }
+  }
+  for (int c = threadIdx.x >> 6; c < nc; c += nw) {
+    double z = (i < M) ? Y[(int64_t)perm[i] * nc + c] : 0.0;
+    for (int t = 0; t < M; ++t) {
+      const double zt = lane_bcast(z, t);
+      if (i > t && i < M) z -= Ls[(int64_t)t * M + i] * zt;
+    }
+    // D: 1x1 and 2x2 pivots, kernel pivots set to 0
+    const double up = __shfl_down(z, 1, 64), dn = __shfl_up(z, 1, 64);
+    if (kind == 1) z = z / e11;
+    else if (kind == 2) z = (z * e22 - up * e12) / (e11 * e22 - e12 * e12);
+    else if (kind == 3) z = (z * e11 - dn * e12) / (e11 * e22 - e12 * e12);
+    else z = 0.0;
+    for (int t = M - 1; t >= 0; --t) {
+      const double zt = lane_bcast(z, t);
+      if (i < t) z -= Lst[(int64_t)t * M + i] * zt;
+    }
+    if (i < M) X[(int64_t)perm[i] * nc + c] = z;
+  }
+}
+
 // unpivoted Cholesky G = R^T R of a small SPD matrix (row-major k x k, k <= 64);
 // coef = R^{-1}.  One wave: lane c owns column c of R (row j of R is formed
 // after row j-1, one lane per entry) and then column c of R^{-1} (back
@@ -795,7 +890,7 @@ static void gram(hf_ctx* ctx, int64_t n, int a, const double* A, int64_t sA, int
   launch_timed(ctx->timer, HF_K_GRAM, by, fl, s, k_gram_partial, grid, dim3(256), n, a, A, sA, b, B,
                w.partial.as<double>());
   timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, [&] {
-    k_gram_reduce<<<cdiv((int64_t)nA * a * b, 256), 256, 0, s>>>(nA, a * b, w.partial.as<double>(), C);
+    k_gram_reduce<<<cdiv((int64_t)nA * a * b, 64), 1024, 0, s>>>(nA, a * b, w.partial.as<double>(), C);
   });
 }
 
@@ -847,7 +942,7 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
   auto colsq = [&](const double* Rd, double* out) {
     launch_timed(ctx->timer, HF_K_GRAM, (double)n * m * 8.0, 2.0 * n * m, s, k_colsq_partial, dim3(GRAM_WG),
                  dim3(256), n, m, Rd, w.partial.as<double>());
-    launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_colsq_reduce, dim3(1), dim3(64), m,
+    launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_colsq_reduce, dim3(1), dim3(1024), m,
                  (const double*)w.partial.as<double>(), nrm);
     HF_HIP(hipMemcpyAsync(out, nrm, sizeof(double) * m, hipMemcpyDeviceToHost, s));
     HF_HIP(hipStreamSynchronize(s));
@@ -889,7 +984,7 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
     double* Qn = Qv + it * sv;
     // alpha = M_n^{-1} Qv_n^T R
     gram(ctx, n, m, Qn, 0, 1, m, R, G, s);
-    k_chol_solve<<<1, 64, 0, s>>>(m, m, Lc + (int64_t)it * m * m, piv + (int64_t)it * m, rank + it, G, 0,
+    k_chol_solve<<<1, 1024, 0, s>>>(m, m, Lc + (int64_t)it * m * m, piv + (int64_t)it * m, rank + it, G, 0,
                                   coef, 0, 1.0);
     combine(ctx, n, m, m, X, X, 1, Pn, 0, coef, s);
     k_neg<<<cdiv((int64_t)m * m, 256), 256, 0, s>>>((int64_t)m * m, coef);
@@ -906,7 +1001,7 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
     const int nb = it + 1;
     gram(ctx, n, m, Qv, sv, nb, m, Qn1, G, s);
     // the nb coefficient solves at once, one workgroup each
-    k_chol_solve<<<nb, 64, 0, s>>>(m, m, Lc, piv, rank, G, (int64_t)m * m, coef, (int64_t)m * m, -1.0);
+    k_chol_solve<<<nb, 1024, 0, s>>>(m, m, Lc, piv, rank, G, (int64_t)m * m, coef, (int64_t)m * m, -1.0);
     combine(ctx, n, m, m, Pn1, Pn1, nb, P, sv, coef, s);
     combine(ctx, n, m, m, Qn1, Qn1, nb, Qv, sv, coef, s);
     gram(ctx, n, m, Qn1, 0, 1, m, Qn1, G, s);
@@ -1081,7 +1176,10 @@ static int solve_core(hf_ctx* ctx, int m, const double* b, double* x, double* b1
     const int64_t MM = (int64_t)M * M;
     int32_t* sperm = ctx->d_s22perm.as<int32_t>();
     const size_t s22_lds = M <= MAXM ? (size_t)(M * M + M * 64) * sizeof(double) : 0;
-    k_s22_solve<<<1, 64, s22_lds, s>>>(M, k, S + MM, S + 2 * MM, sperm, sperm + M, m, y2, x2, wk);
+    if (M <= MAXM)
+      k_s22_solve_w<<<1, 1024, 0, s>>>(M, k, S + MM, S + 2 * MM, sperm, sperm + M, m, y2, x2);
+    else
+      k_s22_solve<<<1, 64, s22_lds, s>>>(M, k, S + MM, S + 2 * MM, sperm, sperm + M, m, y2, x2, wk);
     // x1 = y1 - X12 x2 (x2 rows padded per block)
     const int mb = ctx->mb;
     ctx->d_x2pad.alloc((size_t)ctx->nblk * mb * m * sizeof(double));
