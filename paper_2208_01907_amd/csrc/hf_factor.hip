@@ -737,6 +737,109 @@ k_syrk(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
       }
 }
 
+// The same product for large borders: 128 x 128 tiles of C per workgroup (each
+// wave 64 x 64, 4 x 4 blocks of 16 x 16), half the operand traffic per flop of
+// the 64 x 64 tiles.  The operands of stage s+1 (32 values of k) are fetched
+// into registers while the matrix cores work on stage s, and the LDS stages
+// alternate between two buffers (one barrier per stage).  Every element of C
+// accumulates the same products in the same order as in k_syrk (four values of
+// k per product, in order), so the results are identical.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_syrk128(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
+          const NodeState* __restrict__ st, T* __restrict__ front, const T* __restrict__ dval) {
+  constexpr int KS = 32, LDT = 128 + 4, NQ = KS * 128 / 256;
+  const int j = lnodes[blockIdx.y];
+  const NodeInfo ni = nodes[j];
+  const int r0 = ni.p, K = st[j].npiv, nr = ni.b;
+  if (nr <= 0 || K <= 0) return;
+  const int t = blockIdx.x;
+  int ti = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int nt = (nr + 127) / 128;
+  if (ti >= nt) return;
+  const int64_t f = ni.f;
+  T* F = front + ni.front_off;
+  const T* A = F + r0;  // A(r, k) = A[k*f + r]
+  const T* Dk = dval + ni.start;
+  T* C = F + (int64_t)r0 * f + r0;
+  __shared__ T As[2][KS][LDT];
+  __shared__ T Bs[2][KS][LDT];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+  const int rowA = ti * 128, rowB = tj * 128;
+  typename Mfma<T>::V acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = typename Mfma<T>::V{0, 0, 0, 0};
+  // thread e = tid + 256 q stages row e & 127 of k-value kk + (e >> 7).  The
+  // loads are unconditional (indices clamped into the front) so that they all
+  // stay in flight; out-of-range values are zeroed when they are staged.
+  T ra[NQ], rb[NQ], rd[NQ];
+  int kfet = 0;
+  auto fetch = [&](int kk) {
+    kfet = kk;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + q * 256;
+      const int rr = e & 127, kc = min(kk + (e >> 7), K - 1);
+      ra[q] = A[(int64_t)kc * f + min(rowA + rr, nr - 1)];
+      rb[q] = A[(int64_t)kc * f + min(rowB + rr, nr - 1)];
+      rd[q] = Dk[kc];
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + q * 256;
+      const int rr = e & 127;
+      const bool kin = kfet + (e >> 7) < K;
+      const T va = (kin && rowA + rr < nr) ? ra[q] : (T)0;
+      const T vb = (kin && rowB + rr < nr) ? rb[q] * rd[q] : (T)0;
+      As[buf][e >> 7][rr] = vb;  // transposed product: rows of C on the lanes
+      Bs[buf][e >> 7][rr] = va;
+    }
+  };
+  fetch(0);
+  stage(0);
+  __syncthreads();
+  int buf = 0;
+  for (int kk = 0; kk < K; kk += KS) {
+    const bool more = kk + KS < K;
+    if (more) fetch(kk + KS);
+#pragma unroll
+    for (int k4 = 0; k4 < KS; k4 += 4) {
+      const int k = k4 + (lane >> 4);
+      T a[4], b[4];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) a[bi] = As[buf][k][wr + bi * 16 + (lane & 15)];
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) b[bj] = Bs[buf][k][wc + bj * 16 + (lane & 15)];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Mfma<T>::mma(a[bi], b[bj], acc[bi][bj]);
+    }
+    if (more) stage(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = rowB + wr + bi * 16 + Mfma<T>::row(lane, u);
+        const int r = rowA + wc + bj * 16 + (lane & 15);
+        if (r < nr && c < nr && c <= r) C[(int64_t)c * f + r] -= acc[bi][bj][u];
+      }
+}
+
 // ---------------------------------------------------------------------------
 // F3: L21 = F21 L11^{-T} D^{-1}, one workgroup per 64-row strip of F21
 // ---------------------------------------------------------------------------
@@ -1135,7 +1238,9 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
                                 ctx->d_linv2.as<T>(), j0);
         }
       });
-      const int nt = (maxb + 63) / 64;
+      // borders of 512 rows and more: 128 x 128 tiles (FP32 / FP64 products)
+      const bool big = maxb >= 512 && h16 == 0 && sizeof(T) == 4;
+      const int nt = big ? (maxb + 127) / 128 : (maxb + 63) / 64;
       dim3 g2((unsigned)(nt * (nt + 1) / 2), (unsigned)nl);
       auto w4 = level_sum([&](const NodeInfo& ni, double& by, double& fl) {
         const double b = ni.b, p = ni.p;
@@ -1144,7 +1249,8 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
       });
       constexpr int S1 = sizeof(T) == 4 ? 1 : 0, S2 = sizeof(T) == 4 ? 2 : 0;
       launch_timed(tm, HF_K_SYRK, w4.first, w4.second, s,
-                   h16 == 1 ? k_syrk<T, S1> : h16 == 2 ? k_syrk<T, S2> : k_syrk<T>, g2, dim3(256), lnodes, nodes,
+                   big ? k_syrk128<T> : h16 == 1 ? k_syrk<T, S1> : h16 == 2 ? k_syrk<T, S2> : k_syrk<T>, g2,
+                   dim3(256), lnodes, nodes,
                    (const NodeState*)st, front, (const T*)ctx->d_dval.as<T>());
     }
     HF_HIP(hipGetLastError());
