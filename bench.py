@@ -44,7 +44,8 @@ KERNEL_NAME = {"panel": "k_panel", "permute_l11": "k_l11_gather + k_l11_back", "
                "gather_border": "k_gather_border", "trsm": "k_trsm", "syrk": "k_syrk (contribution)",
                "extend_add": "k_extend_add", "fwd_diag": "k_fwd_diag", "fwd_update": "k_fwd_upd",
                "bwd_border": "k_bwd_border_part", "bwd_diag": "k_bwd_diag", "bwd_update": "k_bwd_upd",
-               "spmm": "k_spmm_k11", "gram": "k_gram_partial", "combine": "k_combine"}
+               "spmm": "k_spmm_k11", "gram": "k_gram_partial", "combine": "k_combine",
+               "fwd_front": "k_fwd_front", "bwd_front": "k_bwd_front"}
 
 
 def parse():

@@ -273,7 +273,9 @@ enum {
   HF_K_COMBINE = 15,      /* k_combine: FP64 block updates X += P C of block GCR */
   HF_K_OTHER = 16,        /* everything else */
   HF_K_VALUE_GRAD = 17,   /* k_value_grad: value gradient of hf_adjoint */
-  HF_K_NCLASS = 18
+  HF_K_FWD_FRONT = 18,    /* k_fwd_front: whole forward step of a small front (one workgroup) */
+  HF_K_BWD_FRONT = 19,    /* k_bwd_front: whole backward step of a small front (one workgroup) */
+  HF_K_NCLASS = 20
 };
 
 typedef struct hf_kstat_t {

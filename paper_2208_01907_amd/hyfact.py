@@ -58,7 +58,7 @@ EXPORTS = ["hf_default_options", "hf_analyse", "hf_factorize", "hf_solve", "hf_k
 # kernel classes of hf_timing_get
 KCLASS = ["panel", "permute_l11", "f11_update", "gather_border", "trsm", "syrk", "extend_add", "fwd_diag",
           "fwd_update", "bwd_border", "bwd_diag", "bwd_update", "solve_gather", "spmm", "gram", "combine",
-          "other", "value_grad"]
+          "other", "value_grad", "fwd_front", "bwd_front"]
 
 
 class HFError(RuntimeError):
