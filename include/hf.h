@@ -82,6 +82,11 @@ typedef struct hf_options {
   double refine_tol;        /* block-GCR tolerance inside a correction pass
                                (default 1e-3): a correction only has to be
                                accurate relative to the residual it corrects */
+  int32_t sweep_front_min;  /* FP32 preconditioner sweeps: a tree level with at
+                               least this many fronts, each of at most 512
+                               pivots, runs every front in one workgroup
+                               (default 256; 0 = never).  Same arithmetic
+                               either way up to the order of the sums. */
 } hf_options;
 
 typedef struct hf_info_t {
@@ -196,6 +201,21 @@ int hf_solve(hf_ctx* ctx, int32_t r, const double* B_dev, int64_t ldb, double* X
  */
 int hf_adjoint(hf_ctx* ctx, int32_t r, const double* X_dev, int64_t ldx, const double* G_dev, int64_t ldg,
                double* Lam_dev, int64_t ldl, double* GV_dev, void* stream);
+
+/*
+ * The preconditioner Q^{-1} of Sec. 3.2 on the current factors: forward and
+ * backward substitution with the low-precision LDL^T of K11 (step 1 of
+ * Algorithm 1), the operator block GCR applies in every iteration.  Works in
+ * the library's own variables, not the caller's: rows in elimination order
+ * (position i is original index perm[i]) of the symmetrically scaled matrix.
+ *   r      number of columns, 0 <= r <= 64
+ *   R_dev  float64, row-major n x r (leading dimension r); the rows of the hard
+ *          part Lambda_2 are not read
+ *   Y_dev  float64, row-major n x r, output (leading dimension r); zero on the
+ *          rows of the hard part; must not alias R_dev
+ * Errors: HF_ERR_STATE (not factorized), HF_ERR_ARG, HF_ERR_OOM, HF_ERR_HIP.
+ */
+int hf_precond(hf_ctx* ctx, int32_t r, const double* R_dev, double* Y_dev, void* stream);
 
 /* Kernel dimension k found by the rank-revealing LDL^T of S22 (Sec. 2.2, Algorithm 1 step 5).
  * Errors: HF_ERR_ARG, HF_ERR_STATE. */

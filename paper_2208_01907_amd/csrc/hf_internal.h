@@ -264,4 +264,5 @@ int kernel_basis_impl(const hf_ctx* ctx, double* N, int64_t ldn, hipStream_t s);
 int adjoint_impl(hf_ctx* ctx, int32_t r, const double* X, int64_t ldx, const double* G, int64_t ldg,
                  double* Lam, int64_t ldl, double* GV, hipStream_t s);
 int scaling_impl(const hf_ctx* ctx, double* q, hipStream_t s);
+int precond_impl(hf_ctx* ctx, int32_t r, const double* R, double* Y, hipStream_t s);
 }  // namespace hf

@@ -1262,6 +1262,28 @@ int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, 
   return HF_OK;
 }
 
+// Q^{-1} of Sec. 3.2 applied to r <= 64 columns in the scaled, permuted
+// variables (row-major n x r, elimination order); the hard part's rows of R are
+// not read and those of Y are zero.
+int precond_impl(hf_ctx* ctx, int32_t r, const double* R, double* Y, hipStream_t s) {
+  if (ctx->state < 2) return HF_ERR_STATE;
+  const int64_t n = ctx->n;
+  if (r < 0 || r > MAXM || (r > 0 && n > 0 && (!R || !Y || R == Y))) return HF_ERR_ARG;
+  if (r == 0 || n == 0) return HF_OK;
+  try {
+    precond(ctx, r, R, Y, s);
+    HF_HIP(hipStreamSynchronize(s));
+    ctx->timer.flush();
+  } catch (const HipError&) {
+    return HF_ERR_HIP;
+  } catch (const Status& st) {
+    return st.code;
+  } catch (const std::bad_alloc&) {
+    return HF_ERR_OOM;
+  }
+  return HF_OK;
+}
+
 // Adjoint of the solve.  Not a step of the paper's method: the derivative of the
 // solution map of Algorithm 2, taken with one more solve on the same factors.
 // For Kbar x = b with ker Kbar fixed and b in its range, x = Kbar^+ b changes by

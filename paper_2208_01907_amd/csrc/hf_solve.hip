@@ -687,54 +687,73 @@ k_bwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
 }
 
 // ---------------------------------------------------------------------------
-// whole fronts in one workgroup (FP32, at most 16 right-hand sides)
+// whole fronts in one workgroup (FP32, at most 64 right-hand sides)
 // ---------------------------------------------------------------------------
-// On the lowest levels of the tree a level has many fronts (at least one per
-// CU) of at most one sweep step (p <= TB); a workgroup takes a whole front
+// On the lowest levels of the tree a level has many fronts (by default at least
+// one per CU) of at most one sweep step (p <= TB); a workgroup takes a whole front
 // through its forward or its backward step, one launch per level, with the
 // right-hand-side block of the pivot rows in LDS.  The step uses the TB x TB
 // inverse of the front's L11 (the same inverse as the level-wide launches):
 //   forward : z = Linv w (pivot rows), w_border -= L21 z;
 //   backward: t = z / d - L21^T x_border, x = Linv^T t.
-// Products run on the matrix cores in 16-row tiles; each output is summed in a
-// fixed order (one wave, or per-wave partial sums added in wave order).
+// Products run on the matrix cores in 16-row tiles of NCB 16-column blocks
+// (m <= 16 NCB); each output is summed in a fixed order (one wave, or per-wave
+// partial sums added in wave order).
 constexpr int FRONT_NT = 512;           // threads of a whole-front workgroup
 constexpr int FRONT_NW = FRONT_NT / 64;
-constexpr int FRONT_LDW = 20;           // LDS row: 16 right-hand sides + 4 (bank spread)
-constexpr int FRONT_MIN_FRONTS = 256;   // levels with fewer fronts keep the level-wide launches
-constexpr int FRONT_BWD_ROWS = 1024;    // largest b + p of a backward whole-front launch
+constexpr int FRONT_LDS = 160 * 1024;   // LDS of a workgroup (bytes)
 
-// acc[q] += sum_{kb <= k < ke} A(k, 16 q + i) B(k, j) over one wave.  A round
-// covers 16 values of k in four matrix-core steps: lane (i, g) = (lane % 16,
-// lane / 16) supplies A and B at k = k0 + 4 g + s in step s, so that the four
-// values of A a lane needs in a round are consecutive in k.  la(kq, r) returns
-// A(kq .. kq + 3, r) with zeros from ke on; fb(k, j) reads B from LDS.  Batches
-// of NR rounds are double-buffered: the loads of the next batch are in flight
-// while the current one is multiplied.  kb is a multiple of 4.
-template <int NA, int NR, class LA, class FB>
-__device__ __forceinline__ void wave_product(int kb, int ke, LA&& la, FB&& fb, hf_f4 (&acc)[NA]) {
+// LDS row of 16 NCB right-hand sides, padded by 4 floats so that the four lane
+// groups of a matrix-core operand read (rows 4 apart) hit different banks
+template <int NCB>
+struct FrontRow {
+  static constexpr int W = 16 * NCB, LD = W + 4;
+};
+// rows of the backward step's LDS block: NCB = 1 keeps x_border and t side by
+// side (b + p rows), wider blocks put t over x_border (max(b, p) rows)
+template <int NCB>
+struct FrontBwdRows {
+  static constexpr int value = NCB == 1 ? 1024 : NCB == 2 ? 1024 : 576;
+};
+static_assert(FrontBwdRows<4>::value * FrontRow<4>::LD * 4 <= FRONT_LDS, "backward block fits LDS");
+static_assert(FrontBwdRows<2>::value * FrontRow<2>::LD * 4 <= FRONT_LDS, "backward block fits LDS");
+
+// acc[q][cb] += sum_{kb <= k < ke} A(k, 16 q + i) B(k, 16 cb + j) over one wave.
+// A round covers 16 values of k in four matrix-core steps: lane (i, g) =
+// (lane % 16, lane / 16) supplies A and B at k = k0 + 4 g + s in step s, so
+// that the four values of A a lane needs in a round are consecutive in k.
+// la(kq, r) returns A(kq .. kq + 3, r) with zeros from ke on; fb(k, c) reads B
+// from LDS.  Batches of NR rounds are double-buffered: the loads of the next
+// batch are in flight while the current one is multiplied.  kb is a multiple
+// of 4.
+template <int NA, int NCB, int NR, class LA, class FB>
+__device__ __forceinline__ void wave_product(int kb, int ke, LA&& la, FB&& fb, hf_f4 (&acc)[NA][NCB]) {
   const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   constexpr int STEP = 16 * NR;
   hf_f4 a0[NR][NA], a1[NR][NA];
-  float b0[NR][4], b1[NR][4];
-  auto load = [&](int k0, hf_f4 (&a)[NR][NA], float (&bb)[NR][4]) {
+  float b0[NR][NCB][4], b1[NR][NCB][4];
+  auto load = [&](int k0, hf_f4 (&a)[NR][NA], float (&bb)[NR][NCB][4]) {
 #pragma unroll
     for (int rd = 0; rd < NR; ++rd) {
       const int kq = k0 + 16 * rd + 4 * g;
 #pragma unroll
       for (int q = 0; q < NA; ++q) a[rd][q] = la(kq, 16 * q + li);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) bb[rd][s] = kq + s < ke ? fb(kq + s, li) : 0.f;
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) bb[rd][cb][s] = kq + s < ke ? fb(kq + s, 16 * cb + li) : 0.f;
     }
   };
-  auto comp = [&](int k0, const hf_f4 (&a)[NR][NA], const float (&bb)[NR][4]) {
+  auto comp = [&](int k0, const hf_f4 (&a)[NR][NA], const float (&bb)[NR][NCB][4]) {
 #pragma unroll
     for (int rd = 0; rd < NR; ++rd) {
       if (k0 + 16 * rd >= ke) break;  // uniform in the wave
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
-        for (int q = 0; q < NA; ++q) acc[q] = Mfma<float>::mma(a[rd][q][s], bb[rd][s], acc[q]);
+        for (int q = 0; q < NA; ++q)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = Mfma<float>::mma(a[rd][q][s], bb[rd][cb][s], acc[q][cb]);
     }
   };
   if (kb >= ke) return;
@@ -746,6 +765,14 @@ __device__ __forceinline__ void wave_product(int kb, int ke, LA&& la, FB&& fb, h
     if (k0 + 2 * STEP < ke) load(k0 + 2 * STEP, a0, b0);
     if (more) comp(k0 + STEP, a1, b1);
   }
+}
+
+template <int NA, int NCB>
+__device__ __forceinline__ void zero_tiles(hf_f4 (&acc)[NA][NCB]) {
+#pragma unroll
+  for (int q = 0; q < NA; ++q)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[q][cb] = hf_f4{0.f, 0.f, 0.f, 0.f};
 }
 
 // base[i] for a base shared by the wave and an index below 2^30: the byte
@@ -782,51 +809,54 @@ __device__ __forceinline__ hf_f4 load4_strided(const float* __restrict__ base, u
 
 typedef double hf_d2 __attribute__((ext_vector_type(2)));
 
-// One row of m <= 16 right-hand sides, widened to 16 with zeros: FP64 input
-// (cast to FP32; zeros when !on), FP32 accumulation and store.  m = 16 rows are
-// 16-byte aligned and move in 16-byte pieces.
-__device__ __forceinline__ void load_row16(const double* __restrict__ src, int64_t off, int m, bool on,
-                                           float (&v)[16]) {
+// One row of m <= W right-hand sides, widened to W with zeros: FP64 input (cast
+// to FP32; zeros when !on), FP32 accumulation and store.  Rows of m = W values
+// are 16-byte aligned and move in 16-byte pieces.
+template <int W>
+__device__ __forceinline__ void load_row(const double* __restrict__ src, int64_t off, int m, bool on,
+                                         float (&v)[W]) {
 #pragma unroll
-  for (int c = 0; c < 16; ++c) v[c] = 0.f;
+  for (int c = 0; c < W; ++c) v[c] = 0.f;
   if (!on) return;
-  if (m == 16) {
+  if (m == W) {
     const hf_d2* q = reinterpret_cast<const hf_d2*>(src + off);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < W / 2; ++c) {
       const hf_d2 x = q[c];
       v[2 * c] = (float)x[0];
       v[2 * c + 1] = (float)x[1];
     }
   } else {
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
+    for (int c = 0; c < W; ++c)
       if (c < m) v[c] = (float)src[off + c];
   }
 }
-__device__ __forceinline__ void add_row16(const float* __restrict__ src, int m, float (&v)[16]) {
-  if (m == 16) {
+template <int W>
+__device__ __forceinline__ void add_row(const float* __restrict__ src, int m, float (&v)[W]) {
+  if (m == W) {
     const hf_f4* q = reinterpret_cast<const hf_f4*>(src);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < W / 4; ++c) {
       const hf_f4 x = q[c];
 #pragma unroll
       for (int u = 0; u < 4; ++u) v[4 * c + u] += x[u];
     }
   } else {
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
+    for (int c = 0; c < W; ++c)
       if (c < m) v[c] += src[c];
   }
 }
-__device__ __forceinline__ void store_row16(float* __restrict__ dst, int m, const float (&v)[16]) {
-  if (m == 16) {
+template <int W>
+__device__ __forceinline__ void store_row(float* __restrict__ dst, int m, const float (&v)[W]) {
+  if (m == W) {
     hf_f4* q = reinterpret_cast<hf_f4*>(dst);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) q[c] = hf_f4{v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]};
+    for (int c = 0; c < W / 4; ++c) q[c] = hf_f4{v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]};
   } else {
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
+    for (int c = 0; c < W; ++c)
       if (c < m) dst[c] = v[c];
   }
 }
@@ -839,9 +869,13 @@ __device__ __forceinline__ int snake_tile(int w, int q) {
 
 // Forward step of a whole front: gather (own accepted rows from the FP64 input,
 // children's border rows added in child-rank order), z = Linv w for the pivot
-// rows (to zb and LDS), then w_border -= L21 z in 64-row tiles, the k range of
-// each tile split over the waves and the eight partial sums added in wave order.
-// Postponed rows are not part of the moderate solve and are not written.
+// rows (to zb and LDS), then w_border -= L21 z.  One column block: z has its
+// own LDS block and the border product runs in 64-row tiles whose k range is
+// split over the waves, the eight partial sums added in wave order (in the LDS
+// of w).  Wider blocks: z replaces w in LDS and each wave takes whole 16-row
+// tiles of the border.  Postponed rows are not part of the moderate solve and
+// are not written.
+template <int NCB>
 __global__ void __launch_bounds__(FRONT_NT)
 k_fwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
             const NodeState* __restrict__ st, const int32_t* __restrict__ ipos,
@@ -849,9 +883,12 @@ k_fwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
             const double* __restrict__ R, const float* __restrict__ front, const int64_t* __restrict__ linv2_off,
             const float* __restrict__ linv2, float* __restrict__ rb, float* __restrict__ zb) {
   constexpr int MT = TB / 16 / FRONT_NW;  // 16-row tiles of the pivot block per wave
-  __shared__ float ws[TB][FRONT_LDW];     // w of the pivot rows; later the partial sums
-  __shared__ float zs[TB][FRONT_LDW];     // z of the pivot rows
-  static_assert(FRONT_NW * 64 * 16 <= TB * FRONT_LDW, "partial sums fit in ws");
+  constexpr int W = FrontRow<NCB>::W, LD = FrontRow<NCB>::LD;
+  constexpr bool SPLIT = NCB == 1;
+  __shared__ float ws[TB][LD];                 // w of the pivot rows (then z, or the partial sums)
+  __shared__ float zsep[SPLIT ? TB : 1][LD];   // z of the pivot rows (one column block)
+  static_assert(!SPLIT || FRONT_NW * 64 * 16 <= TB * LD, "partial sums fit in ws");
+  float(*zs)[LD] = SPLIT ? zsep : ws;
   const int j = lnodes[blockIdx.x];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -861,74 +898,102 @@ k_fwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
   for (int a = tid; a < f; a += FRONT_NT) {
     const int pr = a < p ? ipos[ni.start + a] : a;
     if (pr >= npiv && pr < p) continue;
-    float v[16];
-    load_row16(R, (int64_t)(ni.start + a) * m, m, a < p, v);
+    float v[W];
+    load_row<W>(R, (int64_t)(ni.start + a) * m, m, a < p, v);
     const int64_t slot = ni.rhs_off + a;
-    for (int64_t i = gat_ptr[slot]; i < gat_ptr[slot + 1]; ++i) add_row16(rb + gat_src[i] * m, m, v);
+    for (int64_t i = gat_ptr[slot]; i < gat_ptr[slot + 1]; ++i) add_row<W>(rb + gat_src[i] * m, m, v);
     if (pr < npiv) {
 #pragma unroll
-      for (int c = 0; c < 16; ++c) ws[pr][c] = v[c];
+      for (int c = 0; c < W; ++c) ws[pr][c] = v[c];
     } else {
-      store_row16(rb + (ni.rhs_off + pr) * m, m, v);
+      store_row<W>(rb + (ni.rhs_off + pr) * m, m, v);
     }
   }
   __syncthreads();
   const float* X = linv2 + linv2_off[j];  // the front's single step, column-major TB x TB
   const int ntile = (npiv + 15) / 16;
+  hf_f4 zt[MT][1][NCB];
+#pragma unroll
   for (int q = 0; q < MT; ++q) {
+    zero_tiles(zt[q]);
     const int t = snake_tile(w, q);
     if (t >= ntile) continue;
     const int r0 = 16 * t;
     const bool row_ok = r0 + li < npiv;
     const int ke = min(npiv, r0 + 16);
-    hf_f4 one[1] = {hf_f4{0.f, 0.f, 0.f, 0.f}};
-    wave_product<1, 2>(
+    wave_product<1, NCB, SPLIT ? 2 : 1>(
         0, ke, [&](int kq, int r) { return load4_strided(X, (uint32_t)(r0 + r), TB, kq, ke, row_ok); },
-        [&](int k, int c) { return ws[k][c]; }, one);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = r0 + Mfma<float>::row(lane, u);
-      if (r < npiv) {
-        zs[r][li] = one[0][u];
-        if (li < m) zb[(ni.rhs_off + r) * m + li] = one[0][u];
-      }
-    }
+        [&](int k, int c) { return ws[k][c]; }, zt[q]);
   }
-  __syncthreads();  // z complete; ws free for the partial sums
-  const float* F = front + ni.front_off;
-  const int kc = ((npiv + FRONT_NW - 1) / FRONT_NW + 15) & ~15;  // k range of one wave
-  const int kb = min(npiv, w * kc), ke = min(npiv, kb + kc);
-  float* part = &ws[0][0];  // [wave][64 rows][16]
-  for (int r0 = 0; r0 < b; r0 += 64) {
-    hf_f4 acc[4];
+  if constexpr (!SPLIT) __syncthreads();  // every read of w is done: z replaces it
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = hf_f4{0.f, 0.f, 0.f, 0.f};
-    // A(k, r) = F[p + r0 + r + k f]
-    wave_product<4, 1>(
-        kb, ke, [&](int kq, int r) { return load4_strided(F, (uint32_t)(p + r0 + r), f, kq, ke, r0 + r < b); },
-        [&](int k, int c) { return zs[k][c]; }, acc);
+  for (int q = 0; q < MT; ++q) {
+    const int t = snake_tile(w, q);
+    if (t >= ntile) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) part[(w * 64 + 16 * q + Mfma<float>::row(lane, u)) * 16 + li] = acc[q][u];
-    __syncthreads();
-    for (int e = tid; e < 64 * 16; e += FRONT_NT) {
-      const int r = e >> 4, c = e & 15;
-      if (r0 + r < b && c < m) {
-        float sum = 0.f;
-#pragma unroll
-        for (int v = 0; v < FRONT_NW; ++v) sum += part[(v * 64 + r) * 16 + c];
-        rb[(ni.rhs_off + p + r0 + r) * m + c] -= sum;
+      for (int u = 0; u < 4; ++u) {
+        const int r = 16 * t + Mfma<float>::row(lane, u), c = 16 * cb + li;
+        if (r < npiv) {
+          zs[r][c] = zt[q][0][cb][u];
+          if (c < m) zb[(ni.rhs_off + r) * m + c] = zt[q][0][cb][u];
+        }
       }
+  }
+  __syncthreads();
+  const float* F = front + ni.front_off;
+  if constexpr (SPLIT) {
+    const int kc = ((npiv + FRONT_NW - 1) / FRONT_NW + 15) & ~15;  // k range of one wave
+    const int kb = min(npiv, w * kc), ke = min(npiv, kb + kc);
+    float* part = &ws[0][0];  // [wave][64 rows][16]
+    for (int r0 = 0; r0 < b; r0 += 64) {
+      hf_f4 acc[4][1];
+      zero_tiles(acc);
+      // A(k, r) = F[p + r0 + r + k f]
+      wave_product<4, 1, 1>(
+          kb, ke, [&](int kq, int r) { return load4_strided(F, (uint32_t)(p + r0 + r), f, kq, ke, r0 + r < b); },
+          [&](int k, int c) { return zs[k][c]; }, acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) part[(w * 64 + 16 * q + Mfma<float>::row(lane, u)) * 16 + li] = acc[q][0][u];
+      __syncthreads();
+      for (int e = tid; e < 64 * 16; e += FRONT_NT) {
+        const int r = e >> 4, c = e & 15;
+        if (r0 + r < b && c < m) {
+          float sum = 0.f;
+#pragma unroll
+          for (int v = 0; v < FRONT_NW; ++v) sum += part[(v * 64 + r) * 16 + c];
+          rb[(ni.rhs_off + p + r0 + r) * m + c] -= sum;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+    for (int r0 = 16 * w; r0 < b; r0 += 16 * FRONT_NW) {
+      hf_f4 acc[1][NCB];
+      zero_tiles(acc);
+      const bool row_ok = r0 + li < b;
+      wave_product<1, NCB, 1>(
+          0, npiv, [&](int kq, int r) { return load4_strided(F, (uint32_t)(p + r0 + r), f, kq, npiv, row_ok); },
+          [&](int k, int c) { return zs[k][c]; }, acc);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int r = r0 + Mfma<float>::row(lane, u), c = 16 * cb + li;
+          if (r < b && c < m) rb[(ni.rhs_off + p + r) * m + c] -= acc[0][cb][u];
+        }
+    }
   }
 }
 
 // Backward step of a whole front: x_border gathered from the FP64 result of the
-// ancestors into LDS, t = z / d - L21^T x_border for the pivot rows (LDS, after
-// the border rows), then x = Linv^T t scattered to the FP64 result.  b + p <= ROWS.
-template <int ROWS>
+// ancestors into LDS, t = z / d - L21^T x_border for the pivot rows (LDS: after
+// the border rows for one column block, over them for wider blocks), then
+// x = Linv^T t scattered to the FP64 result.
+template <int NCB>
 __global__ void __launch_bounds__(FRONT_NT)
 k_bwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
             const NodeState* __restrict__ st, const float* __restrict__ front,
@@ -936,7 +1001,8 @@ k_bwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
             const int32_t* __restrict__ border, const float* __restrict__ dval, int m, double* __restrict__ Y,
             const float* __restrict__ zb) {
   constexpr int MT = TB / 16 / FRONT_NW;
-  __shared__ float sh[ROWS][FRONT_LDW];  // border values [0, b), then t [b, b + npiv)
+  constexpr int W = FrontRow<NCB>::W, LD = FrontRow<NCB>::LD;
+  __shared__ float sh[FrontBwdRows<NCB>::value][LD];
   const int j = lnodes[blockIdx.x];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -944,49 +1010,66 @@ k_bwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15;
   if (npiv == 0) return;
   for (int r = tid; r < b; r += FRONT_NT) {
-    float v[16];
-    load_row16(Y, (int64_t)border[ni.border_off + r] * m, m, true, v);
+    float v[W];
+    load_row<W>(Y, (int64_t)border[ni.border_off + r] * m, m, true, v);
 #pragma unroll
-    for (int c = 0; c < 16; ++c) sh[r][c] = v[c];
+    for (int c = 0; c < W; ++c) sh[r][c] = v[c];
   }
   __syncthreads();
   const float* F = front + ni.front_off;
   const int ntile = (npiv + 15) / 16;
-  float(*tt)[FRONT_LDW] = sh + b;
+  hf_f4 tt[MT][1][NCB];
+#pragma unroll
   for (int q = 0; q < MT; ++q) {
+    zero_tiles(tt[q]);
     const int t = w + FRONT_NW * q;
     if (t >= ntile) continue;
     const int r0 = 16 * t;
     const bool row_ok = r0 + li < npiv;
-    hf_f4 one[1] = {hf_f4{0.f, 0.f, 0.f, 0.f}};
     const uint32_t o = (uint32_t)(r0 + li) * f + p;  // L21[k, r0 + li] = F[o + k]
-    wave_product<1, 4>(
+    wave_product<1, NCB, NCB == 1 ? 4 : 2>(
         0, b, [&](int kq, int) { return load4_contig(F, o, kq, b, row_ok); },
-        [&](int k, int c) { return sh[k][c]; }, one);
+        [&](int k, int c) { return sh[k][c]; }, tt[q]);
+  }
+  float(*ts)[LD] = NCB == 1 ? sh + b : sh;
+  if constexpr (NCB > 1) __syncthreads();  // every read of x_border is done: t replaces it
+#pragma unroll
+  for (int q = 0; q < MT; ++q) {
+    const int t = w + FRONT_NW * q;
+    if (t >= ntile) continue;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int r = r0 + Mfma<float>::row(lane, u);
-      if (r < npiv)
-        tt[r][li] = li < m ? zb[(ni.rhs_off + r) * m + li] / dval[ni.start + r] - one[0][u] : 0.f;
+      const int r = 16 * t + Mfma<float>::row(lane, u);
+      if (r >= npiv) continue;
+      const float dk = dval[ni.start + r];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int c = 16 * cb + li;
+        ts[r][c] = c < m ? zb[(ni.rhs_off + r) * m + c] / dk - tt[q][0][cb][u] : 0.f;
+      }
     }
   }
   __syncthreads();
   const float* X = linv2 + linv2_off[j];
+#pragma unroll
   for (int q = 0; q < MT; ++q) {
     const int t = snake_tile(w, q);
     if (t >= ntile) continue;
     const int r0 = 16 * t;
     const bool row_ok = r0 + li < npiv;
-    hf_f4 one[1] = {hf_f4{0.f, 0.f, 0.f, 0.f}};
+    hf_f4 acc[1][NCB];
+    zero_tiles(acc);
     const uint32_t o = (uint32_t)(r0 + li) * TB;  // Linv[k, r0 + li] = X[o + k]
-    wave_product<1, 4>(
+    wave_product<1, NCB, NCB == 1 ? 4 : 2>(
         r0, npiv, [&](int kq, int) { return load4_contig(X, o, kq, npiv, row_ok); },
-        [&](int k, int c) { return tt[k][c]; }, one);
+        [&](int k, int c) { return ts[k][c]; }, acc);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = r0 + Mfma<float>::row(lane, u);
-      if (r < npiv && li < m) Y[(int64_t)piv[ni.start + r] * m + li] = (double)one[0][u];
-    }
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + Mfma<float>::row(lane, u), c = 16 * cb + li;
+        if (r < npiv && c < m) Y[(int64_t)piv[ni.start + r] * m + c] = (double)acc[0][cb][u];
+      }
   }
 }
 
@@ -1110,26 +1193,34 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   // (also read as border values) stay zero
   if (ctx->M > 0)
     k_zero_rows<<<cdiv((int64_t)ctx->M * m, 256), 256, 0, s>>>(ctx->M, m, ctx->d_l2.as<int32_t>(), Y);
-  // levels whose fronts each go through one workgroup (FP32, m <= 16, many
-  // fronts of at most one step)
-  auto whole_fronts = [&](int l) {
-    if (!std::is_same<T, float>::value || m > 16) return false;
+  // levels whose fronts each go through one workgroup (FP32; many fronts of at
+  // most one step whose backward LDS block fits)
+  const int fcb = m <= 16 ? 1 : m <= 32 ? 2 : 4;
+  // (forward steps of four column blocks stay level-wide: with their LDS block
+  // one workgroup per CU streams the front no faster than the level launches)
+  auto whole_fronts = [&](int l, bool fwd) {
+    if (!std::is_same<T, float>::value || (fwd && fcb == 4)) return false;
     const int nl = ctx->level_ptr[l + 1] - ctx->level_ptr[l];
-    return nl >= FRONT_MIN_FRONTS && ctx->level_maxp[l] <= TB &&
-           ctx->level_maxb[l] + ctx->level_maxp[l] <= FRONT_BWD_ROWS;
+    const int mp = ctx->level_maxp[l], mb = ctx->level_maxb[l];
+    const int nmin = ctx->opt.sweep_front_min;
+    if (nmin <= 0 || nl < nmin || mp > TB) return false;
+    return fcb == 1 ? mb + mp <= FrontBwdRows<1>::value
+                    : mb <= (fcb == 2 ? FrontBwdRows<2>::value : FrontBwdRows<4>::value);
   };
   for (int l = 0; l < nlev; ++l) {
     const int nl = ctx->level_ptr[l + 1] - ctx->level_ptr[l];
     const int32_t* ln = lall + ctx->level_ptr[l];
     const int maxp = ctx->level_maxp[l], maxf = ctx->level_maxf[l];
     if constexpr (std::is_same<T, float>::value) {
-      if (whole_fronts(l)) {
+      if (whole_fronts(l, true)) {
         auto wf = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
           by += np * dm * 8.0 + 0.5 * np * np * sz + ni.b * np * sz + np * dm * sz + 2.0 * ni.b * dm * sz;
           for (int32_t q = ni.child_begin; q < ni.child_end; ++q) by += ctx->nodes[ctx->child_list[q]].b * dm * sz;
           fl += dm * np * np + 2.0 * dm * ni.b * np;
         });
-        launch_timed(tm, HF_K_FWD_FRONT, wf.first, wf.second, s, k_fwd_front, dim3(nl), dim3(FRONT_NT), ln, nodes,
+        launch_timed(tm, HF_K_FWD_FRONT, wf.first, wf.second, s,
+                     fcb == 1 ? k_fwd_front<1> : fcb == 2 ? k_fwd_front<2> : k_fwd_front<4>, dim3(nl), dim3(FRONT_NT),
+                     ln, nodes,
                      st, (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
                      (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, front, loff2, linv2, rb, zb);
         continue;
@@ -1192,14 +1283,13 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     const int maxp = ctx->level_maxp[l];
     if (maxp == 0) continue;
     if constexpr (std::is_same<T, float>::value) {
-      if (whole_fronts(l)) {
+      if (whole_fronts(l, false)) {
         auto wf = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
           by += ni.b * dm * 8.0 + ni.b * np * sz + np * dm * sz + np * sz + 0.5 * np * np * sz + np * dm * 8.0;
           fl += 2.0 * dm * ni.b * np + dm * np * np;
         });
-        const bool small = ctx->level_maxb[l] + maxp <= FRONT_BWD_ROWS / 2;
         launch_timed(tm, HF_K_BWD_FRONT, wf.first, wf.second, s,
-                     small ? k_bwd_front<FRONT_BWD_ROWS / 2> : k_bwd_front<FRONT_BWD_ROWS>, dim3(nl),
+                     fcb == 1 ? k_bwd_front<1> : fcb == 2 ? k_bwd_front<2> : k_bwd_front<4>, dim3(nl),
                      dim3(FRONT_NT), ln, nodes, st, front, loff2, linv2, (const int32_t*)ctx->d_piv.as<int32_t>(),
                      (const int32_t*)ctx->d_border.as<int32_t>(), (const float*)ctx->d_dval.as<float>(), m, Y,
                      (const float*)zb);

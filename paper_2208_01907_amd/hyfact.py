@@ -19,6 +19,7 @@ The function names follow the C entry points:
     mags = hf_s22_pivots(ctx)                # pivot magnitudes of the LDL^T of S22
     runs, nfac = hf_gcr_history(ctx)         # block-GCR residual histories
     Lam, GV = hf_adjoint(ctx, X, G)          # derivatives of a loss through X
+    Y = hf_precond(ctx, R)                   # the preconditioner Q^{-1} (scaled, permuted)
     X = solve(ctx, values, B)                # torch.autograd-aware factorize + solve
 """
 from __future__ import annotations
@@ -53,7 +54,7 @@ HF_PREC_FP64 = 64
 EXPORTS = ["hf_default_options", "hf_analyse", "hf_factorize", "hf_solve", "hf_kernel_dim",
            "hf_kernel_basis", "hf_schur", "hf_scaling", "hf_info", "hf_strerror", "hf_destroy",
            "hf_timing_enable", "hf_timing_get", "hf_adjoint", "hf_pivots", "hf_s22_pivots", "hf_gcr_history",
-           "hf_schur_noalloc"]
+           "hf_schur_noalloc", "hf_precond"]
 
 # kernel classes of hf_timing_get
 KCLASS = ["panel", "permute_l11", "f11_update", "gather_border", "trsm", "syrk", "extend_add", "fwd_diag",
@@ -72,7 +73,8 @@ class HFOptions(ctypes.Structure):
                 ("first_pivot_unit", ctypes.c_int32), ("n_enlarge", ctypes.c_int32),
                 ("gcr_block", ctypes.c_int32), ("gcr_tol", ctypes.c_double),
                 ("gcr_maxit", ctypes.c_int32), ("ker_tol", ctypes.c_double),
-                ("refine_steps", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
+                ("refine_steps", ctypes.c_int32), ("refine_tol", ctypes.c_double),
+                ("sweep_front_min", ctypes.c_int32)]
 
 
 class HFInfo(ctypes.Structure):
@@ -119,6 +121,7 @@ def _load():
         "hf_s22_pivots": (ctypes.c_int, [P, P]),
         "hf_gcr_history": (ctypes.c_int, [P, P, P, P, P]),
         "hf_schur_noalloc": (ctypes.c_int, [P, P, P, P, I64, P]),
+        "hf_precond": (ctypes.c_int, [P, I32, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -226,6 +229,17 @@ def hf_solve(ctx: Context, B, X=None, stream=None):
         X.copy_(out.reshape(X.shape))
         return X
     return out[:, 0] if one else out
+
+
+def hf_precond(ctx: Context, R, stream=None):
+    """Q^{-1} R (see hf_precond in include/hf.h): R of shape (L, r), r <= 64,
+    float64 on the GPU, rows in elimination order of the scaled matrix."""
+    assert R.is_cuda and R.dtype == torch.float64 and R.dim() == 2
+    Rc = R.contiguous()
+    Y = torch.empty_like(Rc)
+    _check(_lib.hf_precond(ctx.handle, Rc.shape[1], ctypes.c_void_p(Rc.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                           _stream(stream)), "hf_precond")
+    return Y
 
 
 def hf_adjoint(ctx: Context, X, G, with_values=True, stream=None):

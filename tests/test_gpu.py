@@ -162,6 +162,68 @@ def test_parity(name, prec):
         assert np.allclose(N.T @ N, np.eye(ref.k), atol=1e-12)
 
 
+PRECOND_CASES = {"c1": (1, 16, 17, 64), "inc24": (1, 16, 40), "n2d_ragged": (5, 33), "el7_ragged": (3, 64),
+                 "stokes8": (16, 20), "dense_k2": (2, 16), "dense_indef_all_postponed": (7,),
+                 "paired_ne3": (1, 48)}
+
+
+@pytest.mark.parametrize("name", list(PRECOND_CASES))
+def test_preconditioner_sweeps(name):
+    """Q^{-1} R of Sec. 3.2 through hf_precond, element by element.
+
+    FP64 factor: against the oracle's substitution with its own FP64 factor (the
+    two factors agree to cond * eps64; the bar 1e-9 relative to max|Y| leaves
+    room for cond(K11) up to about 1e6).  FP32 factor: the whole-front kernels
+    (every eligible level forced onto them) against the level-wide launches on
+    the same factor (factorizations are bitwise reproducible), so the two differ
+    only in the order of the FP32 sums; the bar is 1e-5 relative to max|Y|
+    (a few hundred FP32 roundings; about 1e-6 is seen).
+    Column counts cover one, several and all four 16-column blocks, ragged
+    counts among them; the cases include trees with every pivot postponed (Y = 0)
+    and single-front trees (no border)."""
+    W = CASES[name]()
+    ne = W.meta.get("n_enlarge", 4)
+    ref = oracle.hybrid_factorize(W.csr(), W.perm, W.node_ptr, W.parent, tau=W.tau, low=np.float64,
+                                  gcr_block=W.gcr_block, n_enlarge=ne)
+    hard = ref.step1.lambda2
+    rng = np.random.default_rng(31)
+    ctx64 = _gpu(W, 64)
+    lam, _ = hy.hf_schur(ctx64)
+    same = np.array_equal(lam, np.sort(W.perm[hard]))
+
+    def ctx32(front_min):
+        opt = hy.hf_default_options(tau=W.tau, low_precision=32, gcr_block=W.gcr_block, n_enlarge=ne,
+                                    sweep_front_min=front_min)
+        c = hy.hf_analyse(W.indptr, W.indices, W.perm, W.node_ptr, W.parent, opt)
+        hy.hf_factorize(c, torch.tensor(W.values, device="cuda"))
+        return c
+
+    whole, wide = ctx32(1), ctx32(0)
+    inv = np.empty(W.n, dtype=np.int64)
+    inv[W.perm] = np.arange(W.n)
+    hard32 = inv[hy.hf_schur(whole)[0]]
+    for m in PRECOND_CASES[name]:
+        R = rng.standard_normal((W.n, m))
+        if same:
+            R64 = R.copy()
+            R64[hard] = 0.0
+            Y = hy.hf_precond(ctx64, torch.tensor(R64, device="cuda")).cpu().numpy()
+            Yref = oracle.precond(ref.step1, R64)
+            err = np.abs(Y - Yref).max() / max(np.abs(Yref).max(), 1e-300)
+            print(f"  {name} m={m}: fp64 vs oracle {err:.1e}", flush=True)
+            assert err <= 1e-9
+            assert np.all(Y[hard] == 0.0)
+        R32 = R.copy()
+        R32[hard32] = 0.0
+        Rt = torch.tensor(R32, device="cuda")
+        Ya = hy.hf_precond(whole, Rt).cpu().numpy()
+        Yb = hy.hf_precond(wide, Rt).cpu().numpy()
+        d = np.abs(Ya - Yb).max() / max(np.abs(Yb).max(), 1e-300)
+        print(f"  {name} m={m}: fp32 whole-front vs level-wide {d:.1e}", flush=True)
+        assert d <= 1e-5
+        assert np.all(Ya[hard32] == 0.0)
+
+
 FP16_CASES = ["c1", "inc20", "n2d_ragged", "el6", "stokes8", "dense_k2"]
 
 
