@@ -525,12 +525,29 @@ struct NarrowRounds {  // rounds per batch, batches (register budget of FP64)
   static constexpr int NBATCH = sizeof(T) == 4 ? 1 : 2;
 };
 
+// A(k .. k + 3, r) for an operand contiguous in k (col = the start of row r's
+// values): one 4-element load where all four are below ke, else element by
+// element with zeros from ke on
+template <class T>
+__device__ __forceinline__ typename Mfma<T>::V load4k(const T* __restrict__ col, int k, int ke) {
+  typename Mfma<T>::V v = {0, 0, 0, 0};
+  if (k + 3 < ke) {
+    __builtin_memcpy(&v, col + k, 4 * sizeof(T));
+    return v;
+  }
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    if (k + s < ke) v[s] = col[k + s];
+  return v;
+}
+
 // out(r, c) = sum_{kb <= k < ke} A(k, r) B(k, c) for r < 16, c < 16 NCB; the
 // lane (i, g) = (lane % 16, lane / 16) of a wave supplies, in step s of round
 // rd, the operands at k = kb + 16 rd + 4 g + s (the same k for A and B, so the
 // k order inside a round is only a relabelling of the sum).  epi(r, c, v) is
-// called once per output.
-template <class T, int NCB, class FA, class FB, class EPI>
+// called once per output.  With CA (A contiguous in k), fa(k, r) returns the
+// four values A(k .. k + 3, r), zero from ke on, in one load.
+template <class T, int NCB, bool CA = false, class FA, class FB, class EPI>
 __device__ __forceinline__ void narrow_product(int kb, int ke, FA&& fa, FB&& fb, EPI&& epi) {
   using V = typename Mfma<T>::V;
   constexpr int NR = NarrowRounds<T>::NR, NBATCH = NarrowRounds<T>::NBATCH;
@@ -547,10 +564,15 @@ __device__ __forceinline__ void narrow_product(int kb, int ke, FA&& fa, FB&& fb,
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       const int k0 = kb + 16 * (w + 4 * (bt * NR + q)) + 4 * g;
+      if constexpr (CA) {
+        const V a4 = fa(k0, li);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[q][s] = a4[s];
+      }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const bool ok = k0 + s < ke;
-        a[q][s] = ok ? fa(k0 + s, li) : (T)0;
+        if constexpr (!CA) a[q][s] = ok ? fa(k0 + s, li) : (T)0;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) b[q][cb][s] = ok ? fb(k0 + s, cb * 16 + li) : (T)0;
       }
@@ -649,8 +671,9 @@ k_bwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
   const T* X = step_inverse(linv2, linv2_off[j], J0) + (int64_t)r0 * TB;  // A(k, r) = X[r TB + k]
   const T* W = rb + (ni.rhs_off + J0) * m;
   const int c0 = J0 + r0;
-  narrow_product<T, NCB>(
-      r0, nc, [&](int k, int r) { return r < nrows ? X[(int64_t)r * TB + k] : (T)0; },
+  narrow_product<T, NCB, true>(
+      r0, nc,
+      [&](int k, int r) { return r < nrows ? load4k(X + (int64_t)r * TB, k, nc) : typename Mfma<T>::V{0, 0, 0, 0}; },
       [&](int k, int c) { return c < m ? W[(int64_t)k * m + c] : (T)0; },
       [&](int r, int c, T v) {
         if (r < nrows && c < m) {
@@ -678,8 +701,9 @@ k_bwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
   const T* A = front + ni.front_off + (int64_t)cs * lf + J0;  // A(k, r) = L[J0 + k, cs + r]
   const T* Z = zb + (ni.rhs_off + J0) * m;
   T* W = rb + (ni.rhs_off + cs) * m;
-  narrow_product<T, NCB>(
-      0, nc, [&](int k, int r) { return r < nrows ? A[(int64_t)r * lf + k] : (T)0; },
+  narrow_product<T, NCB, true>(
+      0, nc,
+      [&](int k, int r) { return r < nrows ? load4k(A + (int64_t)r * lf, k, nc) : typename Mfma<T>::V{0, 0, 0, 0}; },
       [&](int k, int c) { return c < m ? Z[(int64_t)k * m + c] : (T)0; },
       [&](int r, int c, T v) {
         if (r < nrows && c < m) W[(int64_t)r * m + c] -= v;
@@ -1118,8 +1142,9 @@ k_bwd_border_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ 
   const T* Yb = rb + (ni.rhs_off + p) * m;
   const int nrows = min(16, npiv - cs);
   T* P = part + (((int64_t)q * maxch + ch) * maxp + cs) * m;
-  narrow_product<T, NCB>(
-      rlo, rhi, [&](int k, int r) { return r < nrows ? A[(int64_t)r * lf + k] : (T)0; },
+  narrow_product<T, NCB, true>(
+      rlo, rhi,
+      [&](int k, int r) { return r < nrows ? load4k(A + (int64_t)r * lf, k, rhi) : typename Mfma<T>::V{0, 0, 0, 0}; },
       [&](int k, int c) { return c < m ? Yb[(int64_t)k * m + c] : (T)0; },
       [&](int r, int c, T v) {
         if (r < nrows && c < m) {
