@@ -17,6 +17,7 @@ import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -57,6 +58,10 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-full", action="store_true",
+                    help="time the oracle on the whole workload (many minutes) instead of the bounded sample")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="run only the oracle timing (no GPU) and print it as JSON")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain device copy of 256 MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -213,47 +218,85 @@ print(time.perf_counter() - t0)
 """
 
 
-def cpu_baseline(W):
-    """The oracle (unchanged), timed on the host: its whole factor+solve with the
-    FP32 step 1 on this workload (Algorithm 1, then Algorithm 2 with the
-    residual-correction pass), split by phase, with OpenMP over all host cores;
-    and, as a bounded sample, its step 1 on a subtree of about 1/8 of the
-    unknowns run with one thread and with all threads (the whole run with one
-    thread would take tens of minutes)."""
-    import subprocess
-    import tempfile
+def _oracle_run(K, perm, node_ptr, parent, tau, B):
+    """The oracle's FP32 factor+solve (Algorithm 1, then Algorithm 2 with the
+    residual-correction pass), timed by phase."""
     import numpy as np
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    hf = oracle.hybrid_factorize(W.csr(), W.perm, W.node_ptr, W.parent, tau=W.tau, low=np.float32, gcr_block=0)
+    hf = oracle.hybrid_factorize(K, perm, node_ptr, parent, tau=tau, low=np.float32, gcr_block=0)
     t1 = time.perf_counter()
-    oracle.hybrid_solve(hf, W.b)
+    oracle.hybrid_solve(hf, B)
     t2 = time.perf_counter()
     phases = {"step1_s": hf.seconds["step1"], "gcr_s": hf.seconds["gcr"], "s22_s": hf.seconds["s22"],
               "solve_s": t2 - t1}
-    sample = {}
+    return t2 - t0, phases, int(hf.M), int(hf.k)
+
+
+FULL_BASELINE_FILE = os.path.join(ROOT, "profiles", "oracle_c2_full.json")
+
+
+def host_cpu():
+    """Model name of the host CPU (from /proc/cpuinfo where there is one)."""
     try:
-        j, Ksub, nptr, par = _subtree_sample(W, 0.125)
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.machine()
+
+
+def cpu_baseline(W, cfg, full=False):
+    """The oracle (unchanged), timed on the host with OpenMP over all host cores.
+
+    Default (bounded, a few seconds): its whole factor+solve with the FP32 step
+    1 on the nested-dissection subtree holding about 1/8 of the unknowns, as a
+    problem of its own (its principal submatrix, 16 right-hand sides), split by
+    phase; plus its step 1 on that subtree with one thread.  The whole workload
+    takes many minutes on the host: with full=True it is run here; otherwise the
+    committed record of such a run (profiles/oracle_c2_full.json, host and core
+    count stated there) is attached for this workload."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if full:
+        total, phases, M, k = _oracle_run(W.csr(), W.perm, W.node_ptr, W.parent, W.tau, W.b)
+        return {"value": total, "unit": "s", "cores": threads, "kind": "oracle",
+                "sample": "the whole workload: oracle FP32 step 1 + FP64 block GCR + S22 + solve with one "
+                          "correction pass, OpenMP over all host cores (the C step 1 and preconditioner; "
+                          "NumPy/SciPy for the rest)",
+                "phases": phases, "M": M, "kernel_dim": k}
+    j, Ksub, nptr, par = _subtree_sample(W, 0.125)
+    rng = np.random.default_rng(2208)
+    Bs = Ksub @ rng.standard_normal((Ksub.shape[0], W.b.shape[1]))
+    total, phases, M, k = _oracle_run(Ksub, np.arange(Ksub.shape[0], dtype=np.int32), nptr, par, W.tau, Bs)
+    out = {"value": total, "unit": "s", "cores": threads, "kind": "oracle",
+           "sample": f"oracle FP32 factor+solve (Algorithm 1, Algorithm 2 with one correction pass, "
+                     f"{W.b.shape[1]} RHS) of the nested-dissection subtree at node {j}: its principal "
+                     f"submatrix, {Ksub.shape[0]} of the workload's {W.n} unknowns, OpenMP over all host cores",
+           "phases": phases, "M": M, "kernel_dim": k}
+    try:
         with tempfile.TemporaryDirectory() as td:
             path = os.path.join(td, "sub.npz")
             np.savez(path, data=Ksub.data, indices=Ksub.indices, indptr=Ksub.indptr, shape=np.array(Ksub.shape),
                      nptr=nptr, par=par, tau=W.tau)
-            code = SAMPLE_SCRIPT.format(root=ROOT, path=path)
-            for nt in (1, threads):
-                env = dict(os.environ, OMP_NUM_THREADS=str(nt))
-                out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
-                                     timeout=600, check=True)
-                sample[f"step1_s_{nt}_threads"] = float(out.stdout.strip().splitlines()[-1])
-        sample["subtree"] = f"node {j}, {Ksub.shape[0]} unknowns"
+            env = dict(os.environ, OMP_NUM_THREADS="1")
+            res = subprocess.run([sys.executable, "-c", SAMPLE_SCRIPT.format(root=ROOT, path=path)], env=env,
+                                 capture_output=True, text=True, timeout=600, check=True)
+            out["step1_s_1_thread"] = float(res.stdout.strip().splitlines()[-1])
     except (OSError, subprocess.SubprocessError, ValueError) as e:
-        sample["error"] = str(e)
-    return {"value": t2 - t0, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": "the whole workload: oracle FP32 step 1 + FP64 block GCR + S22 + solve with one "
-                      "correction pass, OpenMP over all host cores (the C step 1 and preconditioner; NumPy/SciPy "
-                      "for the rest)",
-            "phases": phases, "M": int(hf.M), "kernel_dim": int(hf.k),
-            "one_thread_sample": sample}
+        out["step1_1_thread_error"] = str(e)
+    try:
+        with open(FULL_BASELINE_FILE) as fh:
+            rec = json.load(fh)
+        if rec.get("workload") == cfg:
+            out["full_workload_measured"] = rec
+    except (OSError, ValueError):
+        pass
+    return out
 
 
 def golden_rel(cfg, X):
@@ -308,6 +351,14 @@ def main():
               "(sharding over GPUs by nested-dissection subtrees is not built).",
               file=sys.stderr)
         sys.exit(2)
+    if args.cpu_baseline_only:  # host only: the oracle's timing, no GPU
+        from paper_2208_01907_amd import workloads as w
+        W = w.CONFIGS[args.config]()
+        rec = cpu_baseline(W, args.config, full=args.cpu_baseline_full)
+        rec.update({"workload": args.config, "host": host_cpu(),
+                    "command": " ".join(["python", "bench.py"] + sys.argv[1:])})
+        print(json.dumps(rec))
+        return
     import numpy as np
     import torch
     from paper_2208_01907_amd import hyfact as hy
@@ -389,7 +440,7 @@ def main():
                 "kernel_rates": rates(stats16)}
             del ctx16
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(W)
+        result["cpu_baseline"] = cpu_baseline(W, args.config, full=args.cpu_baseline_full)
     print(json.dumps(result))
 
 
