@@ -34,6 +34,9 @@ WORKLOADS = {
           "FP32 step 1 + FP64 block GCR, 32 RHS",
     "c4": "enclosed MAC Stokes saddle point 32^3 cells (95232 face velocities + 32768 pressures, L=128000), "
           "viscosity 10^U(-2,2), staggered ND leaf 512, tau=1e-2, FP32 step 1 + FP64 block GCR, 32 RHS",
+    "c5": "batch of 96 independent 3D Neumann 7-point FV Laplacians, sides n ~ U{16..40} (L=2326630 in all), "
+          "cell coefficients 10^U(-3,3), one block-diagonal forest, ND leaf 512, tau=1e-2, FP32 step 1 + FP64 "
+          "block GCR in 8-column blocks, 8 RHS per system",
 }
 CALIB_BYTES = 256 << 20
 # measured HBM traffic of the dominant kernel (FETCH_SIZE / WRITE_SIZE passes),

@@ -25,6 +25,12 @@ static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1
 
 constexpr int GRAM_WG = 256;   // partial sums of a Gram product (fixed: reduction order)
 constexpr int MAXM = 64;       // widest block handled by the small dense kernels
+// The kernel basis (n x k) is stored as column chunks of KC columns, chunk c a
+// row-major n x min(KC, k - c KC) block at offset c n KC, so every dense product
+// with it stays within the small kernels' width.
+constexpr int KC = MAXM;
+constexpr int KMAX = 1024;     // largest kernel dimension handled
+static inline int kchunk(int k, int c) { return std::min(KC, k - c * KC); }
 
 // ---------------------------------------------------------------------------
 // SpMM and friends
@@ -600,9 +606,10 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
   }
 }
 
-// Null vectors of S22: N2 = P^T [-L11^{-T} L21^T; I_k]  (row-major M x k)
+// Null vectors of S22: N2 = P^T [-L11^{-T} L21^T; I_k], stored in column chunks
+// of KC columns (chunk c: row-major rows x kc at N2 + c rows KC)
 __global__ void k_s22_null(int M, int k, const double* __restrict__ L, const int32_t* __restrict__ perm,
-                           double* __restrict__ N2) {
+                           int rows, double* __restrict__ N2c) {
   // the backward substitution runs on a work column in LDS (dynamic, M * blockDim
   // doubles) when M <= MAXM, else directly on the rows of N2
   extern __shared__ double sm[];
@@ -610,9 +617,11 @@ __global__ void k_s22_null(int M, int k, const double* __restrict__ L, const int
   if (q >= k) return;
   const int r = M - k;
   const bool lds = M <= MAXM;
+  const int kc = min(KC, k - (q / KC) * KC), qc = q % KC;
+  double* N2 = N2c + (int64_t)(q / KC) * rows * KC;  // this column's chunk, kc columns
   double* y = lds ? sm + threadIdx.x : nullptr;
   const int ys = blockDim.x;
-  auto Y = [&](int i) -> double& { return lds ? y[i * ys] : N2[(int64_t)perm[i] * k + q]; };
+  auto Y = [&](int i) -> double& { return lds ? y[i * ys] : N2[(int64_t)perm[i] * kc + qc]; };
   // Y = L11^{-T} L21^T[:, q] by backward substitution
   for (int i = 0; i < M; ++i) Y(i) = 0.0;
   for (int i = r - 1; i >= 0; --i) {
@@ -620,8 +629,8 @@ __global__ void k_s22_null(int M, int k, const double* __restrict__ L, const int
     for (int t = i + 1; t < r; ++t) v -= at(const_cast<double*>(L), M, t, i) * Y(t);
     Y(i) = v;
   }
-  for (int i = 0; i < r; ++i) N2[(int64_t)perm[i] * k + q] = -Y(i);
-  for (int t = 0; t < k; ++t) N2[(int64_t)perm[r + t] * k + q] = (t == q) ? 1.0 : 0.0;
+  for (int i = 0; i < r; ++i) N2[(int64_t)perm[i] * kc + qc] = -Y(i);
+  for (int t = 0; t < k; ++t) N2[(int64_t)perm[r + t] * kc + qc] = (t == q) ? 1.0 : 0.0;
 }
 
 // x = S22^+ y restricted to the nonsingular pivots (kernel pivots get 0).
@@ -837,7 +846,8 @@ __global__ void k_kernel_out(int64_t n, int k, const double* __restrict__ N, dou
   const int64_t o = e / k;
   const int q = (int)(e - o * k);
   if (o >= n) return;
-  out[(int64_t)q * ldn + o] = N[e];
+  const int c = q / KC, kc = min(KC, k - c * KC);
+  out[(int64_t)q * ldn + o] = N[(int64_t)c * n * KC + o * kc + (q - c * KC)];
 }
 
 // ---------------------------------------------------------------------------
@@ -846,7 +856,7 @@ __global__ void k_kernel_out(int64_t n, int k, const double* __restrict__ N, dou
 
 struct BgcrWork {
   int64_t n = 0;
-  int m = 0, slots = 0;
+  int m = 0, kw = 0, slots = 0;
   DBuf P, Qv, R, Z, T1, partial, gram, Lc, piv, rank, coef, norms;
 };
 
@@ -855,19 +865,22 @@ void free_work(hf_ctx* ctx) {
   ctx->work = nullptr;
 }
 
-static BgcrWork& get_work(hf_ctx* ctx, int m) {
+// Work space of block GCR on m columns; kw: widest block of the kernel basis a
+// Gram product will pair with them (sizes the partial sums only).
+static BgcrWork& get_work(hf_ctx* ctx, int m, int kw = 0) {
   if (!ctx->work) ctx->work = new BgcrWork();
   BgcrWork& w = *ctx->work;
   const int slots = ctx->opt.gcr_maxit + 1;
-  if (w.n != ctx->n || w.m < m || w.slots < slots) {
+  if (w.n != ctx->n || w.m < m || w.kw < kw || w.slots < slots) {
     const int mm = std::max(m, w.m);
+    const int pw = std::max(std::max(mm, kw), w.kw);
     const size_t vec = (size_t)std::max<int64_t>(ctx->n, 1) * mm * sizeof(double);
     w.P.alloc(vec * slots);
     w.Qv.alloc(vec * slots);
     w.R.alloc(vec);
     w.Z.alloc(vec);
     w.T1.alloc(vec);
-    w.partial.alloc((size_t)slots * GRAM_WG * mm * mm * sizeof(double));
+    w.partial.alloc((size_t)slots * GRAM_WG * pw * pw * sizeof(double));
     w.gram.alloc((size_t)slots * MAXM * MAXM * sizeof(double));
     w.Lc.alloc((size_t)slots * MAXM * MAXM * sizeof(double));
     w.piv.alloc((size_t)slots * MAXM * sizeof(int32_t));
@@ -876,6 +889,7 @@ static BgcrWork& get_work(hf_ctx* ctx, int m) {
     w.norms.alloc((size_t)MAXM * sizeof(double));
     w.n = ctx->n;
     w.m = mm;
+    w.kw = pw;
     w.slots = slots;
   }
   return w;
@@ -1112,34 +1126,48 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
       ctx->rank_gap = info[3];
     }
     const int k = ctx->kdim;
-    if (k > MAXM) throw Status{HF_ERR_NOT_IMPLEMENTED};
+    if (k > KMAX) throw Status{HF_ERR_NOT_IMPLEMENTED};
     if (k > 0) {
-      // lift: N = [-X12 N2; N2], then Q Pi^T, then orthonormalize (CholeskyQR twice)
-      BgcrWork& w = get_work(ctx, std::max(mb, k));
+      // lift: N = [-X12 N2; N2], then Q Pi^T, then orthonormalize; KC columns at
+      // a time (block Gram-Schmidt against the earlier chunks, CholeskyQR of the
+      // chunk, both twice)
+      BgcrWork& w = get_work(ctx, mb, std::min(k, KC));
       const int rows = ctx->nblk * mb;
-      ctx->d_N2.alloc((size_t)rows * k * sizeof(double));
+      const int nkc = (k + KC - 1) / KC;
+      ctx->d_N2.alloc((size_t)rows * KC * nkc * sizeof(double));
       double* N2 = ctx->d_N2.as<double>();
-      HF_HIP(hipMemsetAsync(N2, 0, (size_t)rows * k * sizeof(double), s));
-      k_s22_null<<<1, 64, M <= MAXM ? (size_t)M * 64 * sizeof(double) : 0, s>>>(M, k, Lw, sperm, N2);
-      double* Nperm = w.T1.as<double>();
-      combine(ctx, n, mb, k, Nperm, nullptr, ctx->nblk, X12, (int64_t)n * mb, N2, s);
-      k_neg<<<cdiv(n * k, 256), 256, 0, s>>>(n * k, Nperm);
-      k_set_rows<<<cdiv((int64_t)M * k, 256), 256, 0, s>>>(M, k, ctx->d_l2.as<int32_t>(), N2, Nperm);
-      ctx->d_kern.alloc((size_t)n * k * sizeof(double));
-      double* N = ctx->d_kern.as<double>();
-      double* tmp = w.Z.as<double>();
-      k_kernel_finish<<<cdiv(n * k, 256), 256, 0, s>>>(n, k, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(),
-                                                       Nperm, tmp);
+      HF_HIP(hipMemsetAsync(N2, 0, (size_t)rows * KC * nkc * sizeof(double), s));
+      k_s22_null<<<(k + 63) / 64, 64, M <= MAXM ? (size_t)M * 64 * sizeof(double) : 0, s>>>(M, k, Lw, sperm, rows,
+                                                                                              N2);
+      ctx->d_kern.alloc((size_t)n * KC * nkc * sizeof(double));
+      double* Nall = ctx->d_kern.as<double>();
+      ctx->d_ktmp.alloc((size_t)n * KC * 2 * sizeof(double));
+      double* Nperm = ctx->d_ktmp.as<double>();
+      double* tmp = Nperm + (int64_t)n * KC;
       double* G = w.gram.as<double>();
       double* Ri = w.coef.as<double>();
-      for (int pass = 0; pass < 2; ++pass) {
-        double* src = pass == 0 ? tmp : N;
-        double* dst = pass == 0 ? N : tmp;
-        gram(ctx, n, k, src, 0, 1, k, src, G, s);
-        k_chol_inv<<<1, 64, 0, s>>>(k, G, Ri);
-        combine(ctx, n, k, k, dst, nullptr, 1, src, 0, Ri, s);
+      for (int c = 0; c < nkc; ++c) {
+        const int kc = kchunk(k, c);
+        const double* N2c = N2 + (int64_t)c * rows * KC;
+        double* Nc = Nall + (int64_t)c * n * KC;
+        combine(ctx, n, mb, kc, Nperm, nullptr, ctx->nblk, X12, (int64_t)n * mb, N2c, s);
+        k_neg<<<cdiv(n * kc, 256), 256, 0, s>>>(n * kc, Nperm);
+        k_set_rows<<<cdiv((int64_t)M * kc, 256), 256, 0, s>>>(M, kc, ctx->d_l2.as<int32_t>(), N2c, Nperm);
+        k_kernel_finish<<<cdiv(n * kc, 256), 256, 0, s>>>(n, kc, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(),
+                                                          Nperm, Nc);
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int d = 0; d < c; ++d) {  // Nc -= Nd (Nd^T Nc)
+            const double* Nd = Nall + (int64_t)d * n * KC;
+            gram(ctx, n, KC, Nd, 0, 1, kc, Nc, G, s);
+            k_neg<<<cdiv((int64_t)KC * kc, 256), 256, 0, s>>>((int64_t)KC * kc, G);
+            combine(ctx, n, KC, kc, Nc, Nc, 1, Nd, 0, G, s);
+          }
+          gram(ctx, n, kc, Nc, 0, 1, kc, Nc, G, s);
+          k_chol_inv<<<1, 64, 0, s>>>(kc, G, Ri);
+          combine(ctx, n, kc, kc, tmp, nullptr, 1, Nc, 0, Ri, s);
+          HF_HIP(hipMemcpyAsync(Nc, tmp, (size_t)n * kc * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
       }
-      HF_HIP(hipMemcpyAsync(N, tmp, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     HF_HIP(hipGetLastError());
     HF_HIP(hipStreamSynchronize(s));
@@ -1209,7 +1237,7 @@ int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, 
     ctx->hist.resize(ctx->hist_ptr.back());
     for (int c0 = 0; c0 < r; c0 += MAXM) {
       const int m = std::min(MAXM, r - c0);
-      BgcrWork& w = get_work(ctx, std::max(m, std::max(ctx->mb, k)));
+      BgcrWork& w = get_work(ctx, std::max(m, ctx->mb), std::min(k, KC));
       const int64_t nm = n * m;
       ctx->d_rhs_b.alloc((size_t)nm * sizeof(double) * 6);
       double* b = ctx->d_rhs_b.as<double>();
@@ -1221,11 +1249,13 @@ int solve_impl(hf_ctx* ctx, int32_t r, const double* B, int64_t ldb, double* X, 
       // x -> caller's variables, projected orthogonally to the detected kernel
       auto to_orig = [&](const double* xp, double* out) {
         k_unperm<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(), xp, out);
-        if (k > 0) {
-          double* G = w.gram.as<double>();
-          gram(ctx, n, k, ctx->d_kern.as<double>(), 0, 1, m, out, G, s);
-          k_neg<<<cdiv((int64_t)k * m, 256), 256, 0, s>>>((int64_t)k * m, G);
-          combine(ctx, n, k, m, out, out, 1, ctx->d_kern.as<double>(), 0, G, s);
+        double* G = w.gram.as<double>();
+        for (int c = 0; c * KC < k; ++c) {  // the chunks are orthonormal to each other
+          const int kc = kchunk(k, c);
+          const double* Nc = ctx->d_kern.as<double>() + (int64_t)c * n * KC;
+          gram(ctx, n, kc, Nc, 0, 1, m, out, G, s);
+          k_neg<<<cdiv((int64_t)kc * m, 256), 256, 0, s>>>((int64_t)kc * m, G);
+          combine(ctx, n, kc, m, out, out, 1, Nc, 0, G, s);
         }
       };
       k_load_rhs<<<cdiv(nm, 256), 256, 0, s>>>(n, m, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(), B, ldb,
@@ -1352,16 +1382,18 @@ int adjoint_impl(hf_ctx* ctx, int32_t r, const double* X, int64_t ldx, const dou
     double* P = ctx->d_adj.as<double>();
     for (int c0 = 0; c0 < r; c0 += MAXM) {
       const int m = std::min(MAXM, r - c0);
-      BgcrWork& w = get_work(ctx, std::max(m, std::max(ctx->mb, k)));
+      BgcrWork& w = get_work(ctx, std::max(m, ctx->mb), std::min(k, KC));
       const int64_t nm = n * m;
       ctx->d_rhs_b.alloc((size_t)nm * sizeof(double) * 6);
       double* t = ctx->d_rhs_b.as<double>();
       k_take_cols<<<cdiv(nm, 256), 256, 0, s>>>(n, m, G, ldg, c0, t);
-      if (k > 0) {
-        double* C = w.gram.as<double>();
-        gram(ctx, n, k, Nk, 0, 1, m, t, C, s);
-        k_neg<<<cdiv((int64_t)k * m, 256), 256, 0, s>>>((int64_t)k * m, C);
-        combine(ctx, n, k, m, t, t, 1, Nk, 0, C, s);
+      double* C = w.gram.as<double>();
+      for (int c = 0; c * KC < k; ++c) {
+        const int kc = kchunk(k, c);
+        const double* Nc = Nk + (int64_t)c * n * KC;
+        gram(ctx, n, kc, Nc, 0, 1, m, t, C, s);
+        k_neg<<<cdiv((int64_t)kc * m, 256), 256, 0, s>>>((int64_t)kc * m, C);
+        combine(ctx, n, kc, m, t, t, 1, Nc, 0, C, s);
       }
       k_store_cols<<<cdiv(nm, 256), 256, 0, s>>>(n, m, t, P, n, c0);
       HF_HIP(hipGetLastError());

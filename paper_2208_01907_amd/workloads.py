@@ -500,6 +500,64 @@ def inclusions3d(n, n_incl, seed, radius=(2.0, 6.0), value=1e6, leaf_max=512, r=
                     "incl_frac": float((coef > 1).mean())})
 
 
+def neumann3d(n, seed, lo=-3.0, hi=3.0, leaf_max=512, r=8, tau=1e-2, gcr_block=8):
+    """3D pure-Neumann 7-point FV Laplacian on n^3 cells with per-cell
+    coefficient 10^U(lo,hi) and harmonic-mean faces (the 2D model in 3D)."""
+    rng = np.random.default_rng(seed)
+    coef = 10.0 ** rng.uniform(lo, hi, size=(n, n, n))
+    K = fv_laplacian(coef)
+    perm, node_ptr, parent = grid_nested_dissection((n, n, n), leaf_max)
+    kernel = np.ones((n ** 3, 1))
+    return _finish(f"neumann3d_{n}", K, perm, node_ptr, parent, kernel, r, seed, tau, gcr_block,
+                   {"grid": (n, n, n), "leaf_max": leaf_max, "seed": seed})
+
+
+def batch(parts, name, tau=None, gcr_block=None):
+    """Many independent systems as one block-diagonal matrix.
+
+    The nested-dissection trees of the parts become one forest (node ranges and
+    parents shifted, every part's root a root), so a factorization level holds
+    the fronts of every part at that height and one launch serves them all; the
+    right-hand sides are stacked row-wise (column c of the batch holds column c of
+    every part) and the kernel basis is block-diagonal.  meta['offsets'] gives
+    each part's first row."""
+    r = parts[0].b.shape[1]
+    assert all(W.b.shape[1] == r for W in parts)
+    offs = np.cumsum([0] + [W.n for W in parts])
+    noffs = np.cumsum([0] + [W.n_nodes for W in parts])
+    K = sp.block_diag([W.csr() for W in parts], format="csr")
+    K.sort_indices()
+    perm = np.concatenate([W.perm.astype(np.int64) + o for W, o in zip(parts, offs)]).astype(np.int32)
+    node_ptr = np.concatenate([W.node_ptr[:-1].astype(np.int64) + o for W, o in zip(parts, offs)] +
+                              [np.array([offs[-1]])]).astype(np.int32)
+    parent = np.concatenate([np.where(W.parent >= 0, W.parent.astype(np.int64) + o, -1)
+                             for W, o in zip(parts, noffs)]).astype(np.int32)
+    ktot = sum(W.kernel.shape[1] for W in parts)
+    kernel = np.zeros((offs[-1], ktot))
+    c = 0
+    for W, o in zip(parts, offs):
+        kernel[o:o + W.n, c:c + W.kernel.shape[1]] = W.kernel
+        c += W.kernel.shape[1]
+    x_star = np.concatenate([W.x_star for W in parts])
+    b = np.concatenate([W.b for W in parts])
+    return Workload(name=name, indptr=K.indptr.astype(np.int64), indices=K.indices.astype(np.int32),
+                    values=K.data.astype(np.float64), perm=perm, node_ptr=node_ptr, parent=parent,
+                    kernel=kernel, x_star=x_star, b=b, tau=parts[0].tau if tau is None else tau,
+                    gcr_block=parts[0].gcr_block if gcr_block is None else gcr_block,
+                    meta={"parts": [W.name for W in parts], "offsets": offs.tolist(), "count": len(parts)})
+
+
+def neumann3d_batch(count, seed, lo_n, hi_n, leaf_max=512, r=8, tau=1e-2, gcr_block=8):
+    """count 3D Neumann Laplacians (neumann3d) with sides n ~ U{lo_n..hi_n}."""
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(lo_n, hi_n + 1, size=count)
+    parts = [neumann3d(int(n), seed=1000 * seed + i, leaf_max=leaf_max, r=r, tau=tau, gcr_block=gcr_block)
+             for i, n in enumerate(sides)]
+    W = batch(parts, f"neumann3d_batch{count}_{lo_n}to{hi_n}")
+    W.meta.update({"sides": sides.tolist(), "leaf_max": leaf_max, "seed": seed})
+    return W
+
+
 def elasticity(ne, seed, lo=0.0, hi=6.0, leaf_max=64, r=32, tau=1e-2, gcr_block=32):
     """Floating Q1 elastic cube with per-element Young's modulus 10^U(lo,hi), nu=0.3."""
     rng = np.random.default_rng(seed)
@@ -566,7 +624,15 @@ def config_c4():
     return stokes_mac(32, seed=4, leaf_max=512, r=32, tau=1e-2, gcr_block=0)
 
 
-CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4}
+def config_c5():
+    """96 independent 3D pure-Neumann Laplacians (the 2D configuration's coefficient
+    model, 10^U(-3,3) per cell, harmonic faces) with sides n ~ U{16..40}, as one
+    block-diagonal batch; 8 RHS and Schur-complement blocks of 8 columns, tau 1e-2,
+    nested-dissection leaves of at most 512 cells; kernel = one constant per part."""
+    return neumann3d_batch(96, seed=5, lo_n=16, hi_n=40, leaf_max=512, r=8, tau=1e-2, gcr_block=8)
+
+
+CONFIGS = {"c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4, "c5": config_c5}
 
 
 def single_node_tree(n):

@@ -50,6 +50,16 @@ CASES = {
     "dense_k2": lambda: w.random_dense_workload(150, seed=10, kernel_dim=2, cond=1e3, r=3),
     "dense_indef_all_postponed": lambda: w.random_dense_workload(40, seed=11, indefinite=True, cond=1e2,
                                                                  r=2, tau=2.0),
+    # batches: independent systems as one block-diagonal forest (k = number of parts)
+    "batch6": lambda: w.neumann3d_batch(6, seed=7, lo_n=5, hi_n=9, leaf_max=64, r=2, gcr_block=4),
+    "batch_mixed": lambda: w.batch([w.neumann2d(20, 18, seed=13, leaf_max=30, r=2),
+                                    w.neumann3d(8, seed=14, leaf_max=64, r=2),
+                                    w.elasticity(4, seed=15, leaf_max=27, r=2),
+                                    w.neumann2d(9, 31, seed=16, leaf_max=40, r=2)],
+                                   "batch_mixed", gcr_block=3),
+    # k = 70 > 64: the kernel basis in two column chunks, S22 (M >= 70) in global memory
+    "batch70": lambda: w.batch([w.neumann2d(6 + i % 3, 5 + i % 4, seed=200 + i, leaf_max=12, r=2)
+                                for i in range(70)], "batch70", gcr_block=16),
 }
 
 
@@ -261,6 +271,39 @@ def test_fp16_products(name, prec):
     assert hy.hf_kernel_dim(ctx) == ref.k
     assert rel <= 1e-10
     assert be <= 1e-14
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_batch_equals_parts(prec):
+    """A batch (block-diagonal forest) factorized and solved at once gives every
+    part's own result: the hard part is the union of the parts' hard parts, k the
+    sum of theirs, each part's rows of the solution equal that part's solution on
+    its own (relative 1e-10; both are the minimum-norm solution of the same
+    system), and the kernel basis spans the parts' kernels."""
+    parts = [w.neumann3d(n, seed=70 + i, leaf_max=64, r=3, gcr_block=4) for i, n in enumerate((6, 9, 5, 8, 7))]
+    parts.append(w.neumann2d(17, 13, seed=77, leaf_max=30, r=3))
+    W = w.batch(parts, "parts6", gcr_block=4)
+    ctx = _gpu(W, prec)
+    X = hy.hf_solve(ctx, torch.tensor(W.b, device="cuda")).cpu().numpy()
+    offs = W.meta["offsets"]
+    M = 0
+    lam_all = []
+    for i, Wi in enumerate(parts):
+        ci = _gpu(Wi, prec)
+        Xi = hy.hf_solve(ci, torch.tensor(Wi.b, device="cuda")).cpu().numpy()
+        rel = np.linalg.norm(X[offs[i]:offs[i + 1]] - Xi) / np.linalg.norm(Xi)
+        assert rel <= 1e-10, (i, rel)
+        assert oracle.backward_error(Wi.csr(), X[offs[i]:offs[i + 1]], Wi.b) <= 1e-14
+        li, _ = hy.hf_schur(ci)
+        lam_all.append(li + offs[i])
+        M += hy.hf_info(ci)["M"]
+    lam, _ = hy.hf_schur(ctx)
+    if prec == 64:  # FP32: launch shapes (and so rounding) depend on the level's other fronts
+        assert hy.hf_info(ctx)["M"] == M
+        assert np.array_equal(lam, np.sort(np.concatenate(lam_all)))
+    assert hy.hf_kernel_dim(ctx) == len(parts)
+    N = hy.hf_kernel_basis(ctx).cpu().numpy()
+    assert np.all(_principal_cos(N, W.kernel) > 1 - 1e-8)
 
 
 def test_expected_kernel_dims():
