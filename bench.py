@@ -302,6 +302,22 @@ def cpu_baseline(W, cfg, full=False):
     return out
 
 
+def batch_gates(W, X):
+    """Per-system gate numbers of a batch (block-diagonal forest): the largest
+    backward error and the largest relative error against x* over its systems."""
+    import numpy as np
+    from paper_2208_01907_amd.metrics import backward_error
+    K = W.csr()
+    offs = W.meta["offsets"]
+    be, rel = [], []
+    for i in range(len(offs) - 1):
+        a, b = offs[i], offs[i + 1]
+        be.append(backward_error(K[a:b, a:b], X[a:b], W.b[a:b]))
+        rel.append(float(np.linalg.norm(X[a:b] - W.x_star[a:b]) / np.linalg.norm(W.x_star[a:b])))
+    return {"systems": len(offs) - 1, "backward_error_max": max(be), "gate_1e-14_every_system": bool(max(be) <= 1e-14),
+            "rel_err_vs_xstar_max": max(rel)}
+
+
 def golden_rel(cfg, X):
     """Relative difference between X and the oracle's FP64 minimum-norm solution
     stored for this workload (tests/golden, written by the oracle), over the
@@ -402,6 +418,8 @@ def main():
         "roofline": roofline(stats, args.steps, 32),
         "path_roofline": path_roofline(stats, args.steps, 32, dt * 1e3),
     }
+    if "offsets" in W.meta:  # a batch: the gate holds for every system on its own
+        result["batch"] = batch_gates(W, Xh)
     result["adjoint"] = adjoint_timing(hy, ctx, X, W, args.steps, torch)
     del ctx
     if not args.no_fp64:

@@ -264,8 +264,9 @@ k_inv_merge(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ st
 
 // The forward gather of a level in one launch: every front row takes its own
 // accepted value from the FP64 input (0 for postponed and border rows) plus the
-// border rows of the children that map onto it, in child-rank order.  Thread
-// (a, col) for assembly position a; own rows land at their pivot position.
+// border rows of the children that map onto it, in child-rank order.  One
+// thread per (assembly position, block of 16 right-hand sides), so the row's
+// index loads serve its 16 values; own rows land at their pivot position.
 template <class T>
 __global__ void __launch_bounds__(256)
 k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
@@ -275,14 +276,49 @@ k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
+  const int nch = (m + 15) >> 4;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)ni.f * m) return;
-  const int a = (int)(e / m), col = (int)(e - (int64_t)a * m);
+  if (e >= (int64_t)ni.f * nch) return;
+  const int a = (int)(e / nch), c0 = 16 * (int)(e - (int64_t)a * nch);
+  const int nc = min(16, m - c0);
   const int pr = a < ni.p ? ipos[ni.start + a] : a;
-  T v = (a < ni.p && pr < npiv) ? (T)R[(int64_t)(ni.start + a) * m + col] : (T)0;
+  T v[16];
+  const bool own = a < ni.p && pr < npiv;
+  const double* src0 = R + (int64_t)(ni.start + a) * m + c0;
+  if (nc == 16) {  // whole blocks move in 16-byte pieces
+#pragma unroll
+    for (int c = 0; c < 16; c += 2) {
+      double x[2] = {0.0, 0.0};
+      if (own) __builtin_memcpy(x, src0 + c, 16);
+      v[c] = (T)x[0];
+      v[c + 1] = (T)x[1];
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[c] = (own && c < nc) ? (T)src0[c] : (T)0;
+  }
   const int64_t slot = ni.rhs_off + a;
-  for (int64_t i = gat_ptr[slot]; i < gat_ptr[slot + 1]; ++i) v += rb[gat_src[i] * m + col];
-  rb[(ni.rhs_off + pr) * m + col] = v;
+  for (int64_t i = gat_ptr[slot]; i < gat_ptr[slot + 1]; ++i) {
+    const T* src = rb + gat_src[i] * m + c0;
+    if (nc == 16) {
+      T x[16];
+      __builtin_memcpy(x, src, 16 * sizeof(T));
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v[c] += x[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < nc) v[c] += src[c];
+    }
+  }
+  T* dst = rb + (ni.rhs_off + pr) * m + c0;
+  if (nc == 16) {
+    __builtin_memcpy(dst, v, 16 * sizeof(T));
+  } else {
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c < nc) dst[c] = v[c];
+  }
 }
 
 // z_J = Linv_J w_J; four workgroups (64 rows each) per front, matrix cores
@@ -364,12 +400,29 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_bwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
              const int32_t* __restrict__ border, int m, const double* __restrict__ Y, T* __restrict__ rb) {
+  // one thread per (border row, block of 16 right-hand sides)
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
+  const int nch = (m + 15) >> 4;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)ni.b * m) return;
-  const int r = (int)(e / m), c = (int)(e - (int64_t)r * m);
-  rb[(ni.rhs_off + ni.p + r) * m + c] = (T)Y[(int64_t)border[ni.border_off + r] * m + c];
+  if (e >= (int64_t)ni.b * nch) return;
+  const int r = (int)(e / nch), c0 = 16 * (int)(e - (int64_t)r * nch);
+  const int nc = min(16, m - c0);
+  const double* src = Y + (int64_t)border[ni.border_off + r] * m + c0;
+  T* dst = rb + (ni.rhs_off + ni.p + r) * m + c0;
+  if (nc == 16) {
+    T v[16];
+#pragma unroll
+    for (int c = 0; c < 16; c += 2) {
+      double x[2];
+      __builtin_memcpy(x, src + c, 16);
+      v[c] = (T)x[0];
+      v[c + 1] = (T)x[1];
+    }
+    __builtin_memcpy(dst, v, 16 * sizeof(T));
+  } else {
+    for (int c = 0; c < nc; ++c) dst[c] = (T)src[c];
+  }
 }
 
 // With FIN (every front of the level has one chunk) the product goes straight
@@ -1260,7 +1313,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       }
     });
     launch_timed(tm, HF_K_SOLVE_GATHER, wg.first, wg.second, s, k_fwd_gather<T>,
-                 dim3(cdiv((int64_t)maxf * m, 256), nl), dim3(256), ln, nodes, st,
+                 dim3(cdiv((int64_t)maxf * cdiv(m, 16), 256), nl), dim3(256), ln, nodes, st,
                  (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
                  (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, rb);
     const int tb = step_of(nl);
@@ -1336,7 +1389,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         by += ni.b * dm * (8.0 + sz);
       });
       timed(tm, HF_K_SOLVE_GATHER, wy.first, 0.0, s, [&] {
-        dim3 gy(cdiv((int64_t)ctx->level_maxb[l] * m, 256), nl);
+        dim3 gy(cdiv((int64_t)ctx->level_maxb[l] * cdiv(m, 16), 256), nl);
         k_bwd_gather<T><<<gy, 256, 0, s>>>(ln, nodes, ctx->d_border.as<int32_t>(), m, Y, rb);
       });
       dim3 gp(cdiv(maxp, 64), maxch, nl);
