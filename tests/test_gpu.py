@@ -306,6 +306,25 @@ def test_batch_equals_parts(prec):
     assert np.all(_principal_cos(N, W.kernel) > 1 - 1e-8)
 
 
+def test_batch_c5_full_size():
+    """The 96-system batch at full size (2.3 million unknowns), FP32 step 1: one
+    kernel vector per system (k = 96, the closed form: constants on each system),
+    the basis spanning the per-system constants, and every system's backward error
+    at most 1e-14 on its own.  Parity of batches with the oracle element by
+    element is covered by the small batches of test_parity."""
+    W = w.config_c5()
+    ctx = _gpu(W, 32)
+    assert hy.hf_kernel_dim(ctx) == 96
+    N = hy.hf_kernel_basis(ctx).cpu().numpy()
+    assert np.all(_principal_cos(N, W.kernel) > 1 - 1e-8)
+    X = hy.hf_solve(ctx, torch.tensor(W.b, device="cuda")).cpu().numpy()
+    K = W.csr()
+    offs = W.meta["offsets"]
+    worst = max(oracle.backward_error(K[a:b, a:b], X[a:b], W.b[a:b]) for a, b in zip(offs[:-1], offs[1:]))
+    print(f"  c5: M={hy.hf_info(ctx)['M']} worst per-system backward error {worst:.2e}", flush=True)
+    assert worst <= 1e-14
+
+
 def test_expected_kernel_dims():
     """Closed forms: Neumann Laplacian -> constants (k = 1); floating body -> rigid modes (k = 6)."""
     for W, k, Z in ((w.config_c1(), 1, np.ones((1024, 1))),

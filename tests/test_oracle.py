@@ -7,6 +7,9 @@ states (orthogonality of GCR, Sec. 3.3).
 """
 import math
 
+import json
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -264,6 +267,29 @@ def test_elasticity_cube_tau_rule():
     f64 = oracle.factor_low(Kp, W.node_ptr, W.parent, 0.2, dtype=np.float64, borders=bd)
     assert f32.M == f64.M == 6
     assert oracle.factor_low(Kp, W.node_ptr, W.parent, 0.1, dtype=np.float32, borders=bd).M < 6
+
+
+def test_batch_tau_rule():
+    """The threshold of the 96-system batch follows its stated rule, recorded by
+    tests/golden/make_c5_tau.py (oracle only): at the configured tau the FP32
+    step 1 postpones at least one index of every system, at the grid value below
+    at least one system postpones nothing.  Re-checked here with the oracle on the
+    smallest system that fails at the grid value below."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "c5_tau.json")
+    rec = json.load(open(path))
+    tau = rec["tau"]
+    grid = list(w.C3_TAU_GRID)
+    below = grid[grid.index(tau) - 1]
+    assert w.config_c5.__doc__ and f"{tau}" in w.config_c5.__doc__
+    assert min(rec["M_fp32"][str(tau)]) >= 1 and min(rec["M_fp32"][str(below)]) == 0
+    fails = [i for i, m in enumerate(rec["M_fp32"][str(below)]) if m == 0]
+    i = min(fails, key=lambda i: rec["sides"][i])
+    Wi = w.neumann3d(rec["sides"][i], seed=5000 + i, leaf_max=512, r=1)
+    q, K = oracle.scale(Wi.csr())
+    Kp = oracle.permute(K, Wi.perm)
+    bd = oracle.symbolic(Kp, Wi.node_ptr, Wi.parent)
+    assert oracle.factor_low(Kp, Wi.node_ptr, Wi.parent, below, dtype=np.float32, borders=bd).M == 0
+    assert oracle.factor_low(Kp, Wi.node_ptr, Wi.parent, tau, dtype=np.float32, borders=bd).M >= 1
 
 
 def test_decided_nodes_rule():
