@@ -36,37 +36,54 @@ static inline int kchunk(int k, int c) { return std::min(KC, k - c * KC); }
 // SpMM and friends
 // ---------------------------------------------------------------------------
 
-// Y = K11 W (rows and columns of the hard part masked out)
+// Y = K11 W (rows and columns of the hard part masked out); one thread per (row,
+// pair of columns), the pair moved in 16-byte pieces
 __global__ void k_spmm_k11(int64_t n, const int64_t* __restrict__ ip, const int32_t* __restrict__ ix,
                            const double* __restrict__ kv, const uint8_t* __restrict__ isl2, int m,
                            const double* __restrict__ W, double* __restrict__ Y) {
+  const int mh = (m + 1) >> 1;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t row = e / m;
-  const int col = (int)(e - row * m);
+  const int64_t row = e / mh;
+  const int col = 2 * (int)(e - row * mh);
   if (row >= n) return;
-  double acc = 0.0;
+  const bool two = col + 1 < m;
+  double acc0 = 0.0, acc1 = 0.0;
   if (!isl2[row]) {
     const int64_t q1 = ip[row + 1];
     for (int64_t q0 = ip[row]; q0 < q1; q0 += 8) {  // eight entries' loads in flight, summed in order
-      double a[8], wv[8];
+      double a[8], w0[8], w1[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         a[i] = 0.0;
-        wv[i] = 0.0;
+        w0[i] = 0.0;
+        w1[i] = 0.0;
         if (q0 + i < q1) {
           const int32_t c = ix[q0 + i];
           if (!isl2[c]) {
             a[i] = kv[q0 + i];
-            wv[i] = W[(int64_t)c * m + col];
+            const double* src = W + (int64_t)c * m + col;
+            if (two) {
+              double x[2];
+              __builtin_memcpy(x, src, 16);
+              w0[i] = x[0];
+              w1[i] = x[1];
+            } else {
+              w0[i] = src[0];
+            }
           }
         }
       }
 #pragma unroll
       for (int i = 0; i < 8; ++i)
-        if (q0 + i < q1) acc += a[i] * wv[i];
+        if (q0 + i < q1) {
+          acc0 += a[i] * w0[i];
+          acc1 += a[i] * w1[i];
+        }
     }
   }
-  Y[e] = acc;
+  double* dst = Y + row * m + col;
+  dst[0] = acc0;
+  if (two) dst[1] = acc1;
 }
 
 // Residual of the caller's system, returned scaled and in elimination order:
@@ -452,18 +469,21 @@ k_combine(int64_t n, int a, int b, double* out, const double* base, int nterms,
 
 __device__ inline double& at(double* A, int M, int r, int c) { return A[(int64_t)c * M + r]; }
 
-__global__ void __launch_bounds__(256)
+constexpr int S22_NT = 1024;  // threads of the S22 factorization (16 waves)
+
+__global__ void __launch_bounds__(S22_NT)
 k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __restrict__ D,
            int32_t* __restrict__ perm, double* __restrict__ mags, int32_t* __restrict__ bsize,
            double tau, int n_enlarge, double ker_tol, double* __restrict__ info) {
+  constexpr int NT = S22_NT, NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double alpha = (1.0 + sqrt(17.0)) / 8.0;
-  __shared__ double rv[4];
-  __shared__ int rk[4];
+  __shared__ double rv[NW];
+  __shared__ int rk[NW];
   __shared__ double sA[MAXM * MAXM];  // the working copy stays in LDS when it fits
   double* A = (M <= MAXM) ? sA : Ag;
   if (M <= MAXM)
-    for (int e = tid; e < M * M; e += 256) sA[e] = Ag[e];
+    for (int e = tid; e < M * M; e += NT) sA[e] = Ag[e];
   // workgroup argmax of (v, k): largest v, ties to the smallest k; uniform result
   auto argmax = [&](double& v, int& k) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -476,66 +496,74 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
     __syncthreads();
     v = rv[0];
     k = rk[0];
-    for (int w = 1; w < 4; ++w)
+    for (int w = 1; w < NW; ++w)
       if (rv[w] > v || (rv[w] == v && rk[w] < k)) { v = rv[w]; k = rk[w]; }
   };
-  for (int64_t e = tid; e < (int64_t)M * M; e += 256) {
+  for (int64_t e = tid; e < (int64_t)M * M; e += NT) {
     const int r = (int)(e % M), c = (int)(e / M);
     L[e] = (r == c) ? 1.0 : 0.0;
     D[e] = 0.0;
   }
-  for (int e = tid; e < M; e += 256) { perm[e] = e; mags[e] = 0.0; bsize[e] = 1; }
+  for (int e = tid; e < M; e += NT) { perm[e] = e; mags[e] = 0.0; bsize[e] = 1; }
   __syncthreads();
   auto swap = [&](int i, int k) {
     if (i == k) return;
-    for (int t = tid; t < M; t += 256) { const double x = at(A, M, i, t); at(A, M, i, t) = at(A, M, k, t); at(A, M, k, t) = x; }
+    for (int t = tid; t < M; t += NT) { const double x = at(A, M, i, t); at(A, M, i, t) = at(A, M, k, t); at(A, M, k, t) = x; }
     __syncthreads();
-    for (int t = tid; t < M; t += 256) { const double x = at(A, M, t, i); at(A, M, t, i) = at(A, M, t, k); at(A, M, t, k) = x; }
-    for (int t = tid; t < i; t += 256) { const double x = at(L, M, i, t); at(L, M, i, t) = at(L, M, k, t); at(L, M, k, t) = x; }
+    for (int t = tid; t < M; t += NT) { const double x = at(A, M, t, i); at(A, M, t, i) = at(A, M, t, k); at(A, M, t, k) = x; }
+    for (int t = tid; t < i; t += NT) { const double x = at(L, M, i, t); at(L, M, i, t) = at(L, M, k, t); at(L, M, k, t) = x; }
     if (tid == 0) { const int32_t x = perm[i]; perm[i] = perm[k]; perm[k] = x; }
     __syncthreads();
   };
+  // candidates of the trailing block starting at i0, gathered by this thread:
+  // largest |diagonal| (position t, first occurrence) and largest |off-diagonal|
+  // of the upper triangle (row-major index e over the block, first occurrence).
+  // The trailing update of a step produces them for the next step's block as it
+  // writes it, so the block is not read a second time.
+  double bv = -1.0, ov = -1.0;
+  int bk = INT_MAX, ok = INT_MAX;
+  auto consider = [&](int i0, int r, int c, double v) {
+    const int w = M - i0, rr = r - i0, cc = c - i0;
+    const double x = fabs(v);
+    if (rr == cc) {
+      if (x > bv || (x == bv && rr < bk)) { bv = x; bk = rr; }
+    } else if (rr < cc) {
+      const int e = rr * w + cc;
+      if (x > ov || (x == ov && e < ok)) { ov = x; ok = e; }
+    }
+  };
+  for (int c = wv; c < M; c += NW)  // the first block: read once
+    for (int r = lane; r <= c; r += 64) consider(0, r, c, at(A, M, r, c));
   int i = 0;
   while (i < M) {
     const int w = M - i;
-    // largest |diagonal| (first occurrence)
-    double bv = -1.0;
-    int bk = INT_MAX;
-    for (int t = tid; t < w; t += 256) {
-      const double v = fabs(at(A, M, i + t, i + t));
-      if (v > bv) { bv = v; bk = t; }
-    }
     argmax(bv, bk);
     const double gd = bv;
     const int kd = bk;
-    // largest |off-diagonal| (first in row-major order over the upper triangle)
-    double ov = -1.0;
-    int ok = INT_MAX;
-    for (int r = wv; r < w; r += 4)
-      for (int c = r + 1 + lane; c < w; c += 64) {
-        const double v = fabs(at(A, M, i + r, i + c));
-        const int e = r * w + c;
-        if (v > ov || (v == ov && e < ok)) { ov = v; ok = e; }
-      }
     argmax(ov, ok);
     const double go = (w > 1) ? ov : 0.0;
+    const int s_r = (w > 1) ? ok / w : 0;
+    const int s_c = (w > 1) ? ok % w : 0;
+    bv = -1.0; ov = -1.0; bk = INT_MAX; ok = INT_MAX;  // this step's update gathers the next block's
     int mode;
     if (gd == 0.0 && go == 0.0) mode = 0;
     else if (gd >= alpha * go) mode = 1;
     else mode = 2;
-    const int s_r = (w > 1) ? ok / w : 0;
-    const int s_c = (w > 1) ? ok % w : 0;
     if (mode == 0) break;  // exactly zero remainder: zero pivots
     if (mode == 1) {
       swap(i, i + kd);
       const double d = at(A, M, i, i);
       at(D, M, i, i) = d;
-      for (int r = i + 1 + tid; r < M; r += 256) at(L, M, r, i) = at(A, M, r, i) / d;
+      for (int r = i + 1 + tid; r < M; r += NT) at(L, M, r, i) = at(A, M, r, i) / d;
       __syncthreads();
-      for (int c = i + 1 + wv; c < M; c += 4)
-        for (int r = i + 1 + lane; r < M; r += 64) at(A, M, r, c) -= at(L, M, r, i) * at(A, M, i, c);
+      for (int c = i + 1 + wv; c < M; c += NW)
+        for (int r = i + 1 + lane; r < M; r += 64) {
+          const double v = at(A, M, r, c) - at(L, M, r, i) * at(A, M, i, c);
+          at(A, M, r, c) = v;
+          consider(i + 1, r, c, v);
+        }
       __syncthreads();
-      for (int r = i + 1 + tid; r < M; r += 256) { at(A, M, r, i) = 0.0; at(A, M, i, r) = 0.0; }
+      for (int r = i + 1 + tid; r < M; r += NT) { at(A, M, r, i) = 0.0; at(A, M, i, r) = 0.0; }
       if (tid == 0) mags[i] = fabs(d);
       __syncthreads();
       i += 1;
@@ -546,17 +574,21 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
       const double e11 = at(A, M, i, i), e12 = at(A, M, i + 1, i), e22 = at(A, M, i + 1, i + 1);
       const double det = e11 * e22 - e12 * e12;
       // Lc = C E^{-1}, C = A[i+2:, i:i+2]
-      for (int rr = i + 2 + tid; rr < M; rr += 256) {
+      for (int rr = i + 2 + tid; rr < M; rr += NT) {
         const double c1 = at(A, M, rr, i), c2 = at(A, M, rr, i + 1);
         at(L, M, rr, i) = (c1 * e22 - c2 * e12) / det;
         at(L, M, rr, i + 1) = (c2 * e11 - c1 * e12) / det;
       }
       __syncthreads();
-      for (int cc = i + 2 + wv; cc < M; cc += 4)
-        for (int rr = i + 2 + lane; rr < M; rr += 64)
-          at(A, M, rr, cc) -= at(L, M, rr, i) * at(A, M, cc, i) + at(L, M, rr, i + 1) * at(A, M, cc, i + 1);
+      for (int cc = i + 2 + wv; cc < M; cc += NW)
+        for (int rr = i + 2 + lane; rr < M; rr += 64) {
+          const double v =
+              at(A, M, rr, cc) - (at(L, M, rr, i) * at(A, M, cc, i) + at(L, M, rr, i + 1) * at(A, M, cc, i + 1));
+          at(A, M, rr, cc) = v;
+          consider(i + 2, rr, cc, v);
+        }
       __syncthreads();
-      for (int rr = i + 2 + tid; rr < M; rr += 256) {
+      for (int rr = i + 2 + tid; rr < M; rr += NT) {
         at(A, M, rr, i) = 0.0; at(A, M, i, rr) = 0.0;
         at(A, M, rr, i + 1) = 0.0; at(A, M, i + 1, rr) = 0.0;
       }
@@ -912,7 +944,8 @@ static void spmm_k11(hf_ctx* ctx, int m, const double* W, double* Y, hipStream_t
   const int64_t nm = ctx->n * m;
   if (nm == 0) return;
   const double by = ctx->nnz * 12.0 + ctx->n * 8.0 + 2.0 * nm * 8.0, fl = 2.0 * ctx->nnz * m;
-  launch_timed(ctx->timer, HF_K_SPMM, by, fl, s, k_spmm_k11, dim3((unsigned)cdiv(nm, 256)), dim3(256), ctx->n,
+  launch_timed(ctx->timer, HF_K_SPMM, by, fl, s, k_spmm_k11, dim3((unsigned)cdiv(ctx->n * ((m + 1) / 2), 256)),
+               dim3(256), ctx->n,
                ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(), ctx->d_kval.as<double>(),
                ctx->d_isl2.as<uint8_t>(), m, W, Y);
 }
@@ -1096,6 +1129,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
     ctx->d_S22.alloc((size_t)std::max(M, 1) * std::max(M, 1) * sizeof(double));
     ctx->d_S22f.alloc((size_t)std::max(M, 1) * std::max(M, 1) * sizeof(double) * 3);
     ctx->d_s22perm.alloc((size_t)std::max(M, 1) * sizeof(int32_t) * 2);
+    if (M > 46340) throw Status{HF_ERR_NOT_IMPLEMENTED};  // S22 positions are int32 in its factorization
     ctx->d_s22mag.alloc((size_t)std::max(M, 1) * sizeof(double));
     ctx->d_s22info.alloc(8 * sizeof(double));
     double* S = ctx->d_S22.as<double>();
@@ -1116,7 +1150,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
       }
       k_symmetrize<<<cdiv((int64_t)M * M, 256), 256, 0, s>>>(M, S);
       HF_HIP(hipMemcpyAsync(Aw, S, sizeof(double) * M * M, hipMemcpyDeviceToDevice, s));
-      k_s22_ldlt<<<1, 256, 0, s>>>(M, Aw, Lw, Dw, sperm, ctx->d_s22mag.as<double>(), sbs, ctx->opt.tau,
+      k_s22_ldlt<<<1, S22_NT, 0, s>>>(M, Aw, Lw, Dw, sperm, ctx->d_s22mag.as<double>(), sbs, ctx->opt.tau,
                                    ctx->opt.n_enlarge, ctx->opt.ker_tol, ctx->d_s22info.as<double>());
       double info[4];
       HF_HIP(hipMemcpyAsync(info, ctx->d_s22info.ptr, sizeof(info), hipMemcpyDeviceToHost, s));
