@@ -427,7 +427,10 @@ def main():
                                                                  args.warmup, torch)
         X64h = X64.cpu().numpy()
         be64 = backward_error(W.csr(), X64h, W.b)
-        result["fp64"] = {"s_per_step": dt64, "s_per_step_with_events": dt64_ev, "M": info64["M"],
+        result["fp64"] = {"what": "the same pipeline (Algorithm 1, Algorithm 2 with the correction pass) with an "
+                                  "FP64 step 1: the supernodal LDL^T in FP64, after which block GCR needs one "
+                                  "iteration",
+                          "s_per_step": dt64, "s_per_step_with_events": dt64_ev, "M": info64["M"],
                           "kernel_dim": info64["kernel_dim"],
                           "backward_error": be64, "rel_vs_oracle": golden_rel(args.config, X64h),
                           "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in stats64.items()},
