@@ -62,7 +62,9 @@ def parse():
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-full", action="store_true",
-                    help="time the oracle on the whole workload (many minutes) instead of the bounded sample")
+                    help="time the oracle on the whole workload whatever its size")
+    ap.add_argument("--cpu-baseline-sample", action="store_true",
+                    help="time the oracle on the subtree sample only")
     ap.add_argument("--cpu-baseline-only", action="store_true",
                     help="run only the oracle timing (no GPU) and print it as JSON")
     ap.add_argument("--calib-copy", action="store_true",
@@ -237,6 +239,10 @@ def _oracle_run(K, perm, node_ptr, parent, tau, B):
 
 
 FULL_BASELINE_FILE = os.path.join(ROOT, "profiles", "oracle_c2_full.json")
+# workloads up to this many unknowns get the oracle's whole factor+solve as the
+# baseline (the 64^3 workload: about 40 s on the GPU machine's 16 host cores); larger
+# ones the subtree sample
+FULL_BASELINE_MAX_N = 300_000
 
 
 def host_cpu():
@@ -254,13 +260,13 @@ def host_cpu():
 def cpu_baseline(W, cfg, full=False):
     """The oracle (unchanged), timed on the host with OpenMP over all host cores.
 
-    Default (bounded, a few seconds): its whole factor+solve with the FP32 step
-    1 on the nested-dissection subtree holding about 1/8 of the unknowns, as a
-    problem of its own (its principal submatrix, 16 right-hand sides), split by
-    phase; plus its step 1 on that subtree with one thread.  The whole workload
-    takes many minutes on the host: with full=True it is run here; otherwise the
-    committed record of such a run (profiles/oracle_c2_full.json, host and core
-    count stated there) is attached for this workload."""
+    full=True: its whole factor+solve of the workload with the FP32 step 1,
+    split by phase.  Otherwise (larger workloads): the same on the
+    nested-dissection subtree holding about 1/8 of the unknowns, as a problem of
+    its own (its principal submatrix, the workload's right-hand-side count),
+    plus its step 1 on that subtree with one thread, with the committed record
+    of a whole-workload run (profiles/oracle_c2_full.json) attached when it is
+    for this workload."""
     import subprocess
     import tempfile
     import numpy as np
@@ -373,7 +379,8 @@ def main():
     if args.cpu_baseline_only:  # host only: the oracle's timing, no GPU
         from paper_2208_01907_amd import workloads as w
         W = w.CONFIGS[args.config]()
-        rec = cpu_baseline(W, args.config, full=args.cpu_baseline_full)
+        rec = cpu_baseline(W, args.config, full=args.cpu_baseline_full or (W.n <= FULL_BASELINE_MAX_N and
+                                                                          not args.cpu_baseline_sample))
         rec.update({"workload": args.config, "host": host_cpu(),
                     "command": " ".join(["python", "bench.py"] + sys.argv[1:])})
         print(json.dumps(rec))
@@ -464,7 +471,8 @@ def main():
                 "kernel_rates": rates(stats16)}
             del ctx16
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(W, args.config, full=args.cpu_baseline_full)
+        full = args.cpu_baseline_full or (W.n <= FULL_BASELINE_MAX_N and not args.cpu_baseline_sample)
+        result["cpu_baseline"] = cpu_baseline(W, args.config, full=full)
     print(json.dumps(result))
 
 
