@@ -82,6 +82,9 @@ typedef struct hf_options {
   double refine_tol;        /* block-GCR tolerance inside a correction pass
                                (default 1e-3): a correction only has to be
                                accurate relative to the residual it corrects */
+  int32_t nd_leaf_max;      /* hf_analyse without ordering and tree: largest
+                               leaf of the nested dissection it computes
+                               (default 512; see hf_order) */
   int32_t sweep_front_min;  /* FP32 preconditioner sweeps: a tree level with at
                                least this many fronts, each of at most 512
                                pivots, runs every front in one workgroup
@@ -120,6 +123,32 @@ typedef struct hf_info_t {
 void hf_default_options(hf_options* opt);
 
 /*
+ * Nested-dissection ordering of a pattern (host only; Sec. 2.2: the indices
+ * are bisected recursively by separators into the sets of a tree, each set
+ * eliminated after its subtree).  For patterns without coordinates: in every
+ * connected part a level structure is grown from a pseudo-peripheral vertex and
+ * the level of its median vertex (less the vertices with no neighbour in the
+ * next level) separates the levels before it from those after it; parts of at
+ * most leaf_max indices, or of fewer than three levels, are leaves; connected
+ * parts that a separator leaves become sibling subtrees (a forest at the top).
+ *   n, indptr_host, indices_host   pattern as for hf_analyse (validated)
+ *   leaf_max        largest leaf (>= 1)
+ *   perm_host       int32 [n], out: perm[k] = original index eliminated k-th
+ *   n_nodes_host    out: number of tree nodes
+ *   node_ptr_host   int32 [n + 1] (room for the largest possible tree), out:
+ *                   node j owns positions node_ptr[j] .. node_ptr[j+1]-1
+ *   parent_host     int32 [n], out: parent node or -1; postorder, subtrees
+ *                   contiguous; every off-diagonal entry couples a node with
+ *                   itself, an ancestor or a descendant
+ * The outputs are what hf_analyse takes.  Nodes are not limited here; hf_analyse
+ * refuses nodes of more than 4096 indices.  Host arrays owned by the caller.
+ * Errors: HF_ERR_ARG, HF_ERR_PATTERN, HF_ERR_NOT_IMPLEMENTED (n >= 2^31 - 1),
+ * HF_ERR_OOM.
+ */
+int hf_order(int64_t n, const int64_t* indptr_host, const int32_t* indices_host, int32_t leaf_max,
+             int32_t* perm_host, int32_t* n_nodes_host, int32_t* node_ptr_host, int32_t* parent_host);
+
+/*
  * Symbolic analysis (host only; Sec. 2.2 nested dissection).
  *   n                 order L (>= 0)
  *   indptr_host       int64 [n+1], CSR row pointers, indptr[0] = 0
@@ -134,8 +163,10 @@ void hf_default_options(hf_options* opt);
  *                     postorder (children before parents, subtrees contiguous)
  *   opt               options or NULL for defaults
  *   out               receives the new context
- * With node_ptr_host == NULL and parent_host == NULL the whole matrix is one
- * node (a dense front); usable only for small n.
+ * With node_ptr_host == NULL and parent_host == NULL: if perm_host is NULL too
+ * and n exceeds opt->nd_leaf_max, the ordering and the tree are those hf_order
+ * computes from the pattern; otherwise the whole matrix is one node (a dense
+ * front, usable only for small n) in the order perm_host gives.
  * Errors: HF_ERR_ARG, HF_ERR_PATTERN (includes couplings between sibling
  * subtrees), HF_ERR_NOT_IMPLEMENTED (a node of more than 4096 indices, a front
  * of 2^31 or more entries, or more than 2^31 border entries in total),

@@ -4,7 +4,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = ["hf_api.hip", "hf_analyse.hip", "hf_factor.hip", "hf_solve.hip", "hf_krylov.hip", "hf_noalloc.hip"]
+SRC = ["hf_api.hip", "hf_analyse.hip", "hf_factor.hip", "hf_solve.hip", "hf_krylov.hip", "hf_noalloc.hip",
+       "hf_order.hip"]
 LIB = os.path.join(HERE, "libhyfact.so")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",

@@ -15,8 +15,6 @@
 
 namespace hf {
 
-namespace {
-
 int validate_csr(int64_t n, const int64_t* indptr, const int32_t* indices) {
   if (indptr[0] != 0) return HF_ERR_PATTERN;
   for (int64_t i = 0; i < n; ++i) {
@@ -43,7 +41,6 @@ int validate_csr(int64_t n, const int64_t* indptr, const int32_t* indices) {
   return HF_OK;
 }
 
-}  // namespace
 
 int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, const int32_t* perm_h,
                  int32_t n_nodes, const int32_t* node_ptr_h, const int32_t* parent_h,
@@ -52,11 +49,32 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
   if (!out || n < 0) return HF_ERR_ARG;
   if (n > 0 && (!indptr_h || !indices_h)) return HF_ERR_ARG;
   if (n >= (int64_t)1 << 31) return HF_ERR_ARG;
-  const bool single = (node_ptr_h == nullptr && parent_h == nullptr);
+  bool single = (node_ptr_h == nullptr && parent_h == nullptr);
   if (!single && (!node_ptr_h || !parent_h || n_nodes < 1)) return HF_ERR_ARG;
   hf_options o;
   hf_default_options(&o);
   if (opt) o = *opt;
+  if (o.nd_leaf_max < 1) return HF_ERR_ARG;
+  // neither an ordering nor a tree: nested dissection of the pattern (Sec. 2.2)
+  std::vector<int32_t> nd_perm, nd_ptr, nd_parent;
+  if (single && !perm_h && n > o.nd_leaf_max) {
+    try {
+      nd_perm.resize((size_t)n);
+      nd_ptr.resize((size_t)n + 1);
+      nd_parent.resize((size_t)n);
+    } catch (const std::bad_alloc&) {
+      return HF_ERR_OOM;
+    }
+    int32_t nn = 0;
+    const int rc = order_impl(n, indptr_h, indices_h, o.nd_leaf_max, nd_perm.data(), &nn, nd_ptr.data(),
+                              nd_parent.data());
+    if (rc) return rc;
+    perm_h = nd_perm.data();
+    node_ptr_h = nd_ptr.data();
+    parent_h = nd_parent.data();
+    n_nodes = nn;
+    single = false;
+  }
   if (!(o.tau >= 0.0) || !std::isfinite(o.tau)) return HF_ERR_ARG;
   if (o.low_precision != HF_PREC_FP16 && o.low_precision != HF_PREC_FP16_PAIR && o.low_precision != HF_PREC_FP32 &&
       o.low_precision != HF_PREC_FP64)

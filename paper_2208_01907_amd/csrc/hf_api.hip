@@ -21,6 +21,7 @@ void hf_default_options(hf_options* opt) {
   opt->ker_tol = 1e-10;
   opt->refine_steps = 1;
   opt->refine_tol = 1e-3;
+  opt->nd_leaf_max = 512;
   opt->sweep_front_min = 256;
 }
 

@@ -252,6 +252,9 @@ struct hf_ctx {
 };
 
 namespace hf {
+int validate_csr(int64_t n, const int64_t* indptr, const int32_t* indices);
+int order_impl(int64_t n, const int64_t* indptr, const int32_t* indices, int32_t leaf_max, int32_t* perm,
+               int32_t* n_nodes, int32_t* node_ptr, int32_t* parent);
 int analyse_impl(int64_t n, const int64_t* indptr, const int32_t* indices, const int32_t* perm,
                  int32_t n_nodes, const int32_t* node_ptr, const int32_t* parent,
                  const hf_options* opt, hf_ctx** out);

@@ -8,6 +8,7 @@ no fallback.
 The function names follow the C entry points:
 
     ctx = hf_analyse(indptr, indices, perm, node_ptr, parent, opt)
+    perm, node_ptr, parent = hf_order(indptr, indices)   # nested dissection of a pattern
     hf_factorize(ctx, values_dev)            # values: torch float64 on the GPU
     X = hf_solve(ctx, B_dev)                 # B: (L, r) torch float64 on the GPU
     k = hf_kernel_dim(ctx)
@@ -54,7 +55,7 @@ HF_PREC_FP64 = 64
 EXPORTS = ["hf_default_options", "hf_analyse", "hf_factorize", "hf_solve", "hf_kernel_dim",
            "hf_kernel_basis", "hf_schur", "hf_scaling", "hf_info", "hf_strerror", "hf_destroy",
            "hf_timing_enable", "hf_timing_get", "hf_adjoint", "hf_pivots", "hf_s22_pivots", "hf_gcr_history",
-           "hf_schur_noalloc", "hf_precond"]
+           "hf_schur_noalloc", "hf_precond", "hf_order"]
 
 # kernel classes of hf_timing_get
 KCLASS = ["panel", "permute_l11", "f11_update", "gather_border", "trsm", "syrk", "extend_add", "fwd_diag",
@@ -74,7 +75,7 @@ class HFOptions(ctypes.Structure):
                 ("gcr_block", ctypes.c_int32), ("gcr_tol", ctypes.c_double),
                 ("gcr_maxit", ctypes.c_int32), ("ker_tol", ctypes.c_double),
                 ("refine_steps", ctypes.c_int32), ("refine_tol", ctypes.c_double),
-                ("sweep_front_min", ctypes.c_int32)]
+                ("nd_leaf_max", ctypes.c_int32), ("sweep_front_min", ctypes.c_int32)]
 
 
 class HFInfo(ctypes.Structure):
@@ -122,6 +123,7 @@ def _load():
         "hf_gcr_history": (ctypes.c_int, [P, P, P, P, P]),
         "hf_schur_noalloc": (ctypes.c_int, [P, P, P, P, I64, P]),
         "hf_precond": (ctypes.c_int, [P, I32, P, P, P]),
+        "hf_order": (ctypes.c_int, [I64, P, P, I32, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -189,6 +191,22 @@ class Context:
             self.destroy()
         except Exception:
             pass
+
+
+def hf_order(indptr, indices, leaf_max=512):
+    """Nested-dissection ordering of a CSR pattern (see hf_order in include/hf.h).
+    Returns (perm, node_ptr, parent) as hf_analyse takes them."""
+    indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(indices, dtype=np.int32)
+    n = len(indptr) - 1
+    perm = np.zeros(max(n, 1), dtype=np.int32)
+    node_ptr = np.zeros(n + 1, dtype=np.int32)
+    parent = np.zeros(max(n, 1), dtype=np.int32)
+    nn = ctypes.c_int32()
+    _check(_lib.hf_order(n, _np_ptr(indptr), _np_ptr(indices), int(leaf_max), _np_ptr(perm), ctypes.byref(nn),
+                         _np_ptr(node_ptr), _np_ptr(parent)), "hf_order")
+    k = nn.value
+    return perm[:n].copy(), node_ptr[:k + 1].copy(), parent[:k].copy()
 
 
 def hf_analyse(indptr, indices, perm=None, node_ptr=None, parent=None, opt=None) -> Context:

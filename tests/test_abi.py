@@ -126,11 +126,12 @@ def test_node_above_4096_indices_is_refused():
     """The pivot block of a node lives in the registers of one workgroup (at most
     4096 rows).  A 65^3 grid has a root separator of 65^2 = 4225 indices:
     hf_analyse refuses it with HF_ERR_NOT_IMPLEMENTED before any device work,
-    as it does a single-node matrix of more than 4096 indices."""
+    as it does a single-node matrix of more than 4096 indices (an ordering given
+    without a tree; with neither, hf_analyse orders the pattern itself)."""
     W = w.inclusions3d(65, 0, seed=1, leaf_max=512, r=1)
     assert int(np.max(np.diff(W.node_ptr))) == 65 * 65
     assert _analyse_code(W.indptr, W.indices, W.perm, W.node_ptr, W.parent) == hy.HF_ERR_NOT_IMPLEMENTED
     n = 4097
     indptr = np.arange(n + 1, dtype=np.int64)
     indices = np.arange(n, dtype=np.int32)
-    assert _analyse_code(indptr, indices) == hy.HF_ERR_NOT_IMPLEMENTED
+    assert _analyse_code(indptr, indices, np.arange(n, dtype=np.int32)) == hy.HF_ERR_NOT_IMPLEMENTED

@@ -325,6 +325,34 @@ def test_batch_c5_full_size():
     assert worst <= 1e-14
 
 
+@pytest.mark.parametrize("prec", [32, 64])
+def test_ordering_from_pattern(prec):
+    """hf_analyse without an ordering or a tree computes the nested dissection of
+    the pattern itself (hf_order); the result matches the oracle run with that
+    same ordering: M and the hard part (FP64), k, the solution (1e-10) and the
+    backward error.  A floating elastic body given in its natural node order."""
+    W = w.elasticity(6, seed=8, leaf_max=27, r=3, tau=0.2, gcr_block=0)
+    n = W.n
+    opt = hy.hf_default_options(tau=W.tau, low_precision=prec, gcr_block=0, nd_leaf_max=64)
+    ctx = hy.hf_analyse(W.indptr, W.indices, None, None, None, opt)
+    perm, node_ptr, parent = hy.hf_order(W.indptr, W.indices, 64)
+    assert hy.hf_info(ctx)["n_nodes"] == len(parent) > 1
+    hy.hf_factorize(ctx, torch.tensor(W.values, device="cuda"))
+    low = np.float32 if prec == 32 else np.float64
+    ref = oracle.hybrid_factorize(W.csr(), perm, node_ptr, parent, tau=W.tau, low=low, gcr_block=0)
+    Xref = oracle.hybrid_solve(ref, W.b)
+    lam, _ = hy.hf_schur(ctx)
+    assert hy.hf_kernel_dim(ctx) == ref.k == 6
+    if prec == 64:  # FP32 decisions at rounding level are compared node by node in test_parity
+        assert hy.hf_info(ctx)["M"] == ref.M
+        assert np.array_equal(lam, np.sort(perm[ref.step1.lambda2]))
+    X = hy.hf_solve(ctx, torch.tensor(W.b, device="cuda")).cpu().numpy()
+    rel = np.linalg.norm(X - Xref) / np.linalg.norm(Xref)
+    print(f"  natural-order elastic body n={n}: {len(parent)} nodes, M={ref.M}, rel_vs_oracle={rel:.2e}", flush=True)
+    assert rel <= 1e-10
+    assert oracle.backward_error(W.csr(), X, W.b) <= 1e-14
+
+
 def test_expected_kernel_dims():
     """Closed forms: Neumann Laplacian -> constants (k = 1); floating body -> rigid modes (k = 6)."""
     for W, k, Z in ((w.config_c1(), 1, np.ones((1024, 1))),
