@@ -130,7 +130,10 @@ void hf_default_options(hf_options* opt);
  * the level of its median vertex (less the vertices with no neighbour in the
  * next level) separates the levels before it from those after it; parts of at
  * most leaf_max indices, or of fewer than three levels, are leaves; connected
- * parts that a separator leaves become sibling subtrees (a forest at the top).
+ * parts that a separator leaves become sibling subtrees (a forest at the top);
+ * a separator or leaf of more than 4096 indices (the largest node hf_analyse
+ * takes) becomes a chain of nodes of at most 4096, each the parent of the one
+ * before.
  *   n, indptr_host, indices_host   pattern as for hf_analyse (validated)
  *   leaf_max        largest leaf (>= 1)
  *   perm_host       int32 [n], out: perm[k] = original index eliminated k-th
@@ -140,8 +143,7 @@ void hf_default_options(hf_options* opt);
  *   parent_host     int32 [n], out: parent node or -1; postorder, subtrees
  *                   contiguous; every off-diagonal entry couples a node with
  *                   itself, an ancestor or a descendant
- * The outputs are what hf_analyse takes.  Nodes are not limited here; hf_analyse
- * refuses nodes of more than 4096 indices.  Host arrays owned by the caller.
+ * The outputs are what hf_analyse takes.  Host arrays owned by the caller.
  * Errors: HF_ERR_ARG, HF_ERR_PATTERN, HF_ERR_NOT_IMPLEMENTED (n >= 2^31 - 1),
  * HF_ERR_OOM.
  */

@@ -14,10 +14,15 @@
 //     join the first half: the rest of the level still separates);
 //   - both halves are dissected the same way until a part has at most leaf_max
 //     vertices or is too shallow to split (fewer than three levels);
-//   - disconnected parts become sibling subtrees (roots of a forest at the top).
+//   - disconnected parts become sibling subtrees (roots of a forest at the top);
+//   - a separator (or an unsplittable part) of more than 4096 indices, the
+//     largest node the factorization takes, becomes a chain of nodes of at most
+//     that size, each the parent of the one before (a different, equally valid
+//     elimination order: the ratio test of Sec. 2.2 then runs per chain node).
 // Nodes are numbered in postorder (a subtree's nodes are contiguous and precede
 // its root), and the indices of a node keep their original relative order.
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "hf_internal.h"
@@ -25,6 +30,8 @@
 namespace hf {
 
 namespace {
+
+constexpr size_t MAX_NODE = 4096;  // largest node hf_analyse accepts
 
 struct Dissector {
   const int64_t* ip;
@@ -66,14 +73,27 @@ struct Dissector {
     return depth;
   }
 
-  int32_t emit(const std::vector<int32_t>& verts) {
+  // a node of the given indices; a set above the library's node limit becomes a
+  // chain of nodes of at most MAX_NODE indices (each the parent of the one
+  // before); returns the first and the last node of the chain
+  std::pair<int32_t, int32_t> emit_chain(const std::vector<int32_t>& verts) {
     std::vector<int32_t> s(verts);
     std::sort(s.begin(), s.end());
-    perm.insert(perm.end(), s.begin(), s.end());
-    node_ptr.push_back((int32_t)perm.size());
-    parent.push_back(-1);
-    return (int32_t)parent.size() - 1;
+    const size_t parts = (s.size() + MAX_NODE - 1) / MAX_NODE;
+    int32_t first = -1, last = -1;
+    for (size_t q = 0; q < parts; ++q) {
+      const size_t a = s.size() * q / parts, b = s.size() * (q + 1) / parts;
+      perm.insert(perm.end(), s.begin() + a, s.begin() + b);
+      node_ptr.push_back((int32_t)perm.size());
+      parent.push_back(-1);
+      const int32_t j = (int32_t)parent.size() - 1;
+      if (last >= 0) parent[last] = j;
+      if (first < 0) first = j;
+      last = j;
+    }
+    return {first, last};
   }
+  int32_t emit(const std::vector<int32_t>& verts) { return emit_chain(verts).second; }
 
   // roots of the subtrees covering verts, one per connected part
   std::vector<int32_t> dissect(const std::vector<int32_t>& verts) {
@@ -140,10 +160,10 @@ struct Dissector {
     if (a.empty() || b.empty() || sep.empty()) return emit(comp);
     const std::vector<int32_t> ra = dissect(a);
     const std::vector<int32_t> rb = dissect(b);
-    const int32_t j = emit(sep);
-    for (int32_t r : ra) parent[r] = j;
-    for (int32_t r : rb) parent[r] = j;
-    return j;
+    const std::pair<int32_t, int32_t> c = emit_chain(sep);
+    for (int32_t r : ra) parent[r] = c.first;
+    for (int32_t r : rb) parent[r] = c.first;
+    return c.second;
   }
 };
 

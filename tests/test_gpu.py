@@ -353,6 +353,25 @@ def test_ordering_from_pattern(prec):
     assert oracle.backward_error(W.csr(), X, W.b) <= 1e-14
 
 
+def test_grid_beyond_node_limit_without_tree():
+    """A 65^3 Neumann grid, whose axis-plane root separator (4,225 indices) the
+    factorization cannot take as one node, analysed without an ordering: the
+    computed nested dissection splits oversized separators into chains of nodes
+    (hf_order); k = 1 with the constants as kernel, backward error 1e-14."""
+    W = w.inclusions3d(65, 4, seed=21, leaf_max=512, r=2)
+    opt = hy.hf_default_options(tau=W.tau, low_precision=32, gcr_block=0)
+    ctx = hy.hf_analyse(W.indptr, W.indices, None, None, None, opt)
+    assert hy.hf_info(ctx)["max_pivots"] <= 4096
+    hy.hf_factorize(ctx, torch.tensor(W.values, device="cuda"))
+    assert hy.hf_kernel_dim(ctx) == 1
+    N = hy.hf_kernel_basis(ctx).cpu().numpy()
+    assert np.all(_principal_cos(N, W.kernel) > 1 - 1e-8)
+    X = hy.hf_solve(ctx, torch.tensor(W.b, device="cuda")).cpu().numpy()
+    be = oracle.backward_error(W.csr(), X, W.b)
+    print(f"  65^3 without tree: {hy.hf_info(ctx)['n_nodes']} nodes, M={hy.hf_info(ctx)['M']}, be={be:.2e}", flush=True)
+    assert be <= 1e-14
+
+
 def test_expected_kernel_dims():
     """Closed forms: Neumann Laplacian -> constants (k = 1); floating body -> rigid modes (k = 6)."""
     for W, k, Z in ((w.config_c1(), 1, np.ones((1024, 1))),

@@ -117,3 +117,18 @@ def test_order_drives_the_oracle():
     assert hf.k == 1
     X = oracle.hybrid_solve(hf, W.b)
     assert oracle.backward_error(W.csr(), X, W.b) <= 1e-14
+
+
+def test_order_splits_nodes_above_the_limit():
+    """A 65^3 grid: its largest level-structure separator exceeds the 4096 indices
+    a node may hold (the generator's axis-plane separator has 65^2 = 4225); the
+    ordering splits such separators into chains of nodes of at most 4096, each
+    the parent of the one before, and stays a valid dissection."""
+    P = _sym_pattern(w.fv_laplacian(np.ones((65, 65, 65))))
+    perm, node_ptr, parent = hy.hf_order(P.indptr, P.indices, 512)
+    check_ordering(P, perm, node_ptr, parent, 512)
+    sizes = np.diff(node_ptr)
+    assert sizes.max() <= 4096
+    chained = [j for j in range(len(parent) - 1) if parent[j] == j + 1 and sizes[j] + sizes[j + 1] > 4096
+               and np.sum(parent == j) > 0]
+    assert chained   # at least one separator was split into a chain
