@@ -67,18 +67,30 @@ def parse():
                     help="time the oracle on the subtree sample only")
     ap.add_argument("--cpu-baseline-only", action="store_true",
                     help="run only the oracle timing (no GPU) and print it as JSON")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the sweeps' launch shapes (hf_tune) before timing")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain device copy of 256 MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
-def run_path(hy, W, vals, B, prec, steps, warmup, torch):
+def run_path(hy, W, vals, B, prec, steps, warmup, torch, tune=False):
     """Times `steps` factor+solve steps (after `warmup`), then repeats them with
-    per-launch HIP events to collect the per-kernel times."""
+    per-launch HIP events to collect the per-kernel times.  With tune, the
+    sweeps' launch shapes are first autotuned (hf_tune) on the factors of one
+    factorization, for the wider of the Schur-complement blocks and the
+    right-hand sides; the choice and its cost are kept on the context."""
     opt = hy.hf_default_options(tau=W.tau, low_precision=prec, gcr_block=0)
     t0 = time.perf_counter()
     ctx = hy.hf_analyse(W.indptr, W.indices, W.perm, W.node_ptr, W.parent, opt)
     t_an = time.perf_counter() - t0
+    if tune:
+        hy.hf_factorize(ctx, vals)
+        r = max(1, min(64, max(int(B.shape[1]), min(64, hy.hf_info(ctx)["M"]))))
+        t0 = time.perf_counter()
+        fm, wm, ms = hy.hf_tune(ctx, r)
+        ctx.tuned = {"columns": r, "sweep_front_min": fm, "sweep_wide_min": wm, "ms_per_application": ms,
+                     "tuning_s": time.perf_counter() - t0}
     for _ in range(warmup):
         hy.hf_factorize(ctx, vals)
         hy.hf_solve(ctx, B)
@@ -403,7 +415,7 @@ def main():
     B = torch.tensor(W.b, device=dev)
     torch.cuda.synchronize()
     ctx, X, dt, dt_ev, t_an, stats, info = run_path(hy, W, vals, B, hy.HF_PREC_FP32, args.steps, args.warmup,
-                                                     torch)
+                                                     torch, tune=args.tune)
     Xh = X.cpu().numpy()
     from paper_2208_01907_amd.metrics import backward_error
     be = backward_error(W.csr(), Xh, W.b)
@@ -425,6 +437,8 @@ def main():
         "roofline": roofline(stats, args.steps, 32),
         "path_roofline": path_roofline(stats, args.steps, 32, dt * 1e3),
     }
+    if getattr(ctx, "tuned", None):
+        result["tuned"] = ctx.tuned
     if "offsets" in W.meta:  # a batch: the gate holds for every system on its own
         result["batch"] = batch_gates(W, Xh)
     result["adjoint"] = adjoint_timing(hy, ctx, X, W, args.steps, torch)

@@ -90,6 +90,10 @@ typedef struct hf_options {
                                pivots, runs every front in one workgroup
                                (default 256; 0 = never).  Same arithmetic
                                either way up to the order of the sums. */
+  int32_t sweep_wide_min;   /* sweeps with more than 16 right-hand sides: a
+                               launch of at least this many 64-row tiles uses
+                               the LDS-staged 64x64 tile products, smaller ones
+                               the 16-row register-fed ones (default 256) */
 } hf_options;
 
 typedef struct hf_info_t {
@@ -234,6 +238,21 @@ int hf_solve(hf_ctx* ctx, int32_t r, const double* B_dev, int64_t ldb, double* X
  */
 int hf_adjoint(hf_ctx* ctx, int32_t r, const double* X_dev, int64_t ldx, const double* G_dev, int64_t ldg,
                double* Lam_dev, int64_t ldl, double* GV_dev, void* stream);
+
+/*
+ * Autotuning of the launch shapes of the preconditioner sweeps (Sec. 3.2) for
+ * the current factors: applies Q^{-1} to r columns (1 <= r <= 64) with every
+ * combination of sweep_front_min in {0, 128, 256, 512} and sweep_wide_min in
+ * {128, 256, 512, 1024}, timed with events after one untimed application each,
+ * and keeps the fastest in the context's options (later factorizations and
+ * solves use them).  The choices change which kernels run, not what they
+ * compute (up to the order of the FP32 sums).  Either output may be NULL.
+ *   front_min_host, wide_min_host   out: the chosen values
+ *   ms_host                         out: the chosen combination's time per application
+ * Errors: HF_ERR_STATE (not factorized), HF_ERR_ARG, HF_ERR_OOM, HF_ERR_HIP.
+ */
+int hf_tune(hf_ctx* ctx, int32_t r, int32_t* front_min_host, int32_t* wide_min_host, double* ms_host,
+            void* stream);
 
 /*
  * The preconditioner Q^{-1} of Sec. 3.2 on the current factors: forward and

@@ -81,7 +81,7 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
     return HF_ERR_ARG;
   if (o.n_enlarge < 0 || o.gcr_block < 0 || o.gcr_block > 64 || o.gcr_maxit < 1 || !(o.gcr_tol > 0) ||
       !(o.ker_tol >= 0) || o.refine_steps < 0 || o.refine_steps > 8 || !(o.refine_tol > 0) ||
-      o.sweep_front_min < 0)
+      o.sweep_front_min < 0 || o.sweep_wide_min < 1)
     return HF_ERR_ARG;
   if (n > 0) {
     int rc = validate_csr(n, indptr_h, indices_h);

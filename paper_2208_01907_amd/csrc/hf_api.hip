@@ -23,6 +23,7 @@ void hf_default_options(hf_options* opt) {
   opt->refine_tol = 1e-3;
   opt->nd_leaf_max = 512;
   opt->sweep_front_min = 256;
+  opt->sweep_wide_min = 256;
 }
 
 int hf_analyse(int64_t n, const int64_t* indptr_host, const int32_t* indices_host, const int32_t* perm_host,
@@ -50,6 +51,12 @@ int hf_adjoint(hf_ctx* ctx, int32_t r, const double* X_dev, int64_t ldx, const d
   if (r > 0 && Lam_dev && (Lam_dev == G_dev || Lam_dev == X_dev)) return HF_ERR_ARG;
   if (r > 0 && GV_dev && (GV_dev == Lam_dev || GV_dev == X_dev || GV_dev == G_dev)) return HF_ERR_ARG;
   return hf::adjoint_impl(ctx, r, X_dev, ldx, G_dev, ldg, Lam_dev, ldl, GV_dev, static_cast<hipStream_t>(stream));
+}
+
+int hf_tune(hf_ctx* ctx, int32_t r, int32_t* front_min_host, int32_t* wide_min_host, double* ms_host,
+            void* stream) {
+  if (!ctx) return HF_ERR_ARG;
+  return hf::tune_impl(ctx, r, front_min_host, wide_min_host, ms_host, static_cast<hipStream_t>(stream));
 }
 
 int hf_precond(hf_ctx* ctx, int32_t r, const double* R_dev, double* Y_dev, void* stream) {

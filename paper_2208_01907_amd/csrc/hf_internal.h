@@ -227,7 +227,7 @@ struct hf_ctx {
   hf::DBuf d_l2;
   int32_t M = 0;
   // X12 in column blocks (row-major n x mb each), S22 and its factorization
-  hf::DBuf d_X12, d_S22, d_S22f, d_s22perm, d_s22mag, d_s22info, d_N2, d_kern, d_ktmp;
+  hf::DBuf d_X12, d_S22, d_S22f, d_s22perm, d_s22mag, d_s22info, d_N2, d_kern, d_ktmp, d_tune;
   int32_t mb = 0, nblk = 0;
   int32_t kdim = 0;
   double rank_gap = 0.0;
@@ -268,4 +268,5 @@ int adjoint_impl(hf_ctx* ctx, int32_t r, const double* X, int64_t ldx, const dou
                  double* Lam, int64_t ldl, double* GV, hipStream_t s);
 int scaling_impl(const hf_ctx* ctx, double* q, hipStream_t s);
 int precond_impl(hf_ctx* ctx, int32_t r, const double* R, double* Y, hipStream_t s);
+int tune_impl(hf_ctx* ctx, int32_t r, int32_t* front_min, int32_t* wide_min, double* ms, hipStream_t s);
 }  // namespace hf

@@ -1348,6 +1348,75 @@ int precond_impl(hf_ctx* ctx, int32_t r, const double* R, double* Y, hipStream_t
   return HF_OK;
 }
 
+__global__ void k_tune_fill(int64_t ne, double* __restrict__ R) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne) R[e] = 1.0 + 0.01 * (double)(e % 13);
+}
+
+// The sweeps' launch-shape options timed on the current factors; the fastest
+// combination stays in the context.
+int tune_impl(hf_ctx* ctx, int32_t r, int32_t* front_min, int32_t* wide_min, double* ms, hipStream_t s) {
+  if (ctx->state < 2) return HF_ERR_STATE;
+  const int64_t n = ctx->n;
+  if (r < 1 || r > MAXM) return HF_ERR_ARG;
+  const bool fp32 = ctx->factor_prec == HF_PREC_FP32;
+  std::vector<int32_t> fms = fp32 ? std::vector<int32_t>{0, 128, 256, 512}
+                                  : std::vector<int32_t>{ctx->opt.sweep_front_min};
+  std::vector<int32_t> wms = r > 16 ? std::vector<int32_t>{128, 256, 512, 1024}
+                                    : std::vector<int32_t>{ctx->opt.sweep_wide_min};
+  double best = INFINITY;
+  int32_t bf = ctx->opt.sweep_front_min, bw = ctx->opt.sweep_wide_min;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  const bool timing = ctx->timer.on;
+  ctx->timer.on = false;  // the candidates' launches stay out of the per-class counters
+  try {
+    if (n > 0) {
+      ctx->d_tune.alloc((size_t)n * r * 2 * sizeof(double));
+      double* R = ctx->d_tune.as<double>();
+      double* Y = R + n * r;
+      k_tune_fill<<<cdiv(n * r, 256), 256, 0, s>>>(n * r, R);
+      HF_HIP(hipEventCreate(&ea));
+      HF_HIP(hipEventCreate(&eb));
+      for (int32_t fm : fms)
+        for (int32_t wm : wms) {
+          ctx->opt.sweep_front_min = fm;
+          ctx->opt.sweep_wide_min = wm;
+          precond(ctx, r, R, Y, s);  // untimed: allocations, caches
+          HF_HIP(hipEventRecord(ea, s));
+          constexpr int REPS = 3;
+          for (int q = 0; q < REPS; ++q) precond(ctx, r, R, Y, s);
+          HF_HIP(hipEventRecord(eb, s));
+          HF_HIP(hipEventSynchronize(eb));
+          float t = 0.f;
+          HF_HIP(hipEventElapsedTime(&t, ea, eb));
+          if (t / REPS < best) {
+            best = t / REPS;
+            bf = fm;
+            bw = wm;
+          }
+        }
+    }
+  } catch (const HipError&) {
+    ctx->timer.on = timing;
+    return HF_ERR_HIP;
+  } catch (const Status& st) {
+    ctx->timer.on = timing;
+    return st.code;
+  } catch (const std::bad_alloc&) {
+    ctx->timer.on = timing;
+    return HF_ERR_OOM;
+  }
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  ctx->timer.on = timing;
+  ctx->opt.sweep_front_min = bf;
+  ctx->opt.sweep_wide_min = bw;
+  if (front_min) *front_min = bf;
+  if (wide_min) *wide_min = bw;
+  if (ms) *ms = std::isfinite(best) ? best : 0.0;
+  return HF_OK;
+}
+
 // Adjoint of the solve.  Not a step of the paper's method: the derivative of the
 // solution map of Algorithm 2, taken with one more solve on the same factors.
 // For Kbar x = b with ker Kbar fixed and b in its range, x = Kbar^+ b changes by

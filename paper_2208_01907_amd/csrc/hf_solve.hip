@@ -1226,7 +1226,8 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   // many fronts are throughput bound (short stages, several workgroups per CU).
   constexpr int KBN = SweepStage<T>::value;
   constexpr int KBW = SweepStage<T>::value / 4;
-  auto wide = [](const dim3& g) { return (int64_t)g.x * g.y * g.z >= 256; };
+  const int64_t wide_min = ctx->opt.sweep_wide_min;
+  auto wide = [&](const dim3& g) { return (int64_t)g.x * g.y * g.z >= wide_min; };
   // step length: long steps (fewer sequential launches) over few fronts,
   // half steps (shorter diagonal products) over many
   auto step_of = [](int nl) { return nl < 128 ? TB : HB; };

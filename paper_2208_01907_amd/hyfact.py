@@ -55,7 +55,7 @@ HF_PREC_FP64 = 64
 EXPORTS = ["hf_default_options", "hf_analyse", "hf_factorize", "hf_solve", "hf_kernel_dim",
            "hf_kernel_basis", "hf_schur", "hf_scaling", "hf_info", "hf_strerror", "hf_destroy",
            "hf_timing_enable", "hf_timing_get", "hf_adjoint", "hf_pivots", "hf_s22_pivots", "hf_gcr_history",
-           "hf_schur_noalloc", "hf_precond", "hf_order"]
+           "hf_schur_noalloc", "hf_precond", "hf_order", "hf_tune"]
 
 # kernel classes of hf_timing_get
 KCLASS = ["panel", "permute_l11", "f11_update", "gather_border", "trsm", "syrk", "extend_add", "fwd_diag",
@@ -75,7 +75,8 @@ class HFOptions(ctypes.Structure):
                 ("gcr_block", ctypes.c_int32), ("gcr_tol", ctypes.c_double),
                 ("gcr_maxit", ctypes.c_int32), ("ker_tol", ctypes.c_double),
                 ("refine_steps", ctypes.c_int32), ("refine_tol", ctypes.c_double),
-                ("nd_leaf_max", ctypes.c_int32), ("sweep_front_min", ctypes.c_int32)]
+                ("nd_leaf_max", ctypes.c_int32), ("sweep_front_min", ctypes.c_int32),
+                ("sweep_wide_min", ctypes.c_int32)]
 
 
 class HFInfo(ctypes.Structure):
@@ -124,6 +125,7 @@ def _load():
         "hf_schur_noalloc": (ctypes.c_int, [P, P, P, P, I64, P]),
         "hf_precond": (ctypes.c_int, [P, I32, P, P, P]),
         "hf_order": (ctypes.c_int, [I64, P, P, I32, P, P, P, P]),
+        "hf_tune": (ctypes.c_int, [P, I32, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -247,6 +249,15 @@ def hf_solve(ctx: Context, B, X=None, stream=None):
         X.copy_(out.reshape(X.shape))
         return X
     return out[:, 0] if one else out
+
+
+def hf_tune(ctx: Context, r, stream=None):
+    """Autotune the sweeps' launch shapes for r columns on the current factors
+    (see hf_tune in include/hf.h).  Returns (sweep_front_min, sweep_wide_min, ms)."""
+    fm, wm, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    _check(_lib.hf_tune(ctx.handle, int(r), ctypes.byref(fm), ctypes.byref(wm), ctypes.byref(ms), _stream(stream)),
+           "hf_tune")
+    return fm.value, wm.value, ms.value
 
 
 def hf_precond(ctx: Context, R, stream=None):

@@ -113,13 +113,15 @@ def test_size_limits():
 
 
 def test_diagnostics_reject_null_context():
-    """hf_pivots, hf_s22_pivots and hf_gcr_history validate their arguments on the
-    host (no device work)."""
+    """hf_pivots, hf_s22_pivots, hf_gcr_history, hf_tune and hf_precond validate
+    their arguments on the host (no device work)."""
     lib = hy._lib
     n = ctypes.c_int32()
     assert lib.hf_pivots(None, None, None, None, None) == hy.HF_ERR_ARG
     assert lib.hf_s22_pivots(None, None) == hy.HF_ERR_ARG
     assert lib.hf_gcr_history(None, ctypes.byref(n), None, None, None) == hy.HF_ERR_ARG
+    assert lib.hf_tune(None, 16, None, None, None, None) == hy.HF_ERR_ARG
+    assert lib.hf_precond(None, 16, None, None, None) == hy.HF_ERR_ARG
 
 
 def test_node_above_4096_indices_is_refused():

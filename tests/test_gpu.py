@@ -310,8 +310,9 @@ def test_batch_c5_full_size():
     """The 96-system batch at full size (2.3 million unknowns), FP32 step 1: one
     kernel vector per system (k = 96, the closed form: constants on each system),
     the basis spanning the per-system constants, and every system's backward error
-    at most 1e-14 on its own.  Parity of batches with the oracle element by
-    element is covered by the small batches of test_parity."""
+    at most 1e-14 on its own, and the three smallest systems' rows against the
+    oracle run on each system alone (1e-10).  Parity of whole batches with the
+    oracle element by element is covered by the small batches of test_parity."""
     W = w.config_c5()
     ctx = _gpu(W, 32)
     assert hy.hf_kernel_dim(ctx) == 96
@@ -323,6 +324,17 @@ def test_batch_c5_full_size():
     worst = max(oracle.backward_error(K[a:b, a:b], X[a:b], W.b[a:b]) for a, b in zip(offs[:-1], offs[1:]))
     print(f"  c5: M={hy.hf_info(ctx)['M']} worst per-system backward error {worst:.2e}", flush=True)
     assert worst <= 1e-14
+    # element by element against the oracle on the three smallest systems, each run
+    # on its own with its own tree (both give the minimum-norm solution)
+    for i in np.argsort(W.meta["sides"], kind="stable")[:3]:
+        Wi = w.neumann3d(W.meta["sides"][i], seed=5000 + int(i), leaf_max=512, r=8, tau=W.tau, gcr_block=64)
+        ref = oracle.hybrid_factorize(Wi.csr(), Wi.perm, Wi.node_ptr, Wi.parent, tau=Wi.tau, low=np.float64,
+                                      gcr_block=64)
+        Xi = oracle.hybrid_solve(ref, Wi.b)
+        a, b = offs[i], offs[i + 1]
+        rel = np.linalg.norm(X[a:b] - Xi) / np.linalg.norm(Xi)
+        print(f"  c5 system {i} (side {W.meta['sides'][i]}): rel_vs_oracle {rel:.2e}", flush=True)
+        assert rel <= 1e-10
 
 
 @pytest.mark.parametrize("prec", [32, 64])
@@ -370,6 +382,24 @@ def test_grid_beyond_node_limit_without_tree():
     be = oracle.backward_error(W.csr(), X, W.b)
     print(f"  65^3 without tree: {hy.hf_info(ctx)['n_nodes']} nodes, M={hy.hf_info(ctx)['M']}, be={be:.2e}", flush=True)
     assert be <= 1e-14
+
+
+@pytest.mark.parametrize("r", [16, 40])
+def test_tune_keeps_results(r):
+    """hf_tune picks launch shapes of the sweeps among its stated candidates and
+    keeps them; the solution afterwards still matches the oracle (1e-10) with
+    backward error 1e-14."""
+    W = CASES["inc24"]()
+    ctx = _gpu(W, 32)
+    fm, wm, ms = hy.hf_tune(ctx, r)
+    assert fm in (0, 128, 256, 512) and wm in ((128, 256, 512, 1024) if r > 16 else (256,)) and ms > 0
+    ref = oracle.hybrid_factorize(W.csr(), W.perm, W.node_ptr, W.parent, tau=W.tau, low=np.float32,
+                                  gcr_block=W.gcr_block)
+    Xref = oracle.hybrid_solve(ref, W.b)
+    X = hy.hf_solve(ctx, torch.tensor(W.b, device="cuda")).cpu().numpy()
+    print(f"  tuned for {r} columns: front_min {fm}, wide_min {wm}, {ms:.3f} ms per application", flush=True)
+    assert np.linalg.norm(X - Xref) / np.linalg.norm(Xref) <= 1e-10
+    assert oracle.backward_error(W.csr(), X, W.b) <= 1e-14
 
 
 def test_expected_kernel_dims():
