@@ -94,6 +94,12 @@ typedef struct hf_options {
                                launch of at least this many 64-row tiles uses
                                the LDS-staged 64x64 tile products, smaller ones
                                the 16-row register-fed ones (default 256) */
+  int32_t sweep_node_inverse; /* 1 (default): the L11 of every node of more than
+                               512 pivots also gets one explicit inverse, formed
+                               after step 1 by recursive doubling of its
+                               512-column step inverses, and each sweep direction
+                               takes such a level in one diagonal product instead
+                               of a chain of 512-column steps; 0: the chains */
 } hf_options;
 
 typedef struct hf_info_t {

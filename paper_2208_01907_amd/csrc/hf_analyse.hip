@@ -81,7 +81,8 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
     return HF_ERR_ARG;
   if (o.n_enlarge < 0 || o.gcr_block < 0 || o.gcr_block > 64 || o.gcr_maxit < 1 || !(o.gcr_tol > 0) ||
       !(o.ker_tol >= 0) || o.refine_steps < 0 || o.refine_steps > 8 || !(o.refine_tol > 0) ||
-      o.sweep_front_min < 0 || o.sweep_wide_min < 1)
+      o.sweep_front_min < 0 || o.sweep_wide_min < 1 ||
+      (o.sweep_node_inverse != 0 && o.sweep_node_inverse != 1))
     return HF_ERR_ARG;
   if (n > 0) {
     int rc = validate_csr(n, indptr_h, indices_h);
@@ -382,6 +383,36 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
     }
     ctx->stp_first[n_nodes] = nsteps;
     ctx->linv2_elems = (int64_t)nsteps * HF_SWEEP_STEP * HF_SWEEP_STEP;
+    // node inverses: every node of more than one step, leading dimension p
+    // rounded up to 64; the merges of recursive doubling pair blocks of TB << t
+    // columns [a0, a0 + s) and [a0 + s, a0 + 2s) while the second one starts
+    // inside the node (the pivot count can only trim them)
+    ctx->ninv_off.assign(std::max(n_nodes, 1), -1);
+    ctx->ninv_ld.assign(std::max(n_nodes, 1), 0);
+    ctx->ninv_elems = 0;
+    ctx->ninv_lvl.assign(1, 0);
+    if (o.sweep_node_inverse) {
+      for (int32_t j = 0; j < n_nodes; ++j) {
+        const int32_t p = ctx->nodes[j].p;
+        if (p <= HF_SWEEP_STEP) continue;
+        const int32_t ld = (p + 63) / 64 * 64;
+        ctx->ninv_off[j] = ctx->ninv_elems;
+        ctx->ninv_ld[j] = ld;
+        ctx->ninv_elems += (int64_t)ld * ld;
+        for (int32_t t = ctx->stp_first[j]; t < ctx->stp_first[j] + (p + HF_SWEEP_STEP - 1) / HF_SWEEP_STEP; ++t)
+          ctx->ninv_copy.push_back(t);
+      }
+      for (int64_t sb = HF_SWEEP_STEP; sb < ctx->max_p; sb *= 2) {
+        for (int32_t j = 0; j < n_nodes; ++j) {
+          if (ctx->ninv_off[j] < 0) continue;
+          for (int64_t a0 = 0; a0 + sb < ctx->nodes[j].p; a0 += 2 * sb) {
+            ctx->ninv_jnode.push_back(j);
+            ctx->ninv_ja0.push_back((int32_t)a0);
+          }
+        }
+        ctx->ninv_lvl.push_back((int32_t)ctx->ninv_jnode.size());
+      }
+    }
     // device copies of the pattern
     hipStream_t s = nullptr;
     upload(ctx->d_pindptr, pindptr, s);
@@ -405,6 +436,11 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
     upload(ctx->d_stp_node, ctx->stp_node, s);
     upload(ctx->d_stp_first, ctx->stp_first, s);
     upload(ctx->d_linv2_off, ctx->linv2_off, s);
+    upload(ctx->d_ninv_off, ctx->ninv_off, s);
+    upload(ctx->d_ninv_ld, ctx->ninv_ld, s);
+    upload(ctx->d_ninv_copy, ctx->ninv_copy, s);
+    upload(ctx->d_ninv_jnode, ctx->ninv_jnode, s);
+    upload(ctx->d_ninv_ja0, ctx->ninv_ja0, s);
     HF_HIP(hipStreamSynchronize(s));
     ctx->state = 1;
   } catch (const HipError&) {

@@ -24,6 +24,7 @@ void hf_default_options(hf_options* opt) {
   opt->nd_leaf_max = 512;
   opt->sweep_front_min = 256;
   opt->sweep_wide_min = 256;
+  opt->sweep_node_inverse = 1;
 }
 
 int hf_analyse(int64_t n, const int64_t* indptr_host, const int32_t* indices_host, const int32_t* perm_host,

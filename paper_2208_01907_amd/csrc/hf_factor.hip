@@ -1077,6 +1077,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
   ctx->d_lbuf.alloc((size_t)std::max<int64_t>(ctx->lbuf_elems, 1) * sizeof(T));
   ctx->d_linv.alloc((size_t)std::max<int64_t>(ctx->linv_elems, 1) * sizeof(T));
   ctx->d_linv2.alloc((size_t)std::max<int64_t>(ctx->linv2_elems, 1) * sizeof(T));
+  ctx->d_ninv.alloc((size_t)std::max<int64_t>(ctx->ninv_elems, 1) * sizeof(T));
   ctx->d_dval.alloc((size_t)n * sizeof(T));
   ctx->d_q.alloc((size_t)n * sizeof(double));
   ctx->d_kval.alloc((size_t)ctx->nnz * sizeof(double));
@@ -1255,6 +1256,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
     }
     HF_HIP(hipGetLastError());
   }
+  node_inverses<T>(ctx, s);
   ctx->d_ipos.alloc((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
   if (ctx->n_nodes > 0) {
     k_mark_l2<<<ctx->n_nodes, 256, 0, s>>>(ctx->n_nodes, nodes, st, ctx->d_piv.as<int32_t>(),

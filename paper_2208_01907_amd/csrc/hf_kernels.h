@@ -179,6 +179,11 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s);
 template <class T>
 void step_inverses(hf_ctx* ctx, int l, hipStream_t s);
 
+// explicit inverses of the whole L11 of every node of more than one sweep step
+// (after step 1; recursive doubling of the step inverses)
+template <class T>
+void node_inverses(hf_ctx* ctx, hipStream_t s);
+
 // Q^{-1} of Sec. 3.2: Y = (L D L^T)^{-1} R on the moderate part, R and Y row-major
 // n x m in elimination order, FP64; factors in T.
 template <class T>

@@ -17,11 +17,15 @@
 //              of L11 and the border L21).
 //   Launches over many fronts use 64-row tiles staged through LDS; launches
 //   over few fronts use 16-row tiles fed straight from global memory.
+//   A level with a node of more than one step runs in one pass instead: the
+//   diagonal product with the explicit inverse of each node's whole L11 (formed
+//   after step 1 from the step inverses), then one update of the border rows.
 // Backward sweep, root first, per level:
 //   border   : t = D^{-1} z - L21^T x_border (column strips, x_border read from
 //              the FP64 result of the ancestors);
 //   steps from the last one: diag (x_J = L_JJ^{-T} t_J with the same inverse,
-//              scattered to FP64) and update of the columns left of the step.
+//              scattered to FP64) and update of the columns left of the step
+//              (one diagonal product with the node inverse on one-pass levels).
 // Rows of the hard part are never written, so they stay zero in the result.
 #include <algorithm>
 #include <type_traits>
@@ -40,6 +44,33 @@ template <class T>
 __device__ __forceinline__ const T* step_inverse(const T* linv2, int64_t off, int J0) {
   const int h = (J0 % TB) / HB;
   return linv2 + off + (int64_t)(J0 / TB) * TB * TB + (int64_t)h * HB * TB + h * HB;
+}
+
+// Where a diagonal product of the sweeps finds its inverse: the step inverses,
+// and (NODE: a level that runs in one pass) the explicit inverse of the whole
+// L11 of every node of more than one step.  Without NODE the leading dimension
+// is the constant TB.
+template <class T>
+struct InvSrc {
+  const int64_t* off2;  // step inverses
+  const T* linv2;
+  const int64_t* noff;  // node inverses (offset < 0: the node has a single step)
+  const int32_t* nld;
+  const T* ninv;
+};
+// the inverse for the step at J0 of node j and its leading dimension (a node
+// inverse is only asked for at J0 = 0)
+template <bool NODE, class T>
+__device__ __forceinline__ const T* inverse_of(const InvSrc<T>& v, int j, int J0, int& ld) {
+  if constexpr (NODE) {
+    const int64_t o = v.noff[j];
+    if (o >= 0) {
+      ld = v.nld[j];
+      return v.ninv + o;
+    }
+  }
+  ld = TB;
+  return step_inverse(v.linv2, v.off2[j], J0);
 }
 constexpr int SB = 64;   // sub-block with an explicit inverse
 constexpr int RCH = 512; // border rows per partial product of the backward sweep
@@ -259,6 +290,95 @@ k_inv_merge(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ st
 }
 
 // ---------------------------------------------------------------------------
+// explicit inverse of the whole L11 of a node of more than one step, by
+// recursive doubling: the diagonal blocks are the step inverses; blocks A, B of
+// s columns each ([a0, a0 + s), [a0 + s, a0 + 2s)) merge as
+// X_BA = -X_B L_BA X_A, for s = TB, 2 TB, ... until one block holds the node.
+// Only the lower triangle is meaningful; P = L_BA X_A is kept, transposed, in
+// the unused upper block (A rows, B columns) between the two passes.
+// ---------------------------------------------------------------------------
+
+template <class T>
+__global__ void __launch_bounds__(256)
+k_ninv_copy(const int32_t* __restrict__ steps, const int32_t* __restrict__ stp_node,
+            const int32_t* __restrict__ stp_first, const NodeState* __restrict__ st,
+            const int64_t* __restrict__ linv2_off, const T* __restrict__ linv2,
+            const int64_t* __restrict__ ninv_off, const int32_t* __restrict__ ninv_ld, T* __restrict__ ninv) {
+  const int bi = steps[blockIdx.y];
+  const int j = stp_node[bi];
+  const int S = bi - stp_first[j];
+  const int J0 = S * TB;
+  const int npiv = st[j].npiv;
+  if (J0 >= npiv) return;
+  const int nc = min(TB, npiv - J0);
+  const int64_t ld = ninv_ld[j];
+  const T* X = linv2 + linv2_off[j] + (int64_t)S * TB * TB;  // column-major TB x TB
+  T* N = ninv + ninv_off[j] + (int64_t)J0 * ld + J0;
+  // four consecutive rows of one column per thread
+  const int e = 4 * (blockIdx.x * 256 + threadIdx.x);
+  const int c = e / TB, r = e % TB;
+  if (c >= nc || r >= nc) return;
+  if (r + 3 < nc) {
+    T v[4];
+    __builtin_memcpy(v, X + (int64_t)c * TB + r, sizeof(v));
+    __builtin_memcpy(N + (int64_t)c * ld + r, v, sizeof(v));
+  } else {
+    for (int q = r; q < nc; ++q) N[(int64_t)c * ld + q] = X[(int64_t)c * TB + q];
+  }
+}
+
+// one 64 x 64 tile of P (pass 0) or of X_BA (pass 1) per workgroup; the
+// products skip the zero triangles of X_A and X_B
+template <class T>
+__global__ void __launch_bounds__(256)
+k_ninv_merge(const int32_t* __restrict__ jnode, const int32_t* __restrict__ ja0, const NodeInfo* __restrict__ nodes,
+             const NodeState* __restrict__ st, const T* __restrict__ front, const int64_t* __restrict__ ninv_off,
+             const int32_t* __restrict__ ninv_ld, T* __restrict__ ninv, int sb, int pass, int base) {
+  const int q = base + blockIdx.y;
+  const int j = jnode[q], a0 = ja0[q], b0 = a0 + sb;
+  const int npiv = st[j].npiv;
+  const int nB = min(sb, npiv - b0);
+  if (nB <= 0) return;
+  const int nt = sb / 64;
+  // pass 0 tiles P^T (rows: columns c of A), pass 1 tiles X_BA (rows: rows r of B)
+  const int t0 = (blockIdx.x / nt) * 64, t1 = (blockIdx.x % nt) * 64;
+  const int r0 = pass == 0 ? t1 : t0, c0 = pass == 0 ? t0 : t1;
+  if (r0 >= nB) return;
+  const int nrow = min(64, nB - r0);
+  const NodeInfo ni = nodes[j];
+  const int64_t f = ni.f, ld = ninv_ld[j];
+  const T* F = front + ni.front_off;
+  T* N = ninv + ninv_off[j];
+  constexpr int KB = SweepStage<T>::value / 2;
+  __shared__ T As[KB][68];
+  __shared__ T Bs[KB][68];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  typename Mfma<T>::V acc[2][2];
+  zero_acc<T>(acc);
+  if (pass == 0) {
+    // P^T(c, r) = sum_{k >= c0} X_A(k, c) L[b0 + r, a0 + k]: both operands are
+    // fetched along their contiguous index (k for X_A, r for L)
+    tile_gemm_64<T, KB, 68, true>(
+        acc, As, Bs, c0, sb, [&](int k, int c) { return N[(int64_t)(a0 + c0 + c) * ld + a0 + k]; },
+        [&](int k, int r) { return r < nrow ? F[(int64_t)(a0 + k) * f + b0 + r0 + r] : (T)0; }, tid, lane, wr, wc);
+  } else {
+    // X_BA(r, c) = -sum_{k < r0 + 64} X_B(r, k) P(k, c), P(k, c) at N[(b0 + k) ld + a0 + c]
+    tile_gemm_64<T, KB, 68, false>(
+        acc, As, Bs, 0, min(nB, r0 + 64),
+        [&](int k, int r) { return r < nrow ? N[(int64_t)(b0 + k) * ld + b0 + r0 + r] : (T)0; },
+        [&](int k, int c) { return N[(int64_t)(b0 + k) * ld + a0 + c0 + c]; }, tid, lane, wr, wc);
+  }
+  for_tile<T>(acc, lane, wr, wc, [&](int i, int jj, T v) {
+    if (pass == 0) {
+      if (jj < nrow) N[(int64_t)(b0 + r0 + jj) * ld + a0 + c0 + i] = v;  // P(r0 + jj, c0 + i)
+    } else {
+      if (i < nrow) N[(int64_t)(a0 + c0 + jj) * ld + b0 + r0 + i] = -v;  // X_BA(r0 + i, c0 + jj)
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
 // forward sweep
 // ---------------------------------------------------------------------------
 
@@ -322,11 +442,11 @@ k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
 }
 
 // z_J = Linv_J w_J; four workgroups (64 rows each) per front, matrix cores
-template <class T, int KB>
+template <class T, int KB, bool NODE>
 __global__ void __launch_bounds__(256)
 k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-           const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
-           const T* __restrict__ linv2, int J0, int tb, int m, const T* __restrict__ rb, T* __restrict__ zb) {
+           const NodeState* __restrict__ st, InvSrc<T> inv, int J0, int tb, int m, const T* __restrict__ rb,
+           T* __restrict__ zb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -334,7 +454,8 @@ k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   const int nc = min(tb, npiv - J0);
   const int I = blockIdx.x;
   if (SB * I >= nc) return;
-  const T* X = step_inverse(linv2, linv2_off[j], J0) + SB * I;
+  int ld;
+  const T* X = inverse_of<NODE>(inv, j, J0, ld) + SB * I;
   const T* W = rb + (ni.rhs_off + J0) * m;
   __shared__ T As[KB][MLD];
   __shared__ T Bs[KB][MLD];
@@ -345,7 +466,7 @@ k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   zero_acc<T>(acc);
   const int cend = min(nc, SB * I + SB);
   tile_gemm_64<T, KB, MLD, false>(
-      acc, As, Bs, 0, cend, [&](int k, int r) { return r < nrows ? X[(int64_t)k * TB + r] : (T)0; },
+      acc, As, Bs, 0, cend, [&](int k, int r) { return r < nrows ? X[(int64_t)k * ld + r] : (T)0; },
       [&](int k, int c) { return c < m ? W[(int64_t)k * m + c] : (T)0; }, tid, lane, wr, wc);
   T* Z = zb + (ni.rhs_off + J0 + SB * I) * m;
   for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
@@ -354,7 +475,8 @@ k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
 }
 
 // w_rows -= L[rows, J0:J0+nc] z_J for the rows below the step, 64-row strips
-template <class T, int KB>
+// (ONE: all pivots in one pass; the strips start at the border)
+template <class T, int KB, bool ONE>
 __global__ void __launch_bounds__(256)
 k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
           const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int tb, int m,
@@ -365,7 +487,7 @@ k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
   if (J0 >= npiv) return;
   const int nc = min(tb, npiv - J0);
   const int f = ni.f, p = ni.p;
-  const int rs = J0 + nc + blockIdx.x * 64;
+  const int rs = (ONE ? p : J0 + nc) + blockIdx.x * 64;
   if (rs >= f) return;
   const int64_t lf = f;
   const T* A = front + ni.front_off + (int64_t)J0 * lf + rs;
@@ -493,12 +615,11 @@ k_bwd_border_fin(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict_
 }
 
 // x_J = Linv_J^T t_J (four workgroups of 64 columns), scattered to the FP64 result
-template <class T, int KB>
+template <class T, int KB, bool NODE>
 __global__ void __launch_bounds__(256)
 k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-           const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
-           const T* __restrict__ linv2, const int32_t* __restrict__ piv, int J0, int tb, int m,
-           double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb) {
+           const NodeState* __restrict__ st, InvSrc<T> inv, const int32_t* __restrict__ piv, int J0, int tb,
+           int m, double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -506,7 +627,8 @@ k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   const int nc = min(tb, npiv - J0);
   const int I = blockIdx.x;
   if (SB * I >= nc) return;
-  const T* X = step_inverse(linv2, linv2_off[j], J0) + (int64_t)SB * I * TB;  // A(c, r) = X[c*TB + r]
+  int ld;
+  const T* X = inverse_of<NODE>(inv, j, J0, ld) + (int64_t)SB * I * ld;  // A(c, r) = X[c*ld + r]
   const T* W = rb + (ni.rhs_off + J0) * m;
   __shared__ T As[KB][MLD];
   __shared__ T Bs[KB][MLD];
@@ -516,7 +638,7 @@ k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   typename Mfma<T>::V acc[2][2];
   zero_acc<T>(acc);
   tile_gemm_64<T, KB, MLD, true>(
-      acc, As, Bs, SB * I, nc, [&](int k, int r) { return r < nrows ? X[(int64_t)r * TB + k] : (T)0; },
+      acc, As, Bs, SB * I, nc, [&](int k, int r) { return r < nrows ? X[(int64_t)r * ld + k] : (T)0; },
       [&](int k, int c) { return c < m ? W[(int64_t)k * m + c] : (T)0; }, tid, lane, wr, wc);
   const int c0 = J0 + SB * I;
   for_tile<T>(acc, lane, wr, wc, [&](int r, int c, T v) {
@@ -600,23 +722,28 @@ __device__ __forceinline__ typename Mfma<T>::V load4k(const T* __restrict__ col,
 // k order inside a round is only a relabelling of the sum).  epi(r, c, v) is
 // called once per output.  With CA (A contiguous in k), fa(k, r) returns the
 // four values A(k .. k + 3, r), zero from ke on, in one load.
-template <class T, int NCB, bool CA = false, class FA, class FB, class EPI>
+template <class T, int NCB, bool CA = false, bool LONG = false, class FA, class FB, class EPI>
 __device__ __forceinline__ void narrow_product(int kb, int ke, FA&& fa, FB&& fb, EPI&& epi) {
   using V = typename Mfma<T>::V;
   constexpr int NR = NarrowRounds<T>::NR, NBATCH = NarrowRounds<T>::NBATCH;
-  static_assert(16 * 4 * NR * NBATCH >= TB, "a wave's rounds cover a step");
-  __shared__ T red[4][NCB][4][64];
+  constexpr int NW = LONG ? 8 : 4;            // waves (LONG: two per SIMD, one's loads under the other's products)
+  constexpr int KCH = 16 * NW * NR * NBATCH;  // values of k per pass
+  static_assert(KCH >= TB, "one pass covers a step");
+  __shared__ T red[NW][NCB][4][64];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int li = lane & 15, g = lane >> 4;
   V acc[NCB];
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) acc[cb] = V{0, 0, 0, 0};
+  // a step takes one pass; with LONG (a whole node inverse) a k range takes
+  // several, in order of k
+  for (int kc = kb; kc < ke; kc += KCH) {
 #pragma unroll
   for (int bt = 0; bt < NBATCH; ++bt) {
     T a[NR][4], b[NR][NCB][4];
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      const int k0 = kb + 16 * (w + 4 * (bt * NR + q)) + 4 * g;
+      const int k0 = kc + 16 * (w + NW * (bt * NR + q)) + 4 * g;
       if constexpr (CA) {
         const V a4 = fa(k0, li);
 #pragma unroll
@@ -632,12 +759,14 @@ __device__ __forceinline__ void narrow_product(int kb, int ke, FA&& fa, FB&& fb,
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-      if (kb + 16 * (w + 4 * (bt * NR + q)) >= ke) break;  // uniform in the wave
+      if (kc + 16 * (w + NW * (bt * NR + q)) >= ke) break;  // uniform in the wave
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[cb] = Mfma<T>::mma(a[q][s], b[q][cb][s], acc[cb]);
     }
+  }
+  if constexpr (!LONG) break;
   }
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb)
@@ -645,20 +774,23 @@ __device__ __forceinline__ void narrow_product(int kb, int ke, FA&& fa, FB&& fb,
     for (int t = 0; t < 4; ++t) red[w][cb][t][lane] = acc[cb][t];
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NCB; ++i) {
-    const int e = tid + 256 * i;
+  for (int i = 0; i < (NCB * 4 + NW - 1) / NW; ++i) {
+    const int e = tid + 64 * NW * i;
+    if (e >= 256 * NCB) break;
     const int ln = e & 63, t = (e >> 6) & 3, cb = e >> 8;
-    const T v = red[0][cb][t][ln] + red[1][cb][t][ln] + red[2][cb][t][ln] + red[3][cb][t][ln];
+    T v = red[0][cb][t][ln];
+#pragma unroll
+    for (int u = 1; u < NW; ++u) v += red[u][cb][t][ln];
     epi(Mfma<T>::row(ln, t), cb * 16 + (ln & 15), v);
   }
 }
 
 // z_J = Linv_J w_J, 16 rows of the step per workgroup
-template <class T, int NCB>
-__global__ void __launch_bounds__(256)
+template <class T, int NCB, bool LONG>
+__global__ void __launch_bounds__(LONG ? 512 : 256)
 k_fwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-             const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
-             const T* __restrict__ linv2, int J0, int tb, int m, const T* __restrict__ rb, T* __restrict__ zb) {
+             const NodeState* __restrict__ st, InvSrc<T> inv, int J0, int tb, int m, const T* __restrict__ rb,
+             T* __restrict__ zb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -667,11 +799,12 @@ k_fwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
   const int r0 = 16 * blockIdx.x;
   if (r0 >= nc) return;
   const int nrows = min(16, nc - r0);
-  const T* X = step_inverse(linv2, linv2_off[j], J0) + r0;  // A(k, r) = X[k TB + r]
+  int ld;
+  const T* X = inverse_of<LONG>(inv, j, J0, ld) + r0;  // A(k, r) = X[k ld + r]
   const T* W = rb + (ni.rhs_off + J0) * m;
   T* Z = zb + (ni.rhs_off + J0 + r0) * m;
-  narrow_product<T, NCB>(
-      0, min(nc, r0 + 16), [&](int k, int r) { return r < nrows ? X[(int64_t)k * TB + r] : (T)0; },
+  narrow_product<T, NCB, false, LONG>(
+      0, min(nc, r0 + 16), [&](int k, int r) { return r < nrows ? X[(int64_t)k * ld + r] : (T)0; },
       [&](int k, int c) { return c < m ? W[(int64_t)k * m + c] : (T)0; },
       [&](int r, int c, T v) {
         if (r < nrows && c < m) Z[(int64_t)r * m + c] = v;
@@ -679,8 +812,8 @@ k_fwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
 }
 
 // w_rows -= L[rows, J0:J0+nc] z_J for 16 rows below the step per workgroup
-template <class T, int NCB>
-__global__ void __launch_bounds__(256)
+template <class T, int NCB, bool LONG>
+__global__ void __launch_bounds__(LONG ? 512 : 256)
 k_fwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
             const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int tb, int m,
             const T* __restrict__ zb, T* __restrict__ rb) {
@@ -690,14 +823,15 @@ k_fwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
   if (J0 >= npiv) return;
   const int nc = min(tb, npiv - J0);
   const int f = ni.f, p = ni.p;
-  const int rs = J0 + nc + 16 * blockIdx.x;
+  // LONG (all pivots in one pass): the postponed rows [npiv, p) are skipped
+  const int rs = (LONG ? p : J0 + nc) + 16 * blockIdx.x;
   if (rs >= f) return;
   const int nrows = min(16, f - rs);
   const int64_t lf = f;
   const T* A = front + ni.front_off + (int64_t)J0 * lf + rs;  // A(k, r) = A[k lf + r]
   const T* Z = zb + (ni.rhs_off + J0) * m;
   T* W = rb + (ni.rhs_off + rs) * m;
-  narrow_product<T, NCB>(
+  narrow_product<T, NCB, false, LONG>(
       0, nc, [&](int k, int r) { return r < nrows ? A[(int64_t)k * lf + r] : (T)0; },
       [&](int k, int c) { return c < m ? Z[(int64_t)k * m + c] : (T)0; },
       [&](int r, int c, T v) {
@@ -707,12 +841,11 @@ k_fwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
 }
 
 // x_J = Linv_J^T t_J, 16 columns of the step per workgroup, scattered to the FP64 result
-template <class T, int NCB>
-__global__ void __launch_bounds__(256)
+template <class T, int NCB, bool LONG>
+__global__ void __launch_bounds__(LONG ? 512 : 256)
 k_bwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-             const NodeState* __restrict__ st, const int64_t* __restrict__ linv2_off,
-             const T* __restrict__ linv2, const int32_t* __restrict__ piv, int J0, int tb, int m,
-             double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb) {
+             const NodeState* __restrict__ st, InvSrc<T> inv, const int32_t* __restrict__ piv, int J0, int tb,
+             int m, double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -721,12 +854,13 @@ k_bwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
   const int r0 = 16 * blockIdx.x;
   if (r0 >= nc) return;
   const int nrows = min(16, nc - r0);
-  const T* X = step_inverse(linv2, linv2_off[j], J0) + (int64_t)r0 * TB;  // A(k, r) = X[r TB + k]
+  int ld;
+  const T* X = inverse_of<LONG>(inv, j, J0, ld) + (int64_t)r0 * ld;  // A(k, r) = X[r ld + k]
   const T* W = rb + (ni.rhs_off + J0) * m;
   const int c0 = J0 + r0;
-  narrow_product<T, NCB, true>(
+  narrow_product<T, NCB, true, LONG>(
       r0, nc,
-      [&](int k, int r) { return r < nrows ? load4k(X + (int64_t)r * TB, k, nc) : typename Mfma<T>::V{0, 0, 0, 0}; },
+      [&](int k, int r) { return r < nrows ? load4k(X + (int64_t)r * ld, k, nc) : typename Mfma<T>::V{0, 0, 0, 0}; },
       [&](int k, int c) { return c < m ? W[(int64_t)k * m + c] : (T)0; },
       [&](int r, int c, T v) {
         if (r < nrows && c < m) {
@@ -1172,6 +1306,31 @@ void step_inverses(hf_ctx* ctx, int l, hipStream_t s) {
                  pass, base);
 }
 
+template <class T>
+void node_inverses(hf_ctx* ctx, hipStream_t s) {
+  if (ctx->ninv_copy.empty()) return;
+  const NodeState* st = ctx->d_state.as<NodeState>();
+  T* ninv = ctx->d_ninv.as<T>();
+  const int64_t* noff = ctx->d_ninv_off.as<int64_t>();
+  const int32_t* nld = ctx->d_ninv_ld.as<int32_t>();
+  launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_ninv_copy<T>,
+               dim3(TB * TB / 1024, (unsigned)ctx->ninv_copy.size()), dim3(256),
+               (const int32_t*)ctx->d_ninv_copy.as<int32_t>(), (const int32_t*)ctx->d_stp_node.as<int32_t>(),
+               (const int32_t*)ctx->d_stp_first.as<int32_t>(), st, (const int64_t*)ctx->d_linv2_off.as<int64_t>(),
+               (const T*)ctx->d_linv2.as<T>(), noff, nld, ninv);
+  for (size_t t = 0; t + 1 < ctx->ninv_lvl.size(); ++t) {
+    const int base = ctx->ninv_lvl[t], nj = ctx->ninv_lvl[t + 1] - base;
+    if (nj <= 0) continue;
+    const int sb = TB << t;
+    for (int pass = 0; pass < 2; ++pass)
+      launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_ninv_merge<T>,
+                   dim3((unsigned)((sb / 64) * (sb / 64)), (unsigned)nj), dim3(256),
+                   (const int32_t*)ctx->d_ninv_jnode.as<int32_t>(), (const int32_t*)ctx->d_ninv_ja0.as<int32_t>(),
+                   (const NodeInfo*)ctx->d_nodes.as<NodeInfo>(), st, (const T*)ctx->d_front.as<T>(), noff, nld, ninv,
+                   sb, pass, base);
+  }
+}
+
 // border product of the backward sweep for 16 pivot rows per workgroup (narrow
 // form of k_bwd_border_part: operands loaded straight into MFMA registers)
 template <class T, int NCB, bool FIN>
@@ -1244,6 +1403,13 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   const T* front = ctx->d_front.as<T>();
   const T* linv2 = ctx->d_linv2.as<T>();
   const int64_t* loff2 = ctx->d_linv2_off.as<int64_t>();
+  // levels with a node of more than one step take each direction in one pass
+  // over the node inverses (when they were formed)
+  const InvSrc<T> isteps{loff2, linv2, nullptr, nullptr, nullptr};
+  const InvSrc<T> inodes{loff2, linv2, ctx->d_ninv_off.as<int64_t>(), ctx->d_ninv_ld.as<int32_t>(),
+                         ctx->d_ninv.as<T>()};
+  auto one_pass = [&](int l) { return ctx->opt.sweep_node_inverse && ctx->level_maxp[l] > TB; };
+  constexpr int ALL = 1 << 30;  // step length of a one-pass level
   const NodeInfo* nodes = ctx->d_nodes.as<NodeInfo>();
   const NodeState* st = ctx->d_state.as<NodeState>();
   const int32_t* lall = ctx->d_level_nodes.as<int32_t>();
@@ -1317,7 +1483,10 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
                  dim3(cdiv((int64_t)maxf * cdiv(m, 16), 256), nl), dim3(256), ln, nodes, st,
                  (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
                  (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, rb);
-    const int tb = step_of(nl);
+    const bool op = one_pass(l);
+    const int tb = op ? ALL : step_of(nl);
+    const int span = op ? maxp : tb;  // rows of one diagonal product
+    const InvSrc<T> inv = op ? inodes : isteps;
     for (int J0 = 0; J0 < maxp; J0 += tb) {
       auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
         if (np <= J0) return;
@@ -1326,16 +1495,19 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         fl += dm * nc * nc;
       });
       {
-        dim3 g(tb / SB, nl);
+        dim3 g(cdiv(span, SB), nl);
         if (wide(g) && ncb > 1)
-          launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s, k_fwd_diag<T, KBW>, g, dim3(256), ln, nodes, st,
-                       loff2, linv2, J0, tb, m, rb, zb);
+          launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s,
+                       op ? k_fwd_diag<T, KBW, true> : k_fwd_diag<T, KBW, false>, g, dim3(256), ln, nodes, st, inv,
+                       J0, tb, m, rb, zb);
         else
           launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s,
-                       pick(k_fwd_diag_n<T, 1>, k_fwd_diag_n<T, 2>, k_fwd_diag_n<T, 4>), dim3(tb / 16, nl), dim3(256),
-                       ln, nodes, st, loff2, linv2, J0, tb, m, rb, zb);
+                       op ? pick(k_fwd_diag_n<T, 1, true>, k_fwd_diag_n<T, 2, true>, k_fwd_diag_n<T, 4, true>)
+                          : pick(k_fwd_diag_n<T, 1, false>, k_fwd_diag_n<T, 2, false>, k_fwd_diag_n<T, 4, false>),
+                       dim3(cdiv(span, 16), nl),
+                       dim3(op ? 512 : 256), ln, nodes, st, inv, J0, tb, m, rb, zb);
       }
-      const int rows = maxf - J0 - 1;
+      const int rows = op ? ctx->level_maxb[l] : maxf - J0 - 1;
       if (rows > 0) {
         dim3 g(cdiv(rows, 64), nl);
         auto wu = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
@@ -1347,12 +1519,15 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           fl += 2.0 * dm * below * nc;
         });
         if (wide(g) && ncb > 1)
-          launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s, k_fwd_upd<T, KBW>, g, dim3(256), ln, nodes, st,
-                       front, J0, tb, m, zb, rb);
+          launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s,
+                       op ? k_fwd_upd<T, KBW, true> : k_fwd_upd<T, KBW, false>, g, dim3(256), ln, nodes, st, front,
+                       J0, tb, m, zb, rb);
         else
           launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s,
-                       pick(k_fwd_upd_n<T, 1>, k_fwd_upd_n<T, 2>, k_fwd_upd_n<T, 4>), dim3(cdiv(rows, 16), nl),
-                       dim3(256), ln, nodes, st, front, J0, tb, m, zb, rb);
+                       op ? pick(k_fwd_upd_n<T, 1, true>, k_fwd_upd_n<T, 2, true>, k_fwd_upd_n<T, 4, true>)
+                          : pick(k_fwd_upd_n<T, 1, false>, k_fwd_upd_n<T, 2, false>, k_fwd_upd_n<T, 4, false>),
+                       dim3(cdiv(rows, 16), nl),
+                       dim3(op ? 512 : 256), ln, nodes, st, front, J0, tb, m, zb, rb);
       }
     }
   }
@@ -1415,7 +1590,10 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         k_bwd_border_fin<T><<<gf, 256, 0, s>>>(ln, nodes, st, ctx->d_dval.as<T>(), m, maxch, maxp, part, zb, rb);
       });
     }
-    const int tb = step_of(nl);
+    const bool op = one_pass(l);
+    const int tb = op ? ALL : step_of(nl);
+    const int span = op ? maxp : tb;
+    const InvSrc<T> inv = op ? inodes : isteps;
     for (int J0 = ((maxp - 1) / tb) * tb; J0 >= 0; J0 -= tb) {
       auto wd = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
         if (np <= J0) return;
@@ -1424,14 +1602,17 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         fl += dm * nc * nc;
       });
       {
-        dim3 g(tb / SB, nl);
+        dim3 g(cdiv(span, SB), nl);
         if (wide(g) && ncb > 1)
-          launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s, k_bwd_diag<T, KBW>, g, dim3(256), ln, nodes, st,
-                       loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
+          launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s,
+                       op ? k_bwd_diag<T, KBW, true> : k_bwd_diag<T, KBW, false>, g, dim3(256), ln, nodes, st, inv,
+                       ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
         else
           launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s,
-                       pick(k_bwd_diag_n<T, 1>, k_bwd_diag_n<T, 2>, k_bwd_diag_n<T, 4>), dim3(tb / 16, nl), dim3(256),
-                       ln, nodes, st, loff2, linv2, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
+                       op ? pick(k_bwd_diag_n<T, 1, true>, k_bwd_diag_n<T, 2, true>, k_bwd_diag_n<T, 4, true>)
+                          : pick(k_bwd_diag_n<T, 1, false>, k_bwd_diag_n<T, 2, false>, k_bwd_diag_n<T, 4, false>),
+                       dim3(cdiv(span, 16), nl),
+                       dim3(op ? 512 : 256), ln, nodes, st, inv, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
       }
       if (J0 > 0) {
         dim3 g(cdiv(J0, 64), nl);
@@ -1456,6 +1637,8 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
 
 template void step_inverses<float>(hf_ctx*, int, hipStream_t);
 template void step_inverses<double>(hf_ctx*, int, hipStream_t);
+template void node_inverses<float>(hf_ctx*, hipStream_t);
+template void node_inverses<double>(hf_ctx*, hipStream_t);
 template void precond_apply<float>(hf_ctx*, int, const double*, double*, hipStream_t);
 template void precond_apply<double>(hf_ctx*, int, const double*, double*, hipStream_t);
 

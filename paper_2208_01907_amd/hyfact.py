@@ -76,7 +76,8 @@ class HFOptions(ctypes.Structure):
                 ("gcr_maxit", ctypes.c_int32), ("ker_tol", ctypes.c_double),
                 ("refine_steps", ctypes.c_int32), ("refine_tol", ctypes.c_double),
                 ("nd_leaf_max", ctypes.c_int32), ("sweep_front_min", ctypes.c_int32),
-                ("sweep_wide_min", ctypes.c_int32)]
+                ("sweep_wide_min", ctypes.c_int32),
+                ("sweep_node_inverse", ctypes.c_int32)]
 
 
 class HFInfo(ctypes.Structure):

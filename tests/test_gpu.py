@@ -234,6 +234,55 @@ def test_preconditioner_sweeps(name):
         assert np.all(Ya[hard32] == 0.0)
 
 
+@pytest.mark.parametrize("n,kdim", [(600, 0), (1100, 2), (2100, 0)])
+def test_node_inverse_sweeps(n, kdim):
+    """One node of more than one 512-column sweep step: each sweep direction
+    takes it in one product with the explicit inverse of its whole L11 (formed
+    by recursive doubling of the step inverses: merges of 512-, 1024- and
+    2048-column blocks, the last block of each ragged; with kdim > 0 the last
+    pivots are postponed and the merges are cut at the pivot count).  FP64
+    factor: against the oracle's substitution, 1e-9 of max|Y|.  FP32 factor:
+    against the chains of 512-column steps on the same factor (the two differ in
+    the rounding of the inverse and the order of the sums), 1e-5 of max|Y|."""
+    W = w.random_dense_workload(n, seed=40 + n, kernel_dim=kdim, cond=1e3, r=2)
+    ref = oracle.hybrid_factorize(W.csr(), W.perm, W.node_ptr, W.parent, tau=W.tau, low=np.float64,
+                                  gcr_block=W.gcr_block)
+    hard = ref.step1.lambda2
+    assert len(hard) == kdim
+
+    def ctx(prec, node_inverse):
+        opt = hy.hf_default_options(tau=W.tau, low_precision=prec, gcr_block=W.gcr_block,
+                                    sweep_node_inverse=node_inverse)
+        c = hy.hf_analyse(W.indptr, W.indices, W.perm, W.node_ptr, W.parent, opt)
+        hy.hf_factorize(c, torch.tensor(W.values, device="cuda"))
+        return c
+
+    rng = np.random.default_rng(n)
+    c64 = ctx(64, 1)
+    assert np.array_equal(hy.hf_schur(c64)[0], np.sort(W.perm[hard]))
+    inv = np.empty(W.n, dtype=np.int64)
+    inv[W.perm] = np.arange(W.n)
+    on, off = ctx(32, 1), ctx(32, 0)
+    hard32 = inv[hy.hf_schur(on)[0]]
+    for m in (1, 16, 40):
+        R = rng.standard_normal((W.n, m))
+        R64 = R.copy()
+        R64[hard] = 0.0
+        Y = hy.hf_precond(c64, torch.tensor(R64, device="cuda")).cpu().numpy()
+        Yref = oracle.precond(ref.step1, R64)
+        err = np.abs(Y - Yref).max() / max(np.abs(Yref).max(), 1e-300)
+        R32 = R.copy()
+        R32[hard32] = 0.0
+        Rt = torch.tensor(R32, device="cuda")
+        Ya = hy.hf_precond(on, Rt).cpu().numpy()
+        Yb = hy.hf_precond(off, Rt).cpu().numpy()
+        d = np.abs(Ya - Yb).max() / max(np.abs(Yb).max(), 1e-300)
+        print(f"  n={n} m={m}: fp64 vs oracle {err:.1e}, fp32 node inverse vs steps {d:.1e}", flush=True)
+        assert err <= 1e-9
+        assert d <= 1e-5
+        assert np.all(Y[hard] == 0.0) and np.all(Ya[hard32] == 0.0)
+
+
 FP16_CASES = ["c1", "inc20", "n2d_ragged", "el6", "stokes8", "dense_k2"]
 
 
