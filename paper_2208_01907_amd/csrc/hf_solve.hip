@@ -263,16 +263,18 @@ k_inv_merge(const int32_t* __restrict__ stp_node, const int32_t* __restrict__ st
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = typename Mfma<T>::V{0, 0, 0, 0};
+  // the zero triangles of Linv_A (k < c) and Linv_B (k > r) are skipped in whole
+  // k stages (the stages keep their boundaries, so the sums are unchanged)
   if (pass == 0) {
-    // P(r, c) = sum_k L[J0 + HB + r, J0 + k] Linv_A(k, c)
+    // P(r, c) = sum_{k >= c0} L[J0 + HB + r, J0 + k] Linv_A(k, c)
     tile_gemm_64<T, KB, 68, false>(
-        acc, As, Bs, 0, HB,
+        acc, As, Bs, c0, HB,
         [&](int k, int r) { return r < nrow ? F[(int64_t)(J0 + k) * f + J0 + HB + r0 + r] : (T)0; },
         [&](int k, int c) { return X0[(int64_t)(c0 + c) * TB + k]; }, tid, lane, wr, wc);
   } else {
-    // X21(r, c) = -sum_k Linv_B(r, k) P(k, c), P(k, c) stored at X0[(HB + k) TB + c]
+    // X21(r, c) = -sum_{k < r0 + 64} Linv_B(r, k) P(k, c), P(k, c) stored at X0[(HB + k) TB + c]
     tile_gemm_64<T, KB, 68, false>(
-        acc, As, Bs, 0, nB,
+        acc, As, Bs, 0, min(nB, r0 + 64),
         [&](int k, int r) { return r < nrow ? X0[(int64_t)(HB + k) * TB + HB + r0 + r] : (T)0; },
         [&](int k, int c) { return X0[(int64_t)(HB + k) * TB + c0 + c]; }, tid, lane, wr, wc);
   }
