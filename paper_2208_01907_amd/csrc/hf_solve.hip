@@ -787,6 +787,17 @@ __device__ __forceinline__ void narrow_product(int kb, int ke, FA&& fa, FB&& fb,
   }
 }
 
+// Row tile of a narrow launch whose A operand runs along the rows (16 rows =
+// 64 bytes in FP32, half a 128-byte line).  Workgroups go to the eight XCDs
+// round-robin by their linear index, and each XCD has its own L2; the tiles are
+// renumbered so that the two halves of a line (tiles 2i, 2i + 1) go to
+// workgroups 8 apart, i.e. to the same XCD, and the line is fetched once.
+__device__ __forceinline__ int xcd_pair_tile(int b, int n) {
+  const int g = b >> 4;
+  if (16 * g + 16 > n) return b;  // the last, partial group keeps its order
+  return 16 * g + 2 * (b & 7) + ((b >> 3) & 1);
+}
+
 // z_J = Linv_J w_J, 16 rows of the step per workgroup
 template <class T, int NCB, bool LONG>
 __global__ void __launch_bounds__(LONG ? 512 : 256)
@@ -798,7 +809,7 @@ k_fwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
   const int npiv = st[j].npiv;
   if (J0 >= npiv) return;
   const int nc = min(tb, npiv - J0);
-  const int r0 = 16 * blockIdx.x;
+  const int r0 = 16 * xcd_pair_tile(blockIdx.x, gridDim.x);
   if (r0 >= nc) return;
   const int nrows = min(16, nc - r0);
   int ld;
@@ -826,7 +837,7 @@ k_fwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
   const int nc = min(tb, npiv - J0);
   const int f = ni.f, p = ni.p;
   // LONG (all pivots in one pass): the postponed rows [npiv, p) are skipped
-  const int rs = (LONG ? p : J0 + nc) + 16 * blockIdx.x;
+  const int rs = (LONG ? p : J0 + nc) + 16 * xcd_pair_tile(blockIdx.x, gridDim.x);
   if (rs >= f) return;
   const int nrows = min(16, f - rs);
   const int64_t lf = f;
