@@ -94,12 +94,22 @@ typedef struct hf_options {
                                launch of at least this many 64-row tiles uses
                                the LDS-staged 64x64 tile products, smaller ones
                                the 16-row register-fed ones (default 256) */
-  int32_t sweep_node_inverse; /* 1 (default): the L11 of every node of more than
-                               512 pivots also gets one explicit inverse, formed
-                               after step 1 by recursive doubling of its
-                               512-column step inverses, and each sweep direction
-                               takes such a level in one diagonal product instead
-                               of a chain of 512-column steps; 0: the chains */
+  int32_t sweep_node_inverse; /* the L11 of every node of more than 512 pivots
+                               also gets one explicit inverse, formed after step 1
+                               by recursive doubling of its 512-column step
+                               inverses, and each sweep direction can take such a
+                               level in one diagonal product instead of a chain of
+                               512-column steps.  1 (default): with an FP32
+                               factor, only for the nodes whose L11 has no
+                               positive entry below the diagonal (the factor of
+                               an M-matrix, such as a diffusion operator: its
+                               inverse has no negative entry, so the products
+                               add terms of one sign), since a product with an
+                               inverse of mixed signs loses accuracy to
+                               cancellation that substitution does not; a level
+                               takes the one product when all its nodes of more
+                               than one step pass (FP64 factors: always).
+                               2: always; 0: never */
 } hf_options;
 
 typedef struct hf_info_t {

@@ -82,7 +82,7 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
   if (o.n_enlarge < 0 || o.gcr_block < 0 || o.gcr_block > 64 || o.gcr_maxit < 1 || !(o.gcr_tol > 0) ||
       !(o.ker_tol >= 0) || o.refine_steps < 0 || o.refine_steps > 8 || !(o.refine_tol > 0) ||
       o.sweep_front_min < 0 || o.sweep_wide_min < 1 ||
-      (o.sweep_node_inverse != 0 && o.sweep_node_inverse != 1))
+      o.sweep_node_inverse < 0 || o.sweep_node_inverse > 2)
     return HF_ERR_ARG;
   if (n > 0) {
     int rc = validate_csr(n, indptr_h, indices_h);
@@ -399,6 +399,10 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
         ctx->ninv_off[j] = ctx->ninv_elems;
         ctx->ninv_ld[j] = ld;
         ctx->ninv_elems += (int64_t)ld * ld;
+        for (int32_t c = 0; c < p; ++c) {  // one sign sum per column
+          ctx->ninv_cnode.push_back(j);
+          ctx->ninv_ccol.push_back(c);
+        }
         for (int32_t t = ctx->stp_first[j]; t < ctx->stp_first[j] + (p + HF_SWEEP_STEP - 1) / HF_SWEEP_STEP; ++t)
           ctx->ninv_copy.push_back(t);
       }
@@ -441,6 +445,8 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
     upload(ctx->d_ninv_copy, ctx->ninv_copy, s);
     upload(ctx->d_ninv_jnode, ctx->ninv_jnode, s);
     upload(ctx->d_ninv_ja0, ctx->ninv_ja0, s);
+    upload(ctx->d_ninv_cnode, ctx->ninv_cnode, s);
+    upload(ctx->d_ninv_ccol, ctx->ninv_ccol, s);
     HF_HIP(hipStreamSynchronize(s));
     ctx->state = 1;
   } catch (const HipError&) {

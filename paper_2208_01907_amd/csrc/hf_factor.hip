@@ -1078,6 +1078,7 @@ void step1(hf_ctx* ctx, const double* values, hipStream_t s) {
   ctx->d_linv.alloc((size_t)std::max<int64_t>(ctx->linv_elems, 1) * sizeof(T));
   ctx->d_linv2.alloc((size_t)std::max<int64_t>(ctx->linv2_elems, 1) * sizeof(T));
   ctx->d_ninv.alloc((size_t)std::max<int64_t>(ctx->ninv_elems, 1) * sizeof(T));
+  ctx->d_ninv_bad.alloc((size_t)std::max(ctx->n_nodes, 1) * sizeof(int32_t));
   ctx->d_dval.alloc((size_t)n * sizeof(T));
   ctx->d_q.alloc((size_t)n * sizeof(double));
   ctx->d_kval.alloc((size_t)ctx->nnz * sizeof(double));

@@ -204,6 +204,8 @@ struct hf_ctx {
   std::vector<int32_t> ninv_copy;                  // sweep steps whose inverse is copied in
   std::vector<int32_t> ninv_jnode, ninv_ja0;       // merges: node, first column of the pair
   std::vector<int32_t> ninv_lvl;                   // merges of block size TB << t: [ninv_lvl[t], ninv_lvl[t + 1])
+  std::vector<int32_t> ninv_cnode, ninv_ccol;      // every column of every node inverse: node, column
+  std::vector<uint8_t> level_one_pass;             // per level: the sweeps take the node inverses
   std::vector<int32_t> ea_items;
   std::vector<int64_t> gat_ptr, gat_src;  // per front-row slot: the child slab rows added into it
   int64_t front_elems = 0, rhs_rows = 0, snap_elems = 0, lbuf_elems = 0;
@@ -227,6 +229,7 @@ struct hf_ctx {
   hf::DBuf d_linv, d_linv_off, d_blk_node, d_blk_first;  // inverses of 64x64 diagonal blocks
   hf::DBuf d_linv2, d_linv2_off, d_stp_node, d_stp_first;  // inverses of the sweep step blocks
   hf::DBuf d_ninv, d_ninv_off, d_ninv_ld, d_ninv_copy, d_ninv_jnode, d_ninv_ja0;  // node inverses
+  hf::DBuf d_ninv_cnode, d_ninv_ccol, d_ninv_bad;  // per node: L11 fails the sign test (no node inverse)
   hf::DBuf d_zb_arena;             // second solve arena (step results)
   hf::DBuf d_part;                 // partial products of the backward border step
   hf::DBuf d_isl2, d_flag;         // uint8 mask [n], error flags

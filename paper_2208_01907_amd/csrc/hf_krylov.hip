@@ -1084,8 +1084,25 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
     if (ctx->n_nodes)
       HF_HIP(hipMemcpyAsync(hst.data(), ctx->d_state.ptr, sizeof(NodeState) * ctx->n_nodes,
                             hipMemcpyDeviceToHost, s));
+    // the sign test of the node inverses (FP32, default mode): which levels the
+    // sweeps take in one product
+    const bool ninv = !ctx->ninv_copy.empty();
+    std::vector<int32_t> bad(ninv ? ctx->n_nodes : 0);
+    if (ninv)
+      HF_HIP(hipMemcpyAsync(bad.data(), ctx->d_ninv_bad.ptr, sizeof(int32_t) * bad.size(), hipMemcpyDeviceToHost,
+                            s));
     HF_HIP(hipStreamSynchronize(s));
     ctx->hstate = hst;
+    {
+      const int nlev = (int)ctx->level_ptr.size() - 1;
+      ctx->level_one_pass.assign(std::max(nlev, 0), 0);
+      for (int l = 0; l < nlev; ++l) {
+        bool one = ninv && ctx->level_maxp[l] > HF_SWEEP_STEP;
+        for (int32_t q = ctx->level_ptr[l]; one && q < ctx->level_ptr[l + 1]; ++q)
+          if (bad[ctx->level_nodes[q]]) one = false;
+        ctx->level_one_pass[l] = one;
+      }
+    }
     ctx->lambda2.clear();
     for (int64_t g = 0; g < n; ++g)
       if (isl2[g]) ctx->lambda2.push_back((int32_t)g);

@@ -305,9 +305,11 @@ __global__ void __launch_bounds__(256)
 k_ninv_copy(const int32_t* __restrict__ steps, const int32_t* __restrict__ stp_node,
             const int32_t* __restrict__ stp_first, const NodeState* __restrict__ st,
             const int64_t* __restrict__ linv2_off, const T* __restrict__ linv2,
-            const int64_t* __restrict__ ninv_off, const int32_t* __restrict__ ninv_ld, T* __restrict__ ninv) {
+            const int64_t* __restrict__ ninv_off, const int32_t* __restrict__ ninv_ld, T* __restrict__ ninv,
+            const int32_t* __restrict__ bad) {
   const int bi = steps[blockIdx.y];
   const int j = stp_node[bi];
+  if (bad[j]) return;  // the sweeps keep the chains for this node
   const int S = bi - stp_first[j];
   const int J0 = S * TB;
   const int npiv = st[j].npiv;
@@ -335,9 +337,11 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_ninv_merge(const int32_t* __restrict__ jnode, const int32_t* __restrict__ ja0, const NodeInfo* __restrict__ nodes,
              const NodeState* __restrict__ st, const T* __restrict__ front, const int64_t* __restrict__ ninv_off,
-             const int32_t* __restrict__ ninv_ld, T* __restrict__ ninv, int sb, int pass, int base) {
+             const int32_t* __restrict__ ninv_ld, T* __restrict__ ninv, const int32_t* __restrict__ bad, int sb,
+             int pass, int base) {
   const int q = base + blockIdx.y;
   const int j = jnode[q], a0 = ja0[q], b0 = a0 + sb;
+  if (bad[j]) return;
   const int npiv = st[j].npiv;
   const int nB = min(sb, npiv - b0);
   if (nB <= 0) return;
@@ -1319,6 +1323,29 @@ void step_inverses(hf_ctx* ctx, int l, hipStream_t s) {
                  pass, base);
 }
 
+// Sign test of the L11 of a node of more than one step (one wave per column):
+// bad[j] is set when a strictly lower entry of column c is positive.  An L11 with
+// no positive entry below the diagonal (the factor of an M-matrix, such as a
+// diffusion operator) has an inverse with no negative entry, so the products
+// with the node inverse add terms of one sign; otherwise they can cancel, and
+// the sweeps keep the chains of steps (substitution does not lose accuracy to
+// that cancellation).  Order-independent: the flag is only ever raised.
+template <class T>
+__global__ void __launch_bounds__(256)
+k_l11_sign(int ncols, const int32_t* __restrict__ cnode, const int32_t* __restrict__ ccol,
+           const NodeInfo* __restrict__ nodes, const NodeState* __restrict__ st, const T* __restrict__ front,
+           int32_t* __restrict__ bad) {
+  const int q = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (q >= ncols) return;
+  const int j = cnode[q], c = ccol[q];
+  const int npiv = st[j].npiv;
+  const NodeInfo ni = nodes[j];
+  const T* L = front + ni.front_off + (int64_t)c * ni.f;
+  bool pos = false;
+  for (int r = c + 1 + lane; r < npiv; r += 64) pos |= L[r] > (T)0;
+  if (__any(pos) && lane == 0) atomicOr(bad + j, 1);
+}
+
 template <class T>
 void node_inverses(hf_ctx* ctx, hipStream_t s) {
   if (ctx->ninv_copy.empty()) return;
@@ -1326,11 +1353,20 @@ void node_inverses(hf_ctx* ctx, hipStream_t s) {
   T* ninv = ctx->d_ninv.as<T>();
   const int64_t* noff = ctx->d_ninv_off.as<int64_t>();
   const int32_t* nld = ctx->d_ninv_ld.as<int32_t>();
+  // FP32, default mode: the sign test decides which nodes get an inverse
+  int32_t* bad = ctx->d_ninv_bad.as<int32_t>();
+  HF_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t) * ctx->n_nodes, s));
+  if (ctx->opt.sweep_node_inverse == 1 && std::is_same<T, float>::value) {
+    const int ncols = (int)ctx->ninv_cnode.size();
+    launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_l11_sign<T>, dim3(cdiv(ncols, 4)), dim3(256), ncols,
+                 (const int32_t*)ctx->d_ninv_cnode.as<int32_t>(), (const int32_t*)ctx->d_ninv_ccol.as<int32_t>(),
+                 (const NodeInfo*)ctx->d_nodes.as<NodeInfo>(), st, (const T*)ctx->d_front.as<T>(), bad);
+  }
   launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_ninv_copy<T>,
                dim3(TB * TB / 1024, (unsigned)ctx->ninv_copy.size()), dim3(256),
                (const int32_t*)ctx->d_ninv_copy.as<int32_t>(), (const int32_t*)ctx->d_stp_node.as<int32_t>(),
                (const int32_t*)ctx->d_stp_first.as<int32_t>(), st, (const int64_t*)ctx->d_linv2_off.as<int64_t>(),
-               (const T*)ctx->d_linv2.as<T>(), noff, nld, ninv);
+               (const T*)ctx->d_linv2.as<T>(), noff, nld, ninv, (const int32_t*)bad);
   for (size_t t = 0; t + 1 < ctx->ninv_lvl.size(); ++t) {
     const int base = ctx->ninv_lvl[t], nj = ctx->ninv_lvl[t + 1] - base;
     if (nj <= 0) continue;
@@ -1340,7 +1376,7 @@ void node_inverses(hf_ctx* ctx, hipStream_t s) {
                    dim3((unsigned)((sb / 64) * (sb / 64)), (unsigned)nj), dim3(256),
                    (const int32_t*)ctx->d_ninv_jnode.as<int32_t>(), (const int32_t*)ctx->d_ninv_ja0.as<int32_t>(),
                    (const NodeInfo*)ctx->d_nodes.as<NodeInfo>(), st, (const T*)ctx->d_front.as<T>(), noff, nld, ninv,
-                   sb, pass, base);
+                   (const int32_t*)bad, sb, pass, base);
   }
 }
 
@@ -1421,7 +1457,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   const InvSrc<T> isteps{loff2, linv2, nullptr, nullptr, nullptr};
   const InvSrc<T> inodes{loff2, linv2, ctx->d_ninv_off.as<int64_t>(), ctx->d_ninv_ld.as<int32_t>(),
                          ctx->d_ninv.as<T>()};
-  auto one_pass = [&](int l) { return ctx->opt.sweep_node_inverse && ctx->level_maxp[l] > TB; };
+  auto one_pass = [&](int l) { return l < (int)ctx->level_one_pass.size() && ctx->level_one_pass[l]; };
   constexpr int ALL = 1 << 30;  // step length of a one-pass level
   const NodeInfo* nodes = ctx->d_nodes.as<NodeInfo>();
   const NodeState* st = ctx->d_state.as<NodeState>();

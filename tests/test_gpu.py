@@ -241,9 +241,11 @@ def test_node_inverse_sweeps(n, kdim):
     by recursive doubling of the step inverses: merges of 512-, 1024- and
     2048-column blocks, the last block of each ragged; with kdim > 0 the last
     pivots are postponed and the merges are cut at the pivot count).  FP64
-    factor: against the oracle's substitution, 1e-9 of max|Y|.  FP32 factor:
-    against the chains of 512-column steps on the same factor (the two differ in
-    the rounding of the inverse and the order of the sums), 1e-5 of max|Y|."""
+    factor: against the oracle's substitution, 1e-9 of max|Y|.  FP32 factor (the
+    one product forced, sweep_node_inverse = 2): against the chains of 512-column
+    steps on the same factor (the two differ in the rounding of the inverse and
+    the order of the sums), 1e-5 of max|Y|.  The default mode keeps the chains
+    here: the inverse of a random dense block has entries of both signs."""
     W = w.random_dense_workload(n, seed=40 + n, kernel_dim=kdim, cond=1e3, r=2)
     ref = oracle.hybrid_factorize(W.csr(), W.perm, W.node_ptr, W.parent, tau=W.tau, low=np.float64,
                                   gcr_block=W.gcr_block)
@@ -262,7 +264,7 @@ def test_node_inverse_sweeps(n, kdim):
     assert np.array_equal(hy.hf_schur(c64)[0], np.sort(W.perm[hard]))
     inv = np.empty(W.n, dtype=np.int64)
     inv[W.perm] = np.arange(W.n)
-    on, off = ctx(32, 1), ctx(32, 0)
+    on, off, auto = ctx(32, 2), ctx(32, 0), ctx(32, 1)
     hard32 = inv[hy.hf_schur(on)[0]]
     for m in (1, 16, 40):
         R = rng.standard_normal((W.n, m))
@@ -276,11 +278,41 @@ def test_node_inverse_sweeps(n, kdim):
         Rt = torch.tensor(R32, device="cuda")
         Ya = hy.hf_precond(on, Rt).cpu().numpy()
         Yb = hy.hf_precond(off, Rt).cpu().numpy()
+        assert np.array_equal(hy.hf_precond(auto, Rt).cpu().numpy(), Yb)
         d = np.abs(Ya - Yb).max() / max(np.abs(Yb).max(), 1e-300)
         print(f"  n={n} m={m}: fp64 vs oracle {err:.1e}, fp32 node inverse vs steps {d:.1e}", flush=True)
         assert err <= 1e-9
         assert d <= 1e-5
         assert np.all(Y[hard] == 0.0) and np.all(Ya[hard32] == 0.0)
+
+
+def test_node_inverse_default_mode():
+    """The default mode takes the one product with the node inverses where their
+    entries off the 512-column diagonal blocks have one sign: a diffusion
+    operator with positive coefficients (an M-matrix; 24^3 cells, root separator
+    of 576 pivots) gives the same FP32 preconditioner as the forced one product,
+    bit for bit, and not the same as the chains.  In FP64 the default always
+    takes the one product."""
+    W = CASES["inc24"]()
+
+    def ctx(prec, node_inverse):
+        opt = hy.hf_default_options(tau=W.tau, low_precision=prec, gcr_block=W.gcr_block,
+                                    sweep_node_inverse=node_inverse)
+        c = hy.hf_analyse(W.indptr, W.indices, W.perm, W.node_ptr, W.parent, opt)
+        hy.hf_factorize(c, torch.tensor(W.values, device="cuda"))
+        return c
+
+    inv = np.empty(W.n, dtype=np.int64)
+    inv[W.perm] = np.arange(W.n)
+    for prec in (32, 64):
+        auto, forced, chains = ctx(prec, 1), ctx(prec, 2), ctx(prec, 0)
+        R = np.random.default_rng(24).standard_normal((W.n, 16))
+        R[inv[hy.hf_schur(auto)[0]]] = 0.0
+        Rt = torch.tensor(R, device="cuda")
+        Ya, Yf, Yc = (hy.hf_precond(c, Rt).cpu().numpy() for c in (auto, forced, chains))
+        assert np.array_equal(Ya, Yf)
+        assert not np.array_equal(Ya, Yc)
+        assert np.abs(Ya - Yc).max() <= (1e-5 if prec == 32 else 1e-12) * np.abs(Yc).max()
 
 
 FP16_CASES = ["c1", "inc20", "n2d_ragged", "el6", "stokes8", "dense_k2"]
