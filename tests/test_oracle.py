@@ -495,3 +495,17 @@ def test_adjoint_stokes_viscosity_gradient():
     fd = (loss(mu + h * d) - loss(mu - h * d)) / (2 * h)
     an = float(grad @ d.reshape(-1, order="F"))
     assert abs(an - fd) <= 1e-6 * abs(fd)
+
+
+def test_bench_backward_error_matches_oracle():
+    """The benchmark's backward-error measure (package metrics, SciPy's sparse
+    product in long double) agrees with the oracle's (per-entry accumulation in
+    long double) on exact, perturbed and zero solutions."""
+    from paper_2208_01907_amd import metrics
+    W = w.neumann2d(12, 9, seed=3, leaf_max=16, r=3)
+    K = W.csr()
+    rng = np.random.default_rng(8)
+    X = np.linalg.lstsq(K.toarray(), W.b, rcond=None)[0]
+    for Xt in (X, X + 1e-9 * rng.standard_normal(X.shape), np.zeros_like(X)):
+        a, b = metrics.backward_error(K, Xt, W.b), oracle.backward_error(K, Xt, W.b)
+        assert abs(a - b) <= 1e-3 * max(b, 1e-300) + 1e-20, (a, b)
