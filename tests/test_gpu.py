@@ -536,6 +536,31 @@ def test_refactorize_new_values_and_reproducibility():
     assert np.allclose(4.0 * X4, X1, rtol=1e-12, atol=1e-14 * np.abs(X1).max())
 
 
+@pytest.mark.parametrize("prec", [32, 64])
+def test_refactorize_other_values_matches_fresh_context(prec):
+    """A context factorized with one matrix and then with another of the same
+    pattern gives, bit for bit, what a fresh context gives for the second: no
+    state of the first factorization (front arena, inverses, sweep choices)
+    leaks into the second."""
+    A = w.inclusions3d(16, 5, seed=12, leaf_max=100, r=2, gcr_block=0)
+    B = w.inclusions3d(16, 7, seed=31, leaf_max=100, r=2, gcr_block=0)
+    assert np.array_equal(A.indptr, B.indptr) and np.array_equal(A.indices, B.indices)
+    assert np.array_equal(A.perm, B.perm) and np.array_equal(A.parent, B.parent)
+    opt = hy.hf_default_options(tau=A.tau, low_precision=prec)
+    reused = hy.hf_analyse(A.indptr, A.indices, A.perm, A.node_ptr, A.parent, opt)
+    fresh = hy.hf_analyse(B.indptr, B.indices, B.perm, B.node_ptr, B.parent, opt)
+    rhs = torch.tensor(B.b, device="cuda")
+    hy.hf_factorize(reused, torch.tensor(A.values, device="cuda"))
+    hy.hf_solve(reused, torch.tensor(A.b, device="cuda"))
+    hy.hf_factorize(reused, torch.tensor(B.values, device="cuda"))
+    hy.hf_factorize(fresh, torch.tensor(B.values, device="cuda"))
+    assert np.array_equal(hy.hf_pivots(reused)["npiv"], hy.hf_pivots(fresh)["npiv"])
+    l1, S1 = hy.hf_schur(reused)
+    l2, S2 = hy.hf_schur(fresh)
+    assert np.array_equal(l1, l2) and np.array_equal(S1.cpu().numpy(), S2.cpu().numpy())
+    assert np.array_equal(hy.hf_solve(reused, rhs).cpu().numpy(), hy.hf_solve(fresh, rhs).cpu().numpy())
+
+
 def test_zero_and_many_rhs():
     W = w.neumann2d(20, 18, seed=13, leaf_max=30, r=70)   # more than one 64-column chunk
     ctx = _gpu(W, 32, gcr_block=0)
