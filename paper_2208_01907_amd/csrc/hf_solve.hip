@@ -1453,7 +1453,8 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   const T* linv2 = ctx->d_linv2.as<T>();
   const int64_t* loff2 = ctx->d_linv2_off.as<int64_t>();
   // levels with a node of more than one step take each direction in one pass
-  // over the node inverses (when they were formed)
+  // over the node inverses where step 1 formed them for all such nodes of the
+  // level (level_one_pass, set after step 1 from the sign test of L11)
   const InvSrc<T> isteps{loff2, linv2, nullptr, nullptr, nullptr};
   const InvSrc<T> inodes{loff2, linv2, ctx->d_ninv_off.as<int64_t>(), ctx->d_ninv_ld.as<int32_t>(),
                          ctx->d_ninv.as<T>()};
