@@ -890,6 +890,14 @@ struct BgcrWork {
   int64_t n = 0;
   int m = 0, kw = 0, slots = 0;
   DBuf P, Qv, R, Z, T1, partial, gram, Lc, piv, rank, coef, norms;
+  // the convergence test's column norms come back through pinned host memory,
+  // and the host polls an event for them (a blocking wait wakes up later)
+  double* hnorm = nullptr;
+  hipEvent_t ready = nullptr;
+  ~BgcrWork() {
+    if (hnorm) (void)hipHostFree(hnorm);
+    if (ready) (void)hipEventDestroy(ready);
+  }
 };
 
 void free_work(hf_ctx* ctx) {
@@ -900,7 +908,12 @@ void free_work(hf_ctx* ctx) {
 // Work space of block GCR on m columns; kw: widest block of the kernel basis a
 // Gram product will pair with them (sizes the partial sums only).
 static BgcrWork& get_work(hf_ctx* ctx, int m, int kw = 0) {
-  if (!ctx->work) ctx->work = new BgcrWork();
+  if (!ctx->work) {
+    auto* nw = new BgcrWork();
+    ctx->work = nw;
+    HF_HIP(hipHostMalloc((void**)&nw->hnorm, sizeof(double) * MAXM, hipHostMallocDefault));
+    HF_HIP(hipEventCreateWithFlags(&nw->ready, hipEventDisableTiming));
+  }
   BgcrWork& w = *ctx->work;
   const int slots = ctx->opt.gcr_maxit + 1;
   if (w.n != ctx->n || w.m < m || w.kw < kw || w.slots < slots) {
@@ -991,8 +1004,14 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
                  dim3(256), n, m, Rd, w.partial.as<double>());
     launch_timed(ctx->timer, HF_K_OTHER, 0.0, 0.0, s, k_colsq_reduce, dim3(1), dim3(1024), m,
                  (const double*)w.partial.as<double>(), nrm);
-    HF_HIP(hipMemcpyAsync(out, nrm, sizeof(double) * m, hipMemcpyDeviceToHost, s));
-    HF_HIP(hipStreamSynchronize(s));
+    HF_HIP(hipMemcpyAsync(w.hnorm, nrm, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    HF_HIP(hipEventRecord(w.ready, s));
+    for (;;) {
+      const hipError_t e = hipEventQuery(w.ready);
+      if (e == hipSuccess) break;
+      if (e != hipErrorNotReady) HF_HIP(e);
+    }
+    std::copy(w.hnorm, w.hnorm + m, out);
   };
   // ||b_k||^2
   colsq(B, hb.data());
