@@ -4,13 +4,19 @@ The adjoint is an extension of Algorithm 2: one more solve on the same factors
 gives Lam = Kbar^+ P G for a loss gradient G = dl/dX (P projects onto the range),
 and dl/dvalues[(i, j)] = -sum_c Lam[i, c] X[j, c] on the stored pattern.
 
-Parity: Lam and the value gradient against oracle.adjoint_solve /
-oracle.value_gradient on the same seeded inputs (G is drawn from its own seed,
-with a kernel component that the projection must remove).  Tolerances follow the
-solution bar of the parity tests: relative error <= max(1e-10, 4 x the oracle's
-forward error on X) for Lam (same matrix, same conditioning), twice that for the
-value gradient (a product of two such quantities), and backward error <= 1e-14 of
-Lam against P G.  At the benchmark sizes the oracle's dense solve does not fit;
+Parity, against two references computed by the oracle alone:
+- the oracle's hybrid method (oracle.hybrid_solve, oracle.value_gradient) for a G
+  already in the range (projected with the closed-form kernel), and
+- the oracle's dense pseudo-inverse solve (oracle.adjoint_solve) for a G with a
+  kernel component (drawn from its own seed) that the projection must remove.
+Bar: relative error <= max(1e-10, 4 x the dense solver's own forward error on X)
+for Lam, twice that for the value gradient (a product of two such quantities),
+and backward error <= 1e-14 of Lam against P G.  Unlike the solution X, whose
+right-hand side is K x* with x* smooth, a random G excites the smallest
+eigenvalues, and one correction pass (refine_steps = 1, as in hf_solve) leaves
+both hybrid solves about cond(K) * eps apart: on the 14^3 inclusions (contrast
+1e6) Lam agrees with the hybrid oracle to 2.5e-10 and with the dense one to
+6e-10, inside the bar of 2.7e-9; the other cases agree to 1e-12 or better.  At the benchmark sizes the oracle's dense solve does not fit;
 there the checks are properties that hold at any size: the backward error of Lam
 and the identity sum(GV * values) = -trace(Lam^T B) for K X = B.  The backward
 error bar there is looser (see the test): the projection uses the detected kernel,
@@ -74,12 +80,25 @@ def test_adjoint_parity(name, prec):
     X = hy.hf_solve(ctx, torch.tensor(W.b, device="cuda"))
     Lam, GV = hy.hf_adjoint(ctx, X, torch.tensor(G, device="cuda"))
     Lam, GV = Lam.cpu().numpy(), GV.cpu().numpy()
+    # the oracle's hybrid method, same precision of step 1 as the GPU run
+    ref = oracle.hybrid_factorize(K, W.perm, W.node_ptr, W.parent, tau=W.tau,
+                                  low=np.float32 if prec == 32 else np.float64, gcr_block=W.gcr_block,
+                                  n_enlarge=W.meta.get("n_enlarge", 4))
+    Gc = _project(W, G)
+    Lc, GVc = hy.hf_adjoint(ctx, X, torch.tensor(Gc, device="cuda"))
+    Xh, Lh = oracle.hybrid_solve(ref, W.b), oracle.hybrid_solve(ref, Gc)
+    GVh = oracle.value_gradient(W.indptr, W.indices, Xh, Lh)
+    rh = np.linalg.norm(Lc.cpu().numpy() - Lh) / np.linalg.norm(Lh)
+    rgh = np.linalg.norm(GVc.cpu().numpy() - GVh) / np.linalg.norm(GVh)
     fwd = np.linalg.norm(Xref - W.x_star) / np.linalg.norm(W.x_star)
     bar = max(1e-10, 4 * fwd)
     rl = np.linalg.norm(Lam - Lref) / np.linalg.norm(Lref)
     rg = np.linalg.norm(GV - GVref) / np.linalg.norm(GVref)
     be = oracle.backward_error(K, Lam, _project(W, G))
-    print(f"  rel(Lam)={rl:.2e} rel(GV)={rg:.2e} be(Lam)={be:.2e} bar={bar:.1e}", flush=True)
+    print(f"  vs hybrid oracle: rel(Lam)={rh:.2e} rel(GV)={rgh:.2e}; vs dense oracle: rel(Lam)={rl:.2e} "
+          f"rel(GV)={rg:.2e} bar={bar:.1e}; be(Lam)={be:.2e}", flush=True)
+    assert rh <= bar
+    assert rgh <= 2 * bar
     assert rl <= bar
     assert rg <= 2 * bar
     assert be <= 1e-14
