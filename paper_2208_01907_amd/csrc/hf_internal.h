@@ -232,6 +232,8 @@ struct hf_ctx {
   hf::DBuf d_ninv_cnode, d_ninv_ccol, d_ninv_bad;  // per node: L11 fails the sign test (no node inverse)
   hf::DBuf d_zb_arena;             // second solve arena (step results)
   hf::DBuf d_part;                 // partial products of the backward border step
+  hf::DBuf d_live;                 // per node: last preconditioner application with a nonzero forward block
+  int32_t live_gen = 0;
   hf::DBuf d_isl2, d_flag;         // uint8 mask [n], error flags
   int32_t factor_prec = 0;         // precision of d_front
   // hard part

@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(256)
 k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
              const NodeState* __restrict__ st, const int32_t* __restrict__ ipos,
              const int64_t* __restrict__ gat_ptr, const int64_t* __restrict__ gat_src, int m,
-             const double* __restrict__ R, T* __restrict__ rb) {
+             const double* __restrict__ R, T* __restrict__ rb, int32_t* __restrict__ live, int gen) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -437,6 +437,13 @@ k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
         if (c < nc) v[c] += src[c];
     }
   }
+  // a front whose gathered block is all zero skips its forward products (a
+  // right-hand side with few nonzero rows, such as the columns of K12)
+  bool nz = false;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) nz |= v[c] != (T)0;
+  const unsigned long long anyw = __ballot(nz);  // one store per wave
+  if (anyw && (int)(threadIdx.x & 63) == __ffsll((long long)anyw) - 1) live[j] = gen;
   T* dst = rb + (ni.rhs_off + pr) * m + c0;
   if (nc == 16) {
     __builtin_memcpy(dst, v, 16 * sizeof(T));
@@ -452,7 +459,7 @@ template <class T, int KB, bool NODE>
 __global__ void __launch_bounds__(256)
 k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
            const NodeState* __restrict__ st, InvSrc<T> inv, int J0, int tb, int m, const T* __restrict__ rb,
-           T* __restrict__ zb) {
+           T* __restrict__ zb, const int32_t* __restrict__ live, int gen) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -460,6 +467,11 @@ k_fwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   const int nc = min(tb, npiv - J0);
   const int I = blockIdx.x;
   if (SB * I >= nc) return;
+  if (live[j] != gen) {  // zero right-hand side block: z = 0
+    T* Z0 = zb + (ni.rhs_off + J0 + SB * I) * m;
+    for (int e = threadIdx.x; e < min(SB, nc - SB * I) * m; e += blockDim.x) Z0[e] = (T)0;
+    return;
+  }
   int ld;
   const T* X = inverse_of<NODE>(inv, j, J0, ld) + SB * I;
   const T* W = rb + (ni.rhs_off + J0) * m;
@@ -486,11 +498,11 @@ template <class T, int KB, bool ONE>
 __global__ void __launch_bounds__(256)
 k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
           const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int tb, int m,
-          const T* __restrict__ zb, T* __restrict__ rb) {
+          const T* __restrict__ zb, T* __restrict__ rb, const int32_t* __restrict__ live, int gen) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
-  if (J0 >= npiv) return;
+  if (J0 >= npiv || live[j] != gen) return;
   const int nc = min(tb, npiv - J0);
   const int f = ni.f, p = ni.p;
   const int rs = (ONE ? p : J0 + nc) + blockIdx.x * 64;
@@ -807,7 +819,7 @@ template <class T, int NCB, bool LONG>
 __global__ void __launch_bounds__(LONG ? 512 : 256)
 k_fwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
              const NodeState* __restrict__ st, InvSrc<T> inv, int J0, int tb, int m, const T* __restrict__ rb,
-             T* __restrict__ zb) {
+             T* __restrict__ zb, const int32_t* __restrict__ live, int gen) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -816,6 +828,11 @@ k_fwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
   const int r0 = 16 * xcd_pair_tile(blockIdx.x, gridDim.x);
   if (r0 >= nc) return;
   const int nrows = min(16, nc - r0);
+  if (live[j] != gen) {  // zero right-hand side block: z = 0
+    T* Z0 = zb + (ni.rhs_off + J0 + r0) * m;
+    for (int e = threadIdx.x; e < nrows * m; e += blockDim.x) Z0[e] = (T)0;
+    return;
+  }
   int ld;
   const T* X = inverse_of<LONG>(inv, j, J0, ld) + r0;  // A(k, r) = X[k ld + r]
   const T* W = rb + (ni.rhs_off + J0) * m;
@@ -833,11 +850,11 @@ template <class T, int NCB, bool LONG>
 __global__ void __launch_bounds__(LONG ? 512 : 256)
 k_fwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
             const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int tb, int m,
-            const T* __restrict__ zb, T* __restrict__ rb) {
+            const T* __restrict__ zb, T* __restrict__ rb, const int32_t* __restrict__ live, int gen) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
-  if (J0 >= npiv) return;
+  if (J0 >= npiv || live[j] != gen) return;
   const int nc = min(tb, npiv - J0);
   const int f = ni.f, p = ni.p;
   // LONG (all pivots in one pass): the postponed rows [npiv, p) are skipped
@@ -1484,6 +1501,20 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     }
     ctx->d_part.alloc(need * sizeof(T));
   }
+  // per front: the number of the last application whose gathered forward block
+  // had a nonzero (written by the gathers; no clearing between applications)
+  if (ctx->d_live.bytes < (size_t)std::max(ctx->n_nodes, 1) * sizeof(int32_t)) {
+    ctx->d_live.alloc((size_t)std::max(ctx->n_nodes, 1) * sizeof(int32_t));
+    HF_HIP(hipMemsetAsync(ctx->d_live.ptr, 0, ctx->d_live.bytes, s));
+    ctx->live_gen = 0;
+  }
+  if (ctx->live_gen == INT32_MAX) {  // all numbers used: start again from a cleared array
+    HF_HIP(hipMemsetAsync(ctx->d_live.ptr, 0, ctx->d_live.bytes, s));
+    ctx->live_gen = 0;
+  }
+  ++ctx->live_gen;
+  int32_t* live = ctx->d_live.as<int32_t>();
+  const int gen = ctx->live_gen;
   // the backward sweep writes every row of the moderate part; the hard part's rows
   // (also read as border values) stay zero
   if (ctx->M > 0)
@@ -1532,7 +1563,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     launch_timed(tm, HF_K_SOLVE_GATHER, wg.first, wg.second, s, k_fwd_gather<T>,
                  dim3(cdiv((int64_t)maxf * cdiv(m, 16), 256), nl), dim3(256), ln, nodes, st,
                  (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
-                 (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, rb);
+                 (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, rb, live, gen);
     const bool op = one_pass(l);
     const int tb = op ? ALL : step_of(nl);
     const int span = op ? maxp : tb;  // rows of one diagonal product
@@ -1549,13 +1580,13 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s,
                        op ? k_fwd_diag<T, KBW, true> : k_fwd_diag<T, KBW, false>, g, dim3(256), ln, nodes, st, inv,
-                       J0, tb, m, rb, zb);
+                       J0, tb, m, rb, zb, (const int32_t*)live, gen);
         else
           launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s,
                        op ? pick(k_fwd_diag_n<T, 1, true>, k_fwd_diag_n<T, 2, true>, k_fwd_diag_n<T, 4, true>)
                           : pick(k_fwd_diag_n<T, 1, false>, k_fwd_diag_n<T, 2, false>, k_fwd_diag_n<T, 4, false>),
                        dim3(cdiv(span, 16), nl),
-                       dim3(op ? 512 : 256), ln, nodes, st, inv, J0, tb, m, rb, zb);
+                       dim3(op ? 512 : 256), ln, nodes, st, inv, J0, tb, m, rb, zb, (const int32_t*)live, gen);
       }
       const int rows = op ? ctx->level_maxb[l] : maxf - J0 - 1;
       if (rows > 0) {
@@ -1571,13 +1602,13 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s,
                        op ? k_fwd_upd<T, KBW, true> : k_fwd_upd<T, KBW, false>, g, dim3(256), ln, nodes, st, front,
-                       J0, tb, m, zb, rb);
+                       J0, tb, m, zb, rb, (const int32_t*)live, gen);
         else
           launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s,
                        op ? pick(k_fwd_upd_n<T, 1, true>, k_fwd_upd_n<T, 2, true>, k_fwd_upd_n<T, 4, true>)
                           : pick(k_fwd_upd_n<T, 1, false>, k_fwd_upd_n<T, 2, false>, k_fwd_upd_n<T, 4, false>),
                        dim3(cdiv(rows, 16), nl),
-                       dim3(op ? 512 : 256), ln, nodes, st, front, J0, tb, m, zb, rb);
+                       dim3(op ? 512 : 256), ln, nodes, st, front, J0, tb, m, zb, rb, (const int32_t*)live, gen);
       }
     }
   }
