@@ -1140,6 +1140,7 @@ k_fwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
   const int f = ni.f, p = ni.p, b = ni.b;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15;
   // one thread per front row: every load of a row is issued at once
+  int nz = 0;
   for (int a = tid; a < f; a += FRONT_NT) {
     const int pr = a < p ? ipos[ni.start + a] : a;
     if (pr >= npiv && pr < p) continue;
@@ -1147,6 +1148,8 @@ k_fwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
     load_row<W>(R, (int64_t)(ni.start + a) * m, m, a < p, v);
     const int64_t slot = ni.rhs_off + a;
     for (int64_t i = gat_ptr[slot]; i < gat_ptr[slot + 1]; ++i) add_row<W>(rb + gat_src[i] * m, m, v);
+#pragma unroll
+    for (int c = 0; c < W; ++c) nz |= v[c] != 0.f;
     if (pr < npiv) {
 #pragma unroll
       for (int c = 0; c < W; ++c) ws[pr][c] = v[c];
@@ -1154,7 +1157,13 @@ k_fwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
       store_row<W>(rb + (ni.rhs_off + pr) * m, m, v);
     }
   }
-  __syncthreads();
+  // an all-zero block (a right-hand side with few nonzero rows, such as the
+  // columns of K12): z = 0, and the border rows keep the zeros just stored
+  if (!__syncthreads_or(nz)) {
+    float* Z = zb + ni.rhs_off * m;
+    for (int e = tid; e < npiv * m; e += FRONT_NT) Z[e] = 0.f;
+    return;
+  }
   const float* X = linv2 + linv2_off[j];  // the front's single step, column-major TB x TB
   const int ntile = (npiv + 15) / 16;
   hf_f4 zt[MT][1][NCB];
