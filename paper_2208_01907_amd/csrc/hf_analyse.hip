@@ -445,6 +445,14 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
     upload(ctx->d_ninv_copy, ctx->ninv_copy, s);
     upload(ctx->d_ninv_jnode, ctx->ninv_jnode, s);
     upload(ctx->d_ninv_ja0, ctx->ninv_ja0, s);
+    {
+      // the root of every node's tree (nodes are numbered children first)
+      std::vector<int32_t> rootof(std::max(n_nodes, 1), 0);
+      for (int32_t j = n_nodes - 1; j >= 0; --j) rootof[j] = par[j] >= 0 ? rootof[par[j]] : j;
+      ctx->n_roots = 0;
+      for (int32_t j = 0; j < n_nodes; ++j) ctx->n_roots += par[j] < 0;
+      upload(ctx->d_rootof, rootof, s);
+    }
     upload(ctx->d_ninv_cnode, ctx->ninv_cnode, s);
     upload(ctx->d_ninv_ccol, ctx->ninv_ccol, s);
     HF_HIP(hipStreamSynchronize(s));

@@ -233,6 +233,9 @@ struct hf_ctx {
   hf::DBuf d_zb_arena;             // second solve arena (step results)
   hf::DBuf d_part;                 // partial products of the backward border step
   hf::DBuf d_live;                 // per node: last preconditioner application with a nonzero forward block
+  hf::DBuf d_tree_live;            // per tree root: the same for any front of the tree
+  hf::DBuf d_rootof;               // per node: the root of its tree
+  int32_t n_roots = 0;             // trees of the forest
   int32_t live_gen = 0;
   hf::DBuf d_isl2, d_flag;         // uint8 mask [n], error flags
   int32_t factor_prec = 0;         // precision of d_front

@@ -384,6 +384,19 @@ k_ninv_merge(const int32_t* __restrict__ jnode, const int32_t* __restrict__ ja0,
   });
 }
 
+// Generation-stamped marks of one preconditioner application: live[j] = gen
+// when front j gathered a nonzero forward block, tree[root] = gen when any front
+// of that tree did.  A tree with no mark (a system of a block-diagonal forest
+// that the right-hand sides do not touch) has z = 0 everywhere, hence x = 0: the
+// backward sweep skips it (rootof null: a single tree, never skipped).
+struct SweepMarks {
+  int32_t* live;
+  int32_t* tree;
+  const int32_t* rootof;
+  int gen;
+  __device__ bool zero_tree(int j) const { return rootof && tree[rootof[j]] != gen; }
+};
+
 // ---------------------------------------------------------------------------
 // forward sweep
 // ---------------------------------------------------------------------------
@@ -398,7 +411,7 @@ __global__ void __launch_bounds__(256)
 k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
              const NodeState* __restrict__ st, const int32_t* __restrict__ ipos,
              const int64_t* __restrict__ gat_ptr, const int64_t* __restrict__ gat_src, int m,
-             const double* __restrict__ R, T* __restrict__ rb, int32_t* __restrict__ live, int gen) {
+             const double* __restrict__ R, T* __restrict__ rb, SweepMarks mk) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -443,7 +456,10 @@ k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
 #pragma unroll
   for (int c = 0; c < 16; ++c) nz |= v[c] != (T)0;
   const unsigned long long anyw = __ballot(nz);  // one store per wave
-  if (anyw && (int)(threadIdx.x & 63) == __ffsll((long long)anyw) - 1) live[j] = gen;
+  if (anyw && (int)(threadIdx.x & 63) == __ffsll((long long)anyw) - 1) {
+    mk.live[j] = mk.gen;
+    if (mk.rootof) mk.tree[mk.rootof[j]] = mk.gen;
+  }
   T* dst = rb + (ni.rhs_off + pr) * m + c0;
   if (nc == 16) {
     __builtin_memcpy(dst, v, 16 * sizeof(T));
@@ -539,9 +555,11 @@ k_fwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes
 template <class T>
 __global__ void __launch_bounds__(256)
 k_bwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
-             const int32_t* __restrict__ border, int m, const double* __restrict__ Y, T* __restrict__ rb) {
+             const int32_t* __restrict__ border, int m, const double* __restrict__ Y, T* __restrict__ rb,
+             SweepMarks mk) {
   // one thread per (border row, block of 16 right-hand sides)
   const int j = lnodes[blockIdx.y];
+  if (mk.zero_tree(j)) return;
   const NodeInfo ni = nodes[j];
   const int nch = (m + 15) >> 4;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -573,9 +591,10 @@ __global__ void __launch_bounds__(256)
 k_bwd_border_part(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
                   const NodeState* __restrict__ st, const T* __restrict__ front,
                   T* rb, int m, int maxch, int maxp, T* __restrict__ part, const T* __restrict__ dval,
-                  const T* __restrict__ zb) {
+                  const T* __restrict__ zb, SweepMarks mk) {
   const int q = blockIdx.z;
   const int j = lnodes[q];
+  if (mk.zero_tree(j)) return;
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
   const int cs = blockIdx.x * 64;
@@ -617,9 +636,10 @@ template <class T>
 __global__ void __launch_bounds__(256)
 k_bwd_border_fin(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
                  const NodeState* __restrict__ st, const T* __restrict__ dval, int m, int maxch, int maxp,
-                 const T* __restrict__ part, const T* __restrict__ zb, T* __restrict__ rb) {
+                 const T* __restrict__ part, const T* __restrict__ zb, T* __restrict__ rb, SweepMarks mk) {
   const int q = blockIdx.y;
   const int j = lnodes[q];
+  if (mk.zero_tree(j)) return;
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -637,7 +657,7 @@ template <class T, int KB, bool NODE>
 __global__ void __launch_bounds__(256)
 k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
            const NodeState* __restrict__ st, InvSrc<T> inv, const int32_t* __restrict__ piv, int J0, int tb,
-           int m, double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb) {
+           int m, double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb, SweepMarks mk) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -645,6 +665,15 @@ k_bwd_diag(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ node
   const int nc = min(tb, npiv - J0);
   const int I = blockIdx.x;
   if (SB * I >= nc) return;
+  if (mk.zero_tree(j)) {  // x = 0
+    const int nr = min(SB, nc - SB * I), cz = J0 + SB * I;
+    for (int e = threadIdx.x; e < nr * m; e += blockDim.x) {
+      const int r = e / m, c = e - r * m;
+      zb[(ni.rhs_off + cz + r) * m + c] = (T)0;
+      Y[(int64_t)piv[ni.start + cz + r] * m + c] = 0.0;
+    }
+    return;
+  }
   int ld;
   const T* X = inverse_of<NODE>(inv, j, J0, ld) + (int64_t)SB * I * ld;  // A(c, r) = X[c*ld + r]
   const T* W = rb + (ni.rhs_off + J0) * m;
@@ -672,11 +701,11 @@ template <class T, int KB>
 __global__ void __launch_bounds__(256)
 k_bwd_upd(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
           const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int tb, int m,
-          const T* __restrict__ zb, T* __restrict__ rb) {
+          const T* __restrict__ zb, T* __restrict__ rb, SweepMarks mk) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
-  if (J0 >= npiv) return;
+  if (J0 >= npiv || mk.zero_tree(j)) return;
   const int cs = blockIdx.x * 64;
   if (cs >= J0) return;
   const int nc = min(tb, npiv - J0);
@@ -879,7 +908,7 @@ template <class T, int NCB, bool LONG>
 __global__ void __launch_bounds__(LONG ? 512 : 256)
 k_bwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
              const NodeState* __restrict__ st, InvSrc<T> inv, const int32_t* __restrict__ piv, int J0, int tb,
-             int m, double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb) {
+             int m, double* __restrict__ Y, const T* __restrict__ rb, T* __restrict__ zb, SweepMarks mk) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
@@ -888,6 +917,15 @@ k_bwd_diag_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ no
   const int r0 = 16 * blockIdx.x;
   if (r0 >= nc) return;
   const int nrows = min(16, nc - r0);
+  if (mk.zero_tree(j)) {  // x = 0
+    const int cz = J0 + r0;
+    for (int e = threadIdx.x; e < nrows * m; e += blockDim.x) {
+      const int r = e / m, c = e - r * m;
+      zb[(ni.rhs_off + cz + r) * m + c] = (T)0;
+      Y[(int64_t)piv[ni.start + cz + r] * m + c] = 0.0;
+    }
+    return;
+  }
   int ld;
   const T* X = inverse_of<LONG>(inv, j, J0, ld) + (int64_t)r0 * ld;  // A(k, r) = X[r ld + k]
   const T* W = rb + (ni.rhs_off + J0) * m;
@@ -909,11 +947,11 @@ template <class T, int NCB>
 __global__ void __launch_bounds__(256)
 k_bwd_upd_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
             const NodeState* __restrict__ st, const T* __restrict__ front, int J0, int tb, int m,
-            const T* __restrict__ zb, T* __restrict__ rb) {
+            const T* __restrict__ zb, T* __restrict__ rb, SweepMarks mk) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
-  if (J0 >= npiv) return;
+  if (J0 >= npiv || mk.zero_tree(j)) return;
   const int cs = 16 * blockIdx.x;
   if (cs >= J0) return;
   const int nc = min(tb, npiv - J0);
@@ -1126,7 +1164,7 @@ k_fwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
             const NodeState* __restrict__ st, const int32_t* __restrict__ ipos,
             const int64_t* __restrict__ gat_ptr, const int64_t* __restrict__ gat_src, int m,
             const double* __restrict__ R, const float* __restrict__ front, const int64_t* __restrict__ linv2_off,
-            const float* __restrict__ linv2, float* __restrict__ rb, float* __restrict__ zb) {
+            const float* __restrict__ linv2, float* __restrict__ rb, float* __restrict__ zb, SweepMarks mk) {
   constexpr int MT = TB / 16 / FRONT_NW;  // 16-row tiles of the pivot block per wave
   constexpr int W = FrontRow<NCB>::W, LD = FrontRow<NCB>::LD;
   constexpr bool SPLIT = NCB == 1;
@@ -1164,6 +1202,7 @@ k_fwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
     for (int e = tid; e < npiv * m; e += FRONT_NT) Z[e] = 0.f;
     return;
   }
+  if (tid == 0 && mk.rootof) mk.tree[mk.rootof[j]] = mk.gen;
   const float* X = linv2 + linv2_off[j];  // the front's single step, column-major TB x TB
   const int ntile = (npiv + 15) / 16;
   hf_f4 zt[MT][1][NCB];
@@ -1253,13 +1292,20 @@ k_bwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
             const NodeState* __restrict__ st, const float* __restrict__ front,
             const int64_t* __restrict__ linv2_off, const float* __restrict__ linv2, const int32_t* __restrict__ piv,
             const int32_t* __restrict__ border, const float* __restrict__ dval, int m, double* __restrict__ Y,
-            const float* __restrict__ zb) {
+            const float* __restrict__ zb, SweepMarks mk) {
   constexpr int MT = TB / 16 / FRONT_NW;
   constexpr int W = FrontRow<NCB>::W, LD = FrontRow<NCB>::LD;
   __shared__ float sh[FrontBwdRows<NCB>::value][LD];
   const int j = lnodes[blockIdx.x];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
+  if (mk.zero_tree(j)) {  // x = 0
+    for (int e = threadIdx.x; e < npiv * m; e += FRONT_NT) {
+      const int r = e / m, c = e - r * m;
+      Y[(int64_t)piv[ni.start + r] * m + c] = 0.0;
+    }
+    return;
+  }
   const int f = ni.f, p = ni.p, b = ni.b;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15;
   if (npiv == 0) return;
@@ -1413,9 +1459,10 @@ __global__ void __launch_bounds__(256)
 k_bwd_border_n(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
                const NodeState* __restrict__ st, const T* __restrict__ front,
                T* rb, int m, int maxch, int maxp, T* __restrict__ part, const T* __restrict__ dval,
-               const T* __restrict__ zb) {
+               const T* __restrict__ zb, SweepMarks mk) {
   const int q = blockIdx.z;
   const int j = lnodes[q];
+  if (mk.zero_tree(j)) return;
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
   const int cs = blockIdx.x * 16;
@@ -1512,18 +1559,20 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   }
   // per front: the number of the last application whose gathered forward block
   // had a nonzero (written by the gathers; no clearing between applications)
-  if (ctx->d_live.bytes < (size_t)std::max(ctx->n_nodes, 1) * sizeof(int32_t)) {
-    ctx->d_live.alloc((size_t)std::max(ctx->n_nodes, 1) * sizeof(int32_t));
+  const size_t nmark = (size_t)std::max(ctx->n_nodes, 1) * sizeof(int32_t);
+  if (ctx->d_live.bytes < nmark || ctx->d_tree_live.bytes < nmark || ctx->live_gen == INT32_MAX) {
+    // new arrays, or all numbers used: start again from cleared ones
+    ctx->d_live.alloc(nmark);
+    ctx->d_tree_live.alloc(nmark);
     HF_HIP(hipMemsetAsync(ctx->d_live.ptr, 0, ctx->d_live.bytes, s));
-    ctx->live_gen = 0;
-  }
-  if (ctx->live_gen == INT32_MAX) {  // all numbers used: start again from a cleared array
-    HF_HIP(hipMemsetAsync(ctx->d_live.ptr, 0, ctx->d_live.bytes, s));
+    HF_HIP(hipMemsetAsync(ctx->d_tree_live.ptr, 0, ctx->d_tree_live.bytes, s));
     ctx->live_gen = 0;
   }
   ++ctx->live_gen;
   int32_t* live = ctx->d_live.as<int32_t>();
   const int gen = ctx->live_gen;
+  const SweepMarks mk{live, ctx->d_tree_live.as<int32_t>(),
+                      ctx->n_roots > 1 ? (const int32_t*)ctx->d_rootof.as<int32_t>() : nullptr, gen};
   // the backward sweep writes every row of the moderate part; the hard part's rows
   // (also read as border values) stay zero
   if (ctx->M > 0)
@@ -1557,7 +1606,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
                      fcb == 1 ? k_fwd_front<1> : fcb == 2 ? k_fwd_front<2> : k_fwd_front<4>, dim3(nl), dim3(FRONT_NT),
                      ln, nodes,
                      st, (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
-                     (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, front, loff2, linv2, rb, zb);
+                     (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, front, loff2, linv2, rb, zb, mk);
         continue;
       }
     }
@@ -1572,7 +1621,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     launch_timed(tm, HF_K_SOLVE_GATHER, wg.first, wg.second, s, k_fwd_gather<T>,
                  dim3(cdiv((int64_t)maxf * cdiv(m, 16), 256), nl), dim3(256), ln, nodes, st,
                  (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
-                 (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, rb, live, gen);
+                 (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, rb, mk);
     const bool op = one_pass(l);
     const int tb = op ? ALL : step_of(nl);
     const int span = op ? maxp : tb;  // rows of one diagonal product
@@ -1636,7 +1685,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
                      fcb == 1 ? k_bwd_front<1> : fcb == 2 ? k_bwd_front<2> : k_bwd_front<4>, dim3(nl),
                      dim3(FRONT_NT), ln, nodes, st, front, loff2, linv2, (const int32_t*)ctx->d_piv.as<int32_t>(),
                      (const int32_t*)ctx->d_border.as<int32_t>(), (const float*)ctx->d_dval.as<float>(), m, Y,
-                     (const float*)zb);
+                     (const float*)zb, mk);
         continue;
       }
     }
@@ -1656,7 +1705,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       });
       timed(tm, HF_K_SOLVE_GATHER, wy.first, 0.0, s, [&] {
         dim3 gy(cdiv((int64_t)ctx->level_maxb[l] * cdiv(m, 16), 256), nl);
-        k_bwd_gather<T><<<gy, 256, 0, s>>>(ln, nodes, ctx->d_border.as<int32_t>(), m, Y, rb);
+        k_bwd_gather<T><<<gy, 256, 0, s>>>(ln, nodes, ctx->d_border.as<int32_t>(), m, Y, rb, mk);
       });
       dim3 gp(cdiv(maxp, 64), maxch, nl);
       const T* dv = ctx->d_dval.as<T>();
@@ -1665,11 +1714,11 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       if (ncb == 1)
         launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
                      fused_fin ? k_bwd_border_n<T, 1, true> : k_bwd_border_n<T, 1, false>, gn, dim3(256), ln, nodes,
-                     st, front, rb, m, maxch, maxp, part, dv, (const T*)zb);
+                     st, front, rb, m, maxch, maxp, part, dv, (const T*)zb, mk);
       else
         launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
                      fused_fin ? k_bwd_border_part<T, KBN / 2, true> : k_bwd_border_part<T, KBN / 2, false>, gp,
-                     dim3(256), ln, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb);
+                     dim3(256), ln, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb, mk);
     }
     if (!fused_fin) {
       auto wf = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
@@ -1677,7 +1726,8 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       });
       timed(tm, HF_K_SOLVE_GATHER, wf.first, wf.second, s, [&] {
         dim3 gf(cdiv((int64_t)maxp * m, 256), nl);
-        k_bwd_border_fin<T><<<gf, 256, 0, s>>>(ln, nodes, st, ctx->d_dval.as<T>(), m, maxch, maxp, part, zb, rb);
+        k_bwd_border_fin<T><<<gf, 256, 0, s>>>(ln, nodes, st, ctx->d_dval.as<T>(), m, maxch, maxp, part, zb, rb,
+                                               mk);
       });
     }
     const bool op = one_pass(l);
@@ -1696,13 +1746,13 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s,
                        op ? k_bwd_diag<T, KBW, true> : k_bwd_diag<T, KBW, false>, g, dim3(256), ln, nodes, st, inv,
-                       ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
+                       ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb, mk);
         else
           launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s,
                        op ? pick(k_bwd_diag_n<T, 1, true>, k_bwd_diag_n<T, 2, true>, k_bwd_diag_n<T, 4, true>)
                           : pick(k_bwd_diag_n<T, 1, false>, k_bwd_diag_n<T, 2, false>, k_bwd_diag_n<T, 4, false>),
                        dim3(cdiv(span, 16), nl),
-                       dim3(op ? 512 : 256), ln, nodes, st, inv, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb);
+                       dim3(op ? 512 : 256), ln, nodes, st, inv, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb, mk);
       }
       if (J0 > 0) {
         dim3 g(cdiv(J0, 64), nl);
@@ -1714,11 +1764,11 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         });
         if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, k_bwd_upd<T, KBW>, g, dim3(256), ln, nodes, st,
-                       front, J0, tb, m, zb, rb);
+                       front, J0, tb, m, zb, rb, mk);
         else
           launch_timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s,
                        pick(k_bwd_upd_n<T, 1>, k_bwd_upd_n<T, 2>, k_bwd_upd_n<T, 4>), dim3(cdiv(J0, 16), nl),
-                       dim3(256), ln, nodes, st, front, J0, tb, m, zb, rb);
+                       dim3(256), ln, nodes, st, front, J0, tb, m, zb, rb, mk);
       }
     }
   }
