@@ -449,8 +449,28 @@ int analyse_impl(int64_t n, const int64_t* indptr_h, const int32_t* indices_h, c
       // the root of every node's tree (nodes are numbered children first)
       std::vector<int32_t> rootof(std::max(n_nodes, 1), 0);
       for (int32_t j = n_nodes - 1; j >= 0; --j) rootof[j] = par[j] >= 0 ? rootof[par[j]] : j;
+      // independent trees (no root has a border): the sweeps and block GCR may
+      // leave out the trees a right-hand side does not touch
       ctx->n_roots = 0;
-      for (int32_t j = 0; j < n_nodes; ++j) ctx->n_roots += par[j] < 0;
+      bool indep = true;
+      for (int32_t j = 0; j < n_nodes; ++j)
+        if (par[j] < 0) {
+          ++ctx->n_roots;
+          indep = indep && ctx->nodes[j].b == 0;
+        }
+      if (!indep) ctx->n_roots = 1;
+      // the rows spanned by every tree (block GCR runs on the trees its
+      // right-hand sides touch), and the tree of every row
+      ctx->tree_lo.assign(std::max(n_nodes, 1), INT64_MAX);
+      ctx->tree_hi.assign(std::max(n_nodes, 1), 0);
+      ctx->row_tree.assign((size_t)n, 0);
+      for (int32_t j = 0; j < n_nodes; ++j) {
+        const int32_t r = rootof[j];
+        const NodeInfo& ni = ctx->nodes[j];
+        ctx->tree_lo[r] = std::min<int64_t>(ctx->tree_lo[r], ni.start);
+        ctx->tree_hi[r] = std::max<int64_t>(ctx->tree_hi[r], (int64_t)ni.start + ni.p);
+        for (int32_t g = ni.start; g < ni.start + ni.p; ++g) ctx->row_tree[g] = r;
+      }
       upload(ctx->d_rootof, rootof, s);
     }
     upload(ctx->d_ninv_cnode, ctx->ninv_cnode, s);

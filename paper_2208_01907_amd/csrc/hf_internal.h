@@ -236,6 +236,8 @@ struct hf_ctx {
   hf::DBuf d_tree_live;            // per tree root: the same for any front of the tree
   hf::DBuf d_rootof;               // per node: the root of its tree
   int32_t n_roots = 0;             // trees of the forest
+  std::vector<int64_t> tree_lo, tree_hi;  // per tree root: rows [lo, hi) its nodes span
+  std::vector<int32_t> row_tree;   // per row (elimination order): the root of its tree
   int32_t live_gen = 0;
   hf::DBuf d_isl2, d_flag;         // uint8 mask [n], error flags
   int32_t factor_prec = 0;         // precision of d_front

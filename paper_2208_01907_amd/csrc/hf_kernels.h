@@ -187,6 +187,9 @@ void node_inverses(hf_ctx* ctx, hipStream_t s);
 // Q^{-1} of Sec. 3.2: Y = (L D L^T)^{-1} R on the moderate part, R and Y row-major
 // n x m in elimination order, FP64; factors in T.
 template <class T>
-void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s);
+// [lo, hi): rows outside hold no data of R (whole trees of a forest that the
+// right-hand sides do not touch; their fronts are taken as zero, their rows of Y
+// come out zero); hi < 0: all rows
+void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s, int64_t lo = 0, int64_t hi = -1);
 
 }  // namespace hf

@@ -38,14 +38,16 @@ static inline int kchunk(int k, int c) { return std::min(KC, k - c * KC); }
 
 // Y = K11 W (rows and columns of the hard part masked out); one thread per (row,
 // pair of columns), the pair moved in 16-byte pieces
-__global__ void k_spmm_k11(int64_t n, const int64_t* __restrict__ ip, const int32_t* __restrict__ ix,
-                           const double* __restrict__ kv, const uint8_t* __restrict__ isl2, int m,
-                           const double* __restrict__ W, double* __restrict__ Y) {
+__global__ void k_spmm_k11(int64_t row0, int64_t row1, const int64_t* __restrict__ ip,
+                           const int32_t* __restrict__ ix, const double* __restrict__ kv,
+                           const uint8_t* __restrict__ isl2, int m, const double* __restrict__ W,
+                           double* __restrict__ Y) {
   const int mh = (m + 1) >> 1;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t row = e / mh;
-  const int col = 2 * (int)(e - row * mh);
-  if (row >= n) return;
+  const int64_t rr = e / mh;
+  const int col = 2 * (int)(e - rr * mh);
+  const int64_t row = row0 + rr;
+  if (row >= row1) return;
   const bool two = col + 1 < m;
   double acc0 = 0.0, acc1 = 0.0;
   if (!isl2[row]) {
@@ -953,12 +955,16 @@ static void gram(hf_ctx* ctx, int64_t n, int a, const double* A, int64_t sA, int
   });
 }
 
-static void spmm_k11(hf_ctx* ctx, int m, const double* W, double* Y, hipStream_t s) {
-  const int64_t nm = ctx->n * m;
-  if (nm == 0) return;
-  const double by = ctx->nnz * 12.0 + ctx->n * 8.0 + 2.0 * nm * 8.0, fl = 2.0 * ctx->nnz * m;
-  launch_timed(ctx->timer, HF_K_SPMM, by, fl, s, k_spmm_k11, dim3((unsigned)cdiv(ctx->n * ((m + 1) / 2), 256)),
-               dim3(256), ctx->n,
+// rows [lo, hi) of Y = K11 W (hi < 0: all rows)
+static void spmm_k11(hf_ctx* ctx, int m, const double* W, double* Y, hipStream_t s, int64_t lo = 0,
+                     int64_t hi = -1) {
+  if (hi < 0) hi = ctx->n;
+  const int64_t nr = hi - lo, nm = nr * m;
+  if (nm <= 0) return;
+  const double frac = ctx->n ? (double)nr / (double)ctx->n : 0.0;
+  const double by = frac * ctx->nnz * 12.0 + nr * 8.0 + 2.0 * nm * 8.0, fl = 2.0 * frac * ctx->nnz * m;
+  launch_timed(ctx->timer, HF_K_SPMM, by, fl, s, k_spmm_k11, dim3((unsigned)cdiv(nr * ((m + 1) / 2), 256)),
+               dim3(256), lo, hi,
                ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(), ctx->d_kval.as<double>(),
                ctx->d_isl2.as<uint8_t>(), m, W, Y);
 }
@@ -973,22 +979,32 @@ static void combine(hf_ctx* ctx, int64_t n, int a, int b, double* out, const dou
                base, nterms, V, sV, coef);
 }
 
-static void precond(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s) {
-  if (ctx->factor_prec == HF_PREC_FP32) precond_apply<float>(ctx, m, R, Y, s);
-  else precond_apply<double>(ctx, m, R, Y, s);
+static void precond(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s, int64_t lo = 0,
+                    int64_t hi = -1) {
+  if (ctx->factor_prec == HF_PREC_FP32) precond_apply<float>(ctx, m, R, Y, s, lo, hi);
+  else precond_apply<double>(ctx, m, R, Y, s, lo, hi);
 }
 
 // Algorithm 5 on A = K11 for m right-hand sides B (row-major n x m, zero on the
 // hard part); X receives the solution.  Returns the iteration count.
-static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipStream_t s) {
-  const int64_t n = ctx->n;
+static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipStream_t s, int64_t lo = 0,
+                int64_t hi = -1) {
+  // rows [lo, hi) carry the iteration: outside them B is zero and K11 couples
+  // nothing to them (whole trees of a forest), so X stays zero there (written by
+  // the first preconditioner application) and every other vector is only read
+  // and written inside
+  if (hi < 0) hi = ctx->n;
+  const int64_t n = hi - lo;
   const int64_t nm = n * m;
   BgcrWork& w = get_work(ctx, m);
-  const int64_t sv = (int64_t)n * m;
-  double* P = w.P.as<double>();
-  double* Qv = w.Qv.as<double>();
-  double* R = w.R.as<double>();
-  double* Z = w.Z.as<double>();
+  const int64_t sv = ctx->n * m;  // slot stride: whole vectors (the preconditioner writes all rows)
+  const int64_t o = lo * m;  // offset of the rows that carry the iteration
+  double* P = w.P.as<double>() + o;
+  double* Qv = w.Qv.as<double>() + o;
+  double* R = w.R.as<double>() + o;
+  double* Z = w.Z.as<double>() + o;
+  const double* Bo = B + o;
+  double* Xo = X + o;
   double* G = w.gram.as<double>();
   double* Lc = w.Lc.as<double>();
   int32_t* piv = w.piv.as<int32_t>();
@@ -1014,7 +1030,7 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
     std::copy(w.hnorm, w.hnorm + m, out);
   };
   // ||b_k||^2
-  colsq(B, hb.data());
+  colsq(Bo, hb.data());
   for (int k = 0; k < m; ++k) bn2[k] = hb[k];
   // the run's residual history (max relative residual over the active columns)
   struct HistEnd {
@@ -1035,13 +1051,13 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
     return ok;
   };
   // X0 = Q^{-1} B, R0 = B - A X0
-  precond(ctx, m, B, X, s);
-  spmm_k11(ctx, m, X, Z, s);
-  k_sub<<<cdiv(nm, 256), 256, 0, s>>>(nm, B, Z, R);
+  precond(ctx, m, B, X, s, lo, hi);
+  spmm_k11(ctx, m, X, Z - o, s, lo, hi);
+  k_sub<<<cdiv(nm, 256), 256, 0, s>>>(nm, Bo, Z, R);
   if (converged(R)) return 0;
   // P0 = Q^{-1} R0, Qv0 = A P0, M0
-  precond(ctx, m, R, P, s);
-  spmm_k11(ctx, m, P, Qv, s);
+  precond(ctx, m, R - o, P - o, s, lo, hi);
+  spmm_k11(ctx, m, P - o, Qv - o, s, lo, hi);
   gram(ctx, n, m, Qv, 0, 1, m, Qv, G, s);
   k_chol_piv<<<1, 256, 0, s>>>(m, G, 0, Lc, piv, rank, rel);
   const int maxit = ctx->opt.gcr_maxit;
@@ -1052,7 +1068,7 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
     gram(ctx, n, m, Qn, 0, 1, m, R, G, s);
     k_chol_solve<<<1, 1024, 0, s>>>(m, m, Lc + (int64_t)it * m * m, piv + (int64_t)it * m, rank + it, G, 0,
                                   coef, 0, 1.0);
-    combine(ctx, n, m, m, X, X, 1, Pn, 0, coef, s);
+    combine(ctx, n, m, m, Xo, Xo, 1, Pn, 0, coef, s);
     k_neg<<<cdiv((int64_t)m * m, 256), 256, 0, s>>>((int64_t)m * m, coef);
     combine(ctx, n, m, m, R, R, 1, Qn, 0, coef, s);
     HF_HIP(hipGetLastError());
@@ -1061,8 +1077,8 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
     // W = Q^{-1} R -> P_{n+1}; Z = A W -> Qv_{n+1}
     double* Pn1 = P + (it + 1) * sv;
     double* Qn1 = Qv + (it + 1) * sv;
-    precond(ctx, m, R, Pn1, s);
-    spmm_k11(ctx, m, Pn1, Qn1, s);
+    precond(ctx, m, R - o, Pn1 - o, s, lo, hi);
+    spmm_k11(ctx, m, Pn1 - o, Qn1 - o, s, lo, hi);
     // beta_m = -M_m^{-1} Qv_m^T Z, for m = 0..n
     const int nb = it + 1;
     gram(ctx, n, m, Qv, sv, nb, m, Qn1, G, s);
@@ -1153,7 +1169,16 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
         k_gather_k12<<<nbc, 256, 0, s>>>(ctx->d_pindptr.as<int64_t>(), ctx->d_pindices.as<int32_t>(),
                                          ctx->d_kval.as<double>(), ctx->d_isl2.as<uint8_t>(),
                                          ctx->d_l2.as<int32_t>(), c0, nbc, mb, Bk);
-        const int its = bgcr(ctx, mb, Bk, X12 + (int64_t)blk * n * mb, ctx->opt.gcr_tol, s);
+        // the rows of the trees the block's columns live in (K11 couples no two
+        // trees of a forest; a single tree: all rows)
+        int64_t lo = n, hi = 0;
+        for (int c = c0; c < c0 + nbc; ++c) {
+          const int32_t r = ctx->row_tree[ctx->lambda2[c]];
+          lo = std::min(lo, ctx->tree_lo[r]);
+          hi = std::max(hi, ctx->tree_hi[r]);
+        }
+        if (ctx->n_roots <= 1 || lo >= hi) lo = 0, hi = n;
+        const int its = bgcr(ctx, mb, Bk, X12 + (int64_t)blk * n * mb, ctx->opt.gcr_tol, s, lo, hi);
         ctx->gcr_iters_max = std::max(ctx->gcr_iters_max, its);
         ctx->gcr_iters_total += its;
       }

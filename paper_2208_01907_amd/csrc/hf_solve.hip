@@ -411,10 +411,11 @@ __global__ void __launch_bounds__(256)
 k_fwd_gather(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nodes,
              const NodeState* __restrict__ st, const int32_t* __restrict__ ipos,
              const int64_t* __restrict__ gat_ptr, const int64_t* __restrict__ gat_src, int m,
-             const double* __restrict__ R, T* __restrict__ rb, SweepMarks mk) {
+             const double* __restrict__ R, T* __restrict__ rb, SweepMarks mk, int64_t rlo, int64_t rhi) {
   const int j = lnodes[blockIdx.y];
   const NodeInfo ni = nodes[j];
   const int npiv = st[j].npiv;
+  if (ni.start >= rhi || ni.start + ni.p <= rlo) return;  // outside the rows that hold data: a zero front
   const int nch = (m + 15) >> 4;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)ni.f * nch) return;
@@ -1164,7 +1165,8 @@ k_fwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
             const NodeState* __restrict__ st, const int32_t* __restrict__ ipos,
             const int64_t* __restrict__ gat_ptr, const int64_t* __restrict__ gat_src, int m,
             const double* __restrict__ R, const float* __restrict__ front, const int64_t* __restrict__ linv2_off,
-            const float* __restrict__ linv2, float* __restrict__ rb, float* __restrict__ zb, SweepMarks mk) {
+            const float* __restrict__ linv2, float* __restrict__ rb, float* __restrict__ zb, SweepMarks mk,
+            int64_t rlo, int64_t rhi) {
   constexpr int MT = TB / 16 / FRONT_NW;  // 16-row tiles of the pivot block per wave
   constexpr int W = FrontRow<NCB>::W, LD = FrontRow<NCB>::LD;
   constexpr bool SPLIT = NCB == 1;
@@ -1177,6 +1179,11 @@ k_fwd_front(const int32_t* __restrict__ lnodes, const NodeInfo* __restrict__ nod
   const int npiv = st[j].npiv;
   const int f = ni.f, p = ni.p, b = ni.b;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, li = lane & 15;
+  if (ni.start >= rhi || ni.start + p <= rlo) {  // outside the rows that hold data: z = 0
+    float* Z = zb + ni.rhs_off * m;
+    for (int e = tid; e < npiv * m; e += FRONT_NT) Z[e] = 0.f;
+    return;
+  }
   // one thread per front row: every load of a row is issued at once
   int nz = 0;
   for (int a = tid; a < f; a += FRONT_NT) {
@@ -1500,7 +1507,8 @@ __global__ void k_zero_rows(int M, int m, const int32_t* __restrict__ rows, doub
 }
 
 template <class T>
-void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s) {
+void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s, int64_t lo, int64_t hi) {
+  const int64_t rlo = lo, rhi = hi < 0 ? ctx->n : hi;
   if (m < 1 || m > 64) throw Status{HF_ERR_ARG};  // the sweep tiles hold at most 64 columns
   // Stage sizes of the tile products: launches over few fronts are latency
   // bound (one workgroup per CU, long stages, few round trips); launches over
@@ -1606,7 +1614,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
                      fcb == 1 ? k_fwd_front<1> : fcb == 2 ? k_fwd_front<2> : k_fwd_front<4>, dim3(nl), dim3(FRONT_NT),
                      ln, nodes,
                      st, (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
-                     (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, front, loff2, linv2, rb, zb, mk);
+                     (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, front, loff2, linv2, rb, zb, mk, rlo, rhi);
         continue;
       }
     }
@@ -1621,7 +1629,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
     launch_timed(tm, HF_K_SOLVE_GATHER, wg.first, wg.second, s, k_fwd_gather<T>,
                  dim3(cdiv((int64_t)maxf * cdiv(m, 16), 256), nl), dim3(256), ln, nodes, st,
                  (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
-                 (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, rb, mk);
+                 (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, rb, mk, rlo, rhi);
     const bool op = one_pass(l);
     const int tb = op ? ALL : step_of(nl);
     const int span = op ? maxp : tb;  // rows of one diagonal product
@@ -1779,7 +1787,7 @@ template void step_inverses<float>(hf_ctx*, int, hipStream_t);
 template void step_inverses<double>(hf_ctx*, int, hipStream_t);
 template void node_inverses<float>(hf_ctx*, hipStream_t);
 template void node_inverses<double>(hf_ctx*, hipStream_t);
-template void precond_apply<float>(hf_ctx*, int, const double*, double*, hipStream_t);
-template void precond_apply<double>(hf_ctx*, int, const double*, double*, hipStream_t);
+template void precond_apply<float>(hf_ctx*, int, const double*, double*, hipStream_t, int64_t, int64_t);
+template void precond_apply<double>(hf_ctx*, int, const double*, double*, hipStream_t, int64_t, int64_t);
 
 }  // namespace hf
