@@ -30,6 +30,7 @@ constexpr int MAXM = 64;       // widest block handled by the small dense kernel
 // with it stays within the small kernels' width.
 constexpr int KC = MAXM;
 constexpr int KMAX = 1024;     // largest kernel dimension handled
+constexpr int S22_LDS_M = 8192;  // S22 solves keep their work column (M doubles) in LDS up to this M
 static inline int kchunk(int k, int c) { return std::min(KC, k - c * KC); }
 
 // ---------------------------------------------------------------------------
@@ -641,76 +642,100 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
 }
 
 // Null vectors of S22: N2 = P^T [-L11^{-T} L21^T; I_k], stored in column chunks
-// of KC columns (chunk c: row-major rows x kc at N2 + c rows KC)
-__global__ void k_s22_null(int M, int k, const double* __restrict__ L, const int32_t* __restrict__ perm,
-                           int rows, double* __restrict__ N2c) {
-  // the backward substitution runs on a work column in LDS (dynamic, M * blockDim
-  // doubles) when M <= MAXM, else directly on the rows of N2
+// of KC columns (chunk c: row-major rows x kc at N2 + c rows KC).  One workgroup
+// per kernel column q: y = L11^{-T} l with l = row r+q of L (first r entries),
+// by backward substitution taken a column at a time: each final y_t is
+// broadcast and its multiple of row t of L (column t of Lt = L^T) leaves the
+// earlier positions, last position first.  y sits in LDS (M doubles) when
+// M <= S22_LDS_M, else directly in the rows of N2.
+__global__ void __launch_bounds__(1024)
+k_s22_null(int M, int k, const double* __restrict__ Lt, const int32_t* __restrict__ perm, int rows,
+           double* __restrict__ N2c) {
   extern __shared__ double sm[];
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= k) return;
+  const int q = blockIdx.x, tid = threadIdx.x, NT = blockDim.x;
   const int r = M - k;
-  const bool lds = M <= MAXM;
+  const bool lds = M <= S22_LDS_M;
   const int kc = min(KC, k - (q / KC) * KC), qc = q % KC;
   double* N2 = N2c + (int64_t)(q / KC) * rows * KC;  // this column's chunk, kc columns
-  double* y = lds ? sm + threadIdx.x : nullptr;
-  const int ys = blockDim.x;
-  auto Y = [&](int i) -> double& { return lds ? y[i * ys] : N2[(int64_t)perm[i] * kc + qc]; };
-  // Y = L11^{-T} L21^T[:, q] by backward substitution
-  for (int i = 0; i < M; ++i) Y(i) = 0.0;
-  for (int i = r - 1; i >= 0; --i) {
-    double v = at(const_cast<double*>(L), M, r + q, i);
-    for (int t = i + 1; t < r; ++t) v -= at(const_cast<double*>(L), M, t, i) * Y(t);
-    Y(i) = v;
+  auto Y = [&](int i) -> double& { return lds ? sm[i] : N2[(int64_t)perm[i] * kc + qc]; };
+  const double* l = Lt + (int64_t)(r + q) * M;  // row r+q of L
+  for (int i = tid; i < r; i += NT) Y(i) = l[i];
+  __syncthreads();
+  for (int t = r - 1; t > 0; --t) {
+    const double yt = Y(t);
+    const double* Lr = Lt + (int64_t)t * M;
+    for (int i = tid; i < t; i += NT) Y(i) -= Lr[i] * yt;
+    __syncthreads();
   }
-  for (int i = 0; i < r; ++i) N2[(int64_t)perm[i] * kc + qc] = -Y(i);
-  for (int t = 0; t < k; ++t) N2[(int64_t)perm[r + t] * kc + qc] = (t == q) ? 1.0 : 0.0;
+  for (int i = tid; i < r; i += NT) {
+    const double v = Y(i);
+    N2[(int64_t)perm[i] * kc + qc] = -v;
+  }
+  for (int t = tid; t < k; t += NT) N2[(int64_t)perm[r + t] * kc + qc] = (t == q) ? 1.0 : 0.0;
 }
 
-// x = S22^+ y restricted to the nonsingular pivots (kernel pivots get 0).
-// Y, X: row-major M x nc.  One thread per column.
-__global__ void k_s22_solve(int M, int k, const double* __restrict__ L, const double* __restrict__ D,
-                            const int32_t* __restrict__ perm, const int32_t* __restrict__ bsize, int nc,
-                            const double* __restrict__ Y, double* __restrict__ X, double* __restrict__ work) {
-  // when M <= MAXM, L and every column's work vector live in LDS (dynamic:
-  // (M*M + M*blockDim) doubles); otherwise both stay in global memory
-  extern __shared__ double sm[];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool lds = M <= MAXM;
-  if (lds)
-    for (int e = threadIdx.x; e < M * M; e += blockDim.x) sm[e] = L[e];
-  __syncthreads();
-  if (c >= nc) return;
-  double* z = lds ? sm + M * M + threadIdx.x : work + (int64_t)c * M;
-  const int zs = lds ? blockDim.x : 1;
-  double* Lm = lds ? sm : const_cast<double*>(L);
-  double* Dm = const_cast<double*>(D);
-  for (int i = 0; i < M; ++i) {
-    double v = Y[(int64_t)perm[i] * nc + c];
-    for (int t = 0; t < i; ++t) v -= at(Lm, M, i, t) * z[t * zs];
-    z[i * zs] = v;
+// Lt = L^T for a square column-major M x M matrix (32 x 32 tiles through LDS)
+__global__ void __launch_bounds__(256) k_transpose_sq(int M, const double* __restrict__ A, double* __restrict__ At) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32, tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int j = ty; j < 32; j += 8) {
+    const int r = bx + tx, c = by + j;
+    if (r < M && c < M) tile[j][tx] = A[(int64_t)c * M + r];
   }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int r = by + tx, c = bx + j;
+    if (r < M && c < M) At[(int64_t)c * M + r] = tile[tx][j];
+  }
+}
+
+// x = S22^+ y restricted to the nonsingular pivots (kernel pivots get 0), for
+// M > 64.  Y, X: row-major M x nc.  One workgroup per column.  The forward
+// substitution walks the columns of L: z_i loses L_it z_t for t = 0, 1, ... in
+// turn, the order of row-by-row substitution.  The backward one subtracts the
+// multiple of each final position from the earlier ones, last position first
+// (the order of k_s22_solve_w), reading the rows of L as columns of Lt = L^T.
+// The work column sits in LDS (M doubles) when M <= S22_LDS_M, else at
+// work + c M.
+__global__ void __launch_bounds__(1024)
+k_s22_solve(int M, int k, const double* __restrict__ L, const double* __restrict__ Lt, const double* __restrict__ D,
+            const int32_t* __restrict__ perm, const int32_t* __restrict__ bsize, int nc,
+            const double* __restrict__ Y, double* __restrict__ X, double* __restrict__ work) {
+  extern __shared__ double sm[];
+  const int c = blockIdx.x, tid = threadIdx.x, NT = blockDim.x;
+  double* z = M <= S22_LDS_M ? sm : work + (int64_t)c * M;
+  for (int i = tid; i < M; i += NT) z[i] = Y[(int64_t)perm[i] * nc + c];
+  __syncthreads();
+  for (int t = 0; t + 1 < M; ++t) {
+    const double zt = z[t];
+    const double* Lc = L + (int64_t)t * M;
+    for (int i = t + 1 + tid; i < M; i += NT) z[i] -= Lc[i] * zt;
+    __syncthreads();
+  }
+  // D: a 2x2 block is solved by the thread of its first position
   const int r = M - k;
-  for (int i = 0; i < M;) {
-    if (i >= r) { z[i * zs] = 0.0; ++i; continue; }
-    if (bsize[i] == 2 && i + 1 < r) {
-      const double e11 = at(Dm, M, i, i), e12 = at(Dm, M, i + 1, i), e22 = at(Dm, M, i + 1, i + 1);
+  for (int i = tid; i < M; i += NT) {
+    if (i >= r) {
+      z[i] = 0.0;
+    } else if (bsize[i] == 2 && i + 1 < r) {
+      const double e11 = at(const_cast<double*>(D), M, i, i), e12 = at(const_cast<double*>(D), M, i + 1, i);
+      const double e22 = at(const_cast<double*>(D), M, i + 1, i + 1);
       const double det = e11 * e22 - e12 * e12;
-      const double a = z[i * zs], b = z[(i + 1) * zs];
-      z[i * zs] = (a * e22 - b * e12) / det;
-      z[(i + 1) * zs] = (b * e11 - a * e12) / det;
-      i += 2;
-    } else {
-      z[i * zs] = z[i * zs] / at(Dm, M, i, i);
-      ++i;
+      const double a = z[i], b = z[i + 1];
+      z[i] = (a * e22 - b * e12) / det;
+      z[i + 1] = (b * e11 - a * e12) / det;
+    } else if (!(i > 0 && bsize[i - 1] == 2)) {
+      z[i] = z[i] / at(const_cast<double*>(D), M, i, i);
     }
   }
-  for (int i = M - 1; i >= 0; --i) {
-    double v = z[i * zs];
-    for (int t = i + 1; t < M; ++t) v -= at(Lm, M, t, i) * z[t * zs];
-    z[i * zs] = v;
+  __syncthreads();
+  for (int t = M - 1; t > 0; --t) {
+    const double zt = z[t];
+    const double* Lr = Lt + (int64_t)t * M;
+    for (int i = tid; i < t; i += NT) z[i] -= Lr[i] * zt;
+    __syncthreads();
   }
-  for (int i = 0; i < M; ++i) X[(int64_t)perm[i] * nc + c] = z[i * zs];
+  for (int i = tid; i < M; i += NT) X[(int64_t)perm[i] * nc + c] = z[i];
 }
 
 // The same for M <= 64: one workgroup, each wave takes columns in turn and holds
@@ -1213,6 +1238,9 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
       HF_HIP(hipMemcpyAsync(Aw, S, sizeof(double) * M * M, hipMemcpyDeviceToDevice, s));
       k_s22_ldlt<<<1, S22_NT, 0, s>>>(M, Aw, Lw, Dw, sperm, ctx->d_s22mag.as<double>(), sbs, ctx->opt.tau,
                                    ctx->opt.n_enlarge, ctx->opt.ker_tol, ctx->d_s22info.as<double>());
+      // the working copy is spent: it takes L^T, whose columns are the rows of L
+      // that the backward substitutions read
+      k_transpose_sq<<<dim3(cdiv(M, 32), cdiv(M, 32)), 256, 0, s>>>(M, Lw, Aw);
       double info[4];
       HF_HIP(hipMemcpyAsync(info, ctx->d_s22info.ptr, sizeof(info), hipMemcpyDeviceToHost, s));
       HF_HIP(hipStreamSynchronize(s));
@@ -1232,8 +1260,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
       ctx->d_N2.alloc((size_t)rows * KC * nkc * sizeof(double));
       double* N2 = ctx->d_N2.as<double>();
       HF_HIP(hipMemsetAsync(N2, 0, (size_t)rows * KC * nkc * sizeof(double), s));
-      k_s22_null<<<(k + 63) / 64, 64, M <= MAXM ? (size_t)M * 64 * sizeof(double) : 0, s>>>(M, k, Lw, sperm, rows,
-                                                                                              N2);
+      k_s22_null<<<k, 1024, M <= S22_LDS_M ? (size_t)M * sizeof(double) : 0, s>>>(M, k, Aw, sperm, rows, N2);
       ctx->d_kern.alloc((size_t)n * KC * nkc * sizeof(double));
       double* Nall = ctx->d_kern.as<double>();
       ctx->d_ktmp.alloc((size_t)n * KC * 2 * sizeof(double));
@@ -1298,11 +1325,11 @@ static int solve_core(hf_ctx* ctx, int m, const double* b, double* x, double* b1
     double* S = ctx->d_S22f.as<double>();
     const int64_t MM = (int64_t)M * M;
     int32_t* sperm = ctx->d_s22perm.as<int32_t>();
-    const size_t s22_lds = M <= MAXM ? (size_t)(M * M + M * 64) * sizeof(double) : 0;
     if (M <= MAXM)
       k_s22_solve_w<<<1, 1024, 0, s>>>(M, k, S + MM, S + 2 * MM, sperm, sperm + M, m, y2, x2);
-    else
-      k_s22_solve<<<1, 64, s22_lds, s>>>(M, k, S + MM, S + 2 * MM, sperm, sperm + M, m, y2, x2, wk);
+    else  // S holds [L^T | L | D]
+      k_s22_solve<<<m, 1024, M <= S22_LDS_M ? (size_t)M * sizeof(double) : 0, s>>>(
+          M, k, S + MM, S, S + 2 * MM, sperm, sperm + M, m, y2, x2, wk);
     // x1 = y1 - X12 x2 (x2 rows padded per block)
     const int mb = ctx->mb;
     ctx->d_x2pad.alloc((size_t)ctx->nblk * mb * m * sizeof(double));
