@@ -15,6 +15,9 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <type_traits>
+
+#include <hip/hip_cooperative_groups.h>
 
 #include "hf_internal.h"
 #include "hf_kernels.h"
@@ -30,6 +33,7 @@ constexpr int MAXM = 64;       // widest block handled by the small dense kernel
 // with it stays within the small kernels' width.
 constexpr int KC = MAXM;
 constexpr int KMAX = 1024;     // largest kernel dimension handled
+constexpr int S22_GRID_MAXM = 2048;  // largest S22 factorized over a cooperative grid
 constexpr int S22_LDS_M = 8192;  // S22 solves keep their work column (M doubles) in LDS up to this M
 static inline int kchunk(int k, int c) { return std::min(KC, k - c * KC); }
 
@@ -485,6 +489,8 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
   __shared__ int rk[NW];
   __shared__ double sA[MAXM * MAXM];  // the working copy stays in LDS when it fits
   double* A = (M <= MAXM) ? sA : Ag;
+  // otherwise LDS holds the step's column(s) of L, read by every trailing column
+  const bool stage = M > MAXM && 2 * M <= MAXM * MAXM;
   if (M <= MAXM)
     for (int e = tid; e < M * M; e += NT) sA[e] = Ag[e];
   // workgroup argmax of (v, k): largest v, ties to the smallest k; uniform result
@@ -557,14 +563,31 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
       swap(i, i + kd);
       const double d = at(A, M, i, i);
       at(D, M, i, i) = d;
-      for (int r = i + 1 + tid; r < M; r += NT) at(L, M, r, i) = at(A, M, r, i) / d;
+      for (int r = i + 1 + tid; r < M; r += NT) {
+        const double l = at(A, M, r, i) / d;
+        at(L, M, r, i) = l;
+        if (stage) sA[r] = l;
+      }
       __syncthreads();
-      for (int c = i + 1 + wv; c < M; c += NW)
-        for (int r = i + 1 + lane; r < M; r += 64) {
-          const double v = at(A, M, r, c) - at(L, M, r, i) * at(A, M, i, c);
-          at(A, M, r, c) = v;
+      const double* li = stage ? sA : L + (int64_t)i * M;  // li[r] = L(r, i)
+      for (int c = i + 1 + wv; c < M; c += NW) {
+        const double aic = at(A, M, i, c);
+        double* Ac = A + (int64_t)c * M;
+        int r = i + 1 + lane;
+        for (; r + 192 < M; r += 256) {  // four rows per lane in flight
+          const double a0 = Ac[r], a1 = Ac[r + 64], a2 = Ac[r + 128], a3 = Ac[r + 192];
+          const double v0 = a0 - li[r] * aic, v1 = a1 - li[r + 64] * aic;
+          const double v2 = a2 - li[r + 128] * aic, v3 = a3 - li[r + 192] * aic;
+          Ac[r] = v0; Ac[r + 64] = v1; Ac[r + 128] = v2; Ac[r + 192] = v3;
+          consider(i + 1, r, c, v0); consider(i + 1, r + 64, c, v1);
+          consider(i + 1, r + 128, c, v2); consider(i + 1, r + 192, c, v3);
+        }
+        for (; r < M; r += 64) {
+          const double v = Ac[r] - li[r] * aic;
+          Ac[r] = v;
           consider(i + 1, r, c, v);
         }
+      }
       __syncthreads();
       for (int r = i + 1 + tid; r < M; r += NT) { at(A, M, r, i) = 0.0; at(A, M, i, r) = 0.0; }
       if (tid == 0) mags[i] = fabs(d);
@@ -579,17 +602,34 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
       // Lc = C E^{-1}, C = A[i+2:, i:i+2]
       for (int rr = i + 2 + tid; rr < M; rr += NT) {
         const double c1 = at(A, M, rr, i), c2 = at(A, M, rr, i + 1);
-        at(L, M, rr, i) = (c1 * e22 - c2 * e12) / det;
-        at(L, M, rr, i + 1) = (c2 * e11 - c1 * e12) / det;
+        const double l0 = (c1 * e22 - c2 * e12) / det, l1 = (c2 * e11 - c1 * e12) / det;
+        at(L, M, rr, i) = l0;
+        at(L, M, rr, i + 1) = l1;
+        if (stage) { sA[rr] = l0; sA[M + rr] = l1; }
       }
       __syncthreads();
-      for (int cc = i + 2 + wv; cc < M; cc += NW)
-        for (int rr = i + 2 + lane; rr < M; rr += 64) {
-          const double v =
-              at(A, M, rr, cc) - (at(L, M, rr, i) * at(A, M, cc, i) + at(L, M, rr, i + 1) * at(A, M, cc, i + 1));
-          at(A, M, rr, cc) = v;
+      const double* l0s = stage ? sA : L + (int64_t)i * M;  // L(rr, i), L(rr, i+1)
+      const double* l1s = stage ? sA + M : L + (int64_t)(i + 1) * M;
+      for (int cc = i + 2 + wv; cc < M; cc += NW) {
+        const double b0 = at(A, M, cc, i), b1 = at(A, M, cc, i + 1);
+        double* Ac = A + (int64_t)cc * M;
+        int rr = i + 2 + lane;
+        for (; rr + 192 < M; rr += 256) {
+          const double a0 = Ac[rr], a1 = Ac[rr + 64], a2 = Ac[rr + 128], a3 = Ac[rr + 192];
+          const double v0 = a0 - (l0s[rr] * b0 + l1s[rr] * b1);
+          const double v1 = a1 - (l0s[rr + 64] * b0 + l1s[rr + 64] * b1);
+          const double v2 = a2 - (l0s[rr + 128] * b0 + l1s[rr + 128] * b1);
+          const double v3 = a3 - (l0s[rr + 192] * b0 + l1s[rr + 192] * b1);
+          Ac[rr] = v0; Ac[rr + 64] = v1; Ac[rr + 128] = v2; Ac[rr + 192] = v3;
+          consider(i + 2, rr, cc, v0); consider(i + 2, rr + 64, cc, v1);
+          consider(i + 2, rr + 128, cc, v2); consider(i + 2, rr + 192, cc, v3);
+        }
+        for (; rr < M; rr += 64) {
+          const double v = Ac[rr] - (l0s[rr] * b0 + l1s[rr] * b1);
+          Ac[rr] = v;
           consider(i + 2, rr, cc, v);
         }
+      }
       __syncthreads();
       for (int rr = i + 2 + tid; rr < M; rr += NT) {
         at(A, M, rr, i) = 0.0; at(A, M, i, rr) = 0.0;
@@ -639,6 +679,244 @@ k_s22_ldlt(int M, double* __restrict__ Ag, double* __restrict__ L, double* __res
     info[2] = M - start;
     info[3] = gap;
   }
+}
+
+// The same factorization over the workgroups of a cooperative grid, for
+// MAXM < M <= S22_GRID_MAXM.  No row or column moves: the pivots are eliminated
+// where they stand, and perm (position -> original index) with its inverse pos
+// replays the interchanges, so the search breaks ties on the same positions and
+// every entry of the trailing block goes through the same operations as above.
+// Workgroup g updates the columns b = g (mod G); each workgroup publishes the
+// best candidates of its columns in a slot (two sets, alternating by step) and
+// one grid barrier per step separates an update from the next search.  Lo
+// receives L by original row (column j: step j); k_s22_lorder puts its rows in
+// position order.
+struct S22Cand {
+  double dv, ov;
+  int dk, ok;
+};
+
+__global__ void __launch_bounds__(S22_NT)
+k_s22_ldlt_grid(int M, double* __restrict__ A, double* __restrict__ Lo, double* __restrict__ D,
+                int32_t* __restrict__ perm_out, double* __restrict__ mags, int32_t* __restrict__ bsize, double tau,
+                int n_enlarge, double ker_tol, double* __restrict__ info, S22Cand* __restrict__ slots) {
+  constexpr int NT = S22_NT, NW = NT / 64;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  extern __shared__ double dsm[];
+  double* l0 = dsm;      // the step's column(s) of L by original row
+  double* l1 = dsm + M;
+  int32_t* perm = reinterpret_cast<int32_t*>(dsm + 2 * M);
+  int32_t* pos = perm + M;
+  __shared__ double rv[NW];
+  __shared__ int rk[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int g = blockIdx.x, G = gridDim.x;
+  const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+  auto argmax = [&](double& v, int& k) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off, 64);
+      const int ok = __shfl_xor(k, off, 64);
+      if (ov > v || (ov == v && ok < k)) { v = ov; k = ok; }
+    }
+    __syncthreads();
+    if (lane == 0) { rv[wv] = v; rk[wv] = k; }
+    __syncthreads();
+    v = rv[0];
+    k = rk[0];
+    for (int w = 1; w < NW; ++w)
+      if (rv[w] > v || (rv[w] == v && rk[w] < k)) { v = rv[w]; k = rk[w]; }
+  };
+  for (int e = tid; e < M; e += NT) { perm[e] = e; pos[e] = e; }
+  for (int64_t e = (int64_t)g * NT + tid; e < (int64_t)M * M; e += (int64_t)G * NT) { Lo[e] = 0.0; D[e] = 0.0; }
+  if (g == 0)
+    for (int e = tid; e < M; e += NT) { mags[e] = 0.0; bsize[e] = 1; }
+  double bv = -1.0, ov = -1.0;
+  int bk = INT_MAX, ok = INT_MAX;
+  auto consider = [&](int i0, int rr, int cc, double v) {  // positions relative to i0
+    const int w = M - i0;
+    const double x = fabs(v);
+    if (rr == cc) {
+      if (x > bv || (x == bv && rr < bk)) { bv = x; bk = rr; }
+    } else if (rr < cc) {
+      const int e = rr * w + cc;
+      if (x > ov || (x == ov && e < ok)) { ov = x; ok = e; }
+    }
+  };
+  for (int b = g + wv * G; b < M; b += NW * G)  // the first block, upper triangle
+    for (int a = lane; a <= b; a += 64) consider(0, a, b, A[(int64_t)b * M + a]);
+  __syncthreads();
+  const int nown = (M - g + G - 1) / G, nch = (M + 255) / 256;
+  int i = 0, it = 0;
+  while (i < M) {
+    const int w = M - i;
+    argmax(bv, bk);
+    argmax(ov, ok);
+    S22Cand* sl = slots + (it & 1) * G;
+    if (tid == 0) sl[g] = S22Cand{bv, ov, bk, ok};
+    grid.sync();
+    bv = -1.0; ov = -1.0; bk = INT_MAX; ok = INT_MAX;
+    if (tid < G) { const S22Cand c = sl[tid]; bv = c.dv; bk = c.dk; ov = c.ov; ok = c.ok; }
+    argmax(bv, bk);
+    argmax(ov, ok);
+    const double gd = bv, go = (w > 1) ? ov : 0.0;
+    const int kd = bk, s_r = (w > 1) ? ok / w : 0, s_c = (w > 1) ? ok % w : 0;
+    bv = -1.0; ov = -1.0; bk = INT_MAX; ok = INT_MAX;
+    int mode;
+    if (gd == 0.0 && go == 0.0) mode = 0;
+    else if (gd >= alpha * go) mode = 1;
+    else mode = 2;
+    if (mode == 0) break;
+    __syncthreads();  // every thread has read perm / pos of the last step
+    if (tid == 0) {
+      auto swp = [&](int x, int y) {
+        const int32_t u = perm[x], v = perm[y];
+        perm[x] = v; perm[y] = u; pos[v] = x; pos[u] = y;
+      };
+      if (mode == 1) swp(i, i + kd);
+      else { swp(i, i + s_r); swp(i + 1, i + s_c); }
+    }
+    __syncthreads();
+    const int p = perm[i], q = mode == 2 ? perm[i + 1] : p;
+    const int i0 = i + mode;
+    const double* Ap = A + (int64_t)p * M;
+    const double* Aq = A + (int64_t)q * M;
+    if (mode == 1) {
+      const double d = Ap[p];
+      for (int a = tid; a < M; a += NT)
+        if (pos[a] >= i0) l0[a] = Ap[a] / d;
+      if (g == 0 && tid == 0) { at(D, M, i, i) = d; mags[i] = fabs(d); }
+    } else {
+      const double e11 = Ap[p], e12 = Ap[q], e22 = Aq[q];
+      const double det = e11 * e22 - e12 * e12;
+      for (int a = tid; a < M; a += NT)
+        if (pos[a] >= i0) {
+          const double c1 = Ap[a], c2 = Aq[a];
+          l0[a] = (c1 * e22 - c2 * e12) / det;
+          l1[a] = (c2 * e11 - c1 * e12) / det;
+        }
+      if (g == 0 && tid == 0) {
+        at(D, M, i, i) = e11; at(D, M, i + 1, i) = e12; at(D, M, i, i + 1) = e12; at(D, M, i + 1, i + 1) = e22;
+        const double h = 0.5 * (e11 + e22), qq = sqrt(0.25 * (e11 - e22) * (e11 - e22) + e12 * e12);
+        const double mg = fmin(fabs(h - qq), fabs(h + qq));
+        mags[i] = mg; mags[i + 1] = mg;
+        bsize[i] = 2; bsize[i + 1] = 0;
+      }
+    }
+    __syncthreads();
+    if (g == 0)
+      for (int a = tid; a < M; a += NT)
+        if (pos[a] >= i0) {
+          Lo[(int64_t)i * M + a] = l0[a];
+          if (mode == 2) Lo[(int64_t)(i + 1) * M + a] = l1[a];
+        }
+    // the 1x1 and 2x2 updates are separate instantiations, each with the
+    // expression of the single-workgroup kernel
+    auto update = [&](auto two) {
+      constexpr bool TWO = decltype(two)::value;
+      for (int t = wv; t < nown * nch; t += NW) {
+        const int j = t / nch, ch = t - j * nch;
+        const int b = g + j * G;
+        const int pb = pos[b];
+        if (pb < i0) continue;
+        double* Ab = A + (int64_t)b * M;
+        const double cp = TWO ? Ap[b] : Ab[p];  // A(p, b); A(b, p) and A(b, q) for a 2x2 pivot
+        const double cq = TWO ? Aq[b] : 0.0;
+        const int a0 = ch * 256 + lane;
+        double x[4];
+        int pa[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int a = a0 + 64 * u;
+          pa[u] = a < M ? pos[a] : -1;
+          x[u] = pa[u] >= i0 ? Ab[a] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int a = a0 + 64 * u;
+          if (pa[u] >= i0) {
+            double v;
+            if constexpr (TWO) v = x[u] - (l0[a] * cp + l1[a] * cq);
+            else v = x[u] - l0[a] * cp;
+            Ab[a] = v;
+            consider(i0, pa[u] - i0, pb - i0, v);
+          }
+        }
+      }
+    };
+    if (mode == 1) update(std::false_type{});
+    else update(std::true_type{});
+    __syncthreads();
+    i = i0;
+    ++it;
+  }
+  if (g != 0) return;
+  for (int e = tid; e < M; e += NT) perm_out[e] = perm[e];
+  if (tid == 0) {
+    int t = M;
+    double prev = 1.0;
+    for (int q = 0; q < M; ++q) {
+      if (mags[q] == 0.0 || mags[q] < tau * prev) { t = q; break; }
+      prev = mags[q];
+    }
+    const int postponed = M - t;
+    const int e = postponed > 0 ? min(n_enlarge, t) : 0;
+    int start = t - e;
+    if (start > 0 && start < M && bsize[start] == 0) --start;
+    int k = 0;
+    for (int q = M - 1; q >= start; --q) {
+      if (mags[q] <= ker_tol) ++k;
+      else break;
+    }
+    double gap = INFINITY;
+    if (k > 0 && start < M - k) {
+      double mn = INFINITY, mx = 0.0;
+      for (int q = start; q < M - k; ++q) mn = fmin(mn, mags[q]);
+      for (int q = M - k; q < M; ++q) mx = fmax(mx, mags[q]);
+      gap = mn / fmax(mx, 1e-300);
+    }
+    info[0] = k;
+    info[1] = postponed;
+    info[2] = M - start;
+    info[3] = gap;
+  }
+}
+
+// L in position order from Lo (rows by original index): L(r, j) = Lo(perm_r, j)
+// below the diagonal, 1 on it, 0 above
+__global__ void k_s22_lorder(int M, const double* __restrict__ Lo, const int32_t* __restrict__ perm,
+                             double* __restrict__ L) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)M * M) return;
+  const int j = (int)(e / M), r = (int)(e - (int64_t)j * M);
+  L[e] = r == j ? 1.0 : (r > j ? Lo[(int64_t)j * M + perm[r]] : 0.0);
+}
+
+// Launches k_s22_ldlt_grid when the device runs cooperative grids that hold one
+// workgroup per CU; false (nothing launched) otherwise.
+static bool s22_ldlt_grid(hf_ctx* ctx, int M, double* A, double* Lo, double* D, int32_t* perm, int32_t* bs,
+                          hipStream_t s) {
+  int dev = 0, coop = 0, ncu = 0, nb = 0;
+  HF_HIP(hipGetDevice(&dev));
+  HF_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  HF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  size_t lds = (size_t)M * (2 * sizeof(double) + 2 * sizeof(int32_t));
+  HF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_s22_ldlt_grid, S22_NT, lds));
+  if (!coop || nb < 1 || ncu < 1) return false;
+  int G = std::min(ncu, (M + 7) / 8);  // about 8 columns per workgroup
+  ctx->d_s22slots.alloc((size_t)2 * G * sizeof(S22Cand));
+  S22Cand* slots = ctx->d_s22slots.as<S22Cand>();
+  double* mags = ctx->d_s22mag.as<double>();
+  double* info = ctx->d_s22info.as<double>();
+  double tau = ctx->opt.tau, ker_tol = ctx->opt.ker_tol;
+  int n_enlarge = ctx->opt.n_enlarge;
+  void* args[] = {&M, &A, &Lo, &D, &perm, &mags, &bs, &tau, &n_enlarge, &ker_tol, &info, &slots};
+  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_s22_ldlt_grid), dim3(G),
+                                                  dim3(S22_NT), args, (unsigned)lds, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
 }
 
 // Null vectors of S22: N2 = P^T [-L11^{-T} L21^T; I_k], stored in column chunks
@@ -1213,7 +1491,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
     // step 4: S22 = K22 - K21 X12 (symmetrized); step 5: its LDL^T and kernel
     t0 = std::chrono::steady_clock::now();
     ctx->d_S22.alloc((size_t)std::max(M, 1) * std::max(M, 1) * sizeof(double));
-    ctx->d_S22f.alloc((size_t)std::max(M, 1) * std::max(M, 1) * sizeof(double) * 3);
+    ctx->d_S22f.alloc((size_t)std::max(M, 1) * std::max(M, 1) * sizeof(double) * 4);
     ctx->d_s22perm.alloc((size_t)std::max(M, 1) * sizeof(int32_t) * 2);
     if (M > 46340) throw Status{HF_ERR_NOT_IMPLEMENTED};  // S22 positions are int32 in its factorization
     ctx->d_s22mag.alloc((size_t)std::max(M, 1) * sizeof(double));
@@ -1222,6 +1500,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
     double* Aw = ctx->d_S22f.as<double>();
     double* Lw = Aw + (int64_t)std::max(M, 1) * std::max(M, 1);
     double* Dw = Lw + (int64_t)std::max(M, 1) * std::max(M, 1);
+    double* Lo = Dw + (int64_t)std::max(M, 1) * std::max(M, 1);  // L by original row (grid factorization)
     int32_t* sperm = ctx->d_s22perm.as<int32_t>();
     int32_t* sbs = sperm + std::max(M, 1);
     ctx->kdim = 0;
@@ -1236,8 +1515,11 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
       }
       k_symmetrize<<<cdiv((int64_t)M * M, 256), 256, 0, s>>>(M, S);
       HF_HIP(hipMemcpyAsync(Aw, S, sizeof(double) * M * M, hipMemcpyDeviceToDevice, s));
-      k_s22_ldlt<<<1, S22_NT, 0, s>>>(M, Aw, Lw, Dw, sperm, ctx->d_s22mag.as<double>(), sbs, ctx->opt.tau,
-                                   ctx->opt.n_enlarge, ctx->opt.ker_tol, ctx->d_s22info.as<double>());
+      if (M > MAXM && M <= S22_GRID_MAXM && s22_ldlt_grid(ctx, M, Aw, Lo, Dw, sperm, sbs, s))
+        k_s22_lorder<<<cdiv((int64_t)M * M, 256), 256, 0, s>>>(M, Lo, sperm, Lw);
+      else
+        k_s22_ldlt<<<1, S22_NT, 0, s>>>(M, Aw, Lw, Dw, sperm, ctx->d_s22mag.as<double>(), sbs, ctx->opt.tau,
+                                     ctx->opt.n_enlarge, ctx->opt.ker_tol, ctx->d_s22info.as<double>());
       // the working copy is spent: it takes L^T, whose columns are the rows of L
       // that the backward substitutions read
       k_transpose_sq<<<dim3(cdiv(M, 32), cdiv(M, 32)), 256, 0, s>>>(M, Lw, Aw);
