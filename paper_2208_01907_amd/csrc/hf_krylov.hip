@@ -707,24 +707,28 @@ k_s22_ldlt_grid(int M, double* __restrict__ A, double* __restrict__ Lo, double* 
   double* l1 = dsm + M;
   int32_t* perm = reinterpret_cast<int32_t*>(dsm + 2 * M);
   int32_t* pos = perm + M;
-  __shared__ double rv[NW];
-  __shared__ int rk[NW];
+  __shared__ double rv[2][NW];
+  __shared__ int rk[2][NW];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int g = blockIdx.x, G = gridDim.x;
   const double alpha = (1.0 + sqrt(17.0)) / 8.0;
-  auto argmax = [&](double& v, int& k) {
+  // workgroup argmax of both candidate pairs at once (largest value, ties to the
+  // smallest index); uniform result
+  auto argmax2 = [&](double& v, int& k, double& u, int& m) {
     for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off, 64);
-      const int ok = __shfl_xor(k, off, 64);
+      const double ov = __shfl_xor(v, off, 64), ou = __shfl_xor(u, off, 64);
+      const int ok = __shfl_xor(k, off, 64), om = __shfl_xor(m, off, 64);
       if (ov > v || (ov == v && ok < k)) { v = ov; k = ok; }
+      if (ou > u || (ou == u && om < m)) { u = ou; m = om; }
     }
     __syncthreads();
-    if (lane == 0) { rv[wv] = v; rk[wv] = k; }
+    if (lane == 0) { rv[0][wv] = v; rk[0][wv] = k; rv[1][wv] = u; rk[1][wv] = m; }
     __syncthreads();
-    v = rv[0];
-    k = rk[0];
-    for (int w = 1; w < NW; ++w)
-      if (rv[w] > v || (rv[w] == v && rk[w] < k)) { v = rv[w]; k = rk[w]; }
+    v = rv[0][0]; k = rk[0][0]; u = rv[1][0]; m = rk[1][0];
+    for (int w = 1; w < NW; ++w) {
+      if (rv[0][w] > v || (rv[0][w] == v && rk[0][w] < k)) { v = rv[0][w]; k = rk[0][w]; }
+      if (rv[1][w] > u || (rv[1][w] == u && rk[1][w] < m)) { u = rv[1][w]; m = rk[1][w]; }
+    }
   };
   for (int e = tid; e < M; e += NT) { perm[e] = e; pos[e] = e; }
   for (int64_t e = (int64_t)g * NT + tid; e < (int64_t)M * M; e += (int64_t)G * NT) { Lo[e] = 0.0; D[e] = 0.0; }
@@ -749,15 +753,13 @@ k_s22_ldlt_grid(int M, double* __restrict__ A, double* __restrict__ Lo, double* 
   int i = 0, it = 0;
   while (i < M) {
     const int w = M - i;
-    argmax(bv, bk);
-    argmax(ov, ok);
+    argmax2(bv, bk, ov, ok);
     S22Cand* sl = slots + (it & 1) * G;
     if (tid == 0) sl[g] = S22Cand{bv, ov, bk, ok};
     grid.sync();
     bv = -1.0; ov = -1.0; bk = INT_MAX; ok = INT_MAX;
     if (tid < G) { const S22Cand c = sl[tid]; bv = c.dv; bk = c.dk; ov = c.ov; ok = c.ok; }
-    argmax(bv, bk);
-    argmax(ov, ok);
+    argmax2(bv, bk, ov, ok);
     const double gd = bv, go = (w > 1) ? ov : 0.0;
     const int kd = bk, s_r = (w > 1) ? ok / w : 0, s_c = (w > 1) ? ok % w : 0;
     bv = -1.0; ov = -1.0; bk = INT_MAX; ok = INT_MAX;
@@ -902,7 +904,7 @@ static bool s22_ldlt_grid(hf_ctx* ctx, int M, double* A, double* Lo, double* D, 
   size_t lds = (size_t)M * (2 * sizeof(double) + 2 * sizeof(int32_t));
   HF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_s22_ldlt_grid, S22_NT, lds));
   if (!coop || nb < 1 || ncu < 1) return false;
-  int G = std::min(ncu, (M + 7) / 8);  // about 8 columns per workgroup
+  int G = std::min(ncu, (M + 15) / 16);  // about 16 columns per workgroup
   ctx->d_s22slots.alloc((size_t)2 * G * sizeof(S22Cand));
   S22Cand* slots = ctx->d_s22slots.as<S22Cand>();
   double* mags = ctx->d_s22mag.as<double>();
