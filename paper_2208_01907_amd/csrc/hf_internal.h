@@ -247,6 +247,8 @@ struct hf_ctx {
   int32_t M = 0;
   // X12 in column blocks (row-major n x mb each), S22 and its factorization
   hf::DBuf d_X12, d_S22, d_S22f, d_s22perm, d_s22mag, d_s22info, d_s22slots, d_N2, d_kern, d_ktmp, d_tune;
+  std::vector<int64_t> x12_rng;  // rows [lo, hi) of each block of X12 (zero outside)
+  hf::DBuf d_x12rng;
   int32_t mb = 0, nblk = 0;
   int32_t kdim = 0;
   double rank_gap = 0.0;

@@ -430,29 +430,62 @@ k_chol_solve(int m, int nc, const double* __restrict__ Lc, const int32_t* __rest
 // cores).
 __global__ void __launch_bounds__(256)
 k_combine(int64_t n, int a, int b, double* out, const double* base, int nterms,
-          const double* __restrict__ V, int64_t sV, const double* __restrict__ coef) {
+          const double* __restrict__ V, int64_t sV, const double* __restrict__ coef,
+          const int64_t* __restrict__ rng) {
+  constexpr int NE = CKB * 64 / 256;
   const int r0 = blockIdx.x * 64;
   const int nrows = (int)min((int64_t)64, n - r0);
   __shared__ double As[CKB][GLD];
   __shared__ double Bs[CKB][GLD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int K = a * nterms;
   Mfma<double>::V acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = Mfma<double>::V{0, 0, 0, 0};
-  tile_gemm_64<double, CKB, GLD, true>(
-      acc, As, Bs, 0, a * nterms,
-      [&](int k, int r) {
-        const int t = k / a, kk = k - t * a;
-        return r < nrows ? V[t * sV + (int64_t)(r0 + r) * a + kk] : 0.0;
-      },
-      [&](int k, int c) {
-        const int t = k / a, kk = k - t * a;
-        return c < b ? coef[((int64_t)t * a + kk) * b + c] : 0.0;
-      },
-      tid, lane, wr, wc);
+  // with rng (a a multiple of CKB), term t holds zeros outside rows
+  // [rng[2t], rng[2t+1]): its stages are skipped on tiles outside them, which
+  // leaves out exact zero products only
+  auto next = [&](int k0) {
+    if (rng)
+      while (k0 < K) {
+        const int t = k0 / a;
+        if (r0 + 64 > rng[2 * t] && r0 < rng[2 * t + 1]) break;
+        k0 += CKB;
+      }
+    return k0;
+  };
+  double ra[NE], rb[NE];
+  auto fetch = [&](int k0) {  // A contiguous in k
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + 256 * q;
+      const int kq = e % CKB, row = e / CKB;
+      const int k = k0 + kq, t = k / a, kk = k - t * a;
+      ra[q] = (k < K && row < nrows) ? V[t * sV + (int64_t)(r0 + row) * a + kk] : 0.0;
+      const int kb = k0 + (e >> 6), col = e & 63;
+      const int tb = kb / a, kkb = kb - tb * a;
+      rb[q] = (kb < K && col < b) ? coef[((int64_t)tb * a + kkb) * b + col] : 0.0;
+    }
+  };
+  int k0 = next(0);
+  if (k0 < K) fetch(k0);
+  while (k0 < K) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int e = tid + 256 * q;
+      As[e % CKB][e / CKB] = ra[q];
+      Bs[e >> 6][e & 63] = rb[q];
+    }
+    __syncthreads();
+    const int k1 = next(k0 + CKB);
+    if (k1 < K) fetch(k1);
+    mfma_tile_64<double, CKB, GLD>(As, Bs, acc, lane, wr, wc);
+    __syncthreads();
+    k0 = k1;
+  }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -1275,13 +1308,28 @@ static void spmm_k11(hf_ctx* ctx, int m, const double* W, double* Y, hipStream_t
 }
 
 // out (n x b) = base + sum_t V_t (n x a) C_t (a x b), row-major blocks
+// rng (device, two per term, or nullptr): the rows outside which a term is zero
 static void combine(hf_ctx* ctx, int64_t n, int a, int b, double* out, const double* base, int nterms,
-                    const double* V, int64_t sV, const double* coef, hipStream_t s) {
+                    const double* V, int64_t sV, const double* coef, hipStream_t s,
+                    const int64_t* rng = nullptr) {
   if (n * b == 0) return;
-  const double by = ((double)nterms * n * a + (base ? 2.0 : 1.0) * n * b) * 8.0;
-  const double fl = 2.0 * n * a * b * (double)nterms;
+  if (a % CKB) rng = nullptr;
+  // algorithmic rows of V: all n per term, or (rng, which is only ever the row
+  // ranges of X12's blocks) the rows each term covers
+  double vrows = (double)nterms * n;
+  if (rng) {
+    vrows = 0.0;
+    for (int t = 0; t < nterms; ++t) vrows += (double)(ctx->x12_rng[2 * t + 1] - ctx->x12_rng[2 * t]);
+  }
+  const double by = (vrows * a + (base ? 2.0 : 1.0) * n * b) * 8.0;
+  const double fl = 2.0 * vrows * a * b;
   launch_timed(ctx->timer, HF_K_COMBINE, by, fl, s, k_combine, dim3((unsigned)cdiv(n, 64)), dim3(256), n, a, b, out,
-               base, nterms, V, sV, coef);
+               base, nterms, V, sV, coef, rng);
+}
+
+// row ranges of the blocks of X12 (nullptr for a single tree: every row)
+static const int64_t* x12_rows(hf_ctx* ctx) {
+  return ctx->n_roots > 1 && ctx->nblk > 0 ? ctx->d_x12rng.as<int64_t>() : nullptr;
 }
 
 static void precond(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s, int64_t lo = 0,
@@ -1465,6 +1513,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
     ctx->gcr_iters_max = ctx->gcr_iters_total = 0;
     ctx->d_X12.alloc((size_t)std::max(ctx->nblk, 1) * std::max<int64_t>(n, 1) * mb * sizeof(double));
     double* X12 = ctx->d_X12.as<double>();
+    ctx->x12_rng.assign((size_t)2 * ctx->nblk, 0);
     if (M > 0) {
       BgcrWork& w = get_work(ctx, mb);
       double* Bk = w.T1.as<double>();
@@ -1483,11 +1532,15 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
           hi = std::max(hi, ctx->tree_hi[r]);
         }
         if (ctx->n_roots <= 1 || lo >= hi) lo = 0, hi = n;
+        ctx->x12_rng[2 * blk] = lo;
+        ctx->x12_rng[2 * blk + 1] = hi;
         const int its = bgcr(ctx, mb, Bk, X12 + (int64_t)blk * n * mb, ctx->opt.gcr_tol, s, lo, hi);
         ctx->gcr_iters_max = std::max(ctx->gcr_iters_max, its);
         ctx->gcr_iters_total += its;
       }
     }
+    // the rows each block of X12 lives in, for the products over all of X12
+    if (ctx->n_roots > 1 && ctx->nblk > 0) upload(ctx->d_x12rng, ctx->x12_rng, s);
     ctx->hist_factor_runs = (int32_t)ctx->hist_ptr.size() - 1;
     ctx->t_gcr = ms_since(t0);
     // step 4: S22 = K22 - K21 X12 (symmetrized); step 5: its LDL^T and kernel
@@ -1556,7 +1609,7 @@ int factorize_impl(hf_ctx* ctx, const double* values, hipStream_t s) {
         const int kc = kchunk(k, c);
         const double* N2c = N2 + (int64_t)c * rows * KC;
         double* Nc = Nall + (int64_t)c * n * KC;
-        combine(ctx, n, mb, kc, Nperm, nullptr, ctx->nblk, X12, (int64_t)n * mb, N2c, s);
+        combine(ctx, n, mb, kc, Nperm, nullptr, ctx->nblk, X12, (int64_t)n * mb, N2c, s, x12_rows(ctx));
         k_neg<<<cdiv(n * kc, 256), 256, 0, s>>>(n * kc, Nperm);
         k_set_rows<<<cdiv((int64_t)M * kc, 256), 256, 0, s>>>(M, kc, ctx->d_l2.as<int32_t>(), N2c, Nperm);
         k_kernel_finish<<<cdiv(n * kc, 256), 256, 0, s>>>(n, kc, ctx->d_perm.as<int32_t>(), ctx->d_q.as<double>(),
@@ -1621,8 +1674,7 @@ static int solve_core(hf_ctx* ctx, int m, const double* b, double* x, double* b1
     HF_HIP(hipMemsetAsync(x2p, 0, (size_t)ctx->nblk * mb * m * sizeof(double), s));
     HF_HIP(hipMemcpyAsync(x2p, x2, (size_t)M * m * sizeof(double), hipMemcpyDeviceToDevice, s));
     k_neg<<<cdiv((int64_t)ctx->nblk * mb * m, 256), 256, 0, s>>>((int64_t)ctx->nblk * mb * m, x2p);
-    combine(ctx, n, mb, m, x, x, ctx->nblk, ctx->d_X12.as<double>(), (int64_t)n * mb,
-                                            x2p, s);
+    combine(ctx, n, mb, m, x, x, ctx->nblk, ctx->d_X12.as<double>(), (int64_t)n * mb, x2p, s, x12_rows(ctx));
     k_set_rows<<<cdiv((int64_t)M * m, 256), 256, 0, s>>>(M, m, ctx->d_l2.as<int32_t>(), x2, x);
   }
   HF_HIP(hipGetLastError());
