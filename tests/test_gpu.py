@@ -50,6 +50,10 @@ CASES = {
     "dense_k2": lambda: w.random_dense_workload(150, seed=10, kernel_dim=2, cond=1e3, r=3),
     "dense_indef_all_postponed": lambda: w.random_dense_workload(40, seed=11, indefinite=True, cond=1e2,
                                                                  r=2, tau=2.0),
+    # M = 100 > 64 with 14 2x2 pivots and k = 2: the cooperative-grid LDL^T of
+    # S22 through its 2x2 branch, the null vectors and the S22 solve with 2x2 blocks
+    "dense_indef100_k2": lambda: w.random_dense_workload(100, seed=13, indefinite=True, kernel_dim=2, cond=1e2,
+                                                         r=2, tau=2.0),
     # batches: independent systems as one block-diagonal forest (k = number of parts)
     "batch6": lambda: w.neumann3d_batch(6, seed=7, lo_n=5, hi_n=9, leaf_max=64, r=2, gcr_block=4),
     "batch_mixed": lambda: w.batch([w.neumann2d(20, 18, seed=13, leaf_max=30, r=2),
