@@ -1547,11 +1547,15 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   KTimer& tm = ctx->timer;
   const double sz = sizeof(T), dm = m;
   // algorithmic work of one launch over a level, with the actual pivot counts
+  // algorithmic work of a level: its fronts inside the rows [rlo, rhi) (the
+  // kernels take the trees outside as zero and skip them)
+  const bool ranged = rlo > 0 || rhi < ctx->n;
   auto level_sum = [&](int l, auto&& fn) {
     double by = 0.0, fl = 0.0;
     if (!tm.on) return std::make_pair(by, fl);
     for (int32_t q = ctx->level_ptr[l]; q < ctx->level_ptr[l + 1]; ++q) {
       const int32_t j = ctx->level_nodes[q];
+      if (ranged && (ctx->nodes[j].start < rlo || ctx->nodes[j].start >= rhi)) continue;
       fn(ctx->nodes[j], (double)ctx->hstate[j].npiv, by, fl);
     }
     return std::make_pair(by, fl);
