@@ -1343,9 +1343,9 @@ static void precond(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t 
 static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipStream_t s, int64_t lo = 0,
                 int64_t hi = -1) {
   // rows [lo, hi) carry the iteration: outside them B is zero and K11 couples
-  // nothing to them (whole trees of a forest), so X stays zero there (written by
-  // the first preconditioner application) and every other vector is only read
-  // and written inside
+  // nothing to them (whole trees of a forest), so X is zero there (set after the
+  // first preconditioner application) and every other vector is only read and
+  // written inside
   if (hi < 0) hi = ctx->n;
   const int64_t n = hi - lo;
   const int64_t nm = n * m;
@@ -1405,6 +1405,10 @@ static int bgcr(hf_ctx* ctx, int m, const double* B, double* X, double tol, hipS
   };
   // X0 = Q^{-1} B, R0 = B - A X0
   precond(ctx, m, B, X, s, lo, hi);
+  if (lo > 0 || hi < ctx->n) {  // the preconditioner need not write the rows outside: X is zero there
+    if (lo > 0) HF_HIP(hipMemsetAsync(X, 0, (size_t)lo * m * sizeof(double), s));
+    if (hi < ctx->n) HF_HIP(hipMemsetAsync(X + hi * m, 0, (size_t)(ctx->n - hi) * m * sizeof(double), s));
+  }
   spmm_k11(ctx, m, X, Z - o, s, lo, hi);
   k_sub<<<cdiv(nm, 256), 256, 0, s>>>(nm, Bo, Z, R);
   if (converged(R)) return 0;

@@ -1550,6 +1550,17 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
   // algorithmic work of a level: its fronts inside the rows [rlo, rhi) (the
   // kernels take the trees outside as zero and skip them)
   const bool ranged = rlo > 0 || rhi < ctx->n;
+  // the slice [q0, q1) of level l's node list (ascending starts) whose fronts lie
+  // in the rows [rlo, rhi): the whole-front kernels are launched over it alone
+  auto level_slice = [&](int l) {
+    const int32_t* b = ctx->level_nodes.data() + ctx->level_ptr[l];
+    const int nl = ctx->level_ptr[l + 1] - ctx->level_ptr[l];
+    if (!ranged) return std::make_pair(0, nl);
+    auto first_at = [&](int64_t r) {  // first position whose front starts at or after row r
+      return (int)(std::lower_bound(b, b + nl, r, [&](int32_t j, int64_t v) { return ctx->nodes[j].start < v; }) - b);
+    };
+    return std::make_pair(first_at(rlo), first_at(rhi));
+  };
   auto level_sum = [&](int l, auto&& fn) {
     double by = 0.0, fl = 0.0;
     if (!tm.on) return std::make_pair(by, fl);
@@ -1614,9 +1625,11 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           for (int32_t q = ni.child_begin; q < ni.child_end; ++q) by += ctx->nodes[ctx->child_list[q]].b * dm * sz;
           fl += dm * np * np + 2.0 * dm * ni.b * np;
         });
+        const auto sl = level_slice(l);
+        if (sl.second > sl.first)
         launch_timed(tm, HF_K_FWD_FRONT, wf.first, wf.second, s,
-                     fcb == 1 ? k_fwd_front<1> : fcb == 2 ? k_fwd_front<2> : k_fwd_front<4>, dim3(nl), dim3(FRONT_NT),
-                     ln, nodes,
+                     fcb == 1 ? k_fwd_front<1> : fcb == 2 ? k_fwd_front<2> : k_fwd_front<4>,
+                     dim3((unsigned)(sl.second - sl.first)), dim3(FRONT_NT), ln + sl.first, nodes,
                      st, (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
                      (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, front, loff2, linv2, rb, zb, mk, rlo, rhi);
         continue;
@@ -1693,9 +1706,11 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           by += ni.b * dm * 8.0 + ni.b * np * sz + np * dm * sz + np * sz + 0.5 * np * np * sz + np * dm * 8.0;
           fl += 2.0 * dm * ni.b * np + dm * np * np;
         });
+        const auto sl = level_slice(l);
+        if (sl.second > sl.first)
         launch_timed(tm, HF_K_BWD_FRONT, wf.first, wf.second, s,
-                     fcb == 1 ? k_bwd_front<1> : fcb == 2 ? k_bwd_front<2> : k_bwd_front<4>, dim3(nl),
-                     dim3(FRONT_NT), ln, nodes, st, front, loff2, linv2, (const int32_t*)ctx->d_piv.as<int32_t>(),
+                     fcb == 1 ? k_bwd_front<1> : fcb == 2 ? k_bwd_front<2> : k_bwd_front<4>,
+                     dim3((unsigned)(sl.second - sl.first)), dim3(FRONT_NT), ln + sl.first, nodes, st, front, loff2, linv2, (const int32_t*)ctx->d_piv.as<int32_t>(),
                      (const int32_t*)ctx->d_border.as<int32_t>(), (const float*)ctx->d_dval.as<float>(), m, Y,
                      (const float*)zb, mk);
         continue;
