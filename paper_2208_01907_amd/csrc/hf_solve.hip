@@ -1635,6 +1635,12 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         continue;
       }
     }
+    // the level-wide launches cover the slice of fronts inside the rows (every
+    // front unless row-restricted); the choice of kernels follows the whole level
+    const auto slv = level_slice(l);
+    if (slv.second == slv.first) continue;
+    const int nls = slv.second - slv.first;
+    const int32_t* lns = ln + slv.first;
     auto wg = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
       by += ni.f * dm * sz + np * dm * 8.0;
       for (int32_t q = ni.child_begin; q < ni.child_end; ++q) {
@@ -1644,7 +1650,7 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
       }
     });
     launch_timed(tm, HF_K_SOLVE_GATHER, wg.first, wg.second, s, k_fwd_gather<T>,
-                 dim3(cdiv((int64_t)maxf * cdiv(m, 16), 256), nl), dim3(256), ln, nodes, st,
+                 dim3(cdiv((int64_t)maxf * cdiv(m, 16), 256), nls), dim3(256), lns, nodes, st,
                  (const int32_t*)ctx->d_ipos.as<int32_t>(), (const int64_t*)ctx->d_gat_ptr.as<int64_t>(),
                  (const int64_t*)ctx->d_gat_src.as<int64_t>(), m, R, rb, mk, rlo, rhi);
     const bool op = one_pass(l);
@@ -1662,14 +1668,14 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         dim3 g(cdiv(span, SB), nl);
         if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s,
-                       op ? k_fwd_diag<T, KBW, true> : k_fwd_diag<T, KBW, false>, g, dim3(256), ln, nodes, st, inv,
+                       op ? k_fwd_diag<T, KBW, true> : k_fwd_diag<T, KBW, false>, dim3(g.x, nls), dim3(256), lns, nodes, st, inv,
                        J0, tb, m, rb, zb, (const int32_t*)live, gen);
         else
           launch_timed(tm, HF_K_FWD_DIAG, wd.first, wd.second, s,
                        op ? pick(k_fwd_diag_n<T, 1, true>, k_fwd_diag_n<T, 2, true>, k_fwd_diag_n<T, 4, true>)
                           : pick(k_fwd_diag_n<T, 1, false>, k_fwd_diag_n<T, 2, false>, k_fwd_diag_n<T, 4, false>),
-                       dim3(cdiv(span, 16), nl),
-                       dim3(op ? 512 : 256), ln, nodes, st, inv, J0, tb, m, rb, zb, (const int32_t*)live, gen);
+                       dim3(cdiv(span, 16), nls),
+                       dim3(op ? 512 : 256), lns, nodes, st, inv, J0, tb, m, rb, zb, (const int32_t*)live, gen);
       }
       const int rows = op ? ctx->level_maxb[l] : maxf - J0 - 1;
       if (rows > 0) {
@@ -1684,14 +1690,14 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         });
         if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s,
-                       op ? k_fwd_upd<T, KBW, true> : k_fwd_upd<T, KBW, false>, g, dim3(256), ln, nodes, st, front,
+                       op ? k_fwd_upd<T, KBW, true> : k_fwd_upd<T, KBW, false>, dim3(g.x, nls), dim3(256), lns, nodes, st, front,
                        J0, tb, m, zb, rb, (const int32_t*)live, gen);
         else
           launch_timed(tm, HF_K_FWD_UPDATE, wu.first, wu.second, s,
                        op ? pick(k_fwd_upd_n<T, 1, true>, k_fwd_upd_n<T, 2, true>, k_fwd_upd_n<T, 4, true>)
                           : pick(k_fwd_upd_n<T, 1, false>, k_fwd_upd_n<T, 2, false>, k_fwd_upd_n<T, 4, false>),
-                       dim3(cdiv(rows, 16), nl),
-                       dim3(op ? 512 : 256), ln, nodes, st, front, J0, tb, m, zb, rb, (const int32_t*)live, gen);
+                       dim3(cdiv(rows, 16), nls),
+                       dim3(op ? 512 : 256), lns, nodes, st, front, J0, tb, m, zb, rb, (const int32_t*)live, gen);
       }
     }
   }
@@ -1716,6 +1722,12 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         continue;
       }
     }
+    // the level-wide launches cover the slice of fronts inside the rows (every
+    // front unless row-restricted); the choice of kernels follows the whole level
+    const auto slv = level_slice(l);
+    if (slv.second == slv.first) continue;
+    const int nls = slv.second - slv.first;
+    const int32_t* lns = ln + slv.first;
     const int maxch = std::max(1, (int)cdiv(ctx->level_maxb[l], RCH));
     // one chunk per front and a border on every front: the product writes t itself
     bool fused_fin = maxch == 1;
@@ -1731,29 +1743,29 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         by += ni.b * dm * (8.0 + sz);
       });
       timed(tm, HF_K_SOLVE_GATHER, wy.first, 0.0, s, [&] {
-        dim3 gy(cdiv((int64_t)ctx->level_maxb[l] * cdiv(m, 16), 256), nl);
-        k_bwd_gather<T><<<gy, 256, 0, s>>>(ln, nodes, ctx->d_border.as<int32_t>(), m, Y, rb, mk);
+        dim3 gy(cdiv((int64_t)ctx->level_maxb[l] * cdiv(m, 16), 256), nls);
+        k_bwd_gather<T><<<gy, 256, 0, s>>>(lns, nodes, ctx->d_border.as<int32_t>(), m, Y, rb, mk);
       });
-      dim3 gp(cdiv(maxp, 64), maxch, nl);
+      dim3 gp(cdiv(maxp, 64), maxch, nls);
       const T* dv = ctx->d_dval.as<T>();
       // 16 columns or fewer: the narrow form; wider blocks: 64x64 tiles staged through LDS
-      dim3 gn(cdiv(maxp, 16), maxch, nl);
+      dim3 gn(cdiv(maxp, 16), maxch, nls);
       if (ncb == 1)
         launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
-                     fused_fin ? k_bwd_border_n<T, 1, true> : k_bwd_border_n<T, 1, false>, gn, dim3(256), ln, nodes,
+                     fused_fin ? k_bwd_border_n<T, 1, true> : k_bwd_border_n<T, 1, false>, gn, dim3(256), lns, nodes,
                      st, front, rb, m, maxch, maxp, part, dv, (const T*)zb, mk);
       else
         launch_timed(tm, HF_K_BWD_BORDER, wb.first, wb.second, s,
                      fused_fin ? k_bwd_border_part<T, KBN / 2, true> : k_bwd_border_part<T, KBN / 2, false>, gp,
-                     dim3(256), ln, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb, mk);
+                     dim3(256), lns, nodes, st, front, rb, m, maxch, maxp, part, dv, (const T*)zb, mk);
     }
     if (!fused_fin) {
       auto wf = level_sum(l, [&](const NodeInfo& ni, double np, double& by, double& fl) {
         by += 3.0 * np * dm * sz;
       });
       timed(tm, HF_K_SOLVE_GATHER, wf.first, wf.second, s, [&] {
-        dim3 gf(cdiv((int64_t)maxp * m, 256), nl);
-        k_bwd_border_fin<T><<<gf, 256, 0, s>>>(ln, nodes, st, ctx->d_dval.as<T>(), m, maxch, maxp, part, zb, rb,
+        dim3 gf(cdiv((int64_t)maxp * m, 256), nls);
+        k_bwd_border_fin<T><<<gf, 256, 0, s>>>(lns, nodes, st, ctx->d_dval.as<T>(), m, maxch, maxp, part, zb, rb,
                                                mk);
       });
     }
@@ -1772,14 +1784,14 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
         dim3 g(cdiv(span, SB), nl);
         if (wide(g) && ncb > 1)
           launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s,
-                       op ? k_bwd_diag<T, KBW, true> : k_bwd_diag<T, KBW, false>, g, dim3(256), ln, nodes, st, inv,
+                       op ? k_bwd_diag<T, KBW, true> : k_bwd_diag<T, KBW, false>, dim3(g.x, nls), dim3(256), lns, nodes, st, inv,
                        ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb, mk);
         else
           launch_timed(tm, HF_K_BWD_DIAG, wd.first, wd.second, s,
                        op ? pick(k_bwd_diag_n<T, 1, true>, k_bwd_diag_n<T, 2, true>, k_bwd_diag_n<T, 4, true>)
                           : pick(k_bwd_diag_n<T, 1, false>, k_bwd_diag_n<T, 2, false>, k_bwd_diag_n<T, 4, false>),
-                       dim3(cdiv(span, 16), nl),
-                       dim3(op ? 512 : 256), ln, nodes, st, inv, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb, mk);
+                       dim3(cdiv(span, 16), nls),
+                       dim3(op ? 512 : 256), lns, nodes, st, inv, ctx->d_piv.as<int32_t>(), J0, tb, m, Y, rb, zb, mk);
       }
       if (J0 > 0) {
         dim3 g(cdiv(J0, 64), nl);
@@ -1790,12 +1802,12 @@ void precond_apply(hf_ctx* ctx, int m, const double* R, double* Y, hipStream_t s
           fl += 2.0 * dm * J0 * nc;
         });
         if (wide(g) && ncb > 1)
-          launch_timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, k_bwd_upd<T, KBW>, g, dim3(256), ln, nodes, st,
+          launch_timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s, k_bwd_upd<T, KBW>, dim3(g.x, nls), dim3(256), lns, nodes, st,
                        front, J0, tb, m, zb, rb, mk);
         else
           launch_timed(tm, HF_K_BWD_UPDATE, wu.first, wu.second, s,
-                       pick(k_bwd_upd_n<T, 1>, k_bwd_upd_n<T, 2>, k_bwd_upd_n<T, 4>), dim3(cdiv(J0, 16), nl),
-                       dim3(256), ln, nodes, st, front, J0, tb, m, zb, rb, mk);
+                       pick(k_bwd_upd_n<T, 1>, k_bwd_upd_n<T, 2>, k_bwd_upd_n<T, 4>), dim3(cdiv(J0, 16), nls),
+                       dim3(256), lns, nodes, st, front, J0, tb, m, zb, rb, mk);
       }
     }
   }
